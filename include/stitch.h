@@ -1,0 +1,203 @@
+/*
+ * stitch.h -- C ABI of the per-frame panorama stitching path on MI355X (gfx950).
+ *
+ * The path is the one the paper runs once registration has fixed each camera's
+ * transformation: every camera frame is transformed onto the panorama with its
+ * pre-corrected parameters (Alg. 4, step 1), and the transformed frames are blended
+ * into the panorama (Alg. 4, step 6) with multi-band fusion to remove seams
+ * (Sec. 1, contribution 3).  Buffers are sized once when the system starts and
+ * reused for every frame (Sec. 4.3.2, space pre-allocation); work is queued
+ * asynchronously on a caller stream (Sec. 4.3.2, operation queues).
+ *
+ * Definitions used by every call (the paper gives none of them; these are the
+ * readings of the textbook Burt-Adelson multiresolution spline):
+ *   - pixel (x, y) = (column, row) is a sample at integer coordinates;
+ *   - a homography H (row-major 3x3, double) maps source pixels to canvas pixels;
+ *     the warp pulls each canvas pixel through adj(H)/adj(H)[2][2] rounded to FP32,
+ *     with FP32 coordinate arithmetic (no fused multiply-add, IEEE divide); a
+ *     sample with non-positive homogeneous z is 0;
+ *   - bilinear interpolation of u8/255; taps outside the source contribute 0;
+ *   - REDUCE: 5x5 separable [1,4,6,4,1]/16 filter, keep even samples, sides
+ *     ceil(n/2); EXPAND: zero-insert at even fine samples, same filter times 4;
+ *     borders reflect-101 (-i -> i, n-1+i -> n-1-i), folded in the fine domain;
+ *     every level side must be >= 3;
+ *   - Laplacian level L_k = G_k - EXPAND(G_{k+1}), top level L_{L-1} = G_{L-1};
+ *   - blend: B_k = sum_i Gm_i^k * L_i^k over cameras, R_{L-1} = B_{L-1},
+ *     R_k = B_k + EXPAND(R_{k+1}), panorama = clamp(rint(255 R_0), 0, 255).
+ *
+ * Memory.  Every data pointer is DEVICE memory owned by the caller (frames,
+ * panorama, pyramids, workspace); the library owns only the host-side plan and
+ * batch objects.  All work is enqueued on the given stream (a hipStream_t; NULL is
+ * the null stream) with no implicit device synchronisation, except where a call
+ * says otherwise.
+ *
+ * Errors.  Every call returns a stitch_status.  Argument errors are detected on the
+ * host before anything is enqueued; a HIP launch failure returns STITCH_E_DEVICE.
+ * Faults during asynchronous execution surface at the caller's next
+ * synchronisation.  stitch_last_error() returns a thread-local message describing
+ * the last failure on the calling thread.  No C++ exception crosses this ABI.
+ * Distinct plans may be used from distinct threads; one plan is not re-entrant.
+ */
+#ifndef STITCH_H
+#define STITCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STITCH_ABI_VERSION 1
+#define STITCH_MAX_LEVELS 16
+#define STITCH_MAX_CAMERAS 64
+
+typedef enum {
+  STITCH_OK = 0,
+  STITCH_E_NULL = 1,        /* a required pointer is NULL */
+  STITCH_E_SHAPE = 2,       /* sizes, channels, layout, pitch or dtype inconsistent */
+  STITCH_E_LEVELS = 3,      /* level count outside 1..16 or a level side < 3 */
+  STITCH_E_HOMOGRAPHY = 4,  /* non-finite H, or adj(H)[2][2] == 0 */
+  STITCH_E_MASK = 5,        /* seam weights do not sum to 255 at some canvas pixel */
+  STITCH_E_WORKSPACE = 6,   /* workspace NULL, too small or not 256-byte aligned */
+  STITCH_E_DEVICE = 7,      /* a HIP runtime call failed */
+  STITCH_E_UNSUPPORTED = 8, /* a dtype/layout combination this build does not provide */
+  STITCH_E_STATE = 9        /* object used in the wrong state (e.g. plan not bound) */
+} stitch_status;
+
+typedef enum { STITCH_U8 = 0, STITCH_F16 = 1, STITCH_F32 = 2 } stitch_dtype;
+typedef enum { STITCH_HWC = 0, STITCH_CHW = 1 } stitch_layout;
+
+/* A caller-owned device image.  HWC: pixel (x, y) channel c at
+ * data + y*row_pitch + (x*channels + c)*elem.  CHW: at
+ * data + c*plane_pitch + y*row_pitch + x*elem.  Pitches are in BYTES. */
+typedef struct {
+  void*   data;
+  int32_t width, height, channels;
+  int32_t dtype;          /* stitch_dtype */
+  int32_t layout;         /* stitch_layout */
+  int64_t row_pitch;
+  int64_t plane_pitch;    /* CHW only */
+} stitch_image;
+
+/* A pyramid whose level k covers a rectangle of the level-k canvas.  The level-k
+ * canvas has sides ceil(canvas/2^k).  level[k] element (0,0) sits at level-k canvas
+ * coordinates (origin_x[k], origin_y[k]); samples of the full-canvas array outside
+ * the stored rectangle are taken as 0. */
+typedef struct {
+  int32_t levels;
+  int32_t canvas_w, canvas_h;
+  int32_t origin_x[STITCH_MAX_LEVELS];
+  int32_t origin_y[STITCH_MAX_LEVELS];
+  stitch_image level[STITCH_MAX_LEVELS];
+} stitch_levels;
+
+typedef struct stitch_plan stitch_plan;
+
+/* ---- library ---------------------------------------------------------------- */
+int32_t     stitch_abi_version(void);                 /* STITCH_ABI_VERSION */
+const char* stitch_status_str(stitch_status status);  /* static string */
+const char* stitch_last_error(void);                  /* thread-local, never NULL */
+
+/* ---- single stages ------------------------------------------------------------ */
+
+/* Alg. 4, step 1: transform one camera frame onto the canvas.
+ * src: U8 HWC, 3 channels, the camera frame.  H: source -> canvas.
+ * dst: F32 or F16 CHW, 3 channels; receives G_0 on canvas pixels
+ * [roi_x, roi_x + dst->width) x [roi_y, roi_y + dst->height).  Any roi is allowed
+ * (the warp is pointwise).  Errors: NULL, SHAPE, HOMOGRAPHY, UNSUPPORTED, DEVICE. */
+stitch_status stitch_warp(const stitch_image* src, const double H[9], int32_t roi_x, int32_t roi_y,
+                          stitch_image* dst, void* stream);
+
+/* Diagnostic of the warp's coordinate step: writes the FP32 source coordinates
+ * x (plane 0) and y (plane 1) that stitch_warp computes for canvas pixels of the
+ * rectangle [roi_x, roi_x+width) x [roi_y, roi_y+height) into xy (F32 CHW, 2 channels);
+ * pixels with non-positive z get NaN.  Errors as stitch_warp. */
+stitch_status stitch_warp_coords(const double H[9], int32_t roi_x, int32_t roi_y, stitch_image* xy,
+                                 void* stream);
+
+/* Multi-band fusion, analysis side: the Gaussian (kind 0) or Laplacian (kind 1)
+ * pyramid of one image.  g0: level 0, either F32/F16 CHW with 1..3 channels or a U8
+ * single-channel weight map (read as u8/255).  out: levels, canvas size, origins and
+ * level images preallocated by the caller; out->level[k] has the dtype of out->level[0]
+ * (F32 or F16, CHW, channels of g0), covers the rectangle given by its origin and size,
+ * and receives G_k (kind 0) or L_k (kind 1).  g0 covers the rectangle of level 0.  The
+ * result equals the full-canvas definition when g0 is zero outside its rectangle and
+ * each level's rectangle holds that level's support; with origin 0 and full-canvas
+ * sizes it is the plain pyramid of g0.  Level 0 of the output is overwritten with
+ * G_0 (kind 0) or L_0 (kind 1) and may alias g0 when dtypes match.
+ * workspace: device memory of stitch_pyramid_workspace_bytes(levels) bytes, 256-byte
+ * aligned, holding the launch tables (calls that may overlap must not share it; the
+ * table upload comes from pageable host memory and may wait for the stream).
+ * Errors: NULL, SHAPE, LEVELS, WORKSPACE, UNSUPPORTED, DEVICE. */
+size_t        stitch_pyramid_workspace_bytes(int32_t levels);
+stitch_status stitch_pyramid(const stitch_image* g0, int32_t kind, stitch_levels* out, void* workspace,
+                             size_t workspace_bytes, void* stream);
+
+/* Multi-band fusion, synthesis side (Alg. 4, step 6): blend n (1..64) Laplacian pyramids
+ * with n Gaussian weight pyramids and collapse to the panorama.
+ * bands[i]: F32/F16 CHW 3-channel Laplacian levels; weights[i]: Gaussian weight
+ * levels (F32/F16 1 channel of the band dtype, or U8 at any level read as u8/255); all
+ * pyramids share levels and canvas size, and each level's samples outside its stored
+ * rectangle count as 0.  pano: U8 HWC 3 channels, canvas_w x canvas_h.  keep_r: a
+ * full-canvas pyramid (origins 0, band dtype, CHW, 3 channels) receiving R_k; it is
+ * required when levels > 1 (the collapse reads R_{k+1} from it); its level[0].data may be
+ * NULL to skip storing R_0.  workspace: stitch_blend_workspace_bytes(n, levels) bytes of
+ * 256-byte aligned device memory for the launch tables (same sharing rule as
+ * stitch_pyramid).  Errors: NULL, SHAPE, LEVELS, WORKSPACE, UNSUPPORTED, DEVICE. */
+size_t        stitch_blend_workspace_bytes(int32_t n, int32_t levels);
+stitch_status stitch_blend(int32_t n, const stitch_levels* bands, const stitch_levels* weights,
+                           stitch_image* pano, stitch_levels* keep_r, void* workspace,
+                           size_t workspace_bytes, void* stream);
+
+/* ---- the whole frame, planned once (Sec. 4.3.2: pre-allocation at start-up) --- */
+
+#define STITCH_PLAN_KEEP_R0 1   /* flags bit: also store R_0 (float) in the workspace */
+
+/* Validate a fixed rig and plan the per-frame work: n cameras of frame_w[i] x frame_h[i],
+ * H (n*9 doubles, source -> canvas, row-major per camera), seam weights masks[i]
+ * (host, canvas_h x canvas_w uint8, row-major, summing to 255 at every pixel),
+ * levels L (1..16, every canvas level side >= 3), storage STITCH_F32 or STITCH_F16 for
+ * every stored pyramid level.  Host-only: touches no GPU.  The plan keeps what it
+ * needs from masks; the caller may free them after the call.
+ * Errors: NULL, SHAPE, LEVELS, HOMOGRAPHY, MASK, UNSUPPORTED. */
+stitch_status stitch_plan_create(int32_t n, const int32_t* frame_w, const int32_t* frame_h,
+                                 const double* H, const uint8_t* const* masks, int32_t canvas_w,
+                                 int32_t canvas_h, int32_t levels, int32_t storage, int32_t flags,
+                                 stitch_plan** out);
+
+/* Bytes of device workspace the plan needs (256-byte aligned base required). */
+size_t stitch_plan_workspace_bytes(const stitch_plan* plan);
+
+/* Attach a caller-owned device workspace and upload the plan's tables and seam
+ * weights into it on the stream; returns after the stream has drained (the only call
+ * that synchronises).  The workspace stays attached until rebind or destroy.
+ * Errors: NULL, WORKSPACE, DEVICE. */
+stitch_status stitch_plan_bind(stitch_plan* plan, void* workspace, size_t bytes, void* stream);
+
+/* Stitch one frame set: frames[i] U8 HWC 3-channel of the planned size, pano U8 HWC
+ * 3-channel canvas_w x canvas_h.  Enqueues warp + pyramids + mask pyramids + blend +
+ * collapse.  Errors: NULL, SHAPE, STATE (not bound), DEVICE. */
+stitch_status stitch_frame(stitch_plan* plan, const stitch_image* frames, stitch_image* pano,
+                           void* stream);
+
+/* Views into the bound workspace (for inspection and tests).  what: 0 = L_k of camera
+ * i (3 ch), 1 = G_k of camera i (3 ch, k >= 1), 2 = Gm_k of camera i (1 ch; k = 0 is the
+ * U8 weight crop), 3 = R_k (3 ch, k >= 1, or k = 0 with STITCH_PLAN_KEEP_R0).  Fills
+ * view (device pointer into the workspace) and the level-k canvas origin of its element
+ * (0,0).  An empty region returns width or height 0.  Errors: NULL, SHAPE, STATE. */
+stitch_status stitch_plan_view(const stitch_plan* plan, int32_t what, int32_t camera, int32_t level,
+                               stitch_image* view, int32_t* origin_x, int32_t* origin_y);
+
+/* Level-k rectangle the plan computes camera i's pyramid on (roi) and the rectangle
+ * where its seam weights are non-zero (band window), in level-k canvas coordinates
+ * as {x, y, w, h}.  Host-only.  Errors: NULL, SHAPE. */
+stitch_status stitch_plan_regions(const stitch_plan* plan, int32_t camera, int32_t level,
+                                  int32_t roi[4], int32_t band[4]);
+
+void stitch_plan_destroy(stitch_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STITCH_H */

@@ -1,0 +1,8 @@
+"""MI355X-native per-frame panorama stitching path (warp + multi-band blend).
+
+The compute runs in hand-written gfx950 HIP kernels behind the C ABI declared in
+include/stitch.h (libstitch.so, built in-tree by paper_1810_03988_amd.build);
+paper_1810_03988_amd.stitch is the ctypes binding.
+"""
+from . import stitch  # noqa: F401
+from .stitch import Plan, StitchError, blend, lib, pyramid, warp, warp_coords  # noqa: F401

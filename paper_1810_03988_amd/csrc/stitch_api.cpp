@@ -1,0 +1,887 @@
+// Host runtime of the stitching path: argument validation, the rig plan (the paper's
+// start-up pre-allocation, Sec. 4.3.2), workspace layout, descriptor tables and the
+// kernel launches.  Every host-checkable error is reported before anything is
+// enqueued.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "stitch.h"
+#include "stitch_internal.h"
+
+using namespace stitch;
+
+namespace {
+
+thread_local std::string t_err = "";
+
+stitch_status fail(stitch_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  t_err = buf;
+  return s;
+}
+
+stitch_status hip_fail(hipError_t e, const char* what) {
+  return fail(STITCH_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+int64_t ceil_div(int64_t a, int64_t b) { return -floor_div(-a, b); }
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+struct Rect {
+  int x = 0, y = 0, w = 0, h = 0;
+  bool empty() const { return w <= 0 || h <= 0; }
+};
+
+Rect intersect(const Rect& a, const Rect& b) {
+  Rect r;
+  r.x = std::max(a.x, b.x);
+  r.y = std::max(a.y, b.y);
+  r.w = std::min(a.x + a.w, b.x + b.w) - r.x;
+  r.h = std::min(a.y + a.h, b.y + b.h) - r.y;
+  if (r.w <= 0 || r.h <= 0) r = Rect{};
+  return r;
+}
+
+int elem_size(int dtype) { return dtype == STITCH_F32 ? 4 : dtype == STITCH_F16 ? 2 : 1; }
+
+// Canvas -> source map: adj(H) / adj(H)[2][2] in FP64, cofactors formed as a*b - c*d,
+// each entry rounded to FP32.  Returns false (with a reason) if H is unusable.
+bool hinv_spec(const double* a, float out[9], double* sign_out, const char** why) {
+#pragma clang fp contract(off)
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(a[i])) { *why = "homography has a non-finite entry"; return false; }
+  double adj[9];
+  adj[0] = a[4] * a[8] - a[5] * a[7];
+  adj[1] = a[2] * a[7] - a[1] * a[8];
+  adj[2] = a[1] * a[5] - a[2] * a[4];
+  adj[3] = a[5] * a[6] - a[3] * a[8];
+  adj[4] = a[0] * a[8] - a[2] * a[6];
+  adj[5] = a[2] * a[3] - a[0] * a[5];
+  adj[6] = a[3] * a[7] - a[4] * a[6];
+  adj[7] = a[1] * a[6] - a[0] * a[7];
+  adj[8] = a[0] * a[4] - a[1] * a[3];
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(adj[i])) { *why = "adjugate of H is not finite"; return false; }
+  if (adj[8] == 0.0) { *why = "adj(H)[2][2] == 0: the inverse cannot be normalised"; return false; }
+  for (int i = 0; i < 9; ++i) {
+    const double q = adj[i] / adj[8];
+    const float f = (float)q;
+    if (!std::isfinite(q) || !std::isfinite(f)) { *why = "normalised inverse overflows FP32"; return false; }
+    out[i] = f;
+  }
+  if (sign_out) {
+    // det(H) = sum_j H[0][j] adj[j][0]; z at the canvas side has the sign of
+    // (source-side w) * det / adj22.
+    const double det = a[0] * adj[0] + a[1] * adj[3] + a[2] * adj[6];
+    *sign_out = (det / adj[8]) > 0.0 ? 1.0 : -1.0;
+  }
+  return true;
+}
+
+// Canvas bounding box of the pixels the warp can make non-zero (inclusive), or false
+// when the footprint is unbounded (part of the source lies beyond the horizon).
+bool footprint_bbox(const double* H, double sign, int fw, int fh, int64_t bb[4]) {
+  const double xs[4] = {-1.0, (double)fw, (double)fw, -1.0};
+  const double ys[4] = {-1.0, -1.0, (double)fh, (double)fh};
+  double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+  for (int i = 0; i < 4; ++i) {
+    const double w = H[6] * xs[i] + H[7] * ys[i] + H[8];
+    if (!(w * sign > 0.0)) return false;
+    const double X = (H[0] * xs[i] + H[1] * ys[i] + H[2]) / w;
+    const double Y = (H[3] * xs[i] + H[4] * ys[i] + H[5]) / w;
+    if (!std::isfinite(X) || !std::isfinite(Y) || std::fabs(X) > 1e9 || std::fabs(Y) > 1e9) return false;
+    x0 = std::min(x0, X); x1 = std::max(x1, X);
+    y0 = std::min(y0, Y); y1 = std::max(y1, Y);
+  }
+  // two pixels of slack for the FP32 coordinate arithmetic
+  bb[0] = (int64_t)std::floor(x0) - 2;
+  bb[1] = (int64_t)std::ceil(x1) + 2;
+  bb[2] = (int64_t)std::floor(y0) - 2;
+  bb[3] = (int64_t)std::ceil(y1) + 2;
+  return true;
+}
+
+struct Interval { int64_t a, b; };   // inclusive, a > b means empty
+
+// Support of REDUCE(g) given the support of g (non-negative weights cannot cancel).
+Interval reduce_support(Interval s) { return {ceil_div(s.a - 2, 2), floor_div(s.b + 2, 2)}; }
+
+struct CamPlan {
+  int fw = 0, fh = 0;
+  float hinv[9] = {};
+  Rect roi[kMaxLevels];
+  Rect band[kMaxLevels];
+  std::vector<uint8_t> mask0;     // seam weights on roi[0], rows of mask_row bytes
+  int64_t mask_row = 0;
+  size_t off_mask0 = 0;
+  size_t off_g[kMaxLevels] = {};  int64_t g_row[kMaxLevels] = {}, g_plane[kMaxLevels] = {};
+  size_t off_gm[kMaxLevels] = {}; int64_t gm_row[kMaxLevels] = {};
+  size_t off_l[kMaxLevels] = {};  int64_t l_row[kMaxLevels] = {}, l_plane[kMaxLevels] = {};
+};
+
+}  // namespace
+
+struct stitch_plan {
+  int n = 0, W = 0, H = 0, L = 0, storage = STITCH_F32, flags = 0, es = 4;
+  int dw[kMaxLevels] = {}, dh[kMaxLevels] = {};
+  std::vector<CamPlan> cam;
+  size_t off_r[kMaxLevels] = {};
+  int64_t r_row[kMaxLevels] = {}, r_plane[kMaxLevels] = {};
+  bool has_r[kMaxLevels] = {};
+  // descriptor tables: pyramid passes k = 0..L-2, blend levels k = 0..L-1
+  std::vector<PyrItem> items[kMaxLevels];
+  int tiles[kMaxLevels] = {};
+  size_t off_items[kMaxLevels] = {};
+  std::vector<BlendCam> bcams[kMaxLevels];
+  size_t off_bcams[kMaxLevels] = {};
+  size_t ws_bytes = 0;
+  uint8_t* ws = nullptr;
+};
+
+namespace {
+
+// Bump allocator over the workspace (offsets only, 256-byte aligned).
+struct Layout {
+  size_t top = 0;
+  size_t take(size_t bytes) {
+    const size_t off = top;
+    top = (size_t)align_up((int64_t)(top + bytes), 256);
+    return off;
+  }
+};
+
+int64_t row_elems(int w, int es) { return align_up((int64_t)w * es, 256) / es; }
+
+// Validate a caller image view.
+stitch_status check_image(const stitch_image* im, const char* name, int dtype, int layout, int channels) {
+  if (!im) return fail(STITCH_E_NULL, "%s is NULL", name);
+  if (!im->data) return fail(STITCH_E_NULL, "%s->data is NULL", name);
+  if (im->width <= 0 || im->height <= 0)
+    return fail(STITCH_E_SHAPE, "%s has non-positive size %dx%d", name, im->width, im->height);
+  if (dtype >= 0 && im->dtype != dtype) return fail(STITCH_E_SHAPE, "%s has dtype %d, expected %d", name, im->dtype, dtype);
+  if (layout >= 0 && im->layout != layout)
+    return fail(STITCH_E_SHAPE, "%s has layout %d, expected %d", name, im->layout, layout);
+  if (channels > 0 && im->channels != channels)
+    return fail(STITCH_E_SHAPE, "%s has %d channels, expected %d", name, im->channels, channels);
+  const int es = elem_size(im->dtype);
+  if (im->dtype != STITCH_U8 && im->dtype != STITCH_F16 && im->dtype != STITCH_F32)
+    return fail(STITCH_E_UNSUPPORTED, "%s has unknown dtype %d", name, im->dtype);
+  if (im->layout == STITCH_HWC) {
+    if (im->row_pitch < (int64_t)im->width * im->channels * es)
+      return fail(STITCH_E_SHAPE, "%s row pitch %lld too small", name, (long long)im->row_pitch);
+  } else if (im->layout == STITCH_CHW) {
+    if (im->row_pitch < (int64_t)im->width * es || im->row_pitch % es)
+      return fail(STITCH_E_SHAPE, "%s row pitch %lld invalid", name, (long long)im->row_pitch);
+    if (im->channels > 1 && (im->plane_pitch < im->row_pitch * im->height || im->plane_pitch % es))
+      return fail(STITCH_E_SHAPE, "%s plane pitch %lld invalid", name, (long long)im->plane_pitch);
+  } else {
+    return fail(STITCH_E_SHAPE, "%s has unknown layout %d", name, im->layout);
+  }
+  return STITCH_OK;
+}
+
+stitch_status check_levels_dims(int W, int H, int L, int dw[], int dh[]) {
+  if (L < 1 || L > kMaxLevels) return fail(STITCH_E_LEVELS, "levels %d outside 1..%d", L, kMaxLevels);
+  if (W <= 0 || H <= 0) return fail(STITCH_E_SHAPE, "canvas %dx%d is empty", W, H);
+  dw[0] = W;
+  dh[0] = H;
+  for (int k = 1; k < L; ++k) {
+    dw[k] = (dw[k - 1] + 1) / 2;
+    dh[k] = (dh[k - 1] + 1) / 2;
+  }
+  for (int k = 0; k < L; ++k)
+    if (dw[k] < 3 || dh[k] < 3)
+      return fail(STITCH_E_LEVELS, "level %d of a %dx%d canvas is %dx%d; every side must be >= 3", k, W, H, dw[k],
+                  dh[k]);
+  return STITCH_OK;
+}
+
+stitch_status upload(void* dst, const void* src, size_t bytes, hipStream_t s, const char* what) {
+  if (bytes == 0) return STITCH_OK;
+  const hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  return e == hipSuccess ? STITCH_OK : hip_fail(e, what);
+}
+
+// Fill the pyramid-pass and blend tables of a plan whose workspace base is ws.
+void build_tables(stitch_plan* p) {
+  uint8_t* ws = p->ws;
+  const int L = p->L;
+  for (int k = 0; k + 1 < L; ++k) {
+    p->items[k].clear();
+    int tiles = 0;
+    for (int i = 0; i < p->n; ++i) {
+      const CamPlan& c = p->cam[i];
+      const Rect r = c.roi[k];
+      if (r.empty()) continue;
+      PyrItem it;
+      std::memset(&it, 0, sizeof it);
+      it.tile_begin = tiles;
+      it.tiles_x = (r.w + kPyrTX - 1) / kPyrTX;
+      it.tiles_y = (r.h + kPyrTY - 1) / kPyrTY;
+      it.tile_x0 = r.x;
+      it.tile_y0 = r.y;
+      it.fine_w = p->dw[k];
+      it.fine_h = p->dh[k];
+      it.roi_x = r.x; it.roi_y = r.y; it.roi_w = r.w; it.roi_h = r.h;
+      it.nch = 3;
+      if (k == 0) {
+        it.img_kind = kSrcWarp;
+        it.frame_slot = i;
+        it.frame_w = c.fw;
+        it.frame_h = c.fh;
+        std::memcpy(it.hinv, c.hinv, sizeof it.hinv);
+        it.msk_kind = kSrcU8;
+        it.msk = ws + c.off_mask0;
+        it.msk_row = c.mask_row;
+      } else {
+        it.img_kind = kSrcPlanes;
+        it.img = ws + c.off_g[k];
+        it.img_row = c.g_row[k];
+        it.img_plane = c.g_plane[k];
+        it.msk_kind = kSrcPlanes;
+        it.msk = ws + c.off_gm[k];
+        it.msk_row = c.gm_row[k];
+      }
+      const Rect cr = c.roi[k + 1];
+      it.croi_x = cr.x; it.croi_y = cr.y; it.croi_w = cr.w; it.croi_h = cr.h;
+      it.g_out = ws + c.off_g[k + 1];
+      it.g_row = c.g_row[k + 1];
+      it.g_plane = c.g_plane[k + 1];
+      it.gm_out = ws + c.off_gm[k + 1];
+      it.gm_row = c.gm_row[k + 1];
+      const Rect b = c.band[k];
+      if (!b.empty()) {
+        it.lw_x = b.x; it.lw_y = b.y; it.lw_w = b.w; it.lw_h = b.h;
+        it.l_out = ws + c.off_l[k];
+        it.l_row = c.l_row[k];
+        it.l_plane = c.l_plane[k];
+      }
+      tiles += it.tiles_x * it.tiles_y;
+      p->items[k].push_back(it);
+    }
+    p->tiles[k] = tiles;
+  }
+  for (int k = 0; k < L; ++k) {
+    p->bcams[k].clear();
+    for (int i = 0; i < p->n; ++i) {
+      const CamPlan& c = p->cam[i];
+      const Rect b = c.band[k];
+      if (b.empty()) continue;
+      BlendCam bc;
+      std::memset(&bc, 0, sizeof bc);
+      bc.lx = b.x; bc.ly = b.y; bc.lw = b.w; bc.lh = b.h;
+      if (k + 1 < L) {
+        bc.lap = ws + c.off_l[k];
+        bc.lap_row = c.l_row[k];
+        bc.lap_plane = c.l_plane[k];
+      } else {   // top band = G_{L-1} (or G_0 stored by the warp when L == 1), viewed on the band window
+        const Rect r = c.roi[k];
+        bc.lap = ws + c.off_g[k] + ((int64_t)(b.y - r.y) * c.g_row[k] + (b.x - r.x)) * p->es;
+        bc.lap_row = c.g_row[k];
+        bc.lap_plane = c.g_plane[k];
+      }
+      const Rect r = c.roi[k];
+      bc.wx = r.x; bc.wy = r.y; bc.ww = r.w; bc.wh = r.h;
+      if (k == 0) {
+        bc.wgt = ws + c.off_mask0;
+        bc.wgt_row = c.mask_row;
+        bc.wgt_u8 = 1;
+      } else {
+        bc.wgt = ws + c.off_gm[k];
+        bc.wgt_row = c.gm_row[k];
+      }
+      p->bcams[k].push_back(bc);
+    }
+  }
+}
+
+}  // namespace
+
+// ====================================================================================== API
+extern "C" {
+
+int32_t stitch_abi_version(void) { return STITCH_ABI_VERSION; }
+
+const char* stitch_status_str(stitch_status s) {
+  switch (s) {
+    case STITCH_OK: return "ok";
+    case STITCH_E_NULL: return "null pointer";
+    case STITCH_E_SHAPE: return "inconsistent shape";
+    case STITCH_E_LEVELS: return "invalid level count";
+    case STITCH_E_HOMOGRAPHY: return "invalid homography";
+    case STITCH_E_MASK: return "invalid seam weights";
+    case STITCH_E_WORKSPACE: return "invalid workspace";
+    case STITCH_E_DEVICE: return "device error";
+    case STITCH_E_UNSUPPORTED: return "unsupported";
+    case STITCH_E_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char* stitch_last_error(void) { return t_err.c_str(); }
+
+// ------------------------------------------------------------------------------------ warp
+stitch_status stitch_warp(const stitch_image* src, const double H[9], int32_t roi_x, int32_t roi_y,
+                          stitch_image* dst, void* stream) {
+  stitch_status st = check_image(src, "src", STITCH_U8, STITCH_HWC, 3);
+  if (st) return st;
+  if (!H) return fail(STITCH_E_NULL, "H is NULL");
+  st = check_image(dst, "dst", -1, STITCH_CHW, 3);
+  if (st) return st;
+  if (dst->dtype != STITCH_F32 && dst->dtype != STITCH_F16)
+    return fail(STITCH_E_UNSUPPORTED, "dst must be F32 or F16");
+  float hi[9];
+  const char* why = nullptr;
+  if (!hinv_spec(H, hi, nullptr, &why)) return fail(STITCH_E_HOMOGRAPHY, "%s", why);
+  const int es = elem_size(dst->dtype);
+  const hipError_t e = launch_warp(dst->dtype == STITCH_F16, (const uint8_t*)src->data, src->row_pitch, src->width,
+                                   src->height, hi, roi_x, roi_y, dst->data, dst->row_pitch / es,
+                                   dst->plane_pitch / es, dst->width, dst->height, (hipStream_t)stream);
+  return e == hipSuccess ? STITCH_OK : hip_fail(e, "warp launch");
+}
+
+stitch_status stitch_warp_coords(const double H[9], int32_t roi_x, int32_t roi_y, stitch_image* xy, void* stream) {
+  if (!H) return fail(STITCH_E_NULL, "H is NULL");
+  stitch_status st = check_image(xy, "xy", STITCH_F32, STITCH_CHW, 2);
+  if (st) return st;
+  float hi[9];
+  const char* why = nullptr;
+  if (!hinv_spec(H, hi, nullptr, &why)) return fail(STITCH_E_HOMOGRAPHY, "%s", why);
+  const hipError_t e = launch_warp_coords(hi, roi_x, roi_y, (float*)xy->data, xy->row_pitch / 4, xy->plane_pitch / 4,
+                                          xy->width, xy->height, (hipStream_t)stream);
+  return e == hipSuccess ? STITCH_OK : hip_fail(e, "warp_coords launch");
+}
+
+// ------------------------------------------------------------------------------------ pyramid
+size_t stitch_pyramid_workspace_bytes(int32_t levels) {
+  return (size_t)align_up((int64_t)std::max(levels, 1) * (int64_t)sizeof(PyrItem), 256);
+}
+
+stitch_status stitch_pyramid(const stitch_image* g0, int32_t kind, stitch_levels* out, void* workspace,
+                             size_t ws_bytes, void* stream) {
+  if (!g0) return fail(STITCH_E_NULL, "g0 is NULL");
+  if (!out) return fail(STITCH_E_NULL, "out is NULL");
+  if (kind != 0 && kind != 1) return fail(STITCH_E_UNSUPPORTED, "kind must be 0 (Gaussian) or 1 (Laplacian)");
+  const int L = out->levels;
+  int dw[kMaxLevels], dh[kMaxLevels];
+  stitch_status st = check_levels_dims(out->canvas_w, out->canvas_h, L, dw, dh);
+  if (st) return st;
+  const bool u8 = g0->dtype == STITCH_U8;
+  st = check_image(g0, "g0", -1, u8 ? -1 : STITCH_CHW, -1);
+  if (st) return st;
+  if (u8 && g0->channels != 1) return fail(STITCH_E_SHAPE, "a U8 g0 must have one channel");
+  if (!u8 && (g0->channels < 1 || g0->channels > 3))
+    return fail(STITCH_E_UNSUPPORTED, "float g0 must have 1..3 channels");
+  const int odt = out->level[0].dtype;
+  if (odt != STITCH_F32 && odt != STITCH_F16) return fail(STITCH_E_UNSUPPORTED, "output levels must be F32 or F16");
+  if (!u8 && g0->dtype != odt) return fail(STITCH_E_SHAPE, "float g0 and output levels must share a dtype");
+  const int nch = g0->channels;
+  for (int k = 0; k < L; ++k) {
+    char name[32];
+    snprintf(name, sizeof name, "out->level[%d]", k);
+    st = check_image(&out->level[k], name, odt, STITCH_CHW, nch);
+    if (st) return st;
+    const Rect lr{out->origin_x[k], out->origin_y[k], out->level[k].width, out->level[k].height};
+    if (lr.x < 0 || lr.y < 0 || lr.x + lr.w > dw[k] || lr.y + lr.h > dh[k])
+      return fail(STITCH_E_SHAPE, "level %d rectangle leaves the %dx%d level canvas", k, dw[k], dh[k]);
+  }
+  if (g0->width != out->level[0].width || g0->height != out->level[0].height)
+    return fail(STITCH_E_SHAPE, "g0 and out->level[0] differ in size");
+  if (L > 1 && (!workspace || ws_bytes < stitch_pyramid_workspace_bytes(L) || ((uintptr_t)workspace & 255)))
+    return fail(STITCH_E_WORKSPACE, "workspace missing, misaligned or smaller than %zu bytes",
+                stitch_pyramid_workspace_bytes(L));
+  const hipStream_t s = (hipStream_t)stream;
+  const bool f16 = odt == STITCH_F16;
+  const int es = elem_size(odt);
+  const stitch_image& l0 = out->level[0];
+  hipError_t e = hipSuccess;
+  if (g0->data != l0.data || u8) {
+    e = launch_convert(f16, nch, u8, g0->data, g0->row_pitch / elem_size(g0->dtype),
+                       g0->plane_pitch / elem_size(g0->dtype), l0.data, l0.row_pitch / es, l0.plane_pitch / es,
+                       l0.width, l0.height, s);
+    if (e != hipSuccess) return hip_fail(e, "convert launch");
+  }
+  if (L == 1) return STITCH_OK;
+  std::vector<PyrItem> items(L - 1);
+  std::vector<int> tiles(L - 1);
+  for (int k = 0; k + 1 < L; ++k) {
+    const stitch_image& f = out->level[k];
+    const stitch_image& c = out->level[k + 1];
+    PyrItem it;
+    std::memset(&it, 0, sizeof it);
+    const int fx = out->origin_x[k], fy = out->origin_y[k];
+    const int cx = out->origin_x[k + 1], cy = out->origin_y[k + 1];
+    // tiles cover the level-k rectangle and every fine sample under the level-(k+1) rectangle
+    const int x0 = std::min(fx, 2 * cx) & ~1, y0 = std::min(fy, 2 * cy) & ~1;
+    const int x1 = std::max(fx + f.width, 2 * (cx + c.width)), y1 = std::max(fy + f.height, 2 * (cy + c.height));
+    it.tiles_x = (x1 - x0 + kPyrTX - 1) / kPyrTX;
+    it.tiles_y = (y1 - y0 + kPyrTY - 1) / kPyrTY;
+    it.tile_x0 = x0;
+    it.tile_y0 = y0;
+    it.fine_w = dw[k];
+    it.fine_h = dh[k];
+    it.roi_x = fx; it.roi_y = fy; it.roi_w = f.width; it.roi_h = f.height;
+    it.img_kind = kSrcPlanes;
+    it.nch = nch;
+    it.img = f.data;
+    it.img_row = f.row_pitch / es;
+    it.img_plane = f.plane_pitch / es;
+    it.msk_kind = kSrcNone;
+    it.croi_x = cx; it.croi_y = cy; it.croi_w = c.width; it.croi_h = c.height;
+    it.g_out = c.data;
+    it.g_row = c.row_pitch / es;
+    it.g_plane = c.plane_pitch / es;
+    items[k] = it;
+    tiles[k] = it.tiles_x * it.tiles_y;
+  }
+  st = upload(workspace, items.data(), items.size() * sizeof(PyrItem), s, "pyramid table upload");
+  if (st) return st;
+  FrameArgs fa;
+  std::memset(&fa, 0, sizeof fa);
+  const PyrItem* dev = (const PyrItem*)workspace;
+  for (int k = 0; k + 1 < L; ++k) {
+    e = launch_pyr(f16, false, dev + k, 1, tiles[k], fa, s);
+    if (e != hipSuccess) return hip_fail(e, "pyramid launch");
+  }
+  if (kind == 1) {
+    for (int k = 0; k + 1 < L; ++k) {
+      const stitch_image& f = out->level[k];
+      const stitch_image& c = out->level[k + 1];
+      e = launch_expand_sub(f16, nch, f.data, f.row_pitch / es, f.plane_pitch / es, out->origin_x[k],
+                            out->origin_y[k], f.width, f.height, c.data, c.row_pitch / es, c.plane_pitch / es,
+                            out->origin_x[k + 1], out->origin_y[k + 1], c.width, c.height, dw[k], dh[k], s);
+      if (e != hipSuccess) return hip_fail(e, "expand launch");
+    }
+  }
+  return STITCH_OK;
+}
+
+// ------------------------------------------------------------------------------------ blend
+size_t stitch_blend_workspace_bytes(int32_t n, int32_t levels) {
+  return (size_t)align_up((int64_t)std::max(n, 1) * std::max(levels, 1) * (int64_t)sizeof(BlendCam), 256);
+}
+
+stitch_status stitch_blend(int32_t n, const stitch_levels* bands, const stitch_levels* weights, stitch_image* pano,
+                           stitch_levels* keep_r, void* workspace, size_t ws_bytes, void* stream) {
+  if (n < 1 || n > kMaxCameras) return fail(STITCH_E_SHAPE, "n = %d outside 1..%d", n, kMaxCameras);
+  if (!bands || !weights) return fail(STITCH_E_NULL, "bands or weights is NULL");
+  stitch_status st = check_image(pano, "pano", STITCH_U8, STITCH_HWC, 3);
+  if (st) return st;
+  const int W = pano->width, H = pano->height, L = bands[0].levels;
+  int dw[kMaxLevels], dh[kMaxLevels];
+  st = check_levels_dims(W, H, L, dw, dh);
+  if (st) return st;
+  const int dt = bands[0].level[0].dtype;
+  if (dt != STITCH_F32 && dt != STITCH_F16) return fail(STITCH_E_UNSUPPORTED, "bands must be F32 or F16");
+  const int es = elem_size(dt);
+  for (int i = 0; i < n; ++i) {
+    if (bands[i].levels != L || weights[i].levels != L)
+      return fail(STITCH_E_LEVELS, "pyramid %d has a different level count", i);
+    if (bands[i].canvas_w != W || bands[i].canvas_h != H || weights[i].canvas_w != W || weights[i].canvas_h != H)
+      return fail(STITCH_E_SHAPE, "pyramid %d is on a different canvas than the panorama", i);
+    for (int k = 0; k < L; ++k) {
+      char name[48];
+      snprintf(name, sizeof name, "bands[%d].level[%d]", i, k);
+      st = check_image(&bands[i].level[k], name, dt, STITCH_CHW, 3);
+      if (st) return st;
+      snprintf(name, sizeof name, "weights[%d].level[%d]", i, k);
+      const stitch_image& w = weights[i].level[k];
+      st = check_image(&w, name, -1, w.dtype == STITCH_U8 ? -1 : STITCH_CHW, 1);
+      if (st) return st;
+      if (w.dtype != STITCH_U8 && w.dtype != dt)
+        return fail(STITCH_E_SHAPE, "%s must be U8 or the band dtype", name);
+    }
+  }
+  if (L > 1 && !keep_r) return fail(STITCH_E_NULL, "keep_r is required when levels > 1 (it holds R_k)");
+  if (keep_r) {
+    if (keep_r->levels != L || keep_r->canvas_w != W || keep_r->canvas_h != H)
+      return fail(STITCH_E_SHAPE, "keep_r does not match the panorama pyramid");
+    for (int k = (keep_r->level[0].data ? 0 : 1); k < L; ++k) {
+      char name[32];
+      snprintf(name, sizeof name, "keep_r->level[%d]", k);
+      st = check_image(&keep_r->level[k], name, dt, STITCH_CHW, 3);
+      if (st) return st;
+      if (keep_r->origin_x[k] || keep_r->origin_y[k] || keep_r->level[k].width != dw[k] ||
+          keep_r->level[k].height != dh[k])
+        return fail(STITCH_E_SHAPE, "%s must cover the whole level canvas", name);
+    }
+  }
+  if (!workspace || ws_bytes < stitch_blend_workspace_bytes(n, L) || ((uintptr_t)workspace & 255))
+    return fail(STITCH_E_WORKSPACE, "workspace missing, misaligned or smaller than %zu bytes",
+                stitch_blend_workspace_bytes(n, L));
+  std::vector<BlendCam> tab((size_t)n * L);
+  for (int k = 0; k < L; ++k)
+    for (int i = 0; i < n; ++i) {
+      BlendCam& bc = tab[(size_t)k * n + i];
+      std::memset(&bc, 0, sizeof bc);
+      const stitch_image& b = bands[i].level[k];
+      const stitch_image& w = weights[i].level[k];
+      bc.lap = b.data;
+      bc.lap_row = b.row_pitch / es;
+      bc.lap_plane = b.plane_pitch / es;
+      bc.lx = bands[i].origin_x[k]; bc.ly = bands[i].origin_y[k]; bc.lw = b.width; bc.lh = b.height;
+      bc.wgt = w.data;
+      bc.wgt_u8 = w.dtype == STITCH_U8;
+      bc.wgt_row = w.row_pitch / elem_size(w.dtype);
+      bc.wx = weights[i].origin_x[k]; bc.wy = weights[i].origin_y[k]; bc.ww = w.width; bc.wh = w.height;
+    }
+  const hipStream_t s = (hipStream_t)stream;
+  st = upload(workspace, tab.data(), tab.size() * sizeof(BlendCam), s, "blend table upload");
+  if (st) return st;
+  const BlendCam* dev = (const BlendCam*)workspace;
+  for (int k = L - 1; k >= 0; --k) {
+    BlendArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.W = dw[k]; a.H = dh[k];
+    a.ncam = n;
+    a.cams = dev + (size_t)k * n;
+    if (k + 1 < L) {
+      a.has_coarse = 1;
+      a.cW = dw[k + 1]; a.cH = dh[k + 1];
+      const stitch_image& r = keep_r->level[k + 1];
+      a.r_in = r.data; a.rin_row = r.row_pitch / es; a.rin_plane = r.plane_pitch / es;
+    }
+    if (keep_r && keep_r->level[k].data) {
+      const stitch_image& r = keep_r->level[k];
+      a.r_out = r.data; a.rout_row = r.row_pitch / es; a.rout_plane = r.plane_pitch / es;
+    }
+    if (k == 0) { a.pano = (uint8_t*)pano->data; a.pano_row = pano->row_pitch; }
+    a.tiles_x = (dw[k] + kBlendTX - 1) / kBlendTX;
+    a.tiles_y = (dh[k] + kBlendTY - 1) / kBlendTY;
+    const hipError_t e = launch_blend(dt == STITCH_F16, a, s);
+    if (e != hipSuccess) return hip_fail(e, "blend launch");
+  }
+  return STITCH_OK;
+}
+
+// ------------------------------------------------------------------------------------ plan
+stitch_status stitch_plan_create(int32_t n, const int32_t* frame_w, const int32_t* frame_h, const double* H,
+                                 const uint8_t* const* masks, int32_t canvas_w, int32_t canvas_h, int32_t levels,
+                                 int32_t storage, int32_t flags, stitch_plan** out) {
+  if (!out) return fail(STITCH_E_NULL, "out is NULL");
+  *out = nullptr;
+  if (!frame_w || !frame_h || !H || !masks) return fail(STITCH_E_NULL, "frame_w, frame_h, H or masks is NULL");
+  if (n < 1 || n > kMaxCameras) return fail(STITCH_E_SHAPE, "n = %d outside 1..%d", n, kMaxCameras);
+  if (storage != STITCH_F32 && storage != STITCH_F16)
+    return fail(STITCH_E_UNSUPPORTED, "storage must be STITCH_F32 or STITCH_F16");
+  if (canvas_w > (1 << 20) || canvas_h > (1 << 20)) return fail(STITCH_E_SHAPE, "canvas side above 2^20");
+  stitch_plan* p = new (std::nothrow) stitch_plan();
+  if (!p) return fail(STITCH_E_UNSUPPORTED, "out of host memory");
+  struct Guard { stitch_plan*& p; ~Guard() { delete p; } } guard{p};
+  stitch_status st = check_levels_dims(canvas_w, canvas_h, levels, p->dw, p->dh);
+  if (st) return st;
+  p->n = n; p->W = canvas_w; p->H = canvas_h; p->L = levels;
+  p->storage = storage; p->flags = flags; p->es = elem_size(storage);
+  p->cam.resize(n);
+  const int L = levels;
+  // --- seam weights: present, partition of unity ---
+  std::vector<uint16_t> total((size_t)canvas_w * canvas_h, 0);
+  for (int i = 0; i < n; ++i) {
+    if (!masks[i]) return fail(STITCH_E_NULL, "masks[%d] is NULL", i);
+    const uint8_t* m = masks[i];
+    for (size_t j = 0; j < total.size(); ++j) total[j] += m[j];
+  }
+  for (size_t j = 0; j < total.size(); ++j)
+    if (total[j] != 255)
+      return fail(STITCH_E_MASK, "seam weights sum to %d at canvas pixel (%zu, %zu); they must sum to 255",
+                  (int)total[j], j % canvas_w, j / canvas_w);
+  total.clear();
+  total.shrink_to_fit();
+  const int64_t A = (int64_t)1 << (L - 1);   // every ROI origin is a multiple of 2^(L-1)
+  for (int i = 0; i < n; ++i) {
+    CamPlan& c = p->cam[i];
+    if (frame_w[i] <= 0 || frame_h[i] <= 0 || frame_w[i] > (1 << 20) || frame_h[i] > (1 << 20))
+      return fail(STITCH_E_SHAPE, "frame %d has size %dx%d", i, frame_w[i], frame_h[i]);
+    c.fw = frame_w[i];
+    c.fh = frame_h[i];
+    const double* Hi = H + 9 * i;
+    double sign = 1.0;
+    const char* why = nullptr;
+    if (!hinv_spec(Hi, c.hinv, &sign, &why)) return fail(STITCH_E_HOMOGRAPHY, "camera %d: %s", i, why);
+    // --- where the warp can be non-zero, and what every level then needs ---
+    int64_t bb[4];
+    Rect roi0{0, 0, canvas_w, canvas_h};
+    if (footprint_bbox(Hi, sign, c.fw, c.fh, bb)) {
+      Interval sx{bb[0], bb[1]}, sy{bb[2], bb[3]};
+      int64_t x0 = sx.a, x1 = sx.b, y0 = sy.a, y1 = sy.b;   // level-0 coordinates, inclusive
+      // G_k support s_k; L_k support adds EXPAND(G_{k+1}); keep 3 samples of clearance
+      // at every level (the seam-weight pyramid is exact only that far inside the ROI).
+      Interval gx = sx, gy = sy;
+      for (int k = 0; k < L; ++k) {
+        Interval lx = gx, ly = gy;
+        if (k + 1 < L) {
+          const Interval nx = reduce_support(gx), ny = reduce_support(gy);
+          lx = {std::min(gx.a, 2 * nx.a - 2), std::max(gx.b, 2 * nx.b + 2)};
+          ly = {std::min(gy.a, 2 * ny.a - 2), std::max(gy.b, 2 * ny.b + 2)};
+          x0 = std::min(x0, (lx.a - 3) * (int64_t(1) << k)); x1 = std::max(x1, (lx.b + 4) * (int64_t(1) << k) - 1);
+          y0 = std::min(y0, (ly.a - 3) * (int64_t(1) << k)); y1 = std::max(y1, (ly.b + 4) * (int64_t(1) << k) - 1);
+          gx = nx;
+          gy = ny;
+        } else {
+          x0 = std::min(x0, (lx.a - 3) * (int64_t(1) << k)); x1 = std::max(x1, (lx.b + 4) * (int64_t(1) << k) - 1);
+          y0 = std::min(y0, (ly.a - 3) * (int64_t(1) << k)); y1 = std::max(y1, (ly.b + 4) * (int64_t(1) << k) - 1);
+        }
+      }
+      const int64_t rx0 = std::max<int64_t>(0, floor_div(x0, A) * A);
+      const int64_t ry0 = std::max<int64_t>(0, floor_div(y0, A) * A);
+      const int64_t rx1 = std::min<int64_t>(canvas_w, ceil_div(x1 + 1, A) * A);
+      const int64_t ry1 = std::min<int64_t>(canvas_h, ceil_div(y1 + 1, A) * A);
+      roi0 = (rx0 < rx1 && ry0 < ry1) ? Rect{(int)rx0, (int)ry0, (int)(rx1 - rx0), (int)(ry1 - ry0)} : Rect{};
+    }
+    for (int k = 0; k < L; ++k) {
+      if (roi0.empty()) { c.roi[k] = Rect{}; continue; }
+      const int xa = roi0.x >> k, ya = roi0.y >> k;
+      const int xb = std::min<int>(p->dw[k], (int)ceil_div(roi0.x + roi0.w, (int64_t)1 << k));
+      const int yb = std::min<int>(p->dh[k], (int)ceil_div(roi0.y + roi0.h, (int64_t)1 << k));
+      c.roi[k] = Rect{xa, ya, xb - xa, yb - ya};
+    }
+    // --- seam-weight support per level (bounding box), and the band windows ---
+    const uint8_t* m = masks[i];
+    int64_t mx0 = canvas_w, mx1 = -1, my0 = canvas_h, my1 = -1;
+    for (int y = 0; y < canvas_h; ++y) {
+      const uint8_t* row = m + (size_t)y * canvas_w;
+      for (int x = 0; x < canvas_w; ++x)
+        if (row[x]) {
+          mx0 = std::min<int64_t>(mx0, x); mx1 = std::max<int64_t>(mx1, x);
+          my0 = std::min<int64_t>(my0, y); my1 = std::max<int64_t>(my1, y);
+        }
+    }
+    Interval nx{mx0, mx1}, ny{my0, my1};
+    for (int k = 0; k < L; ++k) {
+      if (k > 0) { nx = reduce_support(nx); ny = reduce_support(ny); }
+      Rect nk;
+      if (nx.a <= nx.b && ny.a <= ny.b) {
+        const int64_t xa = std::max<int64_t>(0, nx.a), xb = std::min<int64_t>(p->dw[k] - 1, nx.b);
+        const int64_t ya = std::max<int64_t>(0, ny.a), yb = std::min<int64_t>(p->dh[k] - 1, ny.b);
+        if (xa <= xb && ya <= yb) nk = Rect{(int)xa, (int)ya, (int)(xb - xa + 1), (int)(yb - ya + 1)};
+      }
+      c.band[k] = intersect(nk, c.roi[k]);
+    }
+    // --- keep the seam weights on roi[0] ---
+    const Rect r0 = c.roi[0];
+    if (!r0.empty()) {
+      c.mask_row = align_up(r0.w, 256);
+      c.mask0.assign((size_t)c.mask_row * r0.h, 0);
+      for (int y = 0; y < r0.h; ++y)
+        std::memcpy(&c.mask0[(size_t)y * c.mask_row], m + (size_t)(r0.y + y) * canvas_w + r0.x, r0.w);
+    }
+  }
+  // --- workspace layout ---
+  Layout lay;
+  const int es = p->es;
+  for (int i = 0; i < n; ++i) {
+    CamPlan& c = p->cam[i];
+    if (c.roi[0].empty()) continue;
+    c.off_mask0 = lay.take((size_t)c.mask_row * c.roi[0].h);
+    for (int k = (L == 1 ? 0 : 1); k < L; ++k) {
+      const Rect r = c.roi[k];
+      c.g_row[k] = row_elems(r.w, es);
+      c.g_plane[k] = c.g_row[k] * r.h;
+      c.off_g[k] = lay.take((size_t)(3 * c.g_plane[k]) * es);
+      if (k >= 1) {
+        c.gm_row[k] = row_elems(r.w, es);
+        c.off_gm[k] = lay.take((size_t)(c.gm_row[k] * r.h) * es);
+      }
+    }
+    for (int k = 0; k + 1 < L; ++k) {
+      const Rect b = c.band[k];
+      if (b.empty()) continue;
+      c.l_row[k] = row_elems(b.w, es);
+      c.l_plane[k] = c.l_row[k] * b.h;
+      c.off_l[k] = lay.take((size_t)(3 * c.l_plane[k]) * es);
+    }
+  }
+  for (int k = 0; k < L; ++k) {
+    if (k == 0 && !(flags & STITCH_PLAN_KEEP_R0)) continue;
+    p->has_r[k] = true;
+    p->r_row[k] = row_elems(p->dw[k], es);
+    p->r_plane[k] = p->r_row[k] * p->dh[k];
+    p->off_r[k] = lay.take((size_t)(3 * p->r_plane[k]) * es);
+  }
+  for (int k = 0; k + 1 < L; ++k) p->off_items[k] = lay.take((size_t)n * sizeof(PyrItem));
+  for (int k = 0; k < L; ++k) p->off_bcams[k] = lay.take((size_t)n * sizeof(BlendCam));
+  p->ws_bytes = lay.top;
+  *out = p;
+  p = nullptr;   // disarm the guard
+  return STITCH_OK;
+}
+
+size_t stitch_plan_workspace_bytes(const stitch_plan* p) { return p ? p->ws_bytes : 0; }
+
+stitch_status stitch_plan_bind(stitch_plan* p, void* workspace, size_t bytes, void* stream) {
+  if (!p) return fail(STITCH_E_NULL, "plan is NULL");
+  if (!workspace) return fail(STITCH_E_WORKSPACE, "workspace is NULL");
+  if (((uintptr_t)workspace & 255) != 0) return fail(STITCH_E_WORKSPACE, "workspace is not 256-byte aligned");
+  if (bytes < p->ws_bytes) return fail(STITCH_E_WORKSPACE, "workspace has %zu bytes, the plan needs %zu", bytes, p->ws_bytes);
+  p->ws = (uint8_t*)workspace;
+  build_tables(p);
+  const hipStream_t s = (hipStream_t)stream;
+  stitch_status st = STITCH_OK;
+  for (int i = 0; i < p->n && !st; ++i) {
+    const CamPlan& c = p->cam[i];
+    if (!c.mask0.empty()) st = upload(p->ws + c.off_mask0, c.mask0.data(), c.mask0.size(), s, "seam weight upload");
+  }
+  for (int k = 0; k + 1 < p->L && !st; ++k)
+    st = upload(p->ws + p->off_items[k], p->items[k].data(), p->items[k].size() * sizeof(PyrItem), s, "table upload");
+  for (int k = 0; k < p->L && !st; ++k)
+    st = upload(p->ws + p->off_bcams[k], p->bcams[k].data(), p->bcams[k].size() * sizeof(BlendCam), s,
+                "table upload");
+  if (!st) {
+    const hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = hip_fail(e, "bind synchronise");
+  }
+  if (st) p->ws = nullptr;
+  return st;
+}
+
+stitch_status stitch_frame(stitch_plan* p, const stitch_image* frames, stitch_image* pano, void* stream) {
+  if (!p) return fail(STITCH_E_NULL, "plan is NULL");
+  if (!frames) return fail(STITCH_E_NULL, "frames is NULL");
+  if (!p->ws) return fail(STITCH_E_STATE, "plan has no workspace bound");
+  stitch_status st = check_image(pano, "pano", STITCH_U8, STITCH_HWC, 3);
+  if (st) return st;
+  if (pano->width != p->W || pano->height != p->H)
+    return fail(STITCH_E_SHAPE, "pano is %dx%d, the plan's canvas is %dx%d", pano->width, pano->height, p->W, p->H);
+  FrameArgs fa;
+  std::memset(&fa, 0, sizeof fa);
+  fa.n = p->n;
+  for (int i = 0; i < p->n; ++i) {
+    char name[32];
+    snprintf(name, sizeof name, "frames[%d]", i);
+    st = check_image(&frames[i], name, STITCH_U8, STITCH_HWC, 3);
+    if (st) return st;
+    if (frames[i].width != p->cam[i].fw || frames[i].height != p->cam[i].fh)
+      return fail(STITCH_E_SHAPE, "frames[%d] is %dx%d, planned %dx%d", i, frames[i].width, frames[i].height,
+                  p->cam[i].fw, p->cam[i].fh);
+    fa.ptr[i] = (const uint8_t*)frames[i].data;
+    fa.row[i] = frames[i].row_pitch;
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  const bool f16 = p->storage == STITCH_F16;
+  const int L = p->L;
+  hipError_t e;
+  if (L == 1) {
+    for (int i = 0; i < p->n; ++i) {
+      const CamPlan& c = p->cam[i];
+      const Rect r = c.roi[0];
+      if (r.empty()) continue;
+      e = launch_warp(f16, fa.ptr[i], fa.row[i], c.fw, c.fh, c.hinv, r.x, r.y, p->ws + c.off_g[0], c.g_row[0],
+                      c.g_plane[0], r.w, r.h, s);
+      if (e != hipSuccess) return hip_fail(e, "warp launch");
+    }
+  }
+  for (int k = 0; k + 1 < L; ++k) {
+    e = launch_pyr(f16, true, (const PyrItem*)(p->ws + p->off_items[k]), (int)p->items[k].size(), p->tiles[k], fa, s);
+    if (e != hipSuccess) return hip_fail(e, "pyramid pass launch");
+  }
+  for (int k = L - 1; k >= 0; --k) {
+    BlendArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.W = p->dw[k]; a.H = p->dh[k];
+    a.ncam = (int)p->bcams[k].size();
+    a.cams = (const BlendCam*)(p->ws + p->off_bcams[k]);
+    if (k + 1 < L) {
+      a.has_coarse = 1;
+      a.cW = p->dw[k + 1]; a.cH = p->dh[k + 1];
+      a.r_in = p->ws + p->off_r[k + 1]; a.rin_row = p->r_row[k + 1]; a.rin_plane = p->r_plane[k + 1];
+    }
+    if (p->has_r[k]) { a.r_out = p->ws + p->off_r[k]; a.rout_row = p->r_row[k]; a.rout_plane = p->r_plane[k]; }
+    if (k == 0) { a.pano = (uint8_t*)pano->data; a.pano_row = pano->row_pitch; }
+    a.tiles_x = (p->dw[k] + kBlendTX - 1) / kBlendTX;
+    a.tiles_y = (p->dh[k] + kBlendTY - 1) / kBlendTY;
+    e = launch_blend(f16, a, s);
+    if (e != hipSuccess) return hip_fail(e, "blend launch");
+  }
+  return STITCH_OK;
+}
+
+stitch_status stitch_plan_view(const stitch_plan* p, int32_t what, int32_t camera, int32_t level, stitch_image* view,
+                               int32_t* origin_x, int32_t* origin_y) {
+  if (!p || !view || !origin_x || !origin_y) return fail(STITCH_E_NULL, "plan, view or origin is NULL");
+  if (!p->ws) return fail(STITCH_E_STATE, "plan has no workspace bound");
+  if (level < 0 || level >= p->L) return fail(STITCH_E_LEVELS, "level %d outside 0..%d", level, p->L - 1);
+  std::memset(view, 0, sizeof *view);
+  view->layout = STITCH_CHW;
+  view->dtype = p->storage;
+  const int es = p->es;
+  if (what == 3) {
+    if (!p->has_r[level]) return fail(STITCH_E_SHAPE, "R_%d is not stored by this plan", level);
+    view->data = p->ws + p->off_r[level];
+    view->width = p->dw[level]; view->height = p->dh[level]; view->channels = 3;
+    view->row_pitch = p->r_row[level] * es; view->plane_pitch = p->r_plane[level] * es;
+    *origin_x = 0; *origin_y = 0;
+    return STITCH_OK;
+  }
+  if (camera < 0 || camera >= p->n) return fail(STITCH_E_SHAPE, "camera %d outside 0..%d", camera, p->n - 1);
+  const CamPlan& c = p->cam[camera];
+  Rect r;
+  if (what == 0) {
+    r = c.band[level];
+    *origin_x = r.x; *origin_y = r.y;
+    if (r.empty()) return STITCH_OK;
+    view->channels = 3;
+    if (level + 1 < p->L) {
+      view->data = p->ws + c.off_l[level];
+      view->row_pitch = c.l_row[level] * es; view->plane_pitch = c.l_plane[level] * es;
+    } else {
+      const Rect g = c.roi[level];
+      view->data = p->ws + c.off_g[level] + ((int64_t)(r.y - g.y) * c.g_row[level] + (r.x - g.x)) * es;
+      view->row_pitch = c.g_row[level] * es; view->plane_pitch = c.g_plane[level] * es;
+    }
+  } else if (what == 1) {
+    if (level == 0 && p->L > 1) return fail(STITCH_E_SHAPE, "G_0 is never stored by the fused path");
+    r = c.roi[level];
+    *origin_x = r.x; *origin_y = r.y;
+    if (r.empty()) return STITCH_OK;
+    view->channels = 3;
+    view->data = p->ws + c.off_g[level];
+    view->row_pitch = c.g_row[level] * es; view->plane_pitch = c.g_plane[level] * es;
+  } else if (what == 2) {
+    r = c.roi[level];
+    *origin_x = r.x; *origin_y = r.y;
+    if (r.empty()) return STITCH_OK;
+    view->channels = 1;
+    if (level == 0) {
+      view->dtype = STITCH_U8;
+      view->data = p->ws + c.off_mask0;
+      view->row_pitch = c.mask_row;
+    } else {
+      view->data = p->ws + c.off_gm[level];
+      view->row_pitch = c.gm_row[level] * es;
+    }
+    view->plane_pitch = view->row_pitch * r.h;
+  } else {
+    return fail(STITCH_E_SHAPE, "what = %d is not 0..3", what);
+  }
+  view->width = r.w;
+  view->height = r.h;
+  return STITCH_OK;
+}
+
+stitch_status stitch_plan_regions(const stitch_plan* p, int32_t camera, int32_t level, int32_t roi[4],
+                                  int32_t band[4]) {
+  if (!p || !roi || !band) return fail(STITCH_E_NULL, "plan, roi or band is NULL");
+  if (camera < 0 || camera >= p->n) return fail(STITCH_E_SHAPE, "camera %d outside 0..%d", camera, p->n - 1);
+  if (level < 0 || level >= p->L) return fail(STITCH_E_LEVELS, "level %d outside 0..%d", level, p->L - 1);
+  const Rect r = p->cam[camera].roi[level], b = p->cam[camera].band[level];
+  roi[0] = r.x; roi[1] = r.y; roi[2] = r.w; roi[3] = r.h;
+  band[0] = b.x; band[1] = b.y; band[2] = b.w; band[3] = b.h;
+  return STITCH_OK;
+}
+
+void stitch_plan_destroy(stitch_plan* p) { delete p; }
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Internal descriptors shared by the host runtime (stitch_api.cpp) and the gfx950
+// kernels (kernels.hip).  Plain structs: they are copied to device memory or passed
+// as kernel arguments.
+#pragma once
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+namespace stitch {
+
+constexpr int kMaxLevels = 16;
+constexpr int kMaxCameras = 64;
+
+// Tile shape of the fused pyramid pass and of the blend pass (level-k pixels).
+constexpr int kPyrTX = 64, kPyrTY = 32;
+constexpr int kBlendTX = 64, kBlendTY = 16;
+constexpr int kThreads = 256;
+
+enum SrcKind : int32_t { kSrcNone = 0, kSrcWarp = 1, kSrcPlanes = 2, kSrcU8 = 3 };
+
+struct Hinv9 { float h[9]; };
+
+// One camera's tile range in a fused REDUCE (+ EXPAND/subtract) pass from level k
+// to level k+1.  Level-k input covers roi (zero outside it, reflect-101 at canvas
+// edges) except for a warp source, which is evaluated wherever it is needed.
+struct PyrItem {
+  int32_t tile_begin, tiles_x, tiles_y;
+  int32_t tile_x0, tile_y0;               // level-k origin of tile (0,0); both even
+  int32_t fine_w, fine_h;                 // level-k canvas sides
+  int32_t roi_x, roi_y, roi_w, roi_h;     // level-k input rectangle
+  // image source (channels nch)
+  int32_t img_kind, nch;
+  const void* img;                        // planes (storage type) or u8 HWC frame
+  int64_t img_row, img_plane;             // elements (planes) / bytes (frame row)
+  int32_t frame_w, frame_h, frame_slot, pad0;
+  float hinv[9];
+  // weight (mask) source, one channel
+  int32_t msk_kind, pad1;
+  const void* msk;                        // u8 plane or storage-type plane on roi
+  int64_t msk_row;                        // elements
+  // outputs at level k+1 on croi
+  int32_t croi_x, croi_y, croi_w, croi_h;
+  void* g_out;  int64_t g_row, g_plane;   // nch planes
+  void* gm_out; int64_t gm_row;           // 1 plane
+  // Laplacian band at level k on the window lw (w == 0: not written)
+  int32_t lw_x, lw_y, lw_w, lw_h;
+  void* l_out;  int64_t l_row, l_plane;
+};
+
+// Per-call frame pointers of the fused level-0 pass (kernel argument).
+struct FrameArgs {
+  int32_t n, pad;
+  const uint8_t* ptr[kMaxCameras];
+  int64_t row[kMaxCameras];               // bytes
+};
+
+// One camera's contribution to a blend level.
+struct BlendCam {
+  const void* lap; int64_t lap_row, lap_plane;   // storage type, 3 planes
+  int32_t lx, ly, lw, lh;                         // band rectangle (level-k canvas)
+  const void* wgt; int64_t wgt_row;               // weights: storage type or u8
+  int32_t wgt_u8, pad;
+  int32_t wx, wy, ww, wh;                         // weight rectangle
+};
+
+struct BlendArgs {
+  int32_t W, H;                     // level-k canvas sides
+  int32_t cW, cH;                   // level-(k+1) canvas sides (unused at the top level)
+  int32_t ncam, has_coarse;
+  const BlendCam* cams;             // device array
+  const void* r_in; int64_t rin_row, rin_plane;    // R_{k+1} (storage type)
+  void* r_out; int64_t rout_row, rout_plane;       // R_k (storage type) or nullptr
+  uint8_t* pano; int64_t pano_row;                 // U8 HWC (level 0) or nullptr
+  int32_t tiles_x, tiles_y;
+};
+
+// Launchers (kernels.hip).  f16 selects half-precision storage.
+hipError_t launch_pyr(bool f16, bool emit_lap, const PyrItem* items_dev, int nitems, int total_tiles,
+                      const FrameArgs& frames, hipStream_t s);
+// Table sizes the kernels accept.
+constexpr int kMaxBlendCams = kMaxCameras;
+hipError_t launch_blend(bool f16, const BlendArgs& a, hipStream_t s);
+hipError_t launch_warp(bool f16, const uint8_t* src, int64_t src_row, int w, int h, const float* hinv9,
+                       int roi_x, int roi_y, void* dst, int64_t dst_row, int64_t dst_plane, int dw, int dh,
+                       hipStream_t s);
+hipError_t launch_warp_coords(const float* hinv9, int roi_x, int roi_y, float* dst, int64_t row,
+                              int64_t plane, int dw, int dh, hipStream_t s);
+hipError_t launch_expand_sub(bool f16, int nch, void* fine, int64_t f_row, int64_t f_plane, int fx, int fy,
+                             int fw, int fh, const void* coarse, int64_t c_row, int64_t c_plane, int cx,
+                             int cy, int cw, int ch, int canvas_w, int canvas_h, hipStream_t s);
+hipError_t launch_convert(bool f16_out, int nch, bool src_u8, const void* src, int64_t s_row, int64_t s_plane,
+                          void* dst, int64_t d_row, int64_t d_plane, int w, int h, hipStream_t s);
+
+}  // namespace stitch

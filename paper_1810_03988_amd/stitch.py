@@ -1,0 +1,317 @@
+"""ctypes binding of libstitch.so: argument marshalling only.
+
+Torch tensors supply device memory (data_ptr) and the stream
+(torch.cuda.current_stream().cuda_stream); every step of the path runs in the HIP
+kernels behind the C ABI.  There is no fallback: if the library is missing or a call
+fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_size_t, c_uint8, c_void_p
+from pathlib import Path
+
+import numpy as np
+import torch
+
+LIB_PATH = Path(__file__).resolve().with_name("libstitch.so")
+
+U8, F16, F32 = 0, 1, 2
+HWC, CHW = 0, 1
+MAX_LEVELS = 16
+KEEP_R0 = 1
+STATUS = ["OK", "E_NULL", "E_SHAPE", "E_LEVELS", "E_HOMOGRAPHY", "E_MASK", "E_WORKSPACE", "E_DEVICE",
+          "E_UNSUPPORTED", "E_STATE"]
+
+
+class StitchImage(ctypes.Structure):
+    _fields_ = [("data", c_void_p), ("width", c_int32), ("height", c_int32), ("channels", c_int32),
+                ("dtype", c_int32), ("layout", c_int32), ("row_pitch", c_int64), ("plane_pitch", c_int64)]
+
+
+class StitchLevels(ctypes.Structure):
+    _fields_ = [("levels", c_int32), ("canvas_w", c_int32), ("canvas_h", c_int32),
+                ("origin_x", c_int32 * MAX_LEVELS), ("origin_y", c_int32 * MAX_LEVELS),
+                ("level", StitchImage * MAX_LEVELS)]
+
+
+class StitchError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        name = STATUS[status] if 0 <= status < len(STATUS) else str(status)
+        super().__init__(f"stitch {name}: {message}")
+
+
+_lib = None
+
+# name -> (restype, argtypes); every symbol of include/stitch.h
+SIGNATURES = {
+    "stitch_abi_version": (c_int32, []),
+    "stitch_status_str": (c_char_p, [c_int32]),
+    "stitch_last_error": (c_char_p, []),
+    "stitch_warp": (c_int32, [POINTER(StitchImage), POINTER(c_double), c_int32, c_int32, POINTER(StitchImage),
+                              c_void_p]),
+    "stitch_warp_coords": (c_int32, [POINTER(c_double), c_int32, c_int32, POINTER(StitchImage), c_void_p]),
+    "stitch_pyramid_workspace_bytes": (c_size_t, [c_int32]),
+    "stitch_pyramid": (c_int32, [POINTER(StitchImage), c_int32, POINTER(StitchLevels), c_void_p, c_size_t,
+                                 c_void_p]),
+    "stitch_blend_workspace_bytes": (c_size_t, [c_int32, c_int32]),
+    "stitch_blend": (c_int32, [c_int32, POINTER(StitchLevels), POINTER(StitchLevels), POINTER(StitchImage),
+                               POINTER(StitchLevels), c_void_p, c_size_t, c_void_p]),
+    "stitch_plan_create": (c_int32, [c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_double),
+                                     POINTER(POINTER(c_uint8)), c_int32, c_int32, c_int32, c_int32, c_int32,
+                                     POINTER(c_void_p)]),
+    "stitch_plan_workspace_bytes": (c_size_t, [c_void_p]),
+    "stitch_plan_bind": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    "stitch_frame": (c_int32, [c_void_p, POINTER(StitchImage), POINTER(StitchImage), c_void_p]),
+    "stitch_plan_view": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(StitchImage), POINTER(c_int32),
+                                   POINTER(c_int32)]),
+    "stitch_plan_regions": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_int32), POINTER(c_int32)]),
+    "stitch_plan_destroy": (None, [c_void_p]),
+}
+
+
+def lib():
+    """Load libstitch.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1810_03988_amd.build` "
+                              "(or __graft_entry__.build()); there is no fallback path")
+        handle = ctypes.CDLL(str(LIB_PATH))
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != 0:
+        raise StitchError(status, lib().stitch_last_error().decode())
+
+
+def last_error() -> str:
+    return lib().stitch_last_error().decode()
+
+
+# ----------------------------------------------------------------------------- marshalling
+_DT = {torch.uint8: U8, torch.float16: F16, torch.float32: F32}
+_TORCH_DT = {U8: torch.uint8, F16: torch.float16, F32: torch.float32}
+
+
+def image_hwc(t: torch.Tensor) -> StitchImage:
+    """(H, W, C) tensor with unit channel stride -> HWC image view."""
+    if t.dim() != 3 or t.stride(2) != 1 or t.stride(1) != t.shape[2]:
+        raise ValueError("HWC images need shape (H, W, C) with packed pixels")
+    es = t.element_size()
+    return StitchImage(t.data_ptr(), t.shape[1], t.shape[0], t.shape[2], _DT[t.dtype], HWC, t.stride(0) * es, 0)
+
+
+def image_chw(t: torch.Tensor) -> StitchImage:
+    """(C, H, W) or (H, W) tensor with unit column stride -> CHW image view."""
+    if t.dim() == 2:
+        t = t.unsqueeze(0)
+    if t.dim() != 3 or t.stride(2) != 1:
+        raise ValueError("CHW images need shape (C, H, W) with unit column stride")
+    es = t.element_size()
+    return StitchImage(t.data_ptr(), t.shape[2], t.shape[1], t.shape[0], _DT[t.dtype], CHW, t.stride(1) * es,
+                       t.stride(0) * es)
+
+
+def levels_struct(levels: list, origins: list, canvas_w: int, canvas_h: int) -> StitchLevels:
+    s = StitchLevels()
+    s.levels = len(levels)
+    s.canvas_w, s.canvas_h = canvas_w, canvas_h
+    for k, t in enumerate(levels):
+        if t is None:
+            s.level[k] = StitchImage()
+            continue
+        s.level[k] = image_chw(t)
+        s.origin_x[k], s.origin_y[k] = origins[k]
+    return s
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _h9(H) -> ctypes.Array:
+    a = np.ascontiguousarray(np.asarray(H, dtype=np.float64).reshape(9))
+    return (c_double * 9)(*a.tolist())
+
+
+def level_dims(canvas_h: int, canvas_w: int, levels: int) -> list:
+    dims = [(canvas_h, canvas_w)]
+    for _ in range(levels - 1):
+        dims.append(((dims[-1][0] + 1) // 2, (dims[-1][1] + 1) // 2))
+    return dims
+
+
+# ----------------------------------------------------------------------------- single stages
+def warp(src: torch.Tensor, H, roi_x: int, roi_y: int, width: int, height: int, dtype=torch.float32,
+         out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """G_0 (3, height, width) of one camera over a canvas rectangle."""
+    if out is None:
+        out = torch.empty((3, height, width), dtype=dtype, device=src.device)
+    check(lib().stitch_warp(ctypes.byref(image_hwc(src)), _h9(H), roi_x, roi_y, ctypes.byref(image_chw(out)),
+                            _stream(stream)))
+    return out
+
+
+def warp_coords(H, roi_x: int, roi_y: int, width: int, height: int, device="cuda", stream=None) -> torch.Tensor:
+    out = torch.empty((2, height, width), dtype=torch.float32, device=device)
+    check(lib().stitch_warp_coords(_h9(H), roi_x, roi_y, ctypes.byref(image_chw(out)), _stream(stream)))
+    return out
+
+
+def pyramid(g0: torch.Tensor, levels: int, kind: str = "laplacian", canvas=None, origin=(0, 0),
+            dtype=None, stream=None) -> list:
+    """Gaussian or Laplacian pyramid of g0 ((C,H,W) float or (H,W) uint8 weights) placed at
+    `origin` on a canvas of size `canvas` (w, h; default: g0's own size), stored on the
+    rectangles [origin >> k, ceil((origin + size) / 2^k))."""
+    if g0.dtype == torch.uint8 and g0.dim() == 2:
+        g0v = g0.unsqueeze(0)
+        dtype = dtype or torch.float32
+    else:
+        g0v = g0
+        dtype = dtype or g0.dtype
+    C, h, w = g0v.shape
+    cw, ch = canvas if canvas is not None else (w, h)
+    ox, oy = origin
+    outs, origins = [], []
+    for k in range(levels):
+        x0, y0 = ox >> k, oy >> k
+        x1 = min(-(-(ox + w) // (1 << k)), -(-cw // (1 << k)))
+        y1 = min(-(-(oy + h) // (1 << k)), -(-ch // (1 << k)))
+        outs.append(torch.empty((C, y1 - y0, x1 - x0), dtype=dtype, device=g0.device))
+        origins.append((x0, y0))
+    s = levels_struct(outs, origins, cw, ch)
+    nbytes = lib().stitch_pyramid_workspace_bytes(levels)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=g0.device)
+    base = (ws.data_ptr() + 255) // 256 * 256
+    src = StitchImage(g0v.data_ptr(), w, h, C, _DT[g0v.dtype], CHW, g0v.stride(1) * g0v.element_size(),
+                      g0v.stride(0) * g0v.element_size())
+    check(lib().stitch_pyramid(ctypes.byref(src), 0 if kind.startswith("g") else 1, ctypes.byref(s), base, nbytes,
+                               _stream(stream)))
+    return outs
+
+
+def blend(bands: list, weights: list, canvas_w: int, canvas_h: int, band_origins=None, weight_origins=None,
+          keep_r: bool = True, stream=None):
+    """Blend n Laplacian pyramids with n weight pyramids; returns (pano uint8 (H,W,3), R levels)."""
+    n = len(bands)
+    L = len(bands[0])
+    dev = bands[0][0].device
+    dt = bands[0][0].dtype
+    zeros = [(0, 0)] * L
+    band_origins = band_origins or [zeros] * n
+    weight_origins = weight_origins or [zeros] * n
+    bs = (StitchLevels * n)(*[levels_struct(b, o, canvas_w, canvas_h) for b, o in zip(bands, band_origins)])
+    ws_ = (StitchLevels * n)(*[levels_struct(w, o, canvas_w, canvas_h) for w, o in zip(weights, weight_origins)])
+    pano = torch.empty((canvas_h, canvas_w, 3), dtype=torch.uint8, device=dev)
+    rs = [torch.empty((3, h, w), dtype=dt, device=dev) for h, w in level_dims(canvas_h, canvas_w, L)]
+    if not keep_r:
+        rs[0] = None
+    rstruct = levels_struct(rs, zeros, canvas_w, canvas_h)
+    nbytes = lib().stitch_blend_workspace_bytes(n, L)
+    wsp = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    base = (wsp.data_ptr() + 255) // 256 * 256
+    check(lib().stitch_blend(n, bs, ws_, ctypes.byref(image_hwc(pano)), ctypes.byref(rstruct), base, nbytes,
+                             _stream(stream)))
+    return pano, rs
+
+
+# ----------------------------------------------------------------------------- planned frame path
+class Plan:
+    """A fixed rig planned once (Sec. 4.3.2 pre-allocation): validation, per-camera
+    regions and the workspace, then stitch_frame per frame set."""
+
+    def __init__(self, frame_sizes, Hs, masks, canvas_w: int, canvas_h: int, levels: int,
+                 storage: str = "f32", keep_r0: bool = False, device="cuda", bind: bool = True):
+        L = lib()
+        n = len(Hs)
+        self.n, self.canvas_w, self.canvas_h, self.levels = n, canvas_w, canvas_h, levels
+        self.storage = F16 if storage in ("f16", torch.float16, F16) else F32
+        self.frame_sizes = [tuple(map(int, s)) for s in frame_sizes]
+        fw = (c_int32 * n)(*[s[0] for s in self.frame_sizes])
+        fh = (c_int32 * n)(*[s[1] for s in self.frame_sizes])
+        Hflat = np.ascontiguousarray(np.stack([np.asarray(h, dtype=np.float64).reshape(9) for h in Hs]))
+        self._masks = [np.ascontiguousarray(np.asarray(m, dtype=np.uint8)) for m in masks]
+        for m in self._masks:
+            if m.shape != (canvas_h, canvas_w):
+                raise ValueError("each mask must be (canvas_h, canvas_w) uint8")
+        mptrs = (POINTER(c_uint8) * n)(*[m.ctypes.data_as(POINTER(c_uint8)) for m in self._masks])
+        handle = c_void_p()
+        check(L.stitch_plan_create(n, fw, fh, Hflat.ctypes.data_as(POINTER(c_double)), mptrs, canvas_w, canvas_h,
+                                   levels, self.storage, KEEP_R0 if keep_r0 else 0, ctypes.byref(handle)))
+        self._h = handle
+        self._masks = None   # the plan keeps its own copy
+        self.ws_bytes = L.stitch_plan_workspace_bytes(self._h)
+        self.device = torch.device(device)
+        self.workspace = None
+        if bind:
+            self.bind()
+
+    def bind(self, workspace: torch.Tensor | None = None, stream=None) -> None:
+        if workspace is None:
+            workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = (workspace.data_ptr() + 255) // 256 * 256
+        check(lib().stitch_plan_bind(self._h, base, self.ws_bytes, _stream(stream)))
+        self.workspace = workspace
+        self._base = base
+
+    def frame(self, frames, pano: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if pano is None:
+            pano = torch.empty((self.canvas_h, self.canvas_w, 3), dtype=torch.uint8, device=frames[0].device)
+        fr = (StitchImage * self.n)(*[image_hwc(f) for f in frames])
+        check(lib().stitch_frame(self._h, fr, ctypes.byref(image_hwc(pano)), _stream(stream)))
+        return pano
+
+    def frame_args(self, frames, pano):
+        """Pre-marshalled arguments for repeated stitch_frame calls (timing loops)."""
+        fr = (StitchImage * self.n)(*[image_hwc(f) for f in frames])
+        return fr, image_hwc(pano)
+
+    def frame_raw(self, args, stream_handle: int) -> None:
+        fr, pv = args
+        check(lib().stitch_frame(self._h, fr, ctypes.byref(pv), stream_handle))
+
+    def view(self, what: str, camera: int, level: int):
+        """(tensor, (origin_x, origin_y)) aliasing the workspace; what in lap|gauss|mask|r."""
+        code = {"lap": 0, "gauss": 1, "mask": 2, "r": 3}[what]
+        im = StitchImage()
+        ox, oy = c_int32(), c_int32()
+        check(lib().stitch_plan_view(self._h, code, camera, level, ctypes.byref(im), ctypes.byref(ox),
+                                     ctypes.byref(oy)))
+        if im.width == 0 or im.height == 0:
+            return None, (ox.value, oy.value)
+        dt = _TORCH_DT[im.dtype]
+        es = torch.empty((), dtype=dt).element_size()
+        base = self.workspace.data_ptr()
+        flat = self.workspace[: (self.workspace.numel() // es) * es].view(dt)
+        off = im.data - base
+        assert off % es == 0 and im.row_pitch % es == 0
+        t = torch.as_strided(flat, (im.channels, im.height, im.width),
+                             (im.plane_pitch // es if im.channels > 1 else 0, im.row_pitch // es, 1), off // es)
+        return t, (ox.value, oy.value)
+
+    def regions(self, camera: int, level: int):
+        roi = (c_int32 * 4)()
+        band = (c_int32 * 4)()
+        check(lib().stitch_plan_regions(self._h, camera, level, roi, band))
+        return tuple(roi), tuple(band)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().stitch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,171 @@
+"""The C ABI on the CPU: the library loads, exports every declared symbol, and rejects
+bad arguments on the host before any HIP call (so none of this needs a GPU)."""
+import ctypes
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import paper_1810_03988_amd as P
+from paper_1810_03988_amd import stitch as S
+import workloads as wl
+
+HEADER = Path(__file__).resolve().parents[1] / "include" / "stitch.h"
+E = {name: i for i, name in enumerate(S.STATUS)}
+
+
+def declared_symbols():
+    text = re.sub(r"/\*.*?\*/", "", HEADER.read_text(), flags=re.S)
+    return sorted(set(re.findall(r"\b(stitch_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.lib()
+    names = declared_symbols()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in S.SIGNATURES, f"{n} has no binding"
+    assert lib.stitch_abi_version() == 1
+    assert lib.stitch_status_str(5) == b"invalid seam weights"
+
+
+def _plan_args(rig=None, masks=None, levels=None, storage=S.F32, H=None):
+    rig = rig or wl.rig_c1()
+    n = rig.n
+    masks = masks if masks is not None else rig.masks()
+    fw = (ctypes.c_int32 * n)(*[s[0] for s in rig.frame_sizes])
+    fh = (ctypes.c_int32 * n)(*[s[1] for s in rig.frame_sizes])
+    Hs = np.ascontiguousarray(np.stack([np.asarray(h, float).reshape(9) for h in (H or rig.H)]))
+    keep = [np.ascontiguousarray(m) for m in masks]
+    mp = (ctypes.POINTER(ctypes.c_uint8) * n)(*[m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) for m in keep])
+    return (n, fw, fh, Hs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), mp, rig.canvas_w, rig.canvas_h,
+            levels or rig.levels, storage, 0), (keep, Hs)
+
+
+def _create(*args):
+    h = ctypes.c_void_p()
+    st = P.lib().stitch_plan_create(*args, ctypes.byref(h))
+    return st, h
+
+
+def test_plan_create_and_regions_are_aligned():
+    args, keep = _plan_args()
+    st, h = _create(*args)
+    assert st == 0, P.stitch.last_error()
+    try:
+        assert P.lib().stitch_plan_workspace_bytes(h) > 0
+        L = args[7]
+        for cam in range(2):
+            roi = (ctypes.c_int32 * 4)()
+            band = (ctypes.c_int32 * 4)()
+            for k in range(L):
+                assert P.lib().stitch_plan_regions(h, cam, k, roi, band) == 0
+                if k == 0:
+                    assert roi[0] % (1 << (L - 1)) == 0 and roi[1] % (1 << (L - 1)) == 0
+                # the band window lies inside the roi
+                assert band[0] >= roi[0] and band[0] + band[2] <= roi[0] + roi[2]
+                assert band[1] >= roi[1] and band[1] + band[3] <= roi[1] + roi[3]
+        # camera B (x from ~392) gets a roi that does not start at the canvas edge
+        assert P.lib().stitch_plan_regions(h, 1, 0, roi, band) == 0
+        assert 0 < roi[0] < 392 - 32
+    finally:
+        P.lib().stitch_plan_destroy(h)
+
+
+@pytest.mark.parametrize("case,code", [
+    ("mask_sum", "E_MASK"), ("levels_deep", "E_LEVELS"), ("levels_zero", "E_LEVELS"), ("nan_h", "E_HOMOGRAPHY"),
+    ("singular_h", "E_HOMOGRAPHY"), ("storage", "E_UNSUPPORTED"), ("null_mask", "E_NULL"),
+])
+def test_plan_create_rejects(case, code):
+    rig = wl.rig_c1()
+    kw = {}
+    if case == "mask_sum":
+        kw["masks"] = [rig.masks()[0], rig.masks()[0]]
+    elif case == "levels_deep":
+        kw["levels"] = 9          # 480 -> ... -> 2 at level 8
+    elif case == "levels_zero":
+        kw["levels"] = 17
+    elif case == "nan_h":
+        H = [h.copy() for h in rig.H]
+        H[1][0, 2] = np.nan
+        kw["H"] = H
+    elif case == "singular_h":
+        H = [h.copy() for h in rig.H]
+        H[1][:2, :2] = [[1.0, 2.0], [2.0, 4.0]]
+        kw["H"] = H
+    elif case == "storage":
+        kw["storage"] = 7
+    args, keep = _plan_args(rig, **kw)
+    if case == "null_mask":
+        args = list(args)
+        mp = (ctypes.POINTER(ctypes.c_uint8) * 2)(args[4][0], ctypes.POINTER(ctypes.c_uint8)())
+        args[4] = mp
+    st, h = _create(*args)
+    assert st == E[code], (st, P.stitch.last_error())
+    assert not h.value
+    assert len(P.stitch.last_error()) > 0
+
+
+def test_frame_requires_bound_workspace_and_valid_views():
+    args, keep = _plan_args()
+    st, h = _create(*args)
+    assert st == 0
+    try:
+        fake = 0x10000
+        frames = (S.StitchImage * 2)(S.StitchImage(fake, 640, 480, 3, S.U8, S.HWC, 1920, 0),
+                                     S.StitchImage(fake, 640, 480, 3, S.U8, S.HWC, 1920, 0))
+        pano = S.StitchImage(fake, 1040, 480, 3, S.U8, S.HWC, 3120, 0)
+        assert P.lib().stitch_frame(h, frames, ctypes.byref(pano), None) == E["E_STATE"]
+        assert P.lib().stitch_frame(h, None, ctypes.byref(pano), None) == E["E_NULL"]
+        assert P.lib().stitch_plan_bind(h, None, 0, None) == E["E_WORKSPACE"]
+        assert P.lib().stitch_plan_bind(h, 0x10001, 1 << 40, None) == E["E_WORKSPACE"]   # misaligned
+        assert P.lib().stitch_plan_bind(h, 0x10000, 16, None) == E["E_WORKSPACE"]        # too small
+    finally:
+        P.lib().stitch_plan_destroy(h)
+
+
+def test_single_stage_calls_validate_on_host():
+    lib = P.lib()
+    fake = 0x10000
+    H = (ctypes.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1)
+    Hbad = (ctypes.c_double * 9)(1, 2, 0, 2, 4, 0, 0, 0, 1)
+    src = S.StitchImage(fake, 64, 48, 3, S.U8, S.HWC, 192, 0)
+    dst = S.StitchImage(fake, 64, 48, 3, S.F32, S.CHW, 256, 256 * 48)
+    assert lib.stitch_warp(None, H, 0, 0, ctypes.byref(dst), None) == E["E_NULL"]
+    assert lib.stitch_warp(ctypes.byref(src), Hbad, 0, 0, ctypes.byref(dst), None) == E["E_HOMOGRAPHY"]
+    bad = S.StitchImage(fake, 64, 48, 3, S.U8, S.CHW, 64, 64 * 48)
+    assert lib.stitch_warp(ctypes.byref(src), H, 0, 0, ctypes.byref(bad), None) == E["E_UNSUPPORTED"]
+    short = S.StitchImage(fake, 64, 48, 3, S.F32, S.CHW, 100, 256 * 48)
+    assert lib.stitch_warp(ctypes.byref(src), H, 0, 0, ctypes.byref(short), None) == E["E_SHAPE"]
+    # pyramid: a level side below 3 is rejected before anything runs
+    lv = S.StitchLevels()
+    lv.levels, lv.canvas_w, lv.canvas_h = 3, 8, 8
+    for k, s in enumerate([8, 4, 2]):
+        lv.level[k] = S.StitchImage(fake, s, s, 1, S.F32, S.CHW, 256, 256 * s)
+    g0 = S.StitchImage(fake, 8, 8, 1, S.F32, S.CHW, 256, 2048)
+    assert lib.stitch_pyramid(ctypes.byref(g0), 1, ctypes.byref(lv), fake, 4096, None) == E["E_LEVELS"]
+    lv.levels = 2
+    assert lib.stitch_pyramid(ctypes.byref(g0), 1, ctypes.byref(lv), None, 0, None) == E["E_WORKSPACE"]
+    assert lib.stitch_pyramid(ctypes.byref(g0), 3, ctypes.byref(lv), fake, 4096, None) == E["E_UNSUPPORTED"]
+    # blend: missing R storage for a multi-level blend
+    pano = S.StitchImage(fake, 8, 8, 3, S.U8, S.HWC, 24, 0)
+    b = S.StitchLevels()
+    b.levels, b.canvas_w, b.canvas_h = 2, 8, 8
+    w = S.StitchLevels()
+    w.levels, w.canvas_w, w.canvas_h = 2, 8, 8
+    for k, s in enumerate([8, 4]):
+        b.level[k] = S.StitchImage(fake, s, s, 3, S.F32, S.CHW, 256, 256 * s)
+        w.level[k] = S.StitchImage(fake, s, s, 1, S.F32, S.CHW, 256, 256 * s)
+    assert lib.stitch_blend(1, ctypes.byref(b), ctypes.byref(w), ctypes.byref(pano), None, fake, 1 << 20,
+                            None) == E["E_NULL"]
+    assert lib.stitch_blend(0, ctypes.byref(b), ctypes.byref(w), ctypes.byref(pano), None, fake, 1 << 20,
+                            None) == E["E_SHAPE"]
+
+
+def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(S, "LIB_PATH", tmp_path / "missing.so")
+    monkeypatch.setattr(S, "_lib", None)
+    with pytest.raises(ImportError):
+        S.lib()

@@ -1,0 +1,123 @@
+"""GPU parity of the single-stage entry points (stitch_warp, stitch_warp_coords,
+stitch_pyramid, stitch_blend) against the FP64 oracle, element by element."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as o
+import paper_1810_03988_amd as P
+import workloads as wl
+from helpers import assert_float_parity, assert_u8_parity, gpu_available, random_partition
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+DEV = "cuda"
+
+
+def _T(tx, ty):
+    return np.array([[1.0, 0, tx], [0, 1.0, ty], [0, 0, 1.0]])
+
+
+PROJ = np.array([[0.97, 0.05, 13.25], [-0.04, 1.02, -6.5], [1.8e-4, -2.2e-4, 1.0]])
+
+
+@pytest.mark.parametrize("H", [np.eye(3), _T(400.0, 3.0), PROJ, "c1b"])
+def test_warp_coordinates_are_bit_identical_to_the_fp32_sequence(H):
+    if isinstance(H, str):
+        H = wl.rig_c1().H[1]
+    xy = P.warp_coords(H, -37, -11, 1100, 520).cpu().numpy()
+    x, y, zpos = o.warp_coords(o.hinv_spec(H), np.arange(-11, 509), np.arange(-37, 1063))
+    assert zpos.all()
+    assert np.array_equal(xy[0].view(np.uint32), x.astype(np.float32).view(np.uint32))
+    assert np.array_equal(xy[1].view(np.uint32), y.astype(np.float32).view(np.uint32))
+
+
+def test_warp_coordinates_random_homographies_bitwise():
+    rng = np.random.default_rng(5)
+    for _ in range(8):
+        H = np.eye(3) + rng.normal(0, [[0.05, 0.05, 30], [0.05, 0.05, 30], [1e-4, 1e-4, 0]])
+        xy = P.warp_coords(H, 0, 0, 700, 300).cpu().numpy()
+        x, y, zpos = o.warp_coords(o.hinv_spec(H), np.arange(300), np.arange(700))
+        ok = zpos
+        assert np.array_equal(xy[0][ok].view(np.uint32), x[ok].view(np.uint32))
+        assert np.array_equal(xy[1][ok].view(np.uint32), y[ok].view(np.uint32))
+        assert np.all(np.isnan(xy[0][~ok]))
+
+
+@pytest.mark.parametrize("case", ["c1b", "proj", "identity", "translate", "f16"])
+def test_warp_matches_oracle(case):
+    r = wl.rig_c1()
+    frames = wl.render_rig_frames(r)
+    src = frames[1]
+    H = {"c1b": r.H[1], "proj": PROJ, "identity": np.eye(3), "translate": _T(-17.0, 9.0), "f16": r.H[1]}[case]
+    dtype = torch.float16 if case == "f16" else torch.float32
+    rx, ry, W, Hh = -5, -3, 1050, 490
+    g = P.warp(src.to(DEV), H, rx, ry, W, Hh, dtype=dtype).float().cpu().numpy()
+    want = o.warp(src.numpy(), o.hinv_spec(H), np.arange(ry, ry + Hh), np.arange(rx, rx + W))
+    tol = 1e-3 if case == "f16" else 1e-4
+    err = assert_float_parity(g, want, tol, case)
+    if case in ("identity", "translate"):
+        assert err < 1e-7       # integer maps: the value is the sample itself
+
+
+def test_pyramid_matches_oracle_odd_even_sizes():
+    rng = np.random.default_rng(0)
+    for (h, w, L) in [(97, 130, 5), (64, 64, 4), (35, 67, 3), (3, 5, 1), (12, 7, 2), (480, 1040, 5)]:
+        img = rng.random((3, h, w)).astype(np.float32)
+        lap = P.pyramid(torch.from_numpy(img).to(DEV), L, "laplacian")
+        gau = P.pyramid(torch.from_numpy(img).to(DEV), L, "gaussian")
+        want_l = o.laplacian_pyramid(img.astype(np.float64), L)
+        want_g = o.gaussian_pyramid(img.astype(np.float64), L)
+        for k in range(L):
+            assert_float_parity(lap[k].cpu().numpy(), want_l[k], 1e-5, f"L{k} {h}x{w}")
+            assert_float_parity(gau[k].cpu().numpy(), want_g[k], 1e-5, f"G{k} {h}x{w}")
+
+
+def test_pyramid_of_u8_weights_and_offset_rectangles():
+    rng = np.random.default_rng(1)
+    m = rng.integers(0, 256, (90, 150), dtype=np.uint8)
+    gm = P.pyramid(torch.from_numpy(m).to(DEV), 4, "gaussian")
+    want = o.gaussian_pyramid(m[None].astype(np.float64) / 255.0, 4)
+    for k in range(4):
+        assert_float_parity(gm[k].cpu().numpy(), want[k], 1e-6, f"Gm{k}")
+    # an image that is zero outside a rectangle placed at an offset on a larger canvas
+    canvas_w, canvas_h, ox, oy, L = 200, 120, 48, 16, 3
+    img = np.zeros((3, canvas_h, canvas_w))
+    patch = rng.random((3, 40, 60))
+    img[:, oy + 12:oy + 52, ox + 20:ox + 80] = patch
+    sub = img[:, oy:oy + 80, ox:ox + 120].astype(np.float32)     # holds the support with a margin
+    lap = P.pyramid(torch.from_numpy(sub).to(DEV), L, "laplacian", canvas=(canvas_w, canvas_h), origin=(ox, oy))
+    want = o.laplacian_pyramid(img, L)
+    for k in range(L):
+        x0, y0 = ox >> k, oy >> k
+        got = lap[k].cpu().numpy()
+        assert_float_parity(got, want[k][:, y0:y0 + got.shape[1], x0:x0 + got.shape[2]], 1e-5, f"roi L{k}")
+
+
+def test_blend_matches_oracle():
+    rng = np.random.default_rng(2)
+    h, w, L, n = 75, 133, 4, 3
+    imgs = [rng.random((3, h, w)) for _ in range(n)]
+    masks = random_partition(rng, n, h, w)
+    laps = [o.laplacian_pyramid(im, L) for im in imgs]
+    gms = [o.gaussian_pyramid(m[None] / 255.0, L) for m in masks]
+    want_r = o.blend_pyramids(laps, gms)
+    bands = [[torch.from_numpy(x.astype(np.float32)).to(DEV) for x in lp] for lp in laps]
+    wts = [[torch.from_numpy(x.astype(np.float32)).to(DEV) for x in g] for g in gms]
+    wts_u8 = [[torch.from_numpy(masks[i]).to(DEV)] + wts[i][1:] for i in range(n)]
+    for weights in (wts, wts_u8):
+        pano, rs = P.blend(bands, weights, w, h)
+        for k in range(L):
+            assert_float_parity(rs[k].cpu().numpy(), want_r[k], 1e-5, f"R{k}")
+        assert_u8_parity(pano.cpu().numpy(), o.quantise(want_r[0]))
+
+
+def test_blend_single_level_is_alpha_blend():
+    rng = np.random.default_rng(3)
+    h, w = 31, 47
+    a, b = rng.random((3, h, w)), rng.random((3, h, w))
+    m = rng.integers(0, 256, (h, w), dtype=np.uint8)
+    pano, rs = P.blend([[torch.from_numpy(a.astype(np.float32)).to(DEV)],
+                        [torch.from_numpy(b.astype(np.float32)).to(DEV)]],
+                       [[torch.from_numpy(m).to(DEV)], [torch.from_numpy(255 - m).to(DEV)]], w, h)
+    want = m / 255.0 * a + (1 - m / 255.0) * b
+    assert_float_parity(rs[0].cpu().numpy(), want, 1e-6, "alpha")
