@@ -195,6 +195,20 @@ stitch_status stitch_plan_view(const stitch_plan* plan, int32_t what, int32_t ca
 stitch_status stitch_plan_regions(const stitch_plan* plan, int32_t camera, int32_t level,
                                   int32_t roi[4], int32_t band[4]);
 
+/* Per-launch timing of stitch_frame (tracing; the paper only analyses grid sizes and
+ * memory, Sec. 4.3.2).  While enabled, stitch_frame records one HIP event on its stream
+ * before its first launch and one after every launch, and the time between consecutive
+ * events is charged to the launch's kind:
+ *   0 warp + level-0 pyramid pass, 1 pyramid passes of levels >= 1, 2 blend of level 0
+ *   (with EXPAND of R_1), 3 blend of a middle level, 4 blend of the top level, 5 blend of
+ *   a single-level plan, 6 warp of a single-level plan.
+ * set_timing clears the totals; read_timing waits for the recorded events and returns
+ * accumulated milliseconds and launch counts per kind.  Errors: NULL, DEVICE. */
+#define STITCH_TIMING_KINDS 8
+stitch_status stitch_plan_set_timing(stitch_plan* plan, int32_t enable);
+stitch_status stitch_plan_read_timing(stitch_plan* plan, double ms[STITCH_TIMING_KINDS],
+                                      int32_t launches[STITCH_TIMING_KINDS]);
+
 void stitch_plan_destroy(stitch_plan* plan);
 
 #ifdef __cplusplus

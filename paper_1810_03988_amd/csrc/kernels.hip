@@ -16,7 +16,6 @@
 // periodic reflect-101 extension makes the locally reduced coarse tile equal to the
 // fine-domain-folded zero-inserted coarse signal, so EXPAND inside a tile needs no
 // border cases at all.
-#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include "stitch_internal.h"
@@ -27,10 +26,23 @@ namespace {
 constexpr float kW0 = 1.0f / 16.0f, kW1 = 4.0f / 16.0f, kW2 = 6.0f / 16.0f;
 constexpr float kInv255 = 1.0f / 255.0f;
 
+#define GLB __attribute__((address_space(1)))
+
+// Views of descriptor-held pointers as global memory, so accesses compile to global (not
+// flat) instructions.
+template <typename T>
+__device__ __forceinline__ const GLB T* cg(const void* p) { return (const GLB T*)p; }
+template <typename T>
+__device__ __forceinline__ GLB T* mg(void* p) { return (GLB T*)p; }
+__device__ __forceinline__ float ldg(const GLB float* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float ldg(const GLB _Float16* p, int64_t i) { return (float)p[i]; }
+__device__ __forceinline__ void stg(GLB float* p, int64_t i, float v) { p[i] = v; }
+__device__ __forceinline__ void stg(GLB _Float16* p, int64_t i, float v) { p[i] = (_Float16)v; }
+
 __device__ __forceinline__ float ldv(const float* p, int64_t i) { return p[i]; }
-__device__ __forceinline__ float ldv(const __half* p, int64_t i) { return __half2float(p[i]); }
+__device__ __forceinline__ float ldv(const _Float16* p, int64_t i) { return (float)p[i]; }
 __device__ __forceinline__ void stv(float* p, int64_t i, float v) { p[i] = v; }
-__device__ __forceinline__ void stv(__half* p, int64_t i, float v) { p[i] = __float2half_rn(v); }
+__device__ __forceinline__ void stv(_Float16* p, int64_t i, float v) { p[i] = (_Float16)v; }
 
 // Periodic reflect-101 extension: index -> [0, n), n >= 2 (period 2(n-1)).
 __device__ __forceinline__ int fold(int i, int n) {
@@ -100,136 +112,353 @@ __device__ __forceinline__ int find_item(const PyrItem* __restrict__ items, int 
 }
 
 // ------------------------------------------------------------------------------------
-// Fused pyramid pass.
-template <typename T, bool EMIT_LAP>
-__global__ void __launch_bounds__(kThreads) k_pyr(const PyrItem* __restrict__ items, int nitems, FrameArgs fa) {
-  constexpr int TX = kPyrTX, TY = kPyrTY;
-  constexpr int EW = TX + 7, EH = TY + 7;            // fine tile + halo (4 before, 3 after)
-  constexpr int CW = TX / 2 + 2, CH = TY / 2 + 2;    // coarse tile + one-sample halo
-  __shared__ float sIn[3][EH][EW + 1];
-  __shared__ float sH[EH][CW + 1];
-  __shared__ float sC[CH][CW + 1];
-  __shared__ float sE[CH][TX + 1];
+// Fused pyramid pass over 64x16 level-k tiles (256 threads, four waves per workgroup).
+//
+// Persistent, XCD-aware schedule: the tiles are split into eight contiguous ranges, one
+// per XCD (workgroup b runs on XCD b % 8), and the workgroups of an XCD stride through
+// its range, so neighbouring tiles -- which share halos -- share that XCD's L2.  While a
+// tile is being computed, the global loads of the workgroup's next tile are already in
+// flight (they land in registers), so each tile costs its compute, not its latency.
+//
+// Stages of one tile, each ended by one barrier:
+//   A  stage the fine tile + halo (71x23) of every channel in LDS: three image channels
+//      (bilinear warp of the source frame at level 0 -- taps read from an LDS copy of the
+//      tile's source footprint -- or stored G_k above) and the seam weight;
+//   B  horizontal REDUCE (two coarse outputs per thread from two b128 LDS reads);
+//   C  vertical REDUCE -> extended 34x10 coarse tile; its interior is G_{k+1} / Gm_{k+1};
+//   D  horizontal EXPAND of the coarse tile (four fine columns per thread);
+//   E  vertical EXPAND and L_k = G_k - EXPAND(G_{k+1}), stored on the band window.
+struct PyrTile {
+  int item, X0, Y0;
+};
 
-  const int tid = threadIdx.x;
-  const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const PyrItem& it = items[find_item(items, nitems, t)];
+__device__ __forceinline__ PyrTile decode_tile(const PyrItem* __restrict__ items, int nitems, int t) {
+  PyrTile d;
+  d.item = find_item(items, nitems, t);
+  const PyrItem& it = items[d.item];
   const int lt = t - it.tile_begin;
   const int tyi = lt / it.tiles_x, txi = lt - tyi * it.tiles_x;
-  const int X0 = it.tile_x0 + txi * TX, Y0 = it.tile_y0 + tyi * TY;   // even
-  const int fw = it.fine_w, fh = it.fine_h;
-  const int nch = it.nch;
+  d.X0 = it.tile_x0 + txi * kPyrTX;
+  d.Y0 = it.tile_y0 + tyi * kPyrTY;
+  return d;
+}
 
-  // ---- stage the fine image tile (all channels) ----
-  if (it.img_kind == kSrcWarp) {
-    const uint8_t* src = fa.n ? fa.ptr[it.frame_slot] : (const uint8_t*)it.img;
-    const int64_t srow = fa.n ? fa.row[it.frame_slot] : it.img_row;
-    float hv[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) hv[i] = it.hinv[i];
-    for (int e = tid; e < EH * EW; e += kThreads) {
-      const int r = e / EW, c = e - r * EW;
-      const int Y = fold(Y0 - 4 + r, fh), X = fold(X0 - 4 + c, fw);
-      float v[3];
-      warp_px(src, srow, it.frame_w, it.frame_h, hv, X, Y, v);
-      sIn[0][r][c] = v[0];
-      sIn[1][r][c] = v[1];
-      sIn[2][r][c] = v[2];
-    }
-  } else if (it.img_kind == kSrcPlanes) {
-    const T* g = (const T*)it.img;
-    for (int e = tid; e < EH * EW; e += kThreads) {
-      const int r = e / EW, c = e - r * EW;
-      const int Y = fold(Y0 - 4 + r, fh) - it.roi_y, X = fold(X0 - 4 + c, fw) - it.roi_x;
-      const bool in = X >= 0 && X < it.roi_w && Y >= 0 && Y < it.roi_h;
-      const int64_t off = in ? (int64_t)Y * it.img_row + X : 0;
-      for (int ch = 0; ch < nch; ++ch) sIn[ch][r][c] = in ? ldv(g, ch * it.img_plane + off) : 0.0f;
-    }
+template <typename T, bool EMIT_LAP, bool WARP>
+__global__ void __launch_bounds__(kThreads) k_pyr(const PyrItem* __restrict__ items, int nitems, int ntiles,
+                                                  FrameArgs fa) {
+  constexpr int TX = kPyrTX, TY = kPyrTY;
+  constexpr int EW = TX + 7, EH = TY + 7;            // staged fine samples: 4 before, 3 after
+  constexpr int SW = 72;                             // LDS row strides are 16-byte multiples
+  constexpr int CW = TX / 2 + 2, CH = TY / 2 + 2;    // coarse tile + one-sample halo
+  constexpr int HS = 36, ES = TX + 4;
+  constexpr int NE = EH * EW;
+  constexpr int NIT = (NE + kThreads - 1) / kThreads;
+  static_assert(3 * CH * ES <= 4 * EH * HS, "sE must fit in sH");
+  __shared__ __attribute__((aligned(16))) float sIn[4][EH][SW];
+  __shared__ __attribute__((aligned(16))) float sH[4][EH][HS];
+  __shared__ __attribute__((aligned(16))) float sC[3][CH][HS];
+  float(*sE)[CH][ES] = reinterpret_cast<float(*)[CH][ES]>(&sH[0][0][0]);   // sH is dead once sC is built
+
+  const int tid = threadIdx.x;
+  // ---- schedule ----
+  const int G = gridDim.x, b = blockIdx.x;
+  int t, t_end, stride;
+  if (G >= 8) {
+    const int xcd = b & 7, rank = b >> 3;
+    const int q = ntiles >> 3, r = ntiles & 7;
+    const int t0 = xcd * q + min(xcd, r);
+    t = t0 + rank;
+    t_end = t0 + q + (xcd < r ? 1 : 0);
+    stride = (G - xcd + 7) >> 3;
+  } else {
+    t = b;
+    t_end = ntiles;
+    stride = G;
   }
 
-  const int cx0 = X0 / 2 - 1, cy0 = Y0 / 2 - 1;    // coarse canvas coords of sC[0][0]
-  const bool lap_tile = EMIT_LAP && it.lw_w > 0 && X0 < it.lw_x + it.lw_w && X0 + TX > it.lw_x &&
-                        Y0 < it.lw_y + it.lw_h && Y0 + TY > it.lw_y;
-  const int nimg = it.img_kind == kSrcNone ? 0 : nch;
-  const int npass = nimg + (it.msk_kind != kSrcNone ? 1 : 0);
+  // ---- prefetched global data of the next tile (registers) ----
+  uint32_t pm[WARP ? NIT : 1];         // warp: seam weights (uint8)
+  float pg[WARP ? 1 : NIT][4];         // planes: G_k channels and Gm_k
 
-  for (int ch = 0; ch < npass; ++ch) {
-    const bool is_mask = ch >= nimg;
-    float(*in)[EW + 1] = sIn[is_mask ? 0 : ch];
-    if (is_mask) {
-      __syncthreads();   // sIn[0] may still be read by the previous channel's subtract
-      if (it.msk_kind == kSrcU8) {
-        const uint8_t* m = (const uint8_t*)it.msk;
-        for (int e = tid; e < EH * EW; e += kThreads) {
-          const int r = e / EW, c = e - r * EW;
-          const int Y = fold(Y0 - 4 + r, fh) - it.roi_y, X = fold(X0 - 4 + c, fw) - it.roi_x;
-          const bool inr = X >= 0 && X < it.roi_w && Y >= 0 && Y < it.roi_h;
-          in[r][c] = inr ? (float)m[(int64_t)Y * it.msk_row + X] * kInv255 : 0.0f;
+  // tile-independent sample positions of this thread: (row << 8) | column, -1 past the end
+  int rc[NIT];
+#pragma unroll
+  for (int q = 0; q < NIT; ++q) {
+    const int e = tid + q * kThreads;
+    rc[q] = e < NE ? ((e / EW) << 8) | (e % EW) : -1;
+  }
+  // canvas position of staged sample q (folded at canvas edges unless the tile is interior)
+  auto sample_pos = [&](int q, int X0, int Y0, bool interior, int fw, int fh, int& X, int& Y) {
+    const int r = rc[q] < 0 ? 0 : rc[q] >> 8, c = rc[q] < 0 ? 0 : rc[q] & 255;
+    X = X0 - 4 + c;
+    Y = Y0 - 4 + r;
+    if (!interior) {
+      X = fold(X, fw);
+      Y = fold(Y, fh);
+    }
+  };
+  // tile-independent work items of stages B, C, D: (channel slot << 16) | (row << 8) | column group
+  constexpr int PB = EH * (CW / 2), NB = (4 * PB + kThreads - 1) / kThreads;
+  constexpr int PC = (CH / 2) * (CW / 2), NCI = (4 * PC + kThreads - 1) / kThreads;
+  constexpr int PD = CH * (TX / 4), ND = (3 * PD + kThreads - 1) / kThreads;
+  int itB[NB], itC[NCI], itD[ND];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int e = tid + q * kThreads, ci = e / PB, rem = e - ci * PB;
+    itB[q] = (ci << 16) | ((rem / (CW / 2)) << 8) | (rem % (CW / 2));
+  }
+#pragma unroll
+  for (int q = 0; q < NCI; ++q) {
+    const int e = tid + q * kThreads, ci = e / PC, rem = e - ci * PC;
+    itC[q] = (ci << 16) | ((rem / (CW / 2)) << 8) | (rem % (CW / 2));
+  }
+#pragma unroll
+  for (int q = 0; q < ND; ++q) {
+    const int e = tid + q * kThreads, ci = e / PD, rem = e - ci * PD;
+    itD[q] = (ci << 16) | ((rem / (TX / 4)) << 8) | (rem % (TX / 4));
+  }
+
+  auto prefetch = [&](int tt) {
+    const PyrTile d = decode_tile(items, nitems, tt);
+    const PyrItem& it = items[d.item];
+    const int fw = it.fine_w, fh = it.fine_h;
+    const int rx = it.roi_x, ry = it.roi_y, rw = it.roi_w, rh = it.roi_h;
+    const bool interior = d.X0 >= 4 && d.X0 + TX + 3 <= fw && d.Y0 >= 4 && d.Y0 + TY + 3 <= fh;
+    if (WARP) {
+      const GLB uint8_t* msk = cg<uint8_t>(it.msk);
+      const bool has_mask = it.msk_kind != kSrcNone;
+#pragma unroll
+      for (int q = 0; q < NIT; ++q) {
+        int X, Y;
+        sample_pos(q, d.X0, d.Y0, interior, fw, fh, X, Y);
+        const int my = Y - ry, mx = X - rx;
+        const bool in = has_mask && my >= 0 && my < rh && mx >= 0 && mx < rw;
+        const uint32_t m = has_mask ? (uint32_t)msk[in ? (int64_t)my * it.msk_row + mx : 0] : 0u;
+        pm[q] = in ? m : 0u;
+      }
+    } else {
+      const GLB T* g = cg<T>(it.img);
+      const GLB T* m = cg<T>(it.msk);
+      const int nimg = it.img_kind == kSrcNone ? 0 : it.nch;
+      const bool has_mask = it.msk_kind != kSrcNone;
+#pragma unroll
+      for (int q = 0; q < NIT; ++q) {
+        int X, Y;
+        sample_pos(q, d.X0, d.Y0, interior, fw, fh, X, Y);
+        Y -= ry;
+        X -= rx;
+        const bool in = X >= 0 && X < rw && Y >= 0 && Y < rh;
+        const int64_t off = in ? (int64_t)Y * it.img_row + X : 0;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) pg[q][ch] = ch < nimg ? ldg(g, ch * it.img_plane + off) : 0.0f;
+        pg[q][3] = has_mask ? ldg(m, in ? (int64_t)Y * it.msk_row + X : 0) : 0.0f;
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) pg[q][ch] = in ? pg[q][ch] : 0.0f;
+      }
+    }
+  };
+
+  if (t < t_end) prefetch(t);
+  for (; t < t_end; t += stride) {
+    const int tn = t + stride;
+    const PyrTile d = decode_tile(items, nitems, t);
+    const PyrItem& it = items[d.item];
+    const int X0 = d.X0, Y0 = d.Y0;
+    const int fw = it.fine_w, fh = it.fine_h;
+    const int nimg = it.img_kind == kSrcNone ? 0 : it.nch;
+    const bool has_mask = it.msk_kind != kSrcNone;
+    __syncthreads();   // the previous tile's readers of LDS are done
+
+    // ---- A: stage ----
+    const bool interior = X0 >= 4 && X0 + TX + 3 <= fw && Y0 >= 4 && Y0 + TY + 3 <= fh;
+    if (WARP) {
+      const GLB uint8_t* src = cg<uint8_t>(fa.n ? (const void*)fa.ptr[it.frame_slot] : it.img);
+      const int64_t srow = fa.n ? fa.row[it.frame_slot] : it.img_row;
+      const int w = it.frame_w, h = it.frame_h;
+      float hv[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) hv[i] = it.hinv[i];
+      uint32_t mreg[NIT];
+#pragma unroll
+      for (int q = 0; q < NIT; ++q) mreg[q] = pm[q];
+      if (tn < t_end) prefetch(tn);    // next tile's seam weights fly while this one computes
+      const float fwf = (float)w, fhf = (float)h;
+      const uint32_t srow32 = (uint32_t)srow;
+#pragma unroll
+      for (int q = 0; q < NIT; ++q) {
+        int Xc, Yc;
+        sample_pos(q, X0, Y0, interior, fw, fh, Xc, Yc);
+        float x, y;
+        bool zpos;
+        warp_coords(hv, Xc, Yc, x, y, zpos);
+        const bool ok = zpos && x >= -1.0f && x < fwf && y >= -1.0f && y < fhf;
+        const float xs = ok ? x : 0.0f, ys = ok ? y : 0.0f;
+        const float x0f = floorf(xs), y0f = floorf(ys);
+        const float fx = xs - x0f, fy = ys - y0f, gx = 1.0f - fx, gy = 1.0f - fy;
+        const int x0 = (int)x0f, y0 = (int)y0f;
+        const bool xa = ok && x0 >= 0, xb = ok && x0 + 1 < w, ya = y0 >= 0, yb = y0 + 1 < h;
+        const float w00 = (ya && xa) ? gy * gx : 0.0f, w01 = (ya && xb) ? gy * fx : 0.0f;
+        const float w10 = (yb && xa) ? fy * gx : 0.0f, w11 = (yb && xb) ? fy * fx : 0.0f;
+        // byte offsets of the four taps (clamped into the frame; outside taps have weight 0)
+        const uint32_t o0 = (uint32_t)(ya ? y0 : 0) * srow32, o1 = (uint32_t)(yb ? y0 + 1 : 0) * srow32;
+        const uint32_t c0 = 3u * (uint32_t)(xa ? x0 : 0), c1 = 3u * (uint32_t)(xb ? x0 + 1 : 0);
+        uint32_t p[12];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          p[ch] = src[o0 + c0 + ch];
+          p[3 + ch] = src[o0 + c1 + ch];
+          p[6 + ch] = src[o1 + c0 + ch];
+          p[9 + ch] = src[o1 + c1 + ch];
         }
-      } else {
-        const T* m = (const T*)it.msk;
-        for (int e = tid; e < EH * EW; e += kThreads) {
-          const int r = e / EW, c = e - r * EW;
-          const int Y = fold(Y0 - 4 + r, fh) - it.roi_y, X = fold(X0 - 4 + c, fw) - it.roi_x;
-          const bool inr = X >= 0 && X < it.roi_w && Y >= 0 && Y < it.roi_h;
-          in[r][c] = inr ? ldv(m, (int64_t)Y * it.msk_row + X) : 0.0f;
+        if (rc[q] >= 0) {
+          const int r = rc[q] >> 8, c = rc[q] & 255;
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch)
+            sIn[ch][r][c] = (w00 * (float)p[ch] + w01 * (float)p[3 + ch] + w10 * (float)p[6 + ch] +
+                             w11 * (float)p[9 + ch]) * kInv255;
+          sIn[3][r][c] = (float)mreg[q] * kInv255;
         }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NIT; ++q) {
+        if (rc[q] >= 0) {
+          const int r = rc[q] >> 8, c = rc[q] & 255;
+#pragma unroll
+          for (int ch = 0; ch < 4; ++ch) sIn[ch][r][c] = pg[q][ch];
+        }
+      }
+      if (tn < t_end) prefetch(tn);
+    }
+    __syncthreads();
+
+    const int nact = nimg + (has_mask ? 1 : 0);
+    // ---- B: horizontal REDUCE, coarse columns cx0 .. cx0+CW-1 of every staged row ----
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int ci = itB[q] >> 16;
+      if (ci < nact) {
+        const int ch = ci < nimg ? ci : 3;
+        const int r = (itB[q] >> 8) & 255, m = itB[q] & 255;
+        const float4 a = *reinterpret_cast<const float4*>(&sIn[ch][r][4 * m]);
+        const float4 bq = *reinterpret_cast<const float4*>(&sIn[ch][r][4 * m + 4]);
+        float2 o;
+        o.x = kW0 * (a.x + bq.x) + kW1 * (a.y + a.w) + kW2 * a.z;
+        o.y = kW0 * (a.z + bq.z) + kW1 * (a.w + bq.y) + kW2 * bq.x;
+        *reinterpret_cast<float2*>(&sH[ch][r][2 * m]) = o;
       }
     }
     __syncthreads();
-    // ---- REDUCE, horizontal: every staged row, coarse columns cx0 .. cx0+CW-1 ----
-    for (int e = tid; e < EH * CW; e += kThreads) {
-      const int r = e / CW, j = e - r * CW;
-      const float* s = &in[r][2 * j];
-      sH[r][j] = kW0 * (s[0] + s[4]) + kW1 * (s[1] + s[3]) + kW2 * s[2];
+
+    // ---- C: vertical REDUCE -> extended coarse tile (2x2 outputs per item); store its interior ----
+    const int cx0 = X0 / 2 - 1, cy0 = Y0 / 2 - 1;      // coarse canvas coordinates of sC[.][0][0]
+#pragma unroll
+    for (int q = 0; q < NCI; ++q) {
+      const int ci = itC[q] >> 16;
+      if (ci < nact) {
+        const int ch = ci < nimg ? ci : 3;
+        const int pp = (itC[q] >> 8) & 255, jp = itC[q] & 255;
+        float2 sv[7];
+#pragma unroll
+        for (int u = 0; u < 7; ++u) sv[u] = *reinterpret_cast<const float2*>(&sH[ch][4 * pp + u][2 * jp]);
+        float2 o0, o1;
+        o0.x = kW0 * (sv[0].x + sv[4].x) + kW1 * (sv[1].x + sv[3].x) + kW2 * sv[2].x;
+        o0.y = kW0 * (sv[0].y + sv[4].y) + kW1 * (sv[1].y + sv[3].y) + kW2 * sv[2].y;
+        o1.x = kW0 * (sv[2].x + sv[6].x) + kW1 * (sv[3].x + sv[5].x) + kW2 * sv[4].x;
+        o1.y = kW0 * (sv[2].y + sv[6].y) + kW1 * (sv[3].y + sv[5].y) + kW2 * sv[4].y;
+        if (ch < 3) {
+          *reinterpret_cast<float2*>(&sC[ch][2 * pp][2 * jp]) = o0;
+          *reinterpret_cast<float2*>(&sC[ch][2 * pp + 1][2 * jp]) = o1;
+        }
+        GLB T* out = ch < 3 ? mg<T>(it.g_out) : mg<T>(it.gm_out);
+        const int64_t orow = ch < 3 ? it.g_row : it.gm_row;
+        const int64_t obase = ch < 3 ? ch * it.g_plane : 0;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int i = 2 * pp + u;
+          const int cy = cy0 + i - it.croi_y;
+          const bool rowin = i >= 1 && i <= TY / 2 && cy >= 0 && cy < it.croi_h;
+#pragma unroll
+          for (int v = 0; v < 2; ++v) {
+            const int j = 2 * jp + v;
+            const int cx = cx0 + j - it.croi_x;
+            if (rowin && j >= 1 && j <= TX / 2 && cx >= 0 && cx < it.croi_w)
+              stg(out, obase + (int64_t)cy * orow + cx, u ? (v ? o1.y : o1.x) : (v ? o0.y : o0.x));
+          }
+        }
+      }
+    }
+    if (!EMIT_LAP) continue;
+    const bool lap_tile = it.lw_w > 0 && X0 < it.lw_x + it.lw_w && X0 + TX > it.lw_x && Y0 < it.lw_y + it.lw_h &&
+                          Y0 + TY > it.lw_y;
+    if (!lap_tile) continue;
+    __syncthreads();
+
+    // ---- D: horizontal EXPAND, four fine columns per item ----
+#pragma unroll
+    for (int q = 0; q < ND; ++q) {
+      const int ch = itD[q] >> 16;
+      if (ch < nimg) {
+        const int i = (itD[q] >> 8) & 255, m = itD[q] & 255;
+        const float2 lo = *reinterpret_cast<const float2*>(&sC[ch][i][2 * m]);
+        const float2 hi = *reinterpret_cast<const float2*>(&sC[ch][i][2 * m + 2]);
+        float4 o;
+        o.x = 0.125f * (lo.x + hi.x) + 0.75f * lo.y;
+        o.y = 0.5f * (lo.y + hi.x);
+        o.z = 0.125f * (lo.y + hi.y) + 0.75f * hi.x;
+        o.w = 0.5f * (hi.x + hi.y);
+        *reinterpret_cast<float4*>(&sE[ch][i][4 * m]) = o;
+      }
     }
     __syncthreads();
-    // ---- REDUCE, vertical -> extended coarse tile; store its interior ----
-    T* gout = (T*)(is_mask ? it.gm_out : it.g_out);
-    const int64_t grow = is_mask ? it.gm_row : it.g_row;
-    const int64_t gplane = is_mask ? 0 : (int64_t)ch * it.g_plane;
-    for (int e = tid; e < CH * CW; e += kThreads) {
-      const int i = e / CW, j = e - i * CW;
-      const float* s = &sH[2 * i][j];
-      constexpr int S = CW + 1;
-      const float v = kW0 * (s[0] + s[4 * S]) + kW1 * (s[S] + s[3 * S]) + kW2 * s[2 * S];
-      sC[i][j] = v;
-      const int cy = cy0 + i - it.croi_y, cx = cx0 + j - it.croi_x;
-      if (i >= 1 && i <= TY / 2 && j >= 1 && j <= TX / 2 && cy >= 0 && cy < it.croi_h && cx >= 0 &&
-          cx < it.croi_w && gout != nullptr)
-        stv(gout, gplane + (int64_t)cy * grow + cx, v);
-    }
-    if (is_mask || !lap_tile) continue;
-    __syncthreads();
-    // ---- EXPAND, horizontal: coarse rows x fine columns (interior form) ----
-    for (int e = tid; e < CH * TX; e += kThreads) {
-      const int i = e / TX, x = e - i * TX;
-      const float* s = &sC[i][x >> 1];
-      sE[i][x] = (x & 1) ? 0.5f * (s[1] + s[2]) : 0.125f * (s[0] + s[2]) + 0.75f * s[1];
-    }
-    __syncthreads();
-    // ---- EXPAND, vertical, and L_k = G_k - EXPAND(G_{k+1}) on the band window ----
-    T* lout = (T*)it.l_out;
-    for (int e = tid; e < TY * TX; e += kThreads) {
-      const int y = e / TX, x = e - y * TX;
-      const float* s = &sE[y >> 1][x];
-      constexpr int S = TX + 1;
-      const float ev = (y & 1) ? 0.5f * (s[S] + s[2 * S]) : 0.125f * (s[0] + s[2 * S]) + 0.75f * s[S];
+
+    // ---- E: vertical EXPAND and the band L_k = G_k - EXPAND(G_{k+1}), four columns per thread ----
+    {
+      const int y = tid >> 4, x = 4 * (tid & 15), yh = y >> 1;
       const int Y = Y0 + y - it.lw_y, X = X0 + x - it.lw_x;
-      if (X >= 0 && X < it.lw_w && Y >= 0 && Y < it.lw_h)
-        stv(lout, (int64_t)ch * it.l_plane + (int64_t)Y * it.l_row + X, in[y + 4][x + 4] - ev);
+      const bool rowin = Y >= 0 && Y < it.lw_h;
+      const bool full = rowin && X >= 0 && X + 3 < it.lw_w;
+      GLB T* lout = mg<T>(it.l_out);
+      for (int ch = 0; ch < nimg; ++ch) {
+        const float4 s1 = *reinterpret_cast<const float4*>(&sE[ch][yh + 1][x]);
+        const float4 s2 = *reinterpret_cast<const float4*>(&sE[ch][yh + 2][x]);
+        float4 ev;
+        if (y & 1) {
+          ev.x = 0.5f * (s1.x + s2.x); ev.y = 0.5f * (s1.y + s2.y);
+          ev.z = 0.5f * (s1.z + s2.z); ev.w = 0.5f * (s1.w + s2.w);
+        } else {
+          const float4 s0 = *reinterpret_cast<const float4*>(&sE[ch][yh][x]);
+          ev.x = 0.125f * (s0.x + s2.x) + 0.75f * s1.x; ev.y = 0.125f * (s0.y + s2.y) + 0.75f * s1.y;
+          ev.z = 0.125f * (s0.z + s2.z) + 0.75f * s1.z; ev.w = 0.125f * (s0.w + s2.w) + 0.75f * s1.w;
+        }
+        const float4 g = *reinterpret_cast<const float4*>(&sIn[ch][y + 4][x + 4]);
+        const float l[4] = {g.x - ev.x, g.y - ev.y, g.z - ev.z, g.w - ev.w};
+        const int64_t base = ch * it.l_plane + (int64_t)Y * it.l_row + X;
+        if (full) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) stg(lout, base + u, l[u]);
+        } else if (rowin) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (X + u >= 0 && X + u < it.lw_w) stg(lout, base + u, l[u]);
+        }
+      }
     }
   }
 }
 
 // ------------------------------------------------------------------------------------
 // One synthesis level: B_k over cameras + EXPAND(R_{k+1}) -> R_k (and the panorama at k = 0).
+// 64x16 tile; thread (x = tid & 63) handles rows (tid >> 6) + 4 j, j = 0..3, so every
+// global access of a wave is one contiguous row segment.
 template <typename T, bool FINAL, bool HAS_COARSE>
 __global__ void __launch_bounds__(kThreads) k_blend(BlendArgs a) {
   constexpr int TX = kBlendTX, TY = kBlendTY;
   constexpr int CW = TX / 2 + 2, CH = TY / 2 + 2;
-  __shared__ float sC[3][CH][CW + 1];
-  __shared__ float sE[3][CH][TX + 1];
+  constexpr int HS = 36, ES = TX + 4;
+  __shared__ __attribute__((aligned(16))) float sC[3][CH][HS];
+  __shared__ __attribute__((aligned(16))) float sE[3][CH][ES];
+  __shared__ __attribute__((aligned(16))) uint32_t sP[TY][TX * 3 / 4];
   __shared__ int sCam[kMaxCameras];
   __shared__ int sNCam;
 
@@ -238,73 +467,148 @@ __global__ void __launch_bounds__(kThreads) k_blend(BlendArgs a) {
   const int tyi = t / a.tiles_x, txi = t - tyi * a.tiles_x;
   const int X0 = txi * TX, Y0 = tyi * TY;
 
-  if (tid == 0) {
-    int m = 0;
-    for (int i = 0; i < a.ncam; ++i) {
+  if (tid < 64) {   // one wave builds the tile's camera list in order
+    const int i = tid;
+    bool hit = false;
+    if (i < a.ncam) {
       const BlendCam& c = a.cams[i];
       const int x0 = max(c.lx, c.wx), x1 = min(c.lx + c.lw, c.wx + c.ww);
       const int y0 = max(c.ly, c.wy), y1 = min(c.ly + c.lh, c.wy + c.wh);
-      if (x0 < x1 && y0 < y1 && x0 < X0 + TX && x1 > X0 && y0 < Y0 + TY && y1 > Y0) sCam[m++] = i;
+      hit = x0 < x1 && y0 < y1 && x0 < X0 + TX && x1 > X0 && y0 < Y0 + TY && y1 > Y0;
     }
-    sNCam = m;
+    const uint64_t mask = __ballot(hit);
+    if (hit) sCam[__popcll(mask & ((1ull << i) - 1ull))] = i;
+    if (tid == 0) sNCam = __popcll(mask);
   }
   if (HAS_COARSE) {
-    const T* r = (const T*)a.r_in;
+    const GLB T* r = cg<T>(a.r_in);
     const int cx0 = X0 / 2 - 1, cy0 = Y0 / 2 - 1;
-    for (int e = tid; e < CH * CW; e += kThreads) {
-      const int i = e / CW, j = e - i * CW;
+    constexpr int NC = 3 * CH * CW;
+    constexpr int NIT = (NC + kThreads - 1) / kThreads;
+    float v[NIT];
+#pragma unroll
+    for (int q = 0; q < NIT; ++q) {
+      const int e = min(tid + q * kThreads, NC - 1);
+      const int c = e / (CH * CW), rem = e - c * (CH * CW);
+      const int i = rem / CW, j = rem - i * CW;
       // coarse index of the fine-domain fold of fine sample 2*c, kept inside the level
       const int cy = min(fold(2 * (cy0 + i), a.H) >> 1, a.cH - 1);
       const int cx = min(fold(2 * (cx0 + j), a.W) >> 1, a.cW - 1);
-      const int64_t off = (int64_t)cy * a.rin_row + cx;
+      v[q] = ldg(r, c * a.rin_plane + (int64_t)cy * a.rin_row + cx);
+    }
 #pragma unroll
-      for (int c = 0; c < 3; ++c) sC[c][i][j] = ldv(r, c * a.rin_plane + off);
+    for (int q = 0; q < NIT; ++q) {
+      const int e = tid + q * kThreads;
+      if (e < NC) {
+        const int c = e / (CH * CW), rem = e - c * (CH * CW);
+        const int i = rem / CW, j = rem - i * CW;
+        sC[c][i][j] = v[q];
+      }
     }
     __syncthreads();
-    for (int e = tid; e < 3 * CH * TX; e += kThreads) {
-      const int c = e / (CH * TX), rem = e - c * CH * TX;
-      const int i = rem / TX, x = rem - i * TX;
-      const float* s = &sC[c][i][x >> 1];
-      sE[c][i][x] = (x & 1) ? 0.5f * (s[1] + s[2]) : 0.125f * (s[0] + s[2]) + 0.75f * s[1];
+    constexpr int PER = CH * (TX / 4);
+    for (int e = tid; e < 3 * PER; e += kThreads) {
+      const int ch = e / PER, rem = e - ch * PER;
+      const int i = rem / (TX / 4), m = rem - i * (TX / 4);
+      const float2 lo = *reinterpret_cast<const float2*>(&sC[ch][i][2 * m]);
+      const float2 hi = *reinterpret_cast<const float2*>(&sC[ch][i][2 * m + 2]);
+      float4 o;
+      o.x = 0.125f * (lo.x + hi.x) + 0.75f * lo.y;
+      o.y = 0.5f * (lo.y + hi.x);
+      o.z = 0.125f * (lo.y + hi.y) + 0.75f * hi.x;
+      o.w = 0.5f * (hi.x + hi.y);
+      *reinterpret_cast<float4*>(&sE[ch][i][4 * m]) = o;
     }
   }
   __syncthreads();
   const int ncam = sNCam;
-  for (int e = tid; e < TY * TX; e += kThreads) {
-    const int y = e / TX, x = e - y * TX;
-    const int X = X0 + x, Y = Y0 + y;
-    if (X >= a.W || Y >= a.H) continue;
-    float acc[3] = {0.0f, 0.0f, 0.0f};
-    for (int q = 0; q < ncam; ++q) {
-      const BlendCam& c = a.cams[sCam[q]];
-      const int lx = X - c.lx, ly = Y - c.ly, wx = X - c.wx, wy = Y - c.wy;
-      if (lx < 0 || lx >= c.lw || ly < 0 || ly >= c.lh || wx < 0 || wx >= c.ww || wy < 0 || wy >= c.wh) continue;
-      const float wgt = c.wgt_u8 ? (float)((const uint8_t*)c.wgt)[(int64_t)wy * c.wgt_row + wx] * kInv255
-                                 : ldv((const T*)c.wgt, (int64_t)wy * c.wgt_row + wx);
-      const T* l = (const T*)c.lap;
-      const int64_t off = (int64_t)ly * c.lap_row + lx;
+  const int x = tid & 63, ybase = tid >> 6;
+  const int X = X0 + x;
+  float acc[4][3];
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) acc[ch] = acc[ch] + wgt * ldv(l, ch * c.lap_plane + off);
+  for (int j = 0; j < 4; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0f;
+  for (int q = 0; q < ncam; ++q) {
+    const BlendCam& c = a.cams[sCam[q]];
+    const GLB T* l = cg<T>(c.lap);
+    const int lx = X - c.lx, wx = X - c.wx;
+    const bool xin = lx >= 0 && lx < c.lw && wx >= 0 && wx < c.ww;
+    float wv[4], lv[4][3];
+    int64_t woff[4];
+    bool in[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int Y = Y0 + ybase + 4 * j;
+      const int ly = Y - c.ly, wy = Y - c.wy;
+      in[j] = xin && ly >= 0 && ly < c.lh && wy >= 0 && wy < c.wh;
+      woff[j] = in[j] ? (int64_t)wy * c.wgt_row + wx : 0;
+      const int64_t loff = in[j] ? (int64_t)ly * c.lap_row + lx : 0;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) lv[j][ch] = ldg(l, ch * c.lap_plane + loff);
     }
+    if (c.wgt_u8) {   // uniform: the weight buffer is either uint8 or storage type
+      const GLB uint8_t* wg = cg<uint8_t>(c.wgt);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) wv[j] = (float)wg[woff[j]] * kInv255;
+    } else {
+      const GLB T* wg = cg<T>(c.wgt);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) wv[j] = ldg(wg, woff[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) wv[j] = in[j] ? wv[j] : 0.0f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) acc[j][ch] = acc[j][ch] + wv[j] * lv[j][ch];
+  }
+  GLB T* ro = mg<T>(a.r_out);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int y = ybase + 4 * j;
+    const int Y = Y0 + y;
     if (HAS_COARSE) {
-      constexpr int S = TX + 1;
+      const int yh = y >> 1;
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
-        const float* s = &sE[ch][y >> 1][x];
-        const float ev = (y & 1) ? 0.5f * (s[S] + s[2 * S]) : 0.125f * (s[0] + s[2 * S]) + 0.75f * s[S];
-        acc[ch] = acc[ch] + ev;
+        const float ev = (y & 1) ? 0.5f * (sE[ch][yh + 1][x] + sE[ch][yh + 2][x])
+                                 : 0.125f * (sE[ch][yh][x] + sE[ch][yh + 2][x]) + 0.75f * sE[ch][yh + 1][x];
+        acc[j][ch] = acc[j][ch] + ev;
       }
     }
-    if (a.r_out != nullptr) {
-      T* ro = (T*)a.r_out;
+    if (X < a.W && Y < a.H && ro != nullptr) {
       const int64_t off = (int64_t)Y * a.rout_row + X;
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) stv(ro, ch * a.rout_plane + off, acc[ch]);
+      for (int ch = 0; ch < 3; ++ch) stg(ro, ch * a.rout_plane + off, acc[j][ch]);
     }
-    if (FINAL) {
-      uint8_t* p = a.pano + (int64_t)Y * a.pano_row + (int64_t)X * 3;
+  }
+  if (FINAL) {
+    // quantise, pack the 64x16 RGB tile in LDS, write it back as whole dwords when aligned
+    uint8_t* sb = reinterpret_cast<uint8_t*>(&sP[0][0]);
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) p[ch] = (uint8_t)fminf(fmaxf(rintf(255.0f * acc[ch]), 0.0f), 255.0f);
+    for (int j = 0; j < 4; ++j) {
+      const int y = ybase + 4 * j;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch)
+        sb[y * (TX * 3) + x * 3 + ch] = (uint8_t)fminf(fmaxf(rintf(255.0f * acc[j][ch]), 0.0f), 255.0f);
+    }
+    __syncthreads();
+    const int nx = min(TX, a.W - X0);
+    const bool words = nx == TX && (a.pano_row & 3) == 0 && ((uintptr_t)a.pano & 3) == 0;
+    GLB uint8_t* pano = mg<uint8_t>(a.pano);
+    if (words) {
+      constexpr int WPR = TX * 3 / 4;   // 48 dwords per row
+      for (int e = tid; e < TY * WPR; e += kThreads) {
+        const int y = e / WPR, wi = e - y * WPR;
+        const int Y = Y0 + y;
+        if (Y < a.H)
+          *reinterpret_cast<GLB uint32_t*>(pano + (int64_t)Y * a.pano_row + (int64_t)X0 * 3 + wi * 4) = sP[y][wi];
+      }
+    } else {
+      for (int e = tid; e < TY * TX * 3; e += kThreads) {
+        const int y = e / (TX * 3), b = e - y * (TX * 3);
+        const int Y = Y0 + y;
+        if (Y < a.H && b < nx * 3) pano[(int64_t)Y * a.pano_row + (int64_t)X0 * 3 + b] = sb[y * (TX * 3) + b];
+      }
     }
   }
 }
@@ -387,20 +691,52 @@ __global__ void __launch_bounds__(kThreads) k_convert(int nch, int src_u8, const
   }
 }
 
+// Workgroups of a persistent launch: as many as fit on the device at once (queried once
+// per kernel), never more than there are tiles.
+int persistent_grid(const void* kernel, int tiles) {
+  static thread_local const void* cached_k[16] = {};
+  static thread_local int cached_n[16] = {};
+  int slot = -1;
+  for (int i = 0; i < 16; ++i)
+    if (cached_k[i] == kernel || cached_k[i] == nullptr) { slot = i; break; }
+  if (slot < 0) slot = 0;
+  if (cached_k[slot] != kernel) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+        hipSuccess || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kThreads, 0) != hipSuccess ||
+        cus <= 0 || per <= 0) {
+      cus = 256;
+      per = 2;
+    }
+    cached_k[slot] = kernel;
+    cached_n[slot] = cus * per;
+  }
+  return tiles < cached_n[slot] ? tiles : cached_n[slot];
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------ launchers
-hipError_t launch_pyr(bool f16, bool emit_lap, const PyrItem* items_dev, int nitems, int total_tiles,
+hipError_t launch_pyr(bool f16, bool emit_lap, bool warp, const PyrItem* items_dev, int nitems, int total_tiles,
                       const FrameArgs& fa, hipStream_t s) {
   if (total_tiles <= 0) return hipSuccess;
   const dim3 grid(total_tiles), block(kThreads);
-  if (f16) {
-    if (emit_lap) hipLaunchKernelGGL((k_pyr<__half, true>), grid, block, 0, s, items_dev, nitems, fa);
-    else hipLaunchKernelGGL((k_pyr<__half, false>), grid, block, 0, s, items_dev, nitems, fa);
-  } else {
-    if (emit_lap) hipLaunchKernelGGL((k_pyr<float, true>), grid, block, 0, s, items_dev, nitems, fa);
-    else hipLaunchKernelGGL((k_pyr<float, false>), grid, block, 0, s, items_dev, nitems, fa);
-  }
+#define STITCH_PYR(TT)                                                                                          \
+  do {                                                                                                          \
+    if (warp) {                                                                                                 \
+      const dim3 g(persistent_grid((const void*)k_pyr<TT, true, true>, total_tiles));                        \
+      hipLaunchKernelGGL((k_pyr<TT, true, true>), g, block, 0, s, items_dev, nitems, total_tiles, fa);         \
+    } else if (emit_lap) {                                                                                      \
+      const dim3 g(persistent_grid((const void*)k_pyr<TT, true, false>, total_tiles));                       \
+      hipLaunchKernelGGL((k_pyr<TT, true, false>), g, block, 0, s, items_dev, nitems, total_tiles, fa);        \
+    } else {                                                                                                    \
+      const dim3 g(persistent_grid((const void*)k_pyr<TT, false, false>, total_tiles));                      \
+      hipLaunchKernelGGL((k_pyr<TT, false, false>), g, block, 0, s, items_dev, nitems, total_tiles, fa);       \
+    }                                                                                                           \
+  } while (0)
+  if (f16) STITCH_PYR(_Float16);
+  else STITCH_PYR(float);
+#undef STITCH_PYR
   return hipGetLastError();
 }
 
@@ -417,7 +753,7 @@ hipError_t launch_blend(bool f16, const BlendArgs& a, hipStream_t s) {
     else if (co) hipLaunchKernelGGL((k_blend<TT, false, true>), grid, block, 0, s, a);          \
     else hipLaunchKernelGGL((k_blend<TT, false, false>), grid, block, 0, s, a);                 \
   } while (0)
-  if (f16) STITCH_BLEND(__half);
+  if (f16) STITCH_BLEND(_Float16);
   else STITCH_BLEND(float);
 #undef STITCH_BLEND
   return hipGetLastError();
@@ -430,7 +766,7 @@ hipError_t launch_warp(bool f16, const uint8_t* src, int64_t src_row, int w, int
   for (int i = 0; i < 9; ++i) hi.h[i] = hinv9[i];
   const dim3 grid((dw + 63) / 64, (dh + 3) / 4), block(kThreads);
   if (f16)
-    hipLaunchKernelGGL((k_warp<__half>), grid, block, 0, s, src, src_row, w, h, hi, roi_x, roi_y, (__half*)dst,
+    hipLaunchKernelGGL((k_warp<_Float16>), grid, block, 0, s, src, src_row, w, h, hi, roi_x, roi_y, (_Float16*)dst,
                        dst_row, dst_plane, dw, dh);
   else
     hipLaunchKernelGGL((k_warp<float>), grid, block, 0, s, src, src_row, w, h, hi, roi_x, roi_y, (float*)dst,
@@ -454,8 +790,8 @@ hipError_t launch_expand_sub(bool f16, int nch, void* fine, int64_t f_row, int64
   if (fw <= 0 || fh <= 0) return hipSuccess;
   const dim3 grid((fw + 63) / 64, (fh + 3) / 4), block(kThreads);
   if (f16)
-    hipLaunchKernelGGL((k_expand_sub<__half>), grid, block, 0, s, nch, (__half*)fine, f_row, f_plane, fx, fy, fw,
-                       fh, (const __half*)coarse, c_row, c_plane, cx, cy, cw, ch, canvas_w, canvas_h);
+    hipLaunchKernelGGL((k_expand_sub<_Float16>), grid, block, 0, s, nch, (_Float16*)fine, f_row, f_plane, fx, fy, fw,
+                       fh, (const _Float16*)coarse, c_row, c_plane, cx, cy, cw, ch, canvas_w, canvas_h);
   else
     hipLaunchKernelGGL((k_expand_sub<float>), grid, block, 0, s, nch, (float*)fine, f_row, f_plane, fx, fy, fw, fh,
                        (const float*)coarse, c_row, c_plane, cx, cy, cw, ch, canvas_w, canvas_h);
@@ -467,8 +803,8 @@ hipError_t launch_convert(bool f16_out, int nch, bool src_u8, const void* src, i
   if (w <= 0 || h <= 0) return hipSuccess;
   const dim3 grid((w + 63) / 64, (h + 3) / 4), block(kThreads);
   if (f16_out)
-    hipLaunchKernelGGL((k_convert<__half>), grid, block, 0, s, nch, (int)src_u8, src, s_row, s_plane,
-                       (__half*)dst, d_row, d_plane, w, h);
+    hipLaunchKernelGGL((k_convert<_Float16>), grid, block, 0, s, nch, (int)src_u8, src, s_row, s_plane,
+                       (_Float16*)dst, d_row, d_plane, w, h);
   else
     hipLaunchKernelGGL((k_convert<float>), grid, block, 0, s, nch, (int)src_u8, src, s_row, s_plane,
                        (float*)dst, d_row, d_plane, w, h);

@@ -149,6 +149,18 @@ struct stitch_plan {
   size_t off_bcams[kMaxLevels] = {};
   size_t ws_bytes = 0;
   uint8_t* ws = nullptr;
+  // optional per-launch event timing (diagnostics)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_free;
+  struct Pending { std::vector<hipEvent_t> ev; std::vector<int> kind; };   // ev[i] .. ev[i+1] = launch i
+  std::vector<Pending> pending;
+  double kind_ms[STITCH_TIMING_KINDS] = {};
+  int32_t kind_n[STITCH_TIMING_KINDS] = {};
+  ~stitch_plan() {
+    for (auto& q : pending)
+      for (hipEvent_t e : q.ev) ev_free.push_back(e);
+    for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -453,7 +465,7 @@ stitch_status stitch_pyramid(const stitch_image* g0, int32_t kind, stitch_levels
   std::memset(&fa, 0, sizeof fa);
   const PyrItem* dev = (const PyrItem*)workspace;
   for (int k = 0; k + 1 < L; ++k) {
-    e = launch_pyr(f16, false, dev + k, 1, tiles[k], fa, s);
+    e = launch_pyr(f16, false, false, dev + k, 1, tiles[k], fa, s);
     if (e != hipSuccess) return hip_fail(e, "pyramid launch");
   }
   if (kind == 1) {
@@ -766,13 +778,43 @@ stitch_status stitch_frame(stitch_plan* p, const stitch_image* frames, stitch_im
     if (frames[i].width != p->cam[i].fw || frames[i].height != p->cam[i].fh)
       return fail(STITCH_E_SHAPE, "frames[%d] is %dx%d, planned %dx%d", i, frames[i].width, frames[i].height,
                   p->cam[i].fw, p->cam[i].fh);
+    if (frames[i].row_pitch * (int64_t)frames[i].height >= ((int64_t)1 << 31))
+      return fail(STITCH_E_SHAPE, "frames[%d] spans 2 GiB or more (byte offsets are 32-bit)", i);
     fa.ptr[i] = (const uint8_t*)frames[i].data;
     fa.row[i] = frames[i].row_pitch;
   }
   const hipStream_t s = (hipStream_t)stream;
   const bool f16 = p->storage == STITCH_F16;
   const int L = p->L;
+  // optional event chain: one event before the first launch and one after each launch
+  stitch_plan::Pending tm;
+  auto mark = [&](int kind) -> stitch_status {
+    if (!p->timing) return STITCH_OK;
+    hipEvent_t ev;
+    if (!p->ev_free.empty()) {
+      ev = p->ev_free.back();
+      p->ev_free.pop_back();
+    } else {
+      const hipError_t ce = hipEventCreate(&ev);
+      if (ce != hipSuccess) return hip_fail(ce, "timing event create");
+    }
+    const hipError_t re = hipEventRecord(ev, s);
+    if (re != hipSuccess) { p->ev_free.push_back(ev); return hip_fail(re, "timing event record"); }
+    tm.ev.push_back(ev);
+    if (kind >= 0) tm.kind.push_back(kind);
+    return STITCH_OK;
+  };
+  struct Flush {
+    stitch_plan* p; stitch_plan::Pending* tm;
+    ~Flush() {
+      if (p->timing && !tm->ev.empty()) {
+        if (tm->kind.size() + 1 == tm->ev.size()) p->pending.push_back(std::move(*tm));
+        else for (hipEvent_t e : tm->ev) p->ev_free.push_back(e);
+      }
+    }
+  } flush{p, &tm};
   hipError_t e;
+  if ((st = mark(-1))) return st;
   if (L == 1) {
     for (int i = 0; i < p->n; ++i) {
       const CamPlan& c = p->cam[i];
@@ -781,11 +823,15 @@ stitch_status stitch_frame(stitch_plan* p, const stitch_image* frames, stitch_im
       e = launch_warp(f16, fa.ptr[i], fa.row[i], c.fw, c.fh, c.hinv, r.x, r.y, p->ws + c.off_g[0], c.g_row[0],
                       c.g_plane[0], r.w, r.h, s);
       if (e != hipSuccess) return hip_fail(e, "warp launch");
+      if ((st = mark(6))) return st;
     }
   }
   for (int k = 0; k + 1 < L; ++k) {
-    e = launch_pyr(f16, true, (const PyrItem*)(p->ws + p->off_items[k]), (int)p->items[k].size(), p->tiles[k], fa, s);
+    if (p->tiles[k] <= 0) continue;
+    e = launch_pyr(f16, true, k == 0, (const PyrItem*)(p->ws + p->off_items[k]), (int)p->items[k].size(),
+                   p->tiles[k], fa, s);
     if (e != hipSuccess) return hip_fail(e, "pyramid pass launch");
+    if ((st = mark(k == 0 ? 0 : 1))) return st;
   }
   for (int k = L - 1; k >= 0; --k) {
     BlendArgs a;
@@ -804,8 +850,43 @@ stitch_status stitch_frame(stitch_plan* p, const stitch_image* frames, stitch_im
     a.tiles_y = (p->dh[k] + kBlendTY - 1) / kBlendTY;
     e = launch_blend(f16, a, s);
     if (e != hipSuccess) return hip_fail(e, "blend launch");
+    const int kind = k == 0 ? (L > 1 ? 2 : 5) : (k + 1 < L ? 3 : 4);
+    if ((st = mark(kind))) return st;
   }
   return STITCH_OK;
+}
+
+stitch_status stitch_plan_set_timing(stitch_plan* p, int32_t enable) {
+  if (!p) return fail(STITCH_E_NULL, "plan is NULL");
+  p->timing = enable != 0;
+  for (auto& q : p->pending)
+    for (hipEvent_t e : q.ev) p->ev_free.push_back(e);
+  p->pending.clear();
+  for (int i = 0; i < STITCH_TIMING_KINDS; ++i) { p->kind_ms[i] = 0.0; p->kind_n[i] = 0; }
+  return STITCH_OK;
+}
+
+stitch_status stitch_plan_read_timing(stitch_plan* p, double ms[STITCH_TIMING_KINDS],
+                                      int32_t launches[STITCH_TIMING_KINDS]) {
+  if (!p || !ms || !launches) return fail(STITCH_E_NULL, "plan, ms or launches is NULL");
+  stitch_status st = STITCH_OK;
+  for (auto& q : p->pending) {
+    if (!st) {
+      const hipError_t e = hipEventSynchronize(q.ev.back());
+      if (e != hipSuccess) st = hip_fail(e, "timing event synchronise");
+    }
+    for (size_t i = 0; !st && i < q.kind.size(); ++i) {
+      float t = 0.0f;
+      const hipError_t e = hipEventElapsedTime(&t, q.ev[i], q.ev[i + 1]);
+      if (e != hipSuccess) { st = hip_fail(e, "timing elapsed"); break; }
+      p->kind_ms[q.kind[i]] += t;
+      p->kind_n[q.kind[i]] += 1;
+    }
+    for (hipEvent_t e : q.ev) p->ev_free.push_back(e);
+  }
+  p->pending.clear();
+  for (int i = 0; i < STITCH_TIMING_KINDS; ++i) { ms[i] = p->kind_ms[i]; launches[i] = p->kind_n[i]; }
+  return st;
 }
 
 stitch_status stitch_plan_view(const stitch_plan* p, int32_t what, int32_t camera, int32_t level, stitch_image* view,

@@ -11,7 +11,7 @@ constexpr int kMaxLevels = 16;
 constexpr int kMaxCameras = 64;
 
 // Tile shape of the fused pyramid pass and of the blend pass (level-k pixels).
-constexpr int kPyrTX = 64, kPyrTY = 32;
+constexpr int kPyrTX = 64, kPyrTY = 16;
 constexpr int kBlendTX = 64, kBlendTY = 16;
 constexpr int kThreads = 256;
 
@@ -74,7 +74,8 @@ struct BlendArgs {
 };
 
 // Launchers (kernels.hip).  f16 selects half-precision storage.
-hipError_t launch_pyr(bool f16, bool emit_lap, const PyrItem* items_dev, int nitems, int total_tiles,
+// warp: level-0 pass whose image source is the homography warp (always emits L_0).
+hipError_t launch_pyr(bool f16, bool emit_lap, bool warp, const PyrItem* items_dev, int nitems, int total_tiles,
                       const FrameArgs& frames, hipStream_t s);
 // Table sizes the kernels accept.
 constexpr int kMaxBlendCams = kMaxCameras;

@@ -67,8 +67,13 @@ SIGNATURES = {
     "stitch_plan_view": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(StitchImage), POINTER(c_int32),
                                    POINTER(c_int32)]),
     "stitch_plan_regions": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_int32), POINTER(c_int32)]),
+    "stitch_plan_set_timing": (c_int32, [c_void_p, c_int32]),
+    "stitch_plan_read_timing": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int32)]),
     "stitch_plan_destroy": (None, [c_void_p]),
 }
+
+TIMING_KINDS = ["warp_level0_pass", "level_pass", "blend_level0", "blend_middle", "blend_top",
+                "blend_single", "warp_single", "unused"]
 
 
 def lib():
@@ -298,6 +303,16 @@ class Plan:
         t = torch.as_strided(flat, (im.channels, im.height, im.width),
                              (im.plane_pitch // es if im.channels > 1 else 0, im.row_pitch // es, 1), off // es)
         return t, (ox.value, oy.value)
+
+    def set_timing(self, enable: bool) -> None:
+        check(lib().stitch_plan_set_timing(self._h, 1 if enable else 0))
+
+    def read_timing(self) -> dict:
+        """{kind: (total_ms, launches)} accumulated since set_timing(True)."""
+        ms = (c_double * 8)()
+        n = (c_int32 * 8)()
+        check(lib().stitch_plan_read_timing(self._h, ms, n))
+        return {TIMING_KINDS[i]: (ms[i], n[i]) for i in range(8) if n[i]}
 
     def regions(self, camera: int, level: int):
         roi = (c_int32 * 4)()
