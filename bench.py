@@ -40,7 +40,8 @@ def parse():
     ap.add_argument("--frames", type=int, default=30, help="frames per step (the sequence length)")
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c4"])
     ap.add_argument("--storage", default="f32", choices=["f32", "f16"])
-    ap.add_argument("--forms", default="f16", help="extra forms timed after the headline (comma list or 'none')")
+    ap.add_argument("--forms", default="f16,batched_f32,batched_f16",
+                    help="extra forms timed after the headline (comma list or 'none')")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the step without per-launch events (roofline then omitted)")
@@ -158,6 +159,33 @@ def time_form(rig, frames, storage, steps, warmup, kernel_events=True):
     return plan, ms, timing, panos
 
 
+def time_batched(rig, frames, storage, steps, warmup, tune_cache=None):
+    """All frames of the sequence as jobs of one batch (one plan per job), captured once
+    into a HIP graph and replayed per step."""
+    import paper_1810_03988_amd as P
+    dev = frames[0][0].device
+    plans = [P.Plan(rig.frame_sizes, rig.H, rig.masks(), rig.canvas_w, rig.canvas_h, rig.levels, storage=storage,
+                    device=dev) for _ in frames]
+    panos = [torch.empty((rig.canvas_h, rig.canvas_w, 3), dtype=torch.uint8, device=dev) for _ in frames]
+    batch = P.Batch(plans, device=dev)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        cfg = batch.autotune(frames, panos, stream=stream, cache_path=tune_cache)
+        args = batch.args(frames, panos)
+        sh = stream.cuda_stream
+        for _ in range(warmup):
+            batch.run_raw(args, sh)
+        stream.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(steps):
+            batch.run_raw(args, sh)
+        t1.record(stream)
+        stream.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    return ms, cfg, batch, panos
+
+
 def kernel_table(plan, rig, timing, steps, s):
     alg = algorithmic_bytes(plan, rig, s)
     table = {}
@@ -230,6 +258,18 @@ def main():
     forms = {f"plain_{a.storage}": {"Mpx_s": round(value, 1), "ms_per_step": round(ms, 4),
                                     "ms_per_step_without_launch_events": round(ms_plain, 4)}}
     for form in [f for f in a.forms.split(",") if f and f != "none" and f != a.storage]:
+        if form.startswith("batched_"):
+            st = form.split("_", 1)[1]
+            bms, cfg, _b, _p = time_batched(rig, frames, st, a.steps, a.warmup,
+                                            tune_cache=os.environ.get("STITCH_TUNE_CACHE"))
+            bval = px_per_step / (bms / 1e3) / 1e6
+            forms[form] = {"Mpx_s": round(bval, 1), "ms_per_step": round(bms, 4),
+                           "wg_per_cu_by_level": cfg[:rig.levels - 1],
+                           "how": f"{a.frames} jobs (one per frame) in one batch, one HIP graph replay per step"}
+            print(f"# {form}: {bms:.3f} ms/step, {bval:.0f} Mpx/s (tuned wg/CU {cfg[:rig.levels - 1]})",
+                  file=sys.stderr, flush=True)
+            del _b, _p
+            continue
         fplan, fms, ftim, _panos = time_form(rig, frames, form, a.steps, a.warmup, True)
         fval = px_per_step / (fms / 1e3) / 1e6
         fk = kernel_table(fplan, rig, ftim, a.steps, 2 if form == "f16" else 4)

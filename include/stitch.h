@@ -211,6 +211,43 @@ stitch_status stitch_plan_read_timing(stitch_plan* plan, double ms[STITCH_TIMING
 
 void stitch_plan_destroy(stitch_plan* plan);
 
+/* ---- many jobs in one captured launch sequence --------------------------------- */
+
+/* A batch stitches several planned jobs (rigs of any camera count, resolution and level
+ * count >= 2) per run.  The paper overlaps images of different resolutions with CUDA
+ * stream queues (Sec. 4.3.2); here all jobs' work of one pyramid level (or one blend
+ * level) is one launch over a table of per-job tiles, the launches of a run are captured
+ * once into a HIP graph, and later runs replay it.  Frame and panorama pointers live in
+ * the device tables (re-uploaded only when they change), so replays never need a new
+ * capture.  The batch uses each plan's bound workspace for the jobs' pyramids: while a
+ * plan belongs to a batch, do not run stitch_frame on it concurrently with the batch. */
+typedef struct stitch_batch stitch_batch;
+
+/* plans: njobs distinct, bound plans of one storage type.  Host-only.
+ * Errors: NULL, SHAPE, STATE (a plan not bound), UNSUPPORTED (a one-level plan, mixed
+ * storage types). */
+stitch_status stitch_batch_create(int32_t njobs, stitch_plan* const* plans, stitch_batch** out);
+size_t        stitch_batch_workspace_bytes(const stitch_batch* batch);   /* launch tables */
+/* Attach caller-owned device memory (256-byte aligned) for the tables.  Host-only;
+ * discards a captured graph.  Errors: NULL, WORKSPACE. */
+stitch_status stitch_batch_bind(stitch_batch* batch, void* workspace, size_t bytes);
+/* One run: frames[j] is job j's array of its plan's camera frames (U8 HWC), panos[j] its
+ * panorama.  On a non-null stream the first run captures a graph and every run launches
+ * it; on the null stream the launches are issued directly.  Errors: NULL, SHAPE, STATE,
+ * DEVICE. */
+stitch_status stitch_batch_run(stitch_batch* batch, const stitch_image* const* frames, stitch_image* panos,
+                               void* stream);
+/* Pick, for every pyramid level of the batch, how many persistent workgroups per compute
+ * unit its pass launches (as many as fit, 1, 2, or one per tile) by timing the candidates
+ * on these inputs (synchronises the stream).  cache_path (optional): a text file of
+ * earlier choices keyed by device and batch geometry; a hit skips the timing and a miss
+ * appends the new choice.  Errors: NULL, SHAPE, STATE, DEVICE. */
+stitch_status stitch_batch_autotune(stitch_batch* batch, const stitch_image* const* frames, stitch_image* panos,
+                                    void* stream, const char* cache_path);
+/* The per-level workgroups-per-CU setting in use (0: as many as fit, -1: one per tile). */
+stitch_status stitch_batch_config(const stitch_batch* batch, int32_t wg_per_cu[STITCH_MAX_LEVELS]);
+void          stitch_batch_destroy(stitch_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

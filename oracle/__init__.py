@@ -8,3 +8,6 @@ from .stitch_oracle import (  # noqa: F401
     reduce_full, expand_full, gaussian_pyramid, laplacian_pyramid, collapse, quantise,
     blend_pyramids, StitchOracle, check_masks,
 )
+from .adjoint_oracle import (  # noqa: F401
+    GradOracle, dlt_from_corners, dlt_jacobian, canvas_map_jacobian, reduce_T, expand_T, corners,
+)

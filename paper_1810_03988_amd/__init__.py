@@ -5,4 +5,4 @@ include/stitch.h (libstitch.so, built in-tree by paper_1810_03988_amd.build);
 paper_1810_03988_amd.stitch is the ctypes binding.
 """
 from . import stitch  # noqa: F401
-from .stitch import Plan, StitchError, blend, lib, pyramid, warp, warp_coords  # noqa: F401
+from .stitch import Batch, Plan, StitchError, blend, lib, pyramid, warp, warp_coords  # noqa: F401

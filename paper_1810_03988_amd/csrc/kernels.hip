@@ -18,6 +18,8 @@
 // border cases at all.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include "stitch_internal.h"
 
 namespace stitch {
@@ -66,6 +68,18 @@ __device__ __forceinline__ void warp_coords(const float* __restrict__ h, int X, 
                                             bool& zpos) {
 #pragma clang fp contract(off)
   const float Xf = (float)X, Yf = (float)Y;
+  const float u = (h[0] * Xf + h[1] * Yf) + h[2];
+  const float v = (h[3] * Xf + h[4] * Yf) + h[5];
+  const float z = (h[6] * Xf + h[7] * Yf) + h[8];
+  zpos = z > 0.0f;
+  x = u / z;
+  y = v / z;
+}
+
+// The same sequence from canvas coordinates already held as (exact) floats.
+__device__ __forceinline__ void warp_coords_f(const float* __restrict__ h, float Xf, float Yf, float& x, float& y,
+                                              bool& zpos) {
+#pragma clang fp contract(off)
   const float u = (h[0] * Xf + h[1] * Yf) + h[2];
   const float v = (h[3] * Xf + h[4] * Yf) + h[5];
   const float z = (h[6] * Xf + h[7] * Yf) + h[8];
@@ -187,6 +201,12 @@ __global__ void __launch_bounds__(kThreads) k_pyr(const PyrItem* __restrict__ it
     const int e = tid + q * kThreads;
     rc[q] = e < NE ? ((e / EW) << 8) | (e % EW) : -1;
   }
+  float cfq[NIT], rfq[NIT];             // the same positions as floats (exact)
+#pragma unroll
+  for (int q = 0; q < NIT; ++q) {
+    cfq[q] = (float)(rc[q] < 0 ? 0 : rc[q] & 255);
+    rfq[q] = (float)(rc[q] < 0 ? 0 : rc[q] >> 8);
+  }
   // canvas position of staged sample q (folded at canvas edges unless the tile is interior)
   auto sample_pos = [&](int q, int X0, int Y0, bool interior, int fw, int fh, int& X, int& Y) {
     const int r = rc[q] < 0 ? 0 : rc[q] >> 8, c = rc[q] < 0 ? 0 : rc[q] & 255;
@@ -227,14 +247,26 @@ __global__ void __launch_bounds__(kThreads) k_pyr(const PyrItem* __restrict__ it
     if (WARP) {
       const GLB uint8_t* msk = cg<uint8_t>(it.msk);
       const bool has_mask = it.msk_kind != kSrcNone;
+      const bool inside = interior && d.X0 - 4 >= rx && d.X0 + TX + 3 <= rx + rw && d.Y0 - 4 >= ry &&
+                          d.Y0 + TY + 3 <= ry + rh;
+      if (has_mask && inside) {   // every sample of the tile lies in the stored weight rectangle
+        const GLB uint8_t* m0 = msk + (int64_t)(d.Y0 - 4 - ry) * it.msk_row + (d.X0 - 4 - rx);
+        const uint32_t mrow = (uint32_t)it.msk_row;
 #pragma unroll
-      for (int q = 0; q < NIT; ++q) {
-        int X, Y;
-        sample_pos(q, d.X0, d.Y0, interior, fw, fh, X, Y);
-        const int my = Y - ry, mx = X - rx;
-        const bool in = has_mask && my >= 0 && my < rh && mx >= 0 && mx < rw;
-        const uint32_t m = has_mask ? (uint32_t)msk[in ? (int64_t)my * it.msk_row + mx : 0] : 0u;
-        pm[q] = in ? m : 0u;
+        for (int q = 0; q < NIT; ++q) {
+          const int r = rc[q] < 0 ? 0 : rc[q] >> 8, c = rc[q] < 0 ? 0 : rc[q] & 255;
+          pm[q] = m0[__umul24((uint32_t)r, mrow) + (uint32_t)c];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < NIT; ++q) {
+          int X, Y;
+          sample_pos(q, d.X0, d.Y0, interior, fw, fh, X, Y);
+          const int my = Y - ry, mx = X - rx;
+          const bool in = has_mask && my >= 0 && my < rh && mx >= 0 && mx < rw;
+          const uint32_t m = has_mask ? (uint32_t)msk[in ? (int64_t)my * it.msk_row + mx : 0] : 0u;
+          pm[q] = in ? m : 0u;
+        }
       }
     } else {
       const GLB T* g = cg<T>(it.img);
@@ -282,40 +314,54 @@ __global__ void __launch_bounds__(kThreads) k_pyr(const PyrItem* __restrict__ it
 #pragma unroll
       for (int q = 0; q < NIT; ++q) mreg[q] = pm[q];
       if (tn < t_end) prefetch(tn);    // next tile's seam weights fly while this one computes
-      const float fwf = (float)w, fhf = (float)h;
+      const float fwf = (float)w, fhf = (float)h, fwm1 = (float)(w - 1), fhm1 = (float)(h - 1);
       const uint32_t srow32 = (uint32_t)srow;
+      const float X0m4 = (float)(X0 - 4), Y0m4 = (float)(Y0 - 4);
 #pragma unroll
       for (int q = 0; q < NIT; ++q) {
-        int Xc, Yc;
-        sample_pos(q, X0, Y0, interior, fw, fh, Xc, Yc);
+        float Xf, Yf;
+        if (interior) {
+          Xf = X0m4 + cfq[q];
+          Yf = Y0m4 + rfq[q];
+        } else {
+          int Xc, Yc;
+          sample_pos(q, X0, Y0, interior, fw, fh, Xc, Yc);
+          Xf = (float)Xc;
+          Yf = (float)Yc;
+        }
         float x, y;
         bool zpos;
-        warp_coords(hv, Xc, Yc, x, y, zpos);
+        warp_coords_f(hv, Xf, Yf, x, y, zpos);
         const bool ok = zpos && x >= -1.0f && x < fwf && y >= -1.0f && y < fhf;
         const float xs = ok ? x : 0.0f, ys = ok ? y : 0.0f;
         const float x0f = floorf(xs), y0f = floorf(ys);
         const float fx = xs - x0f, fy = ys - y0f, gx = 1.0f - fx, gy = 1.0f - fy;
-        const int x0 = (int)x0f, y0 = (int)y0f;
-        const bool xa = ok && x0 >= 0, xb = ok && x0 + 1 < w, ya = y0 >= 0, yb = y0 + 1 < h;
-        const float w00 = (ya && xa) ? gy * gx : 0.0f, w01 = (ya && xb) ? gy * fx : 0.0f;
-        const float w10 = (yb && xa) ? fy * gx : 0.0f, w11 = (yb && xb) ? fy * fx : 0.0f;
-        // byte offsets of the four taps (clamped into the frame; outside taps have weight 0)
-        const uint32_t o0 = (uint32_t)(ya ? y0 : 0) * srow32, o1 = (uint32_t)(yb ? y0 + 1 : 0) * srow32;
-        const uint32_t c0 = 3u * (uint32_t)(xa ? x0 : 0), c1 = 3u * (uint32_t)(xb ? x0 + 1 : 0);
+        const bool xa = ok && x0f >= 0.0f, xb = ok && x0f < fwm1, ya = y0f >= 0.0f, yb = y0f < fhm1;
+        // bilinear weights with 1/255 folded in; taps outside the frame weigh 0
+        const float gyi = gy * kInv255, fyi = fy * kInv255;
+        const float w00 = (ya && xa) ? gyi * gx : 0.0f, w01 = (ya && xb) ? gyi * fx : 0.0f;
+        const float w10 = (yb && xa) ? fyi * gx : 0.0f, w11 = (yb && xb) ? fyi * fx : 0.0f;
+        const uint32_t x0 = (uint32_t)(int)x0f, y0 = (uint32_t)(int)y0f;
+        const uint32_t o0 = ya ? __umul24(y0, srow32) : 0u, o1 = yb ? __umul24(y0 + 1u, srow32) : 0u;
+        const uint32_t c0 = xa ? 3u * x0 : 0u, c1 = xb ? 3u * x0 + 3u : 0u;
+        const GLB uint8_t* t00 = src + (o0 + c0);
+        const GLB uint8_t* t01 = src + (o0 + c1);
+        const GLB uint8_t* t10 = src + (o1 + c0);
+        const GLB uint8_t* t11 = src + (o1 + c1);
         uint32_t p[12];
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
-          p[ch] = src[o0 + c0 + ch];
-          p[3 + ch] = src[o0 + c1 + ch];
-          p[6 + ch] = src[o1 + c0 + ch];
-          p[9 + ch] = src[o1 + c1 + ch];
+          p[ch] = t00[ch];
+          p[3 + ch] = t01[ch];
+          p[6 + ch] = t10[ch];
+          p[9 + ch] = t11[ch];
         }
         if (rc[q] >= 0) {
           const int r = rc[q] >> 8, c = rc[q] & 255;
 #pragma unroll
           for (int ch = 0; ch < 3; ++ch)
-            sIn[ch][r][c] = (w00 * (float)p[ch] + w01 * (float)p[3 + ch] + w10 * (float)p[6 + ch] +
-                             w11 * (float)p[9 + ch]) * kInv255;
+            sIn[ch][r][c] = w00 * (float)p[ch] + w01 * (float)p[3 + ch] + w10 * (float)p[6 + ch] +
+                            w11 * (float)p[9 + ch];
           sIn[3][r][c] = (float)mreg[q] * kInv255;
         }
       }
@@ -451,8 +497,18 @@ __global__ void __launch_bounds__(kThreads) k_pyr(const PyrItem* __restrict__ it
 // One synthesis level: B_k over cameras + EXPAND(R_{k+1}) -> R_k (and the panorama at k = 0).
 // 64x16 tile; thread (x = tid & 63) handles rows (tid >> 6) + 4 j, j = 0..3, so every
 // global access of a wave is one contiguous row segment.
-template <typename T, bool FINAL, bool HAS_COARSE>
-__global__ void __launch_bounds__(kThreads) k_blend(BlendArgs a) {
+__device__ __forceinline__ int find_blend_item(const BlendItem* __restrict__ items, int nitems, int t) {
+  int lo = 0, hi = nitems - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T, bool FINAL, bool KARG>
+__global__ void __launch_bounds__(kThreads) k_blend(const BlendItem* __restrict__ items, int nitems, BlendItem one,
+                                                    PanoArg po) {
   constexpr int TX = kBlendTX, TY = kBlendTY;
   constexpr int CW = TX / 2 + 2, CH = TY / 2 + 2;
   constexpr int HS = 36, ES = TX + 4;
@@ -464,8 +520,11 @@ __global__ void __launch_bounds__(kThreads) k_blend(BlendArgs a) {
 
   const int tid = threadIdx.x;
   const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int tyi = t / a.tiles_x, txi = t - tyi * a.tiles_x;
+  const BlendItem& a = KARG ? one : items[find_blend_item(items, nitems, t)];
+  const int lt = t - a.tile_begin;
+  const int tyi = lt / a.tiles_x, txi = lt - tyi * a.tiles_x;
   const int X0 = txi * TX, Y0 = tyi * TY;
+  const bool has_coarse = a.has_coarse != 0;
 
   if (tid < 64) {   // one wave builds the tile's camera list in order
     const int i = tid;
@@ -480,7 +539,7 @@ __global__ void __launch_bounds__(kThreads) k_blend(BlendArgs a) {
     if (hit) sCam[__popcll(mask & ((1ull << i) - 1ull))] = i;
     if (tid == 0) sNCam = __popcll(mask);
   }
-  if (HAS_COARSE) {
+  if (has_coarse) {
     const GLB T* r = cg<T>(a.r_in);
     const int cx0 = X0 / 2 - 1, cy0 = Y0 / 2 - 1;
     constexpr int NC = 3 * CH * CW;
@@ -566,7 +625,7 @@ __global__ void __launch_bounds__(kThreads) k_blend(BlendArgs a) {
   for (int j = 0; j < 4; ++j) {
     const int y = ybase + 4 * j;
     const int Y = Y0 + y;
-    if (HAS_COARSE) {
+    if (has_coarse) {
       const int yh = y >> 1;
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
@@ -592,22 +651,24 @@ __global__ void __launch_bounds__(kThreads) k_blend(BlendArgs a) {
         sb[y * (TX * 3) + x * 3 + ch] = (uint8_t)fminf(fmaxf(rintf(255.0f * acc[j][ch]), 0.0f), 255.0f);
     }
     __syncthreads();
+    uint8_t* const pano_ptr = po.ptr ? po.ptr : a.pano;
+    const int64_t pano_row = po.ptr ? po.row : a.pano_row;
     const int nx = min(TX, a.W - X0);
-    const bool words = nx == TX && (a.pano_row & 3) == 0 && ((uintptr_t)a.pano & 3) == 0;
-    GLB uint8_t* pano = mg<uint8_t>(a.pano);
+    const bool words = nx == TX && (pano_row & 3) == 0 && ((uintptr_t)pano_ptr & 3) == 0;
+    GLB uint8_t* pano = mg<uint8_t>(pano_ptr);
     if (words) {
       constexpr int WPR = TX * 3 / 4;   // 48 dwords per row
       for (int e = tid; e < TY * WPR; e += kThreads) {
         const int y = e / WPR, wi = e - y * WPR;
         const int Y = Y0 + y;
         if (Y < a.H)
-          *reinterpret_cast<GLB uint32_t*>(pano + (int64_t)Y * a.pano_row + (int64_t)X0 * 3 + wi * 4) = sP[y][wi];
+          *reinterpret_cast<GLB uint32_t*>(pano + (int64_t)Y * pano_row + (int64_t)X0 * 3 + wi * 4) = sP[y][wi];
       }
     } else {
       for (int e = tid; e < TY * TX * 3; e += kThreads) {
         const int y = e / (TX * 3), b = e - y * (TX * 3);
         const int Y = Y0 + y;
-        if (Y < a.H && b < nx * 3) pano[(int64_t)Y * a.pano_row + (int64_t)X0 * 3 + b] = sb[y * (TX * 3) + b];
+        if (Y < a.H && b < nx * 3) pano[(int64_t)Y * pano_row + (int64_t)X0 * 3 + b] = sb[y * (TX * 3) + b];
       }
     }
   }
@@ -691,11 +752,12 @@ __global__ void __launch_bounds__(kThreads) k_convert(int nch, int src_u8, const
   }
 }
 
-// Workgroups of a persistent launch: as many as fit on the device at once (queried once
-// per kernel), never more than there are tiles.
-int persistent_grid(const void* kernel, int tiles) {
+// Workgroups of a persistent launch: at most wg_per_cu per compute unit (0: as many as
+// fit; negative: one per tile), never more than there are tiles.  The occupancy query
+// runs once per kernel.
+int persistent_grid(const void* kernel, int tiles, int wg_per_cu) {
   static thread_local const void* cached_k[16] = {};
-  static thread_local int cached_n[16] = {};
+  static thread_local int cached_cus[16] = {}, cached_per[16] = {};
   int slot = -1;
   for (int i = 0; i < 16; ++i)
     if (cached_k[i] == kernel || cached_k[i] == nullptr) { slot = i; break; }
@@ -709,28 +771,32 @@ int persistent_grid(const void* kernel, int tiles) {
       per = 2;
     }
     cached_k[slot] = kernel;
-    cached_n[slot] = cus * per;
+    cached_cus[slot] = cus;
+    cached_per[slot] = per;
   }
-  return tiles < cached_n[slot] ? tiles : cached_n[slot];
+  if (wg_per_cu < 0) return tiles;
+  const int per = wg_per_cu > 0 && wg_per_cu < cached_per[slot] ? wg_per_cu : cached_per[slot];
+  const int n = cached_cus[slot] * per;
+  return tiles < n ? tiles : n;
 }
 
 }  // namespace
 
 // ------------------------------------------------------------------------------------ launchers
 hipError_t launch_pyr(bool f16, bool emit_lap, bool warp, const PyrItem* items_dev, int nitems, int total_tiles,
-                      const FrameArgs& fa, hipStream_t s) {
+                      const FrameArgs& fa, hipStream_t s, int wg_per_cu) {
   if (total_tiles <= 0) return hipSuccess;
   const dim3 grid(total_tiles), block(kThreads);
 #define STITCH_PYR(TT)                                                                                          \
   do {                                                                                                          \
     if (warp) {                                                                                                 \
-      const dim3 g(persistent_grid((const void*)k_pyr<TT, true, true>, total_tiles));                        \
+      const dim3 g(persistent_grid((const void*)k_pyr<TT, true, true>, total_tiles, wg_per_cu));                        \
       hipLaunchKernelGGL((k_pyr<TT, true, true>), g, block, 0, s, items_dev, nitems, total_tiles, fa);         \
     } else if (emit_lap) {                                                                                      \
-      const dim3 g(persistent_grid((const void*)k_pyr<TT, true, false>, total_tiles));                       \
+      const dim3 g(persistent_grid((const void*)k_pyr<TT, true, false>, total_tiles, wg_per_cu));                       \
       hipLaunchKernelGGL((k_pyr<TT, true, false>), g, block, 0, s, items_dev, nitems, total_tiles, fa);        \
     } else {                                                                                                    \
-      const dim3 g(persistent_grid((const void*)k_pyr<TT, false, false>, total_tiles));                      \
+      const dim3 g(persistent_grid((const void*)k_pyr<TT, false, false>, total_tiles, wg_per_cu));                      \
       hipLaunchKernelGGL((k_pyr<TT, false, false>), g, block, 0, s, items_dev, nitems, total_tiles, fa);       \
     }                                                                                                           \
   } while (0)
@@ -740,21 +806,35 @@ hipError_t launch_pyr(bool f16, bool emit_lap, bool warp, const PyrItem* items_d
   return hipGetLastError();
 }
 
-hipError_t launch_blend(bool f16, const BlendArgs& a, hipStream_t s) {
-  const int tiles = a.tiles_x * a.tiles_y;
-  if (tiles <= 0) return hipSuccess;
-  const dim3 grid(tiles), block(kThreads);
-  const bool fin = a.pano != nullptr;
-  const bool co = a.has_coarse != 0;
-#define STITCH_BLEND(TT)                                                                        \
-  do {                                                                                          \
-    if (fin && co) hipLaunchKernelGGL((k_blend<TT, true, true>), grid, block, 0, s, a);         \
-    else if (fin) hipLaunchKernelGGL((k_blend<TT, true, false>), grid, block, 0, s, a);         \
-    else if (co) hipLaunchKernelGGL((k_blend<TT, false, true>), grid, block, 0, s, a);          \
-    else hipLaunchKernelGGL((k_blend<TT, false, false>), grid, block, 0, s, a);                 \
+void prepare_launches() {
+  // fill the occupancy cache outside any stream capture
+  persistent_grid((const void*)k_pyr<float, true, true>, 1, 0);
+  persistent_grid((const void*)k_pyr<float, true, false>, 1, 0);
+  persistent_grid((const void*)k_pyr<float, false, false>, 1, 0);
+  persistent_grid((const void*)k_pyr<_Float16, true, true>, 1, 0);
+  persistent_grid((const void*)k_pyr<_Float16, true, false>, 1, 0);
+  persistent_grid((const void*)k_pyr<_Float16, false, false>, 1, 0);
+}
+
+hipError_t launch_blend(bool f16, bool final_level, const BlendItem* items_dev, int nitems, int total_tiles,
+                        const PanoArg& po, hipStream_t s, const BlendItem* one) {
+  if (total_tiles <= 0) return hipSuccess;
+  const dim3 grid(total_tiles), block(kThreads);
+  BlendItem k1;
+  if (one) k1 = *one;
+  else std::memset(&k1, 0, sizeof k1);
+#define STITCH_BLEND(TT, FIN)                                                                                    \
+  do {                                                                                                           \
+    if (one) hipLaunchKernelGGL((k_blend<TT, FIN, true>), grid, block, 0, s, items_dev, nitems, k1, po);          \
+    else hipLaunchKernelGGL((k_blend<TT, FIN, false>), grid, block, 0, s, items_dev, nitems, k1, po);             \
   } while (0)
-  if (f16) STITCH_BLEND(_Float16);
-  else STITCH_BLEND(float);
+  if (f16) {
+    if (final_level) STITCH_BLEND(_Float16, true);
+    else STITCH_BLEND(_Float16, false);
+  } else {
+    if (final_level) STITCH_BLEND(float, true);
+    else STITCH_BLEND(float, false);
+  }
 #undef STITCH_BLEND
   return hipGetLastError();
 }

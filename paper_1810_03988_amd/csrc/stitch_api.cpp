@@ -147,6 +147,8 @@ struct stitch_plan {
   size_t off_items[kMaxLevels] = {};
   std::vector<BlendCam> bcams[kMaxLevels];
   size_t off_bcams[kMaxLevels] = {};
+  std::vector<BlendItem> bitems;            // one per level
+  size_t off_bitems = 0;
   size_t ws_bytes = 0;
   uint8_t* ws = nullptr;
   // optional per-launch event timing (diagnostics)
@@ -318,6 +320,30 @@ void build_tables(stitch_plan* p) {
       p->bcams[k].push_back(bc);
     }
   }
+  p->bitems.assign(L, BlendItem{});
+  for (int k = 0; k < L; ++k) {
+    BlendItem& bi = p->bitems[k];
+    std::memset(&bi, 0, sizeof bi);
+    bi.tiles_x = (p->dw[k] + kBlendTX - 1) / kBlendTX;
+    bi.tiles_y = (p->dh[k] + kBlendTY - 1) / kBlendTY;
+    bi.W = p->dw[k];
+    bi.H = p->dh[k];
+    bi.ncam = (int)p->bcams[k].size();
+    bi.cams = (const BlendCam*)(ws + p->off_bcams[k]);
+    if (k + 1 < L) {
+      bi.has_coarse = 1;
+      bi.cW = p->dw[k + 1];
+      bi.cH = p->dh[k + 1];
+      bi.r_in = ws + p->off_r[k + 1];
+      bi.rin_row = p->r_row[k + 1];
+      bi.rin_plane = p->r_plane[k + 1];
+    }
+    if (p->has_r[k]) {
+      bi.r_out = ws + p->off_r[k];
+      bi.rout_row = p->r_row[k];
+      bi.rout_plane = p->r_plane[k];
+    }
+  }
 }
 
 }  // namespace
@@ -483,7 +509,9 @@ stitch_status stitch_pyramid(const stitch_image* g0, int32_t kind, stitch_levels
 
 // ------------------------------------------------------------------------------------ blend
 size_t stitch_blend_workspace_bytes(int32_t n, int32_t levels) {
-  return (size_t)align_up((int64_t)std::max(n, 1) * std::max(levels, 1) * (int64_t)sizeof(BlendCam), 256);
+  const int64_t L = std::max(levels, 1);
+  return (size_t)align_up(std::max(n, 1) * L * (int64_t)sizeof(BlendCam), 256) +
+         (size_t)align_up(L * (int64_t)sizeof(BlendItem), 256);
 }
 
 stitch_status stitch_blend(int32_t n, const stitch_levels* bands, const stitch_levels* weights, stitch_image* pano,
@@ -551,11 +579,11 @@ stitch_status stitch_blend(int32_t n, const stitch_levels* bands, const stitch_l
       bc.wx = weights[i].origin_x[k]; bc.wy = weights[i].origin_y[k]; bc.ww = w.width; bc.wh = w.height;
     }
   const hipStream_t s = (hipStream_t)stream;
-  st = upload(workspace, tab.data(), tab.size() * sizeof(BlendCam), s, "blend table upload");
-  if (st) return st;
   const BlendCam* dev = (const BlendCam*)workspace;
-  for (int k = L - 1; k >= 0; --k) {
-    BlendArgs a;
+  const size_t items_off = (size_t)align_up((int64_t)tab.size() * (int64_t)sizeof(BlendCam), 256);
+  std::vector<BlendItem> items(L);
+  for (int k = 0; k < L; ++k) {
+    BlendItem& a = items[k];
     std::memset(&a, 0, sizeof a);
     a.W = dw[k]; a.H = dh[k];
     a.ncam = n;
@@ -573,7 +601,15 @@ stitch_status stitch_blend(int32_t n, const stitch_levels* bands, const stitch_l
     if (k == 0) { a.pano = (uint8_t*)pano->data; a.pano_row = pano->row_pitch; }
     a.tiles_x = (dw[k] + kBlendTX - 1) / kBlendTX;
     a.tiles_y = (dh[k] + kBlendTY - 1) / kBlendTY;
-    const hipError_t e = launch_blend(dt == STITCH_F16, a, s);
+  }
+  st = upload(workspace, tab.data(), tab.size() * sizeof(BlendCam), s, "blend table upload");
+  if (st) return st;
+  st = upload((uint8_t*)workspace + items_off, items.data(), items.size() * sizeof(BlendItem), s, "blend table upload");
+  if (st) return st;
+  const BlendItem* idev = (const BlendItem*)((uint8_t*)workspace + items_off);
+  for (int k = L - 1; k >= 0; --k) {
+    const hipError_t e = launch_blend(dt == STITCH_F16, k == 0, idev + k, 1, items[k].tiles_x * items[k].tiles_y,
+                                      PanoArg{nullptr, 0}, s, &items[k]);
     if (e != hipSuccess) return hip_fail(e, "blend launch");
   }
   return STITCH_OK;
@@ -725,6 +761,7 @@ stitch_status stitch_plan_create(int32_t n, const int32_t* frame_w, const int32_
   }
   for (int k = 0; k + 1 < L; ++k) p->off_items[k] = lay.take((size_t)n * sizeof(PyrItem));
   for (int k = 0; k < L; ++k) p->off_bcams[k] = lay.take((size_t)n * sizeof(BlendCam));
+  p->off_bitems = lay.take((size_t)L * sizeof(BlendItem));
   p->ws_bytes = lay.top;
   *out = p;
   p = nullptr;   // disarm the guard
@@ -751,6 +788,8 @@ stitch_status stitch_plan_bind(stitch_plan* p, void* workspace, size_t bytes, vo
   for (int k = 0; k < p->L && !st; ++k)
     st = upload(p->ws + p->off_bcams[k], p->bcams[k].data(), p->bcams[k].size() * sizeof(BlendCam), s,
                 "table upload");
+  if (!st)
+    st = upload(p->ws + p->off_bitems, p->bitems.data(), p->bitems.size() * sizeof(BlendItem), s, "table upload");
   if (!st) {
     const hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) st = hip_fail(e, "bind synchronise");
@@ -834,21 +873,10 @@ stitch_status stitch_frame(stitch_plan* p, const stitch_image* frames, stitch_im
     if ((st = mark(k == 0 ? 0 : 1))) return st;
   }
   for (int k = L - 1; k >= 0; --k) {
-    BlendArgs a;
-    std::memset(&a, 0, sizeof a);
-    a.W = p->dw[k]; a.H = p->dh[k];
-    a.ncam = (int)p->bcams[k].size();
-    a.cams = (const BlendCam*)(p->ws + p->off_bcams[k]);
-    if (k + 1 < L) {
-      a.has_coarse = 1;
-      a.cW = p->dw[k + 1]; a.cH = p->dh[k + 1];
-      a.r_in = p->ws + p->off_r[k + 1]; a.rin_row = p->r_row[k + 1]; a.rin_plane = p->r_plane[k + 1];
-    }
-    if (p->has_r[k]) { a.r_out = p->ws + p->off_r[k]; a.rout_row = p->r_row[k]; a.rout_plane = p->r_plane[k]; }
-    if (k == 0) { a.pano = (uint8_t*)pano->data; a.pano_row = pano->row_pitch; }
-    a.tiles_x = (p->dw[k] + kBlendTX - 1) / kBlendTX;
-    a.tiles_y = (p->dh[k] + kBlendTY - 1) / kBlendTY;
-    e = launch_blend(f16, a, s);
+    const BlendItem& bi = p->bitems[k];
+    PanoArg po{nullptr, 0};
+    if (k == 0) { po.ptr = (uint8_t*)pano->data; po.row = pano->row_pitch; }
+    e = launch_blend(f16, k == 0, nullptr, 1, bi.tiles_x * bi.tiles_y, po, s, &bi);
     if (e != hipSuccess) return hip_fail(e, "blend launch");
     const int kind = k == 0 ? (L > 1 ? 2 : 5) : (k + 1 < L ? 3 : 4);
     if ((st = mark(kind))) return st;
@@ -964,5 +992,324 @@ stitch_status stitch_plan_regions(const stitch_plan* p, int32_t camera, int32_t 
 }
 
 void stitch_plan_destroy(stitch_plan* p) { delete p; }
+
+// ------------------------------------------------------------------------------------ batch
+
+}  // extern "C"
+
+struct stitch_batch {
+  int njobs = 0, maxL = 0;
+  bool f16 = false;
+  std::vector<stitch_plan*> plans;
+  std::vector<PyrItem> pyr[kMaxLevels];
+  int pyr_tiles[kMaxLevels] = {};
+  size_t off_pyr[kMaxLevels] = {};
+  int wg_cap[kMaxLevels] = {};                // tuned persistent workgroups per CU per phase
+  std::vector<BlendItem> blend[kMaxLevels];
+  int blend_tiles[kMaxLevels] = {};
+  size_t off_blend[kMaxLevels] = {};
+  std::vector<int> frame_item;                // per job and camera: index into pyr[0] (or -1)
+  std::vector<int> frame_job, frame_cam;
+  size_t ws_bytes = 0;
+  uint8_t* ws = nullptr;
+  bool uploaded = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~stitch_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+namespace {
+
+void drop_graph(stitch_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+// Enqueue every phase of the batch: pyramid passes by level, then blends from the top
+// level down; a job joins the phases its own level count has.
+stitch_status enqueue_batch(stitch_batch* b, hipStream_t s) {
+  FrameArgs fa;
+  std::memset(&fa, 0, sizeof fa);   // n = 0: frames come from the item tables
+  for (int k = 0; k + 1 < b->maxL; ++k) {
+    if (b->pyr_tiles[k] <= 0) continue;
+    const hipError_t e = launch_pyr(b->f16, true, k == 0, (const PyrItem*)(b->ws + b->off_pyr[k]),
+                                    (int)b->pyr[k].size(), b->pyr_tiles[k], fa, s, b->wg_cap[k]);
+    if (e != hipSuccess) return hip_fail(e, "batch pyramid launch");
+  }
+  for (int k = b->maxL - 1; k >= 0; --k) {
+    if (b->blend_tiles[k] <= 0) continue;
+    const hipError_t e = launch_blend(b->f16, k == 0, (const BlendItem*)(b->ws + b->off_blend[k]),
+                                      (int)b->blend[k].size(), b->blend_tiles[k], PanoArg{nullptr, 0}, s);
+    if (e != hipSuccess) return hip_fail(e, "batch blend launch");
+  }
+  return STITCH_OK;
+}
+
+// Check the run's frames and panoramas, write their pointers into the tables and upload
+// the tables when anything changed.
+stitch_status batch_prepare(stitch_batch* b, const stitch_image* const* frames, stitch_image* panos, hipStream_t s) {
+  if (!b->ws) return fail(STITCH_E_STATE, "batch has no workspace bound");
+  if (!frames || !panos) return fail(STITCH_E_NULL, "frames or panos is NULL");
+  bool changed = !b->uploaded;
+  for (int j = 0; j < b->njobs; ++j) {
+    const stitch_plan* p = b->plans[j];
+    if (!frames[j]) return fail(STITCH_E_NULL, "frames[%d] is NULL", j);
+    char name[48];
+    snprintf(name, sizeof name, "panos[%d]", j);
+    stitch_status st = check_image(&panos[j], name, STITCH_U8, STITCH_HWC, 3);
+    if (st) return st;
+    if (panos[j].width != p->W || panos[j].height != p->H)
+      return fail(STITCH_E_SHAPE, "panos[%d] does not match job %d's canvas", j, j);
+    for (int i = 0; i < p->n; ++i) {
+      snprintf(name, sizeof name, "frames[%d][%d]", j, i);
+      st = check_image(&frames[j][i], name, STITCH_U8, STITCH_HWC, 3);
+      if (st) return st;
+      if (frames[j][i].width != p->cam[i].fw || frames[j][i].height != p->cam[i].fh)
+        return fail(STITCH_E_SHAPE, "%s does not match the planned frame size", name);
+      if (frames[j][i].row_pitch * (int64_t)frames[j][i].height >= ((int64_t)1 << 31))
+        return fail(STITCH_E_SHAPE, "%s spans 2 GiB or more", name);
+    }
+  }
+  for (size_t q = 0; q < b->frame_item.size(); ++q) {
+    const stitch_image& f = frames[b->frame_job[q]][b->frame_cam[q]];
+    PyrItem& it = b->pyr[0][b->frame_item[q]];
+    if (it.img != f.data || it.img_row != f.row_pitch) {
+      it.img = f.data;
+      it.img_row = f.row_pitch;
+      changed = true;
+    }
+  }
+  for (size_t q = 0; q < b->blend[0].size(); ++q) {
+    BlendItem& bi = b->blend[0][q];
+    const stitch_image& pv = panos[q];
+    if (bi.pano != pv.data || bi.pano_row != pv.row_pitch) {
+      bi.pano = (uint8_t*)pv.data;
+      bi.pano_row = pv.row_pitch;
+      changed = true;
+    }
+  }
+  if (!changed) return STITCH_OK;
+  for (int k = 0; k < b->maxL; ++k) {
+    stitch_status st = upload(b->ws + b->off_pyr[k], b->pyr[k].data(), b->pyr[k].size() * sizeof(PyrItem), s,
+                              "batch table upload");
+    if (!st) st = upload(b->ws + b->off_blend[k], b->blend[k].data(), b->blend[k].size() * sizeof(BlendItem), s,
+                         "batch table upload");
+    if (st) return st;
+  }
+  b->uploaded = true;
+  return STITCH_OK;
+}
+
+uint64_t fnv1a(uint64_t h, const void* data, size_t n) {
+  const uint8_t* p = (const uint8_t*)data;
+  for (size_t i = 0; i < n; ++i) h = (h ^ p[i]) * 1099511628211ull;
+  return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+stitch_status stitch_batch_create(int32_t njobs, stitch_plan* const* plans, stitch_batch** out) {
+  if (!out) return fail(STITCH_E_NULL, "out is NULL");
+  *out = nullptr;
+  if (!plans) return fail(STITCH_E_NULL, "plans is NULL");
+  if (njobs < 1) return fail(STITCH_E_SHAPE, "njobs = %d", njobs);
+  stitch_batch* b = new (std::nothrow) stitch_batch();
+  if (!b) return fail(STITCH_E_UNSUPPORTED, "out of host memory");
+  struct Guard { stitch_batch*& b; ~Guard() { delete b; } } guard{b};
+  b->njobs = njobs;
+  for (int j = 0; j < njobs; ++j) {
+    stitch_plan* p = plans[j];
+    if (!p) return fail(STITCH_E_NULL, "plans[%d] is NULL", j);
+    if (!p->ws) return fail(STITCH_E_STATE, "plans[%d] has no workspace bound", j);
+    if (p->L < 2) return fail(STITCH_E_UNSUPPORTED, "plans[%d] has one level; batches need two or more", j);
+    for (int q = 0; q < j; ++q)
+      if (plans[q] == p) return fail(STITCH_E_SHAPE, "plans[%d] repeats plans[%d] (each job needs its own plan)", j, q);
+    if (j == 0) b->f16 = p->storage == STITCH_F16;
+    else if (b->f16 != (p->storage == STITCH_F16))
+      return fail(STITCH_E_UNSUPPORTED, "all plans of a batch must share the storage type");
+    b->plans.push_back(p);
+    b->maxL = std::max(b->maxL, p->L);
+  }
+  for (int j = 0; j < njobs; ++j) {
+    stitch_plan* p = b->plans[j];
+    for (int k = 0; k + 1 < p->L; ++k)
+      for (size_t q = 0; q < p->items[k].size(); ++q) {
+        PyrItem it = p->items[k][q];
+        it.tile_begin = b->pyr_tiles[k];
+        b->pyr_tiles[k] += it.tiles_x * it.tiles_y;
+        if (k == 0) {
+          b->frame_item.push_back((int)b->pyr[0].size());
+          b->frame_job.push_back(j);
+          b->frame_cam.push_back(it.frame_slot);
+          it.img = nullptr;
+          it.img_row = 0;
+        }
+        b->pyr[k].push_back(it);
+      }
+  }
+  // blends: level-0 items in job order, so blend[0][j] belongs to job j
+  for (int k = 0; k < b->maxL; ++k)
+    for (int j = 0; j < njobs; ++j) {
+      stitch_plan* p = b->plans[j];
+      if (k >= p->L) continue;
+      BlendItem bi = p->bitems[k];
+      bi.tile_begin = b->blend_tiles[k];
+      b->blend_tiles[k] += bi.tiles_x * bi.tiles_y;
+      b->blend[k].push_back(bi);
+    }
+  Layout lay;
+  for (int k = 0; k < b->maxL; ++k) {
+    b->off_pyr[k] = lay.take(std::max<size_t>(1, b->pyr[k].size()) * sizeof(PyrItem));
+    b->off_blend[k] = lay.take(std::max<size_t>(1, b->blend[k].size()) * sizeof(BlendItem));
+  }
+  b->ws_bytes = lay.top;
+  *out = b;
+  b = nullptr;
+  return STITCH_OK;
+}
+
+size_t stitch_batch_workspace_bytes(const stitch_batch* b) { return b ? b->ws_bytes : 0; }
+
+stitch_status stitch_batch_bind(stitch_batch* b, void* workspace, size_t bytes) {
+  if (!b) return fail(STITCH_E_NULL, "batch is NULL");
+  if (!workspace) return fail(STITCH_E_WORKSPACE, "workspace is NULL");
+  if (((uintptr_t)workspace & 255) != 0) return fail(STITCH_E_WORKSPACE, "workspace is not 256-byte aligned");
+  if (bytes < b->ws_bytes) return fail(STITCH_E_WORKSPACE, "workspace has %zu bytes, the batch needs %zu", bytes, b->ws_bytes);
+  b->ws = (uint8_t*)workspace;
+  b->uploaded = false;
+  drop_graph(b);
+  return STITCH_OK;
+}
+
+stitch_status stitch_batch_run(stitch_batch* b, const stitch_image* const* frames, stitch_image* panos, void* stream) {
+  if (!b) return fail(STITCH_E_NULL, "batch is NULL");
+  const hipStream_t s = (hipStream_t)stream;
+  stitch_status st = batch_prepare(b, frames, panos, s);
+  if (st) return st;
+  if (!s) return enqueue_batch(b, s);   // the null stream cannot be captured: launch eagerly
+  if (!b->exec) {
+    prepare_launches();
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "batch capture begin");
+    st = enqueue_batch(b, s);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    if (st) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "batch capture end");
+    b->graph = g;
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      drop_graph(b);
+      return hip_fail(e, "batch graph instantiate");
+    }
+  }
+  const hipError_t e = hipGraphLaunch(b->exec, s);
+  return e == hipSuccess ? STITCH_OK : hip_fail(e, "batch graph launch");
+}
+
+stitch_status stitch_batch_autotune(stitch_batch* b, const stitch_image* const* frames, stitch_image* panos,
+                                    void* stream, const char* cache_path) {
+  if (!b) return fail(STITCH_E_NULL, "batch is NULL");
+  const hipStream_t s = (hipStream_t)stream;
+  stitch_status st = batch_prepare(b, frames, panos, s);
+  if (st) return st;
+  prepare_launches();
+  hipDeviceProp_t prop;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(STITCH_E_DEVICE, "cannot query the device");
+  // cache key: device, storage type and each phase's tile count
+  uint64_t key = fnv1a(1469598103934665603ull, prop.gcnArchName, strlen(prop.gcnArchName));
+  key = fnv1a(key, &b->f16, sizeof b->f16);
+  key = fnv1a(key, b->pyr_tiles, sizeof b->pyr_tiles);
+  int cached[kMaxLevels];
+  bool hit = false;
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "r");
+    if (f) {
+      char line[512];
+      while (!hit && fgets(line, sizeof line, f)) {
+        unsigned long long k2 = 0;
+        int n = 0, off = 0;
+        if (sscanf(line, "%llx %d%n", &k2, &n, &off) == 2 && k2 == key && n == kMaxLevels) {
+          hit = true;
+          const char* q = line + off;
+          for (int i = 0; i < kMaxLevels && hit; ++i) {
+            int used = 0;
+            if (sscanf(q, "%d%n", &cached[i], &used) != 1) hit = false;
+            q += used;
+          }
+        }
+      }
+      fclose(f);
+    }
+  }
+  if (hit) {
+    for (int k = 0; k < kMaxLevels; ++k) b->wg_cap[k] = cached[k];
+    drop_graph(b);
+    return STITCH_OK;
+  }
+  // time each candidate cap per pyramid phase (the other phases keep their settings)
+  const int cands[] = {0, 1, 2, -1};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(STITCH_E_DEVICE, "event create failed");
+  FrameArgs fa;
+  std::memset(&fa, 0, sizeof fa);
+  for (int k = 0; k + 1 < b->maxL && !st; ++k) {
+    if (b->pyr_tiles[k] <= 0) continue;
+    float best = 1e30f;
+    int best_c = 0;
+    for (int c : cands) {
+      float total = 0.0f;
+      for (int rep = 0; rep < 4 && !st; ++rep) {
+        hipError_t e = hipEventRecord(e0, s);
+        if (e == hipSuccess)
+          e = launch_pyr(b->f16, true, k == 0, (const PyrItem*)(b->ws + b->off_pyr[k]), (int)b->pyr[k].size(),
+                         b->pyr_tiles[k], fa, s, c);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) st = hip_fail(e, "autotune timing");
+        if (rep > 0) total += ms;   // the first launch warms caches
+      }
+      if (!st && total < best) { best = total; best_c = c; }
+    }
+    b->wg_cap[k] = best_c;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "a");
+    if (f) {
+      fprintf(f, "%llx %d", (unsigned long long)key, kMaxLevels);
+      for (int k = 0; k < kMaxLevels; ++k) fprintf(f, " %d", b->wg_cap[k]);
+      fprintf(f, "\n");
+      fclose(f);
+    }
+  }
+  drop_graph(b);
+  return STITCH_OK;
+}
+
+stitch_status stitch_batch_config(const stitch_batch* b, int32_t wg_per_cu[STITCH_MAX_LEVELS]) {
+  if (!b || !wg_per_cu) return fail(STITCH_E_NULL, "batch or wg_per_cu is NULL");
+  for (int k = 0; k < kMaxLevels; ++k) wg_per_cu[k] = b->wg_cap[k];
+  return STITCH_OK;
+}
+
+void stitch_batch_destroy(stitch_batch* b) { delete b; }
 
 }  // extern "C"

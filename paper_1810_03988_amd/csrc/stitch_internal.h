@@ -62,24 +62,40 @@ struct BlendCam {
   int32_t wx, wy, ww, wh;                         // weight rectangle
 };
 
-struct BlendArgs {
+// One canvas level of one stitch job in a blend launch; a launch covers the tiles of
+// several items (jobs), tile_begin being each item's first tile.
+struct BlendItem {
+  int32_t tile_begin, tiles_x, tiles_y;
   int32_t W, H;                     // level-k canvas sides
-  int32_t cW, cH;                   // level-(k+1) canvas sides (unused at the top level)
-  int32_t ncam, has_coarse;
-  const BlendCam* cams;             // device array
+  int32_t cW, cH;                   // level-(k+1) canvas sides (used when has_coarse)
+  int32_t ncam, has_coarse, pad;
+  const BlendCam* cams;             // device array of ncam cameras
   const void* r_in; int64_t rin_row, rin_plane;    // R_{k+1} (storage type)
   void* r_out; int64_t rout_row, rout_plane;       // R_k (storage type) or nullptr
   uint8_t* pano; int64_t pano_row;                 // U8 HWC (level 0) or nullptr
-  int32_t tiles_x, tiles_y;
 };
 
 // Launchers (kernels.hip).  f16 selects half-precision storage.
 // warp: level-0 pass whose image source is the homography warp (always emits L_0).
+// wg_per_cu: persistent workgroups per compute unit (0: as many as fit, < 0: one per tile).
 hipError_t launch_pyr(bool f16, bool emit_lap, bool warp, const PyrItem* items_dev, int nitems, int total_tiles,
-                      const FrameArgs& frames, hipStream_t s);
+                      const FrameArgs& frames, hipStream_t s, int wg_per_cu = 0);
+// Runs the occupancy queries the launchers cache, so later launches (e.g. inside a stream
+// capture) make no device queries.
+void prepare_launches();
 // Table sizes the kernels accept.
 constexpr int kMaxBlendCams = kMaxCameras;
-hipError_t launch_blend(bool f16, const BlendArgs& a, hipStream_t s);
+// Per-call panorama of a single-item level-0 launch (kernel argument; ptr == nullptr:
+// every item's own pano field is used).
+struct PanoArg {
+  uint8_t* ptr;
+  int64_t row;
+};
+
+// final_level: level 0, which writes the uint8 panorama of every item.
+// one != nullptr: a single item passed by value (items_dev unused).
+hipError_t launch_blend(bool f16, bool final_level, const BlendItem* items_dev, int nitems, int total_tiles,
+                        const PanoArg& po, hipStream_t s, const BlendItem* one = nullptr);
 hipError_t launch_warp(bool f16, const uint8_t* src, int64_t src_row, int w, int h, const float* hinv9,
                        int roi_x, int roi_y, void* dst, int64_t dst_row, int64_t dst_plane, int dw, int dh,
                        hipStream_t s);

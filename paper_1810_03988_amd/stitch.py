@@ -70,6 +70,14 @@ SIGNATURES = {
     "stitch_plan_set_timing": (c_int32, [c_void_p, c_int32]),
     "stitch_plan_read_timing": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int32)]),
     "stitch_plan_destroy": (None, [c_void_p]),
+    "stitch_batch_create": (c_int32, [c_int32, POINTER(c_void_p), POINTER(c_void_p)]),
+    "stitch_batch_workspace_bytes": (c_size_t, [c_void_p]),
+    "stitch_batch_bind": (c_int32, [c_void_p, c_void_p, c_size_t]),
+    "stitch_batch_run": (c_int32, [c_void_p, POINTER(POINTER(StitchImage)), POINTER(StitchImage), c_void_p]),
+    "stitch_batch_autotune": (c_int32, [c_void_p, POINTER(POINTER(StitchImage)), POINTER(StitchImage), c_void_p,
+                                        c_char_p]),
+    "stitch_batch_config": (c_int32, [c_void_p, POINTER(c_int32)]),
+    "stitch_batch_destroy": (None, [c_void_p]),
 }
 
 TIMING_KINDS = ["warp_level0_pass", "level_pass", "blend_level0", "blend_middle", "blend_top",
@@ -323,6 +331,63 @@ class Plan:
     def close(self) -> None:
         if getattr(self, "_h", None):
             lib().stitch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many planned jobs per run: one launch per pyramid level and per blend level over
+    every job's tiles, captured once into a HIP graph on a non-null stream."""
+
+    def __init__(self, plans, device="cuda"):
+        self.plans = list(plans)          # keeps the plans (and their workspaces) alive
+        n = len(self.plans)
+        arr = (c_void_p * n)(*[p._h for p in self.plans])
+        h = c_void_p()
+        check(lib().stitch_batch_create(n, arr, ctypes.byref(h)))
+        self._h = h
+        self.ws_bytes = lib().stitch_batch_workspace_bytes(self._h)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        base = (self.workspace.data_ptr() + 255) // 256 * 256
+        check(lib().stitch_batch_bind(self._h, base, self.ws_bytes))
+        self._args = None
+
+    def _marshal(self, frames, panos):
+        rows = [(StitchImage * len(f))(*[image_hwc(x) for x in f]) for f in frames]
+        fr = (POINTER(StitchImage) * len(rows))(*[ctypes.cast(r, POINTER(StitchImage)) for r in rows])
+        pv = (StitchImage * len(panos))(*[image_hwc(p) for p in panos])
+        return rows, fr, pv
+
+    def args(self, frames, panos):
+        """Pre-marshalled arguments for repeated runs."""
+        return self._marshal(frames, panos)
+
+    def run(self, frames, panos, stream=None, args=None) -> None:
+        a = args or self._marshal(frames, panos)
+        check(lib().stitch_batch_run(self._h, a[1], a[2], _stream(stream)))
+
+    def run_raw(self, args, stream_handle: int) -> None:
+        check(lib().stitch_batch_run(self._h, args[1], args[2], stream_handle))
+
+    def autotune(self, frames, panos, stream=None, cache_path=None):
+        a = self._marshal(frames, panos)
+        check(lib().stitch_batch_autotune(self._h, a[1], a[2], _stream(stream),
+                                          None if cache_path is None else str(cache_path).encode()))
+        return self.config()
+
+    def config(self):
+        out = (c_int32 * MAX_LEVELS)()
+        check(lib().stitch_batch_config(self._h, out))
+        return list(out)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().stitch_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

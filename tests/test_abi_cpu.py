@@ -169,3 +169,19 @@ def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(S, "_lib", None)
     with pytest.raises(ImportError):
         S.lib()
+
+
+def test_batch_create_validates_on_host():
+    lib = P.lib()
+    args, keep = _plan_args()
+    st, h = _create(*args)
+    assert st == 0
+    try:
+        out = ctypes.c_void_p()
+        arr = (ctypes.c_void_p * 1)(h.value)
+        assert lib.stitch_batch_create(1, arr, ctypes.byref(out)) == E["E_STATE"]   # not bound
+        assert lib.stitch_batch_create(0, arr, ctypes.byref(out)) == E["E_SHAPE"]
+        assert lib.stitch_batch_create(1, None, ctypes.byref(out)) == E["E_NULL"]
+        assert not out.value
+    finally:
+        lib.stitch_plan_destroy(h)
