@@ -248,6 +248,59 @@ stitch_status stitch_batch_autotune(stitch_batch* batch, const stitch_image* con
 stitch_status stitch_batch_config(const stitch_batch* batch, int32_t wg_per_cu[STITCH_MAX_LEVELS]);
 void          stitch_batch_destroy(stitch_batch* batch);
 
+/* ---- differentiable form: refining a pair's transformation -------------------- */
+
+/* The paper fixes each frame's transformation by feature matching and PROSAC (Alg. 3,
+ * Alg. 4 step 5) and stitches with it (Alg. 4 step 6).  This form makes the stitched
+ * result differentiable so that the transformation of a pair can be refined by gradient
+ * descent on it.  For two FLOAT frames (F32 CHW, 3 channels, values in [0, 1]) it
+ * evaluates, in FP64 with the forward path's FP32 source coordinates,
+ *   loss = 1/(6|Omega|) sum_{p in Omega, c} (P_c - A_c)^2 + (P_c - B_c)^2
+ * where A, B are the warped frames G_0 (Alg. 4 step 6, bilinear with zero taps outside),
+ * P is R_0 of their multi-band blend (Alg. 4 step 1 and step 6, before quantisation) and
+ * Omega is the set of canvas pixels where both frames have all four bilinear taps inside
+ * and z > 0.  Bilinear cells (floor of the source coordinates) and Omega are frozen by
+ * stitch_grad_freeze, so the loss is smooth in the maps; backward returns the exact
+ * gradient of that frozen loss.  Canvases up to 2^26 pixels; intended for pairs, not
+ * for the throughput path. */
+typedef struct stitch_grad stitch_grad;
+
+/* frame_w/frame_h: the two frames' sizes.  masks: two HOST arrays of canvas_h x
+ * canvas_w U8 seam weights summing to 255 per pixel (copied).  levels >= 1, every level's
+ * sides >= 3.  Host-only.  Errors: NULL, LEVELS, SHAPE, MASK. */
+stitch_status stitch_grad_create(const int32_t frame_w[2], const int32_t frame_h[2], const uint8_t* const* masks,
+                                 int32_t canvas_w, int32_t canvas_h, int32_t levels, stitch_grad** out);
+size_t        stitch_grad_workspace_bytes(const stitch_grad* grad);
+/* Attach caller-owned device memory (256-byte aligned, >= workspace_bytes) and build the
+ * seam-weight pyramids in it; synchronises the stream.  Errors: NULL, WORKSPACE, DEVICE. */
+stitch_status stitch_grad_bind(stitch_grad* grad, void* workspace, size_t bytes, void* stream);
+/* Freeze the bilinear cells and Omega at the source -> canvas homographies H (2 x 9,
+ * row-major); writes |Omega| to omega_count (optional).  Synchronises the stream.
+ * Errors: NULL, STATE (not bound), HOMOGRAPHY, SHAPE (|Omega| = 0), DEVICE. */
+stitch_status stitch_grad_freeze(stitch_grad* grad, const double H[18], int64_t* omega_count, void* stream);
+/* Loss at the homographies H with the frozen cells.  The frame pointers are kept for
+ * stitch_grad_backward: the frames must stay alive and unchanged until it has run.
+ * Synchronises the stream.  Errors: NULL, STATE (not frozen), SHAPE, UNSUPPORTED,
+ * HOMOGRAPHY, DEVICE. */
+stitch_status stitch_grad_forward(stitch_grad* grad, const stitch_image* frames, const double H[18], double* loss,
+                                  void* stream);
+/* Gradient of the last forward's loss: d_frames[i] (F32 CHW, 3 channels, the frame's
+ * size; overwritten) receives d loss / d frame i, d_map (host) receives d loss / d M_i
+ * (row-major, 9 per camera), M_i being the FP32 canvas -> source map adj(H_i)/adj(H_i)[2][2]
+ * the warp uses.  Synchronises the stream.  Errors: NULL, STATE, SHAPE, UNSUPPORTED,
+ * DEVICE. */
+stitch_status stitch_grad_backward(stitch_grad* grad, stitch_image* d_frames, double d_map[18], void* stream);
+void          stitch_grad_destroy(stitch_grad* grad);
+
+/* Corner parameterisation of a homography (host, FP64): H (h33 = 1) is the direct linear
+ * transform taking the frame corners (0,0), (w-1,0), (w-1,h-1), (0,h-1) to the canvas
+ * points q = (X0,Y0, X1,Y1, X2,Y2, X3,Y3).  Errors: NULL, SHAPE, HOMOGRAPHY (degenerate). */
+stitch_status stitch_corners_to_h(const double q[8], int32_t w, int32_t h, double H[9]);
+/* Chain rule from d loss / d M (M = H(q)^-1 normalised to M22 = 1, as above) to
+ * d loss / d q.  Errors: NULL, HOMOGRAPHY. */
+stitch_status stitch_map_grad_to_corners(const double q[8], int32_t w, int32_t h, const double d_map[9],
+                                         double d_q[8]);
+
 #ifdef __cplusplus
 }
 #endif

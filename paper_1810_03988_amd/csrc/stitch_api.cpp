@@ -19,9 +19,10 @@
 using namespace stitch;
 
 namespace {
-
 thread_local std::string t_err = "";
+}  // namespace
 
+namespace stitch {
 stitch_status fail(stitch_status s, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -35,6 +36,9 @@ stitch_status fail(stitch_status s, const char* fmt, ...) {
 stitch_status hip_fail(hipError_t e, const char* what) {
   return fail(STITCH_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
+}  // namespace stitch
+
+namespace {
 
 int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 int64_t ceil_div(int64_t a, int64_t b) { return -floor_div(-a, b); }
@@ -57,9 +61,11 @@ Rect intersect(const Rect& a, const Rect& b) {
 
 int elem_size(int dtype) { return dtype == STITCH_F32 ? 4 : dtype == STITCH_F16 ? 2 : 1; }
 
+}  // namespace
+
 // Canvas -> source map: adj(H) / adj(H)[2][2] in FP64, cofactors formed as a*b - c*d,
 // each entry rounded to FP32.  Returns false (with a reason) if H is unusable.
-bool hinv_spec(const double* a, float out[9], double* sign_out, const char** why) {
+bool stitch::hinv_spec(const double* a, float out[9], double* sign_out, const char** why) {
 #pragma clang fp contract(off)
   for (int i = 0; i < 9; ++i)
     if (!std::isfinite(a[i])) { *why = "homography has a non-finite entry"; return false; }
@@ -90,6 +96,8 @@ bool hinv_spec(const double* a, float out[9], double* sign_out, const char** why
   }
   return true;
 }
+
+namespace {
 
 // Canvas bounding box of the pixels the warp can make non-zero (inclusive), or false
 // when the footprint is unbounded (part of the source lies beyond the horizon).
@@ -179,8 +187,10 @@ struct Layout {
 
 int64_t row_elems(int w, int es) { return align_up((int64_t)w * es, 256) / es; }
 
+}  // namespace
+
 // Validate a caller image view.
-stitch_status check_image(const stitch_image* im, const char* name, int dtype, int layout, int channels) {
+stitch_status stitch::check_image(const stitch_image* im, const char* name, int dtype, int layout, int channels) {
   if (!im) return fail(STITCH_E_NULL, "%s is NULL", name);
   if (!im->data) return fail(STITCH_E_NULL, "%s->data is NULL", name);
   if (im->width <= 0 || im->height <= 0)
@@ -206,6 +216,8 @@ stitch_status check_image(const stitch_image* im, const char* name, int dtype, i
   }
   return STITCH_OK;
 }
+
+namespace {
 
 stitch_status check_levels_dims(int W, int H, int L, int dw[], int dh[]) {
   if (L < 1 || L > kMaxLevels) return fail(STITCH_E_LEVELS, "levels %d outside 1..%d", L, kMaxLevels);

@@ -5,6 +5,8 @@
 #include <stdint.h>
 #include <hip/hip_runtime.h>
 
+#include "stitch.h"
+
 namespace stitch {
 
 constexpr int kMaxLevels = 16;
@@ -106,5 +108,11 @@ hipError_t launch_expand_sub(bool f16, int nch, void* fine, int64_t f_row, int64
                              int cy, int cw, int ch, int canvas_w, int canvas_h, hipStream_t s);
 hipError_t launch_convert(bool f16_out, int nch, bool src_u8, const void* src, int64_t s_row, int64_t s_plane,
                           void* dst, int64_t d_row, int64_t d_plane, int w, int h, hipStream_t s);
+
+// Host helpers shared by the API files (stitch_api.cpp).
+stitch_status fail(stitch_status s, const char* fmt, ...);
+stitch_status hip_fail(hipError_t e, const char* what);
+stitch_status check_image(const stitch_image* im, const char* name, int dtype, int layout, int channels);
+bool hinv_spec(const double* H, float out[9], double* sign_out, const char** why);
 
 }  // namespace stitch

@@ -78,6 +78,18 @@ SIGNATURES = {
                                         c_char_p]),
     "stitch_batch_config": (c_int32, [c_void_p, POINTER(c_int32)]),
     "stitch_batch_destroy": (None, [c_void_p]),
+    "stitch_grad_create": (c_int32, [POINTER(c_int32), POINTER(c_int32), POINTER(POINTER(c_uint8)), c_int32,
+                                     c_int32, c_int32, POINTER(c_void_p)]),
+    "stitch_grad_workspace_bytes": (c_size_t, [c_void_p]),
+    "stitch_grad_bind": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    "stitch_grad_freeze": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64), c_void_p]),
+    "stitch_grad_forward": (c_int32, [c_void_p, POINTER(StitchImage), POINTER(c_double), POINTER(c_double),
+                                      c_void_p]),
+    "stitch_grad_backward": (c_int32, [c_void_p, POINTER(StitchImage), POINTER(c_double), c_void_p]),
+    "stitch_grad_destroy": (None, [c_void_p]),
+    "stitch_corners_to_h": (c_int32, [POINTER(c_double), c_int32, c_int32, POINTER(c_double)]),
+    "stitch_map_grad_to_corners": (c_int32, [POINTER(c_double), c_int32, c_int32, POINTER(c_double),
+                                             POINTER(c_double)]),
 }
 
 TIMING_KINDS = ["warp_level0_pass", "level_pass", "blend_level0", "blend_middle", "blend_top",
@@ -395,3 +407,148 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------------------- differentiable pair form
+def _dvec(a, n: int) -> ctypes.Array:
+    a = np.asarray(a, dtype=np.float64).reshape(n)
+    return (c_double * n)(*a.tolist())
+
+
+def corners_to_h(q, w: int, h: int) -> np.ndarray:
+    """H (3x3, h33 = 1) taking the corners of a w x h frame to the canvas points q (8,)."""
+    out = (c_double * 9)()
+    check(lib().stitch_corners_to_h(_dvec(q, 8), w, h, out))
+    return np.array(out[:], dtype=np.float64).reshape(3, 3)
+
+
+def map_grad_to_corners(q, w: int, h: int, d_map) -> np.ndarray:
+    """d loss / d q (8,) from d loss / d M (3x3) of the frame whose corners sit at q."""
+    out = (c_double * 8)()
+    check(lib().stitch_map_grad_to_corners(_dvec(q, 8), w, h, _dvec(d_map, 9), out))
+    return np.array(out[:], dtype=np.float64)
+
+
+class Grad:
+    """Loss of a stitched pair and its adjoint (float CHW frames in [0, 1]); cells and the
+    overlap Omega are frozen by freeze().  One forward/backward in flight per object."""
+
+    def __init__(self, frame_sizes, masks, canvas_w: int, canvas_h: int, levels: int, device="cuda"):
+        self.frame_sizes = [tuple(map(int, s)) for s in frame_sizes]
+        if len(self.frame_sizes) != 2 or len(masks) != 2:
+            raise ValueError("the differentiable form takes a pair of frames")
+        fw = (c_int32 * 2)(*[s[0] for s in self.frame_sizes])
+        fh = (c_int32 * 2)(*[s[1] for s in self.frame_sizes])
+        ms = [np.ascontiguousarray(np.asarray(m, dtype=np.uint8)) for m in masks]
+        for m in ms:
+            if m.shape != (canvas_h, canvas_w):
+                raise ValueError("each mask must be (canvas_h, canvas_w) uint8")
+        mptrs = (POINTER(c_uint8) * 2)(*[m.ctypes.data_as(POINTER(c_uint8)) for m in ms])
+        h = c_void_p()
+        check(lib().stitch_grad_create(fw, fh, mptrs, canvas_w, canvas_h, levels, ctypes.byref(h)))
+        self._h = h
+        self.device = torch.device(device)
+        self.ws_bytes = lib().stitch_grad_workspace_bytes(self._h)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = (self.workspace.data_ptr() + 255) // 256 * 256
+        check(lib().stitch_grad_bind(self._h, base, self.ws_bytes, _stream(None)))
+        self.omega = 0
+        self._frames = None
+        self.generation = 0
+
+    @staticmethod
+    def _h18(Hs) -> ctypes.Array:
+        return _dvec(np.stack([np.asarray(H, dtype=np.float64).reshape(9) for H in Hs]), 18)
+
+    def freeze(self, Hs, stream=None) -> int:
+        n = c_int64()
+        check(lib().stitch_grad_freeze(self._h, self._h18(Hs), ctypes.byref(n), _stream(stream)))
+        self.omega = n.value
+        return self.omega
+
+    def forward(self, frames, Hs, stream=None) -> float:
+        frames = [f.contiguous() for f in frames]
+        arr = (StitchImage * 2)(*[image_chw(f) for f in frames])
+        loss = c_double()
+        check(lib().stitch_grad_forward(self._h, arr, self._h18(Hs), ctypes.byref(loss), _stream(stream)))
+        self._frames = frames          # the library reads them again in backward
+        self.generation += 1
+        return loss.value
+
+    def backward(self, stream=None):
+        """(d loss / d frames as two (3, h, w) float32 tensors, d loss / d M as (2, 3, 3))."""
+        outs = [torch.empty((3, h, w), dtype=torch.float32, device=self.device) for w, h in self.frame_sizes]
+        arr = (StitchImage * 2)(*[image_chw(t) for t in outs])
+        dm = (c_double * 18)()
+        check(lib().stitch_grad_backward(self._h, arr, dm, _stream(stream)))
+        return outs, np.array(dm[:], dtype=np.float64).reshape(2, 3, 3)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().stitch_grad_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class StitchPairLoss(torch.autograd.Function):
+    """loss(frame_a, frame_b, q): camera A at the fixed homography H_a, camera B at the
+    homography whose frame corners land on q (8 canvas coordinates, float64 CPU tensor).
+    Gradients flow to both frames and to q."""
+
+    @staticmethod
+    def forward(ctx, frame_a, frame_b, q, grad: Grad, H_a):
+        w, h = grad.frame_sizes[1]
+        qn = q.detach().cpu().double().numpy().copy()
+        H_b = corners_to_h(qn, w, h)
+        loss = grad.forward([frame_a.detach(), frame_b.detach()], [H_a, H_b])
+        ctx.grad_obj, ctx.q, ctx.gen = grad, qn, grad.generation
+        return torch.tensor(loss, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, g_out):
+        grad = ctx.grad_obj
+        if grad.generation != ctx.gen:
+            raise RuntimeError("another forward ran on this Grad object since this loss was computed")
+        d_frames, d_map = grad.backward()
+        w, h = grad.frame_sizes[1]
+        dq = torch.from_numpy(map_grad_to_corners(ctx.q, w, h, d_map[1]))
+        gs = float(g_out)
+        return d_frames[0] * gs, d_frames[1] * gs, dq * gs, None, None
+
+
+def refine_pair(grad: Grad, frame_a, frame_b, H_a, q0, steps: int = 50, lr: float = 1e-3,
+                record=(0, 10, 25, 50), q_true=None):
+    """Adam (betas 0.9/0.999, eps 1e-8) on the normalised corners q~ = (q_x / (w/2),
+    q_y / (h/2)) of frame B.  Before every step the cells and Omega are frozen at the
+    current corners, so each gradient is the exact one of the loss piece the corners are
+    on.  Returns (q, {step: (loss, mean corner distance to q_true in px, or None)})."""
+    w, h = grad.frame_sizes[1]
+    scale = torch.tensor([w / 2.0, h / 2.0] * 4, dtype=torch.float64)
+    qt = (torch.as_tensor(np.asarray(q0, dtype=np.float64)) / scale).requires_grad_(True)
+    opt = torch.optim.Adam([qt], lr=lr, betas=(0.9, 0.999), eps=1e-8)
+    log = {}
+
+    def err(qv):
+        if q_true is None:
+            return None
+        d = (qv - np.asarray(q_true, dtype=np.float64)).reshape(4, 2)
+        return float(np.mean(np.linalg.norm(d, axis=1)))
+
+    for step in range(steps + 1):
+        q = (qt * scale)
+        qn = q.detach().numpy()
+        grad.freeze([H_a, corners_to_h(qn, w, h)])
+        opt.zero_grad()
+        loss = StitchPairLoss.apply(frame_a, frame_b, q, grad, H_a)
+        if step in record:
+            log[step] = (float(loss), err(qn))
+        if step == steps:
+            break
+        loss.backward()
+        opt.step()
+    return (qt * scale).detach().numpy(), log

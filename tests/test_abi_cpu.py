@@ -185,3 +185,63 @@ def test_batch_create_validates_on_host():
         assert not out.value
     finally:
         lib.stitch_plan_destroy(h)
+
+
+def _grad_create(masks, W, H, L, fw=(64, 64), fh=(48, 48)):
+    ms = [np.ascontiguousarray(m) for m in masks]
+    mp = (ctypes.POINTER(ctypes.c_uint8) * 2)(*[m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) for m in ms])
+    h = ctypes.c_void_p()
+    st = P.lib().stitch_grad_create((ctypes.c_int32 * 2)(*fw), (ctypes.c_int32 * 2)(*fh), mp, W, H, L,
+                                    ctypes.byref(h))
+    return st, h
+
+
+def test_grad_form_validates_on_host():
+    lib = P.lib()
+    W, H = 96, 48
+    m0 = np.zeros((H, W), np.uint8)
+    m0[:, : W // 2] = 255
+    good = [m0, 255 - m0]
+    st, h = _grad_create(good, W, H, 3)
+    assert st == 0, S.last_error()
+    try:
+        assert lib.stitch_grad_workspace_bytes(h) > 0
+        H18 = (ctypes.c_double * 18)(*np.tile(np.eye(3).ravel(), 2))
+        # freeze / forward / backward before bind
+        assert lib.stitch_grad_freeze(h, H18, None, None) == E["E_STATE"]
+        loss = ctypes.c_double()
+        assert lib.stitch_grad_forward(h, (S.StitchImage * 2)(), H18, ctypes.byref(loss), None) == E["E_STATE"]
+        assert lib.stitch_grad_backward(h, (S.StitchImage * 2)(), (ctypes.c_double * 18)(), None) == E["E_STATE"]
+        # bind with no or misaligned memory
+        assert lib.stitch_grad_bind(h, None, 1 << 30, None) == E["E_WORKSPACE"]
+        assert lib.stitch_grad_bind(h, 0x1001, 1 << 30, None) == E["E_WORKSPACE"]
+    finally:
+        lib.stitch_grad_destroy(h)
+    bad = [m0, m0]
+    assert _grad_create(bad, W, H, 3)[0] == E["E_MASK"]
+    assert _grad_create(good, W, H, 0)[0] == E["E_LEVELS"]
+    assert _grad_create(good, W, H, 6)[0] == E["E_LEVELS"]          # top level side below 3
+    assert _grad_create(good, W, H, 2, fw=(0, 64))[0] == E["E_SHAPE"]
+    assert lib.stitch_grad_create(None, None, None, W, H, 2, ctypes.byref(ctypes.c_void_p())) == E["E_NULL"]
+
+
+def test_corner_parameterisation_matches_the_oracle_chain_rule():
+    """Host FP64 code: DLT of the corners and the chain rule d loss/dM -> d loss/dq agree
+    with the oracle's Jacobians; degenerate corners are rejected."""
+    import oracle as o
+
+    rng = np.random.default_rng(7)
+    for _ in range(5):
+        w, h = int(rng.integers(64, 1400)), int(rng.integers(48, 800))
+        q = (o.corners(w, h) + rng.uniform(-0.2, 0.2, (4, 2)) * [w, h] + [900, 10]).ravel()
+        Hq = P.corners_to_h(q, w, h)
+        Ho = o.dlt_from_corners(q, w, h)
+        assert np.allclose(Hq, Ho, rtol=1e-12, atol=1e-15)
+        dm = rng.normal(size=9)
+        want = o.dlt_jacobian(q, w, h).T @ (o.canvas_map_jacobian(Ho).T @ dm)
+        got = P.map_grad_to_corners(q, w, h, dm)
+        assert np.linalg.norm(got - want) <= 1e-10 * np.linalg.norm(want)
+    flat = np.array([0.0, 0, 10, 0, 20, 0, 30, 0])       # all four corners on one line
+    with pytest.raises(P.StitchError) as e:
+        P.corners_to_h(flat, 64, 48)
+    assert e.value.status == E["E_HOMOGRAPHY"]
