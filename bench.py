@@ -45,7 +45,207 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the step without per-launch events (roofline then omitted)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after the forms, run a plain float32 copy kernel (y = -x) over this many MiB, "
+                         "three times: the reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--precision", action="store_true",
+                    help="instead of timing: error of the FP32- and FP16-storage paths against the FP64 "
+                         "oracle per level (on windows through their dependency cones) and on the uint8 "
+                         "output, and FP16 against FP32 on the whole canvas; prints one JSON line")
+    ap.add_argument("--windows", type=int, default=8, help="oracle windows for --precision")
+    ap.add_argument("--rocprof-summary", metavar="DIR",
+                    help="summarise the rocprofv3 CSV output under DIR (kernel stats and counters per "
+                         "kernel) and exit; needs no GPU")
     return ap.parse_args()
+
+
+# rocprofv3 kernel names of the path -> the kinds this script reports
+KERNEL_KINDS = {
+    "k_pyr<float, true, true>": "warp_level0_pass (f32)", "k_pyr<float, true, false>": "level_pass (f32)",
+    "k_pyr<_Float16, true, true>": "warp_level0_pass (f16)", "k_pyr<_Float16, true, false>": "level_pass (f16)",
+    "k_blend<float, true, true>": "blend_level0 (f32)", "k_blend<float, false, true>": "blend_middle/top (f32)",
+    "k_blend<_Float16, true, true>": "blend_level0 (f16)", "k_blend<_Float16, false, true>": "blend_middle/top (f16)",
+    "k_blend<float, true, false>": "blend_level0, batched (f32)",
+    "k_blend<float, false, false>": "blend_middle/top, batched (f32)",
+}
+COPY_KERNEL_HINT = "neg"
+
+
+def _short_kernel(name: str) -> str:
+    import re
+    m = re.search(r"(k_[a-z_]+)<([^()]*)>", name)
+    if m:
+        return m.group(1) + "<" + m.group(2).replace("(anonymous namespace)::", "") + ">"
+    return name.split("(")[0][-90:]
+
+
+def rocprof_summary(root: str) -> None:
+    """Per-kernel figures from rocprofv3 CSV files: average durations from the kernel
+    trace, and per-dispatch averages of every collected counter.  FETCH_SIZE / WRITE_SIZE
+    (KiB per dispatch) are also scaled by what they read for the calibration copy kernel
+    (y = -x over a known number of bytes), when it is in the same run."""
+    import csv
+    import glob
+    from collections import defaultdict
+    files = sorted(glob.glob(os.path.join(root, "**", "*.csv"), recursive=True))
+    for f in files:
+        if f.endswith("kernel_trace.csv"):
+            dur = defaultdict(list)
+            with open(f) as fh:
+                for row in csv.DictReader(fh):
+                    dur[_short_kernel(row["Kernel_Name"])].append(
+                        (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e3)
+            print(f"## kernel trace ({os.path.relpath(f, root)}): average duration per kernel")
+            print(f"{'kernel':44s} {'kind':34s} {'calls':>6s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s}")
+            for k, v in sorted(dur.items(), key=lambda kv: -sum(kv[1])):
+                print(f"{k:44s} {KERNEL_KINDS.get(k, ''):34s} {len(v):6d} {np.mean(v):9.2f} {np.min(v):9.2f} "
+                      f"{np.max(v):9.2f}")
+        elif f.endswith("counter_collection.csv"):
+            agg = defaultdict(lambda: defaultdict(float))
+            disp = defaultdict(set)
+            with open(f) as fh:
+                for row in csv.DictReader(fh):
+                    k = _short_kernel(row["Kernel_Name"])
+                    agg[k][row["Counter_Name"]] += float(row["Counter_Value"])
+                    disp[k].add(row["Dispatch_Id"])
+            print(f"## counters ({os.path.relpath(f, root)}): average per dispatch")
+            copy = [k for k in agg if COPY_KERNEL_HINT in k]
+            for k, d in sorted(agg.items()):
+                n = max(1, len(disp[k]))
+                print(f"{k:44s} {KERNEL_KINDS.get(k, ''):34s} n={n:5d} " +
+                      " ".join(f"{c}={v / n:.6g}" for c, v in sorted(d.items())))
+            if copy:
+                k = copy[0]
+                n = max(1, len(disp[k]))
+                print(f"# calibration kernel: {k} ({n} dispatches)")
+                for c, v in sorted(agg[k].items()):
+                    print(f"#   {c} reads {v / n:.6g} KiB per dispatch")
+        elif f.endswith("kernel_stats.csv"):
+            print(f"## kernel stats ({os.path.relpath(f, root)})")
+            with open(f) as fh:
+                for row in csv.DictReader(fh):
+                    print(f"{_short_kernel(row['Name']):44s} calls={row['Calls']:>6s} "
+                          f"avg_ns={float(row['AverageNs']):12.1f} total_ns={float(row['TotalDurationNs']):14.1f} "
+                          f"pct={float(row['Percentage']):6.2f}")
+
+
+def _window_list(rig, n, win):
+    """Level-0 window origins: seam columns, canvas corners and edges, interior points."""
+    W, H = rig.canvas_w, rig.canvas_h
+    cand = [(H // 2 - win // 2, x - win // 2) for x in rig.seams]
+    cand += [(0, 0), (H - win, W - win), (0, W - win), (H - win, 0), (H // 3, W // 5), (2 * H // 3, 3 * W // 5),
+             (H // 2, W // 2 + 7), (5, W // 3)]
+    out = []
+    for y, x in cand:
+        y, x = min(max(y, 0), H - win), min(max(x, 0), W - win)
+        if (y, x) not in out:
+            out.append((y, x))
+    return out[:n]
+
+
+def precision_report(rig, nwin: int = 8, win: int = 32, full: bool = False) -> dict:
+    """Max / mean |delta| of R_k and of every stored band L_k against the FP64 oracle, per
+    level, for FP32 and FP16 storage; uint8 output |delta| histograms against the oracle
+    (on the windows) and of FP16 against FP32 (whole canvas)."""
+    import oracle
+    import paper_1810_03988_amd as P
+    import workloads as wl
+    frames_d = wl.render_rig_frames(rig, frame=0, device="cuda")
+    frames = [f.cpu().numpy() for f in frames_d]
+    masks = rig.masks()
+    so = oracle.StitchOracle(frames, rig.H, masks, rig.canvas_w, rig.canvas_h, rig.levels)
+    L = rig.levels
+    wins = [(0, 0)] if full else _window_list(rig, nwin, win)
+    wsz = (rig.canvas_h, rig.canvas_w) if full else (win, win)
+
+    def level_window(k, y, x):
+        hk, wk = so.dims[k]
+        r0, c0 = y >> k, x >> k
+        r1 = min(hk, -(-(y + wsz[0]) // (1 << k)))
+        c1 = min(wk, -(-(x + wsz[1]) // (1 << k)))
+        return np.arange(r0, r1), np.arange(c0, c1)
+
+    # oracle values on the windows, once
+    want_R = [[None] * len(wins) for _ in range(L)]
+    want_L = [[[None] * len(wins) for _ in range(L)] for _ in range(rig.n)]
+    want_u8 = []
+    plan32 = P.Plan(rig.frame_sizes, rig.H, masks, rig.canvas_w, rig.canvas_h, L, storage="f32", keep_r0=True)
+    bands = [[plan32.regions(i, k)[1] for k in range(L)] for i in range(rig.n)]
+    t = time.perf_counter()
+    for j, (y, x) in enumerate(wins):
+        for k in range(L):
+            rows, cols = level_window(k, y, x)
+            want_R[k][j] = so.R(k, rows, cols)
+            for i in range(rig.n):
+                bx, by, bw, bh = bands[i][k]
+                rr = rows[(rows >= by) & (rows < by + bh)]
+                cc = cols[(cols >= bx) & (cols < bx + bw)]
+                if len(rr) and len(cc):
+                    want_L[i][k][j] = (rr, cc, so.Lap(i, k, rr, cc))
+        want_u8.append(oracle.quantise(want_R[0][j]))
+        so.clear()
+    oracle_s = time.perf_counter() - t
+
+    def hist(d):
+        v, c = np.unique(np.abs(d.astype(np.int64)), return_counts=True)
+        return {int(a): int(b) for a, b in zip(v, c)}
+
+    report = {"workload": workload_name(rig, 1), "windows": [list(w) for w in wins], "window": list(wsz),
+              "oracle_seconds": round(oracle_s, 1)}
+    panos = {}
+    for storage in ("f32", "f16"):
+        plan = plan32 if storage == "f32" else P.Plan(rig.frame_sizes, rig.H, masks, rig.canvas_w, rig.canvas_h, L,
+                                                      storage="f16", keep_r0=True)
+        pano = plan.frame(frames_d)
+        torch.cuda.synchronize()
+        panos[storage] = pano.cpu().numpy()
+        levels = []
+        for k in range(L):
+            r, _ = plan.view("r", 0, k)
+            if r is None:
+                continue
+            r = r.float().cpu().numpy()
+            dR = np.concatenate([np.abs(r[:, rows[:, None], cols[None, :]] - want_R[k][j]).ravel()
+                                 for j, (rows, cols) in enumerate(level_window(k, y, x) for y, x in wins)])
+            dL = []
+            for i in range(rig.n):
+                lap, (ox, oy) = plan.view("lap", i, k)
+                if lap is None:
+                    continue
+                lap = lap.float().cpu().numpy()
+                for j in range(len(wins)):
+                    if want_L[i][k][j] is None:
+                        continue
+                    rr, cc, wv = want_L[i][k][j]
+                    dL.append(np.abs(lap[:, rr[:, None] - oy, cc[None, :] - ox] - wv).ravel())
+            dL = np.concatenate(dL) if dL else np.zeros(1)
+            levels.append({"k": k, "R_max": float(dR.max()), "R_mean": float(dR.mean()),
+                           "L_max": float(dL.max()), "L_mean": float(dL.mean()), "R_samples": int(dR.size),
+                           "L_samples": int(dL.size)})
+        got_u8 = np.concatenate([panos[storage][y:y + wsz[0], x:x + wsz[1]].transpose(2, 0, 1).ravel()
+                                 for y, x in wins])
+        want = np.concatenate([w_.ravel() for w_ in want_u8])
+        h = hist(got_u8.astype(np.int64) - want)
+        report[storage] = {"levels": levels, "u8_vs_oracle_hist": h,
+                           "u8_vs_oracle_frac_off": float(1.0 - h.get(0, 0) / want.size)}
+        del plan
+    h = hist(panos["f16"].astype(np.int64) - panos["f32"])
+    report["f16_vs_f32_u8_hist_full_canvas"] = h
+    report["f16_vs_f32_u8_frac_off"] = float(1.0 - h.get(0, 0) / panos["f32"].size)
+    return report
+
+
+def copy_calibration(mib: int) -> None:
+    """A plain streaming kernel of known traffic: y = -x over mib MiB of float32, three
+    dispatches (each reads and writes mib MiB)."""
+    n = mib * (1 << 20) // 4
+    x = torch.rand(n, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    print(f"# copy calibration: 3 x y = -x over {mib} MiB float32", file=sys.stderr, flush=True)
 
 
 def rig_for(name):
@@ -120,6 +320,24 @@ def algorithmic_bytes(plan, rig, s, keep_r0=False):
         if mids:
             out["blend_middle"] = mids
     return out
+
+
+def profiled_traffic(config: str, storage: str, kind: str):
+    """HBM bytes per launch of one kernel kind from the committed rocprofv3 counter summary
+    of this workload (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration), or
+    None when there is none or the kernel source has changed since it was taken."""
+    import hashlib
+    import re
+    f = ROOT / "profiles" / f"hbm_traffic_{config}_{storage}.txt"
+    if not f.exists():
+        return None
+    text = f.read_text()
+    m = re.search(r"kernels\.hip sha256: ([0-9a-f]{64})", text)
+    src = ROOT / "paper_1810_03988_amd" / "csrc" / "kernels.hip"
+    if not m or hashlib.sha256(src.read_bytes()).hexdigest() != m.group(1):
+        return None
+    m = re.search(rf"^traffic {re.escape(kind)}\s+.*?\s(\d+)$", text, re.M)
+    return int(m.group(1)) if m else None
 
 
 def make_frames(rig, nframes, device):
@@ -225,6 +443,9 @@ def cpu_baseline(rig, frames0):
 
 def main():
     a = parse()
+    if a.rocprof_summary:
+        rocprof_summary(a.rocprof_summary)
+        return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(f"bench.py: this build measures one GPU; --gpus {a.gpus} is not supported "
               "(independent frames and jobs would shard round-robin across GPUs with no exchange)",
@@ -235,6 +456,9 @@ def main():
         sys.exit(2)
     torch.cuda.set_device(0)
     rig = rig_for(a.config)
+    if a.precision:
+        print(json.dumps(precision_report(rig, a.windows, full=a.config == "c1")), flush=True)
+        return
     t = time.perf_counter()
     frames = make_frames(rig, a.frames, "cuda")
     torch.cuda.synchronize()
@@ -254,7 +478,9 @@ def main():
         dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
         kd = kernels[dom]
         roof = {"bound": "hbm", "achieved": kd["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom}
+                "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                "traffic": profiled_traffic(a.config, a.storage, dom), "kernel": dom,
+                "alg_bytes": kd["alg_bytes_per_launch"], "avg_us": kd["avg_us"]}
     forms = {f"plain_{a.storage}": {"Mpx_s": round(value, 1), "ms_per_step": round(ms, 4),
                                     "ms_per_step_without_launch_events": round(ms_plain, 4)}}
     for form in [f for f in a.forms.split(",") if f and f != "none" and f != a.storage]:
@@ -276,6 +502,8 @@ def main():
         forms[f"plain_{form}"] = {"Mpx_s": round(fval, 1), "ms_per_step": round(fms, 4),
                                   "kernels": fk}
         print(f"# {form}: {fms:.3f} ms/step, {fval:.0f} Mpx/s", file=sys.stderr, flush=True)
+    if a.copy_calibration_mib > 0:
+        copy_calibration(a.copy_calibration_mib)
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(rig, frames[0])
