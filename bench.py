@@ -38,10 +38,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--frames", type=int, default=30, help="frames per step (the sequence length)")
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c4"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"],
+                    help="c3: 64 jobs of 2-6 cameras, one frame each, batched against one by one")
+    ap.add_argument("--jobs", type=int, default=64, help="jobs of the c3 batch")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16"])
-    ap.add_argument("--forms", default="f16,batched_f32,batched_f16",
-                    help="extra forms timed after the headline (comma list or 'none')")
+    ap.add_argument("--form", default="batched", choices=["batched", "plain"],
+                    help="the headline form: all frames of the step as one batch, or one stitch_frame per frame")
+    ap.add_argument("--forms", default="batched_graph_f16,plain_f32,plain_f16",
+                    help="extra forms timed after the headline (comma list of batched_graph_<s> / plain_<s>, "
+                         "or 'none')")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the step without per-launch events (roofline then omitted)")
@@ -182,7 +187,7 @@ def precision_report(rig, nwin: int = 8, win: int = 32, full: bool = False) -> d
                 cc = cols[(cols >= bx) & (cols < bx + bw)]
                 if len(rr) and len(cc):
                     want_L[i][k][j] = (rr, cc, so.Lap(i, k, rr, cc))
-        want_u8.append(oracle.quantise(want_R[0][j]))
+        want_u8.append(oracle.quantise(want_R[0][j]))          # HWC uint8
         so.clear()
     oracle_s = time.perf_counter() - t
 
@@ -222,8 +227,7 @@ def precision_report(rig, nwin: int = 8, win: int = 32, full: bool = False) -> d
             levels.append({"k": k, "R_max": float(dR.max()), "R_mean": float(dR.mean()),
                            "L_max": float(dL.max()), "L_mean": float(dL.mean()), "R_samples": int(dR.size),
                            "L_samples": int(dL.size)})
-        got_u8 = np.concatenate([panos[storage][y:y + wsz[0], x:x + wsz[1]].transpose(2, 0, 1).ravel()
-                                 for y, x in wins])
+        got_u8 = np.concatenate([panos[storage][y:y + wsz[0], x:x + wsz[1]].ravel() for y, x in wins])   # HWC
         want = np.concatenate([w_.ravel() for w_ in want_u8])
         h = hist(got_u8.astype(np.int64) - want)
         report[storage] = {"levels": levels, "u8_vs_oracle_hist": h,
@@ -273,62 +277,68 @@ def source_pixels_in(rig, i, roi):
     return n
 
 
-def algorithmic_bytes(plan, rig, s, keep_r0=False):
-    """Compulsory HBM bytes per launch of each kernel kind, from the plan's stored regions
-    (G and weight levels on each camera's ROI, Laplacian bands on the seam-weight support,
-    R levels on the whole canvas), s = bytes per stored sample."""
+def phase_bytes(plan, rig, s, keep_r0=False):
+    """Compulsory HBM bytes of each launch of one frame, from the plan's stored regions (G
+    and weight levels on each camera's ROI, Laplacian bands on the seam-weight support, R
+    levels on the whole canvas), s = bytes per stored sample.  Keys: "pyr0" (warp + level-0
+    pass), "pyr<k>" (pass from level k), "blend<k>" (blend of level k)."""
     L, n = rig.levels, rig.n
     area = lambda r: r[2] * r[3]
     reg = [[plan.regions(i, k) for k in range(L)] for i in range(n)]
     dims = [((rig.canvas_h + (1 << k) - 1) >> k, (rig.canvas_w + (1 << k) - 1) >> k) for k in range(L)]
     C = [a * b for a, b in dims]
     out = {}
-    if L > 1:
-        b0 = 0
+    if L < 2:
+        return out
+    b0 = 0
+    for i in range(n):
+        roi0, band0 = reg[i][0]
+        roi1, _ = reg[i][1]
+        if area(roi0) == 0:
+            continue
+        b0 += 3 * source_pixels_in(rig, i, roi0) + area(roi0)          # frame + u8 weights
+        b0 += 3 * s * area(band0) + 4 * s * area(roi1)                   # L_0; G_1 and Gm_1
+    out["pyr0"] = b0
+    for k in range(1, L - 1):
+        b = 0
         for i in range(n):
-            roi0, band0 = reg[i][0]
-            roi1, _ = reg[i][1]
-            if area(roi0) == 0:
-                continue
-            b0 += 3 * source_pixels_in(rig, i, roi0) + area(roi0)          # frame + u8 weights
-            b0 += 3 * s * area(band0) + 4 * s * area(roi1)                   # L_0; G_1 and Gm_1
-        out["warp_level0_pass"] = [b0]
-        lv = []
-        for k in range(1, L - 1):
-            b = 0
-            for i in range(n):
-                roi, band = reg[i][k]
-                roi1, _ = reg[i][k + 1]
-                b += 4 * s * area(roi) + 3 * s * area(band) + 4 * s * area(roi1)
-            lv.append(b)
-        if lv:
-            out["level_pass"] = lv
-        mids = []
-        for k in range(L - 1, -1, -1):
-            bands = sum(area(reg[i][k][1]) for i in range(n))
-            wbytes = 1 if k == 0 else s
-            b = (3 * s + wbytes) * bands
-            if k + 1 < L:
-                b += 3 * s * C[k + 1]
-            if k == 0:
-                b += 3 * C[0] + (3 * s * C[0] if keep_r0 else 0)
-                out["blend_level0"] = [b]
-            elif k == L - 1:
-                out["blend_top"] = [b + 3 * s * C[k]]
-            else:
-                mids.append(b + 3 * s * C[k])
-        if mids:
-            out["blend_middle"] = mids
+            roi, band = reg[i][k]
+            roi1, _ = reg[i][k + 1]
+            b += 4 * s * area(roi) + 3 * s * area(band) + 4 * s * area(roi1)
+        out[f"pyr{k}"] = b
+    for k in range(L - 1, -1, -1):
+        bands = sum(area(reg[i][k][1]) for i in range(n))
+        b = (3 * s + (1 if k == 0 else s)) * bands
+        if k + 1 < L:
+            b += 3 * s * C[k + 1]
+        b += 3 * C[0] + (3 * s * C[0] if keep_r0 else 0) if k == 0 else 3 * s * C[k]
+        out[f"blend{k}"] = b
     return out
 
 
-def profiled_traffic(config: str, storage: str, kind: str):
+# launch kinds of the plain form's event timing -> the phases each covers
+PLAIN_KINDS = {"warp_level0_pass": lambda L: ["pyr0"],
+               "level_pass": lambda L: [f"pyr{k}" for k in range(1, L - 1)],
+               "blend_level0": lambda L: ["blend0"],
+               "blend_middle": lambda L: [f"blend{k}" for k in range(L - 2, 0, -1)],
+               "blend_top": lambda L: [f"blend{L - 1}"]}
+
+
+def phase_name(key):
+    """Batch timing kind -> readable phase name."""
+    what, k = key
+    if what == "pyr":
+        return "warp_level0_pass" if k == 0 else f"level_pass_{k}"
+    return f"blend_level{k}"
+
+
+def profiled_traffic(config: str, form: str, storage: str, kind: str):
     """HBM bytes per launch of one kernel kind from the committed rocprofv3 counter summary
     of this workload (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration), or
     None when there is none or the kernel source has changed since it was taken."""
     import hashlib
     import re
-    f = ROOT / "profiles" / f"hbm_traffic_{config}_{storage}.txt"
+    f = ROOT / "profiles" / f"hbm_traffic_{config}_{form}_{storage}.txt"
     if not f.exists():
         return None
     text = f.read_text()
@@ -377,9 +387,10 @@ def time_form(rig, frames, storage, steps, warmup, kernel_events=True):
     return plan, ms, timing, panos
 
 
-def time_batched(rig, frames, storage, steps, warmup, tune_cache=None):
-    """All frames of the sequence as jobs of one batch (one plan per job), captured once
-    into a HIP graph and replayed per step."""
+def time_batched(rig, frames, storage, steps, warmup, tune_cache=None, kernel_events=True):
+    """All frames of the sequence as jobs of one batch (one plan per job).  Timed twice on
+    one stream: with per-launch HIP events (launches issued directly, an event after each)
+    and as HIP graph replays (one capture, one replay per step)."""
     import paper_1810_03988_amd as P
     dev = frames[0][0].device
     plans = [P.Plan(rig.frame_sizes, rig.H, rig.masks(), rig.canvas_w, rig.canvas_h, rig.levels, storage=storage,
@@ -387,38 +398,115 @@ def time_batched(rig, frames, storage, steps, warmup, tune_cache=None):
     panos = [torch.empty((rig.canvas_h, rig.canvas_w, 3), dtype=torch.uint8, device=dev) for _ in frames]
     batch = P.Batch(plans, device=dev)
     stream = torch.cuda.Stream()
+    res = {}
     with torch.cuda.stream(stream):
         cfg = batch.autotune(frames, panos, stream=stream, cache_path=tune_cache)
         args = batch.args(frames, panos)
         sh = stream.cuda_stream
-        for _ in range(warmup):
-            batch.run_raw(args, sh)
-        stream.synchronize()
-        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0.record(stream)
-        for _ in range(steps):
-            batch.run_raw(args, sh)
-        t1.record(stream)
-        stream.synchronize()
-    ms = t0.elapsed_time(t1) / steps
-    return ms, cfg, batch, panos
+        for mode in (["events"] if kernel_events else []) + ["graph"]:
+            batch.set_timing(mode == "events")
+            for _ in range(warmup):
+                batch.run_raw(args, sh)
+            stream.synchronize()
+            batch.set_timing(mode == "events")    # clears the warm-up's events
+            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0.record(stream)
+            for _ in range(steps):
+                batch.run_raw(args, sh)
+            t1.record(stream)
+            stream.synchronize()
+            res[mode] = (t0.elapsed_time(t1) / steps, batch.read_timing() if mode == "events" else {})
+        batch.set_timing(False)
+    return res, cfg, plans[0], batch, panos
+
+
+def run_c3(a):
+    """The batching workload: njobs stitch jobs of uneven camera counts, resolutions and
+    level counts, one frame each; the same plans stitched one by one (one stitch_frame
+    per job, eager launches) and as one batch (one HIP graph replay per step)."""
+    import paper_1810_03988_amd as P
+    import workloads as wl
+    rigs = wl.rig_c3_jobs(a.jobs)
+    t = time.perf_counter()
+    frames = [wl.render_rig_frames(r, 0, "cuda") for r in rigs]
+    plans = [P.Plan(r.frame_sizes, r.H, r.masks(), r.canvas_w, r.canvas_h, r.levels, storage=a.storage)
+             for r in rigs]
+    panos = [torch.empty((r.canvas_h, r.canvas_w, 3), dtype=torch.uint8, device="cuda") for r in rigs]
+    torch.cuda.synchronize()
+    print(f"# {len(rigs)} jobs planned and rendered in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    px = sum(r.canvas_pixels() for r in rigs)
+    stream = torch.cuda.Stream()
+    sh = stream.cuda_stream
+    args = [p.frame_args(f, o) for p, f, o in zip(plans, frames, panos)]
+
+    def one_by_one():
+        for p, ar in zip(plans, args):
+            p.frame_raw(ar, sh)
+
+    batch = P.Batch(plans)
+    with torch.cuda.stream(stream):
+        cfg = batch.autotune(frames, panos, stream=stream, cache_path=os.environ.get("STITCH_TUNE_CACHE"))
+        bargs = batch.args(frames, panos)
+        res = {}
+        for name, fn in (("one_by_one", one_by_one), ("batched", lambda: batch.run_raw(bargs, sh))):
+            for _ in range(a.warmup):
+                fn()
+            stream.synchronize()
+            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0.record(stream)
+            for _ in range(a.steps):
+                fn()
+            t1.record(stream)
+            stream.synchronize()
+            ms = t0.elapsed_time(t1) / a.steps
+            res[name] = {"Mpx_s": round(px / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms, 4)}
+            print(f"# c3 {name}: {ms:.3f} ms/step, {res[name]['Mpx_s']:.0f} Mpx/s", file=sys.stderr, flush=True)
+    cams = [r.n for r in rigs]
+    line = {
+        "metric": METRIC, "value": res["batched"]["Mpx_s"], "unit": "Mpx/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": res["batched"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if a.storage == "f32" else "f32 (f16 storage)",
+        "data": "synthetic",
+        "config": {"workload": f"C3: {len(rigs)} stitch jobs, {min(cams)}-{max(cams)} cameras of 640x480 to "
+                   f"3840x2160, {px / 1e6:.1f} Mpx of canvas per step, one frame per job",
+                   "form": "batched: one launch per level over all jobs, one HIP graph replay per step"},
+        "forms": res, "speedup_batched_vs_one_by_one": round(res["one_by_one"]["ms_per_step"] /
+                                                            res["batched"]["ms_per_step"], 3),
+        "wg_per_cu_by_level": cfg, "device": torch.cuda.get_device_name(0),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def _row(tot_ms, launches, steps, nbytes):
+    avg_s = tot_ms / launches / 1e3
+    gbs = nbytes / avg_s / 1e9
+    return {"launches_per_step": launches // steps, "avg_us": round(avg_s * 1e6, 3),
+            "alg_bytes_per_launch": int(nbytes), "achieved_GBs": round(gbs, 1),
+            "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "ms_per_step": round(tot_ms / steps, 4)}
 
 
 def kernel_table(plan, rig, timing, steps, s):
-    alg = algorithmic_bytes(plan, rig, s)
+    """Plain form: per launch kind, average launch time and bytes (the kind's phases of a
+    frame averaged the same way as its launches)."""
+    ph = phase_bytes(plan, rig, s)
     table = {}
     for kind, (tot_ms, launches) in timing.items():
-        per_launch = alg.get(kind)
-        if not per_launch:
+        keys = PLAIN_KINDS.get(kind, lambda L: [])(rig.levels)
+        if not keys:
             continue
-        # every frame launches each level once: average the per-launch bytes the same way
-        avg_bytes = float(np.mean(per_launch))
-        avg_s = tot_ms / launches / 1e3
-        gbs = avg_bytes / avg_s / 1e9
-        table[kind] = {"launches_per_step": launches // steps, "avg_us": round(avg_s * 1e6, 3),
-                       "alg_bytes_per_launch": int(avg_bytes), "achieved_GBs": round(gbs, 1),
-                       "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
-                       "ms_per_step": round(tot_ms / steps, 4)}
+        table[kind] = _row(tot_ms, launches, steps, float(np.mean([ph[k] for k in keys])))
+    return table
+
+
+def batch_kernel_table(plan, rig, timing, steps, s, njobs):
+    """Batched form: one launch per phase per step covering all njobs frames."""
+    ph = phase_bytes(plan, rig, s)
+    table = {}
+    for key, (tot_ms, launches) in sorted(timing.items()):
+        name = phase_name(key)
+        pk = f"{key[0]}{key[1]}"
+        if pk in ph:
+            table[name] = _row(tot_ms, launches, steps, njobs * ph[pk])
     return table
 
 
@@ -455,6 +543,9 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if a.config == "c3":
+        run_c3(a)
+        return
     rig = rig_for(a.config)
     if a.precision:
         print(json.dumps(precision_report(rig, a.windows, full=a.config == "c1")), flush=True)
@@ -464,44 +555,61 @@ def main():
     torch.cuda.synchronize()
     print(f"# generated {a.frames} x {rig.n} frames in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
     s = 2 if a.storage == "f16" else 4
-    plan, ms, timing, _ = time_form(rig, frames, a.storage, a.steps, a.warmup, not a.no_kernel_events)
-    ms_plain = time_form(rig, frames, a.storage, a.steps, a.warmup, False)[1] if timing else ms
     px_per_step = rig.canvas_w * rig.canvas_h * a.frames
+    mpx = lambda ms_: round(px_per_step / (ms_ / 1e3) / 1e6, 1)
+    tune = os.environ.get("STITCH_TUNE_CACHE")
+    forms = {}
+    events = not a.no_kernel_events
+    if a.form == "batched":
+        res, cfg, plan0, _b, _p = time_batched(rig, frames, a.storage, a.steps, a.warmup, tune, events)
+        ms = res["events"][0] if events else res["graph"][0]
+        kernels = batch_kernel_table(plan0, rig, res["events"][1], a.steps, s, a.frames) if events else {}
+        forms[f"batched_{a.storage}"] = {"Mpx_s": mpx(ms), "ms_per_step": round(ms, 4),
+                                         "how": "launches issued directly, an event after each"}
+        forms[f"batched_graph_{a.storage}"] = {"Mpx_s": mpx(res["graph"][0]),
+                                               "ms_per_step": round(res["graph"][0], 4),
+                                               "how": "one HIP graph replay per step"}
+        form_desc = (f"batched, {a.storage} storage: the {a.frames} frames as {a.frames} jobs of one batch, one "
+                     f"launch per pyramid level and per blend level (tuned workgroups/CU {cfg[:rig.levels - 1]})")
+        del _b, _p
+    else:
+        plan0, ms, timing, _ = time_form(rig, frames, a.storage, a.steps, a.warmup, events)
+        kernels = kernel_table(plan0, rig, timing, a.steps, s) if events else {}
+        forms[f"plain_{a.storage}"] = {"Mpx_s": mpx(ms), "ms_per_step": round(ms, 4)}
+        form_desc = f"plain, {a.storage} storage, one stitch_frame per frame"
     value = px_per_step / (ms / 1e3) / 1e6
-    print(f"# {a.storage}: {ms:.3f} ms/step, {value:.0f} Mpx/s", file=sys.stderr, flush=True)
-    kernels = kernel_table(plan, rig, timing, a.steps, s) if timing else {}
+    print(f"# {a.form} {a.storage}: {ms:.3f} ms/step, {value:.0f} Mpx/s", file=sys.stderr, flush=True)
     for k, v in kernels.items():
         print(f"#   {k:18s} {v['avg_us']:9.2f} us/launch x{v['launches_per_step']:4d}  "
-              f"{v['alg_bytes_per_launch'] / 1e6:8.2f} MB  {v['achieved_GBs']:8.1f} GB/s", file=sys.stderr, flush=True)
+              f"{v['alg_bytes_per_launch'] / 1e6:9.2f} MB  {v['achieved_GBs']:8.1f} GB/s", file=sys.stderr, flush=True)
     roof = None
     if kernels:
         dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
         kd = kernels[dom]
         roof = {"bound": "hbm", "achieved": kd["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4),
-                "traffic": profiled_traffic(a.config, a.storage, dom), "kernel": dom,
+                "traffic": profiled_traffic(a.config, a.form, a.storage, dom), "kernel": dom,
                 "alg_bytes": kd["alg_bytes_per_launch"], "avg_us": kd["avg_us"]}
-    forms = {f"plain_{a.storage}": {"Mpx_s": round(value, 1), "ms_per_step": round(ms, 4),
-                                    "ms_per_step_without_launch_events": round(ms_plain, 4)}}
-    for form in [f for f in a.forms.split(",") if f and f != "none" and f != a.storage]:
-        if form.startswith("batched_"):
-            st = form.split("_", 1)[1]
-            bms, cfg, _b, _p = time_batched(rig, frames, st, a.steps, a.warmup,
-                                            tune_cache=os.environ.get("STITCH_TUNE_CACHE"))
-            bval = px_per_step / (bms / 1e3) / 1e6
-            forms[form] = {"Mpx_s": round(bval, 1), "ms_per_step": round(bms, 4),
-                           "wg_per_cu_by_level": cfg[:rig.levels - 1],
-                           "how": f"{a.frames} jobs (one per frame) in one batch, one HIP graph replay per step"}
-            print(f"# {form}: {bms:.3f} ms/step, {bval:.0f} Mpx/s (tuned wg/CU {cfg[:rig.levels - 1]})",
-                  file=sys.stderr, flush=True)
-            del _b, _p
+    for form in [f for f in a.forms.split(",") if f and f != "none"]:
+        kind, st = form.rsplit("_", 1)
+        if (kind == a.form and st == a.storage) or (kind == "batched_graph" and a.form == "batched" and
+                                                    st == a.storage):
             continue
-        fplan, fms, ftim, _panos = time_form(rig, frames, form, a.steps, a.warmup, True)
-        fval = px_per_step / (fms / 1e3) / 1e6
-        fk = kernel_table(fplan, rig, ftim, a.steps, 2 if form == "f16" else 4)
-        forms[f"plain_{form}"] = {"Mpx_s": round(fval, 1), "ms_per_step": round(fms, 4),
-                                  "kernels": fk}
-        print(f"# {form}: {fms:.3f} ms/step, {fval:.0f} Mpx/s", file=sys.stderr, flush=True)
+        if kind in ("batched", "batched_graph"):
+            res, cfg, _pl, _b, _p = time_batched(rig, frames, st, a.steps, a.warmup, tune, False)
+            forms[f"batched_graph_{st}"] = {"Mpx_s": mpx(res["graph"][0]), "ms_per_step": round(res["graph"][0], 4),
+                                            "how": "one HIP graph replay per step"}
+            del _b, _p, _pl
+        else:
+            fplan, fms, ftim, _panos = time_form(rig, frames, st, a.steps, a.warmup, True)
+            fms_plain = time_form(rig, frames, st, a.steps, a.warmup, False)[1]
+            forms[f"plain_{st}"] = {"Mpx_s": mpx(fms), "ms_per_step": round(fms, 4),
+                                    "ms_per_step_without_launch_events": round(fms_plain, 4),
+                                    "Mpx_s_without_launch_events": mpx(fms_plain),
+                                    "kernels": kernel_table(fplan, rig, ftim, a.steps, 2 if st == "f16" else 4)}
+            del fplan, _panos
+        print(f"# {form}: {json.dumps({k: v for k, v in list(forms.items())[-1][1].items() if k != 'kernels'})}",
+              file=sys.stderr, flush=True)
     if a.copy_calibration_mib > 0:
         copy_calibration(a.copy_calibration_mib)
     cpu = None
@@ -512,8 +620,8 @@ def main():
         "metric": METRIC, "value": round(value, 1), "unit": "Mpx/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if a.storage == "f32" else "f32 (f16 storage)", "data": "synthetic",
-        "config": {"workload": workload_name(rig, a.frames), "form": f"plain, {a.storage} storage, one "
-                   "stitch_frame per frame", "frames_per_step": a.frames, "cameras": rig.n,
+        "config": {"workload": workload_name(rig, a.frames), "form": form_desc, "frames_per_step": a.frames,
+                   "cameras": rig.n,
                    "canvas": [rig.canvas_w, rig.canvas_h], "levels": rig.levels},
         "roofline": roof, "cpu_baseline": cpu, "kernels": kernels, "forms": forms,
         "device": torch.cuda.get_device_name(0),

@@ -175,9 +175,10 @@ size_t stitch_plan_workspace_bytes(const stitch_plan* plan);
  * Errors: NULL, WORKSPACE, DEVICE. */
 stitch_status stitch_plan_bind(stitch_plan* plan, void* workspace, size_t bytes, void* stream);
 
-/* Stitch one frame set: frames[i] U8 HWC 3-channel of the planned size, pano U8 HWC
- * 3-channel canvas_w x canvas_h.  Enqueues warp + pyramids + mask pyramids + blend +
- * collapse.  Errors: NULL, SHAPE, STATE (not bound), DEVICE. */
+/* Stitch one frame set: frames[i] U8 HWC 3-channel of the planned size (each under
+ * 2 GiB with rows under 16 MiB), pano U8 HWC 3-channel canvas_w x canvas_h.  Enqueues
+ * warp + pyramids + mask pyramids + blend + collapse.  Errors: NULL, SHAPE, STATE (not
+ * bound), DEVICE. */
 stitch_status stitch_frame(stitch_plan* plan, const stitch_image* frames, stitch_image* pano,
                            void* stream);
 
@@ -244,6 +245,16 @@ stitch_status stitch_batch_run(stitch_batch* batch, const stitch_image* const* f
  * appends the new choice.  Errors: NULL, SHAPE, STATE, DEVICE. */
 stitch_status stitch_batch_autotune(stitch_batch* batch, const stitch_image* const* frames, stitch_image* panos,
                                     void* stream, const char* cache_path);
+/* Per-launch timing of stitch_batch_run (tracing, as for plans).  While enabled, runs are
+ * launched eagerly (no graph) with one HIP event before the first launch and one after
+ * every launch; kind k < 16 is the pyramid pass from level k (k = 0: warp + level 0), kind
+ * 16 + k the blend of level k.  set_timing clears the totals; read_timing waits for the
+ * recorded events and returns accumulated milliseconds and launch counts per kind.
+ * Errors: NULL, DEVICE. */
+#define STITCH_BATCH_TIMING_KINDS (2 * STITCH_MAX_LEVELS)
+stitch_status stitch_batch_set_timing(stitch_batch* batch, int32_t enable);
+stitch_status stitch_batch_read_timing(stitch_batch* batch, double ms[STITCH_BATCH_TIMING_KINDS],
+                                       int32_t launches[STITCH_BATCH_TIMING_KINDS]);
 /* The per-level workgroups-per-CU setting in use (0: as many as fit, -1: one per tile). */
 stitch_status stitch_batch_config(const stitch_batch* batch, int32_t wg_per_cu[STITCH_MAX_LEVELS]);
 void          stitch_batch_destroy(stitch_batch* batch);

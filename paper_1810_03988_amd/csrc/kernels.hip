@@ -29,6 +29,23 @@ constexpr float kW0 = 1.0f / 16.0f, kW1 = 4.0f / 16.0f, kW2 = 6.0f / 16.0f;
 constexpr float kInv255 = 1.0f / 255.0f;
 
 #define GLB __attribute__((address_space(1)))
+#define CST __attribute__((address_space(4)))
+
+// Descriptor tables are written by the host before a launch and never during it: read them
+// through the constant address space, so uniform reads become scalar loads.
+template <typename T>
+__device__ __forceinline__ const CST T* cst(const T* p) { return (const CST T*)p; }
+// A whole descriptor by value (dword copies, merged into wide scalar loads).
+template <typename T>
+__device__ __forceinline__ T ld_cst(const CST T* p) {
+  static_assert(sizeof(T) % 4 == 0, "descriptors are dword multiples");
+  T v;
+  uint32_t* d = reinterpret_cast<uint32_t*>(&v);
+  const CST uint32_t* s = reinterpret_cast<const CST uint32_t*>(p);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = s[i];
+  return v;
+}
 
 // Views of descriptor-held pointers as global memory, so accesses compile to global (not
 // flat) instructions.
@@ -88,6 +105,21 @@ __device__ __forceinline__ void warp_coords_f(const float* __restrict__ h, float
   y = v / z;
 }
 
+// The same sequence, also returning z.
+__device__ __forceinline__ void warp_coords_z(const float* __restrict__ h, float Xf, float Yf, float& x, float& y,
+                                              float& z) {
+#pragma clang fp contract(off)
+  const float u = (h[0] * Xf + h[1] * Yf) + h[2];
+  const float v = (h[3] * Xf + h[4] * Yf) + h[5];
+  z = (h[6] * Xf + h[7] * Yf) + h[8];
+  x = u / z;
+  y = v / z;
+}
+
+// Eight bytes at any byte address (global memory accepts unaligned dword accesses).
+typedef unsigned long long __attribute__((aligned(1))) u64_unaligned;
+__device__ __forceinline__ unsigned long long ld8(const GLB uint8_t* p) { return *(const GLB u64_unaligned*)p; }
+
 // Bilinear sample of a uint8 HWC RGB frame at the preimage of canvas pixel (X, Y);
 // taps outside the frame contribute 0.  Values in [0, 1].
 __device__ __forceinline__ void warp_px(const uint8_t* __restrict__ src, int64_t row, int w, int h,
@@ -120,7 +152,7 @@ __device__ __forceinline__ int find_item(const PyrItem* __restrict__ items, int 
   int lo = 0, hi = nitems - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (items[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+    if (cst(items)[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
   }
   return lo;
 }
@@ -149,7 +181,7 @@ struct PyrTile {
 __device__ __forceinline__ PyrTile decode_tile(const PyrItem* __restrict__ items, int nitems, int t) {
   PyrTile d;
   d.item = find_item(items, nitems, t);
-  const PyrItem& it = items[d.item];
+  const CST PyrItem& it = cst(items)[d.item];
   const int lt = t - it.tile_begin;
   const int tyi = lt / it.tiles_x, txi = lt - tyi * it.tiles_x;
   d.X0 = it.tile_x0 + txi * kPyrTX;
@@ -240,7 +272,7 @@ __global__ void __launch_bounds__(kThreads) k_pyr(const PyrItem* __restrict__ it
 
   auto prefetch = [&](int tt) {
     const PyrTile d = decode_tile(items, nitems, tt);
-    const PyrItem& it = items[d.item];
+    const CST PyrItem& it = cst(items)[d.item];
     const int fw = it.fine_w, fh = it.fine_h;
     const int rx = it.roi_x, ry = it.roi_y, rw = it.roi_w, rh = it.roi_h;
     const bool interior = d.X0 >= 4 && d.X0 + TX + 3 <= fw && d.Y0 >= 4 && d.Y0 + TY + 3 <= fh;
@@ -294,7 +326,7 @@ __global__ void __launch_bounds__(kThreads) k_pyr(const PyrItem* __restrict__ it
   for (; t < t_end; t += stride) {
     const int tn = t + stride;
     const PyrTile d = decode_tile(items, nitems, t);
-    const PyrItem& it = items[d.item];
+    const CST PyrItem& it = cst(items)[d.item];
     const int X0 = d.X0, Y0 = d.Y0;
     const int fw = it.fine_w, fh = it.fine_h;
     const int nimg = it.img_kind == kSrcNone ? 0 : it.nch;
@@ -317,6 +349,59 @@ __global__ void __launch_bounds__(kThreads) k_pyr(const PyrItem* __restrict__ it
       const float fwf = (float)w, fhf = (float)h, fwm1 = (float)(w - 1), fhm1 = (float)(h - 1);
       const uint32_t srow32 = (uint32_t)srow;
       const float X0m4 = (float)(X0 - 4), Y0m4 = (float)(Y0 - 4);
+      // Source-interior tile: z > 0 at the four corners of the staged rectangle (so on all
+      // of it: z is affine) and their source positions inside [1, w-3) x [1, h-2).  The map
+      // is projective there, so every staged sample lies in the convex hull of the corner
+      // images (up to FP32 rounding, far below the one-sample margin): its four taps are in
+      // the frame and the pair of taps of a row is one 8-byte read that ends inside the row.
+      bool fast = false;
+      if (interior) {
+        bool bad = false;
+        const int lane = tid & 63;
+        if (lane < 4) {
+          float xc, yc, zc;
+          warp_coords_z(hv, X0m4 + (float)((lane & 1) ? EW - 1 : 0), Y0m4 + (float)((lane & 2) ? EH - 1 : 0), xc,
+                        yc, zc);
+          bad = !(zc >= 0x1p-10f && xc >= 1.0f && xc < (float)(w - 3) && yc >= 1.0f && yc < (float)(h - 2));
+        }
+        fast = __ballot(bad) == 0ull;   // the same in every wave of the workgroup
+      }
+      if (fast) {
+        // every sample: coordinates and both row reads issued first, so a wave keeps
+        // 2 * NIT reads in flight; then the bilinear combination
+        unsigned long long ra[NIT], rb[NIT];
+        float fxq[NIT], fyq[NIT];
+#pragma unroll
+        for (int q = 0; q < NIT; ++q) {
+          float x, y, z;
+          warp_coords_z(hv, X0m4 + cfq[q], Y0m4 + rfq[q], x, y, z);
+          const float x0f = floorf(x), y0f = floorf(y);
+          fxq[q] = x - x0f;
+          fyq[q] = y - y0f;
+          const uint32_t off = __umul24((uint32_t)(int)y0f, srow32) + 3u * (uint32_t)(int)x0f;
+          ra[q] = ld8(src + off);
+          rb[q] = ld8(src + off + srow32);
+        }
+#pragma unroll
+        for (int q = 0; q < NIT; ++q) {
+          const float fx = fxq[q], fy = fyq[q], gx = 1.0f - fx, gy = 1.0f - fy;
+          const float gyi = gy * kInv255, fyi = fy * kInv255;
+          const float w00 = gyi * gx, w01 = gyi * fx, w10 = fyi * gx, w11 = fyi * fx;
+          const uint32_t a0 = (uint32_t)ra[q], a1 = (uint32_t)(ra[q] >> 32);
+          const uint32_t b0 = (uint32_t)rb[q], b1 = (uint32_t)(rb[q] >> 32);
+          const float p00[3] = {(float)(a0 & 255u), (float)((a0 >> 8) & 255u), (float)((a0 >> 16) & 255u)};
+          const float p01[3] = {(float)(a0 >> 24), (float)(a1 & 255u), (float)((a1 >> 8) & 255u)};
+          const float p10[3] = {(float)(b0 & 255u), (float)((b0 >> 8) & 255u), (float)((b0 >> 16) & 255u)};
+          const float p11[3] = {(float)(b0 >> 24), (float)(b1 & 255u), (float)((b1 >> 8) & 255u)};
+          if (rc[q] >= 0) {
+            const int r = rc[q] >> 8, c = rc[q] & 255;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch)
+              sIn[ch][r][c] = w00 * p00[ch] + w01 * p01[ch] + w10 * p10[ch] + w11 * p11[ch];
+            sIn[3][r][c] = (float)mreg[q] * kInv255;
+          }
+        }
+      } else
 #pragma unroll
       for (int q = 0; q < NIT; ++q) {
         float Xf, Yf;
@@ -501,7 +586,7 @@ __device__ __forceinline__ int find_blend_item(const BlendItem* __restrict__ ite
   int lo = 0, hi = nitems - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (items[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+    if (cst(items)[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
   }
   return lo;
 }
@@ -520,7 +605,7 @@ __global__ void __launch_bounds__(kThreads) k_blend(const BlendItem* __restrict_
 
   const int tid = threadIdx.x;
   const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const BlendItem& a = KARG ? one : items[find_blend_item(items, nitems, t)];
+  const BlendItem a = KARG ? one : ld_cst(cst(items) + find_blend_item(items, nitems, t));
   const int lt = t - a.tile_begin;
   const int tyi = lt / a.tiles_x, txi = lt - tyi * a.tiles_x;
   const int X0 = txi * TX, Y0 = tyi * TY;
@@ -530,7 +615,7 @@ __global__ void __launch_bounds__(kThreads) k_blend(const BlendItem* __restrict_
     const int i = tid;
     bool hit = false;
     if (i < a.ncam) {
-      const BlendCam& c = a.cams[i];
+      const CST BlendCam& c = cst(a.cams)[i];
       const int x0 = max(c.lx, c.wx), x1 = min(c.lx + c.lw, c.wx + c.ww);
       const int y0 = max(c.ly, c.wy), y1 = min(c.ly + c.lh, c.wy + c.wh);
       hit = x0 < x1 && y0 < y1 && x0 < X0 + TX && x1 > X0 && y0 < Y0 + TY && y1 > Y0;
@@ -587,7 +672,9 @@ __global__ void __launch_bounds__(kThreads) k_blend(const BlendItem* __restrict_
 #pragma unroll
   for (int j = 0; j < 4; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0f;
   for (int q = 0; q < ncam; ++q) {
-    const BlendCam& c = a.cams[sCam[q]];
+    // the camera index is the same in every lane: read it as such, so the descriptor
+    // comes through scalar loads instead of one dependent vector load per field
+    const CST BlendCam& c = cst(a.cams)[__builtin_amdgcn_readfirstlane(sCam[q])];
     const GLB T* l = cg<T>(c.lap);
     const int lx = X - c.lx, wx = X - c.wx;
     const bool xin = lx >= 0 && lx < c.lw && wx >= 0 && wx < c.ww;

@@ -127,6 +127,81 @@ struct Interval { int64_t a, b; };   // inclusive, a > b means empty
 // Support of REDUCE(g) given the support of g (non-negative weights cannot cancel).
 Interval reduce_support(Interval s) { return {ceil_div(s.a - 2, 2), floor_div(s.b + 2, 2)}; }
 
+// Per-launch HIP-event timing (diagnostics).  While enabled, a call records one event on
+// its stream before its first launch and one after every launch; the time between two
+// consecutive events is charged to the launch's kind.
+struct EventLog {
+  static constexpr int kKinds = 2 * kMaxLevels;
+  bool on = false;
+  std::vector<hipEvent_t> spare;
+  struct Call { std::vector<hipEvent_t> ev; std::vector<int> kind; };   // ev[i] .. ev[i+1] = launch i
+  std::vector<Call> done;
+  Call cur;
+  double ms[kKinds] = {};
+  int32_t n[kKinds] = {};
+
+  ~EventLog() {
+    recycle();
+    for (hipEvent_t e : spare) (void)hipEventDestroy(e);
+  }
+  void recycle() {
+    for (auto& c : done)
+      for (hipEvent_t e : c.ev) spare.push_back(e);
+    done.clear();
+    for (hipEvent_t e : cur.ev) spare.push_back(e);
+    cur = Call();
+  }
+  void reset(bool enable) {
+    on = enable;
+    recycle();
+    for (int i = 0; i < kKinds; ++i) { ms[i] = 0.0; n[i] = 0; }
+  }
+  // kind < 0: the event before a call's first launch
+  stitch_status mark(hipStream_t s, int kind) {
+    if (!on) return STITCH_OK;
+    hipEvent_t ev;
+    if (!spare.empty()) {
+      ev = spare.back();
+      spare.pop_back();
+    } else {
+      const hipError_t ce = hipEventCreate(&ev);
+      if (ce != hipSuccess) return hip_fail(ce, "timing event create");
+    }
+    const hipError_t re = hipEventRecord(ev, s);
+    if (re != hipSuccess) { spare.push_back(ev); return hip_fail(re, "timing event record"); }
+    cur.ev.push_back(ev);
+    if (kind >= 0) cur.kind.push_back(kind);
+    return STITCH_OK;
+  }
+  // end of a call: keep its events if they are complete, else give them back
+  void end_call() {
+    if (!cur.ev.empty() && cur.kind.size() + 1 == cur.ev.size()) done.push_back(std::move(cur));
+    else
+      for (hipEvent_t e : cur.ev) spare.push_back(e);
+    cur = Call();
+  }
+  // wait for the recorded events and add their intervals to the totals
+  stitch_status collect() {
+    stitch_status st = STITCH_OK;
+    for (auto& c : done) {
+      if (!st) {
+        const hipError_t e = hipEventSynchronize(c.ev.back());
+        if (e != hipSuccess) st = hip_fail(e, "timing event synchronise");
+      }
+      for (size_t i = 0; !st && i < c.kind.size(); ++i) {
+        float t = 0.0f;
+        const hipError_t e = hipEventElapsedTime(&t, c.ev[i], c.ev[i + 1]);
+        if (e != hipSuccess) { st = hip_fail(e, "timing elapsed"); break; }
+        ms[c.kind[i]] += t;
+        n[c.kind[i]] += 1;
+      }
+      for (hipEvent_t e : c.ev) spare.push_back(e);
+    }
+    done.clear();
+    return st;
+  }
+};
+
 struct CamPlan {
   int fw = 0, fh = 0;
   float hinv[9] = {};
@@ -159,18 +234,7 @@ struct stitch_plan {
   size_t off_bitems = 0;
   size_t ws_bytes = 0;
   uint8_t* ws = nullptr;
-  // optional per-launch event timing (diagnostics)
-  bool timing = false;
-  std::vector<hipEvent_t> ev_free;
-  struct Pending { std::vector<hipEvent_t> ev; std::vector<int> kind; };   // ev[i] .. ev[i+1] = launch i
-  std::vector<Pending> pending;
-  double kind_ms[STITCH_TIMING_KINDS] = {};
-  int32_t kind_n[STITCH_TIMING_KINDS] = {};
-  ~stitch_plan() {
-    for (auto& q : pending)
-      for (hipEvent_t e : q.ev) ev_free.push_back(e);
-    for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
-  }
+  EventLog timing;   // optional per-launch event timing (diagnostics)
 };
 
 namespace {
@@ -829,8 +893,10 @@ stitch_status stitch_frame(stitch_plan* p, const stitch_image* frames, stitch_im
     if (frames[i].width != p->cam[i].fw || frames[i].height != p->cam[i].fh)
       return fail(STITCH_E_SHAPE, "frames[%d] is %dx%d, planned %dx%d", i, frames[i].width, frames[i].height,
                   p->cam[i].fw, p->cam[i].fh);
-    if (frames[i].row_pitch * (int64_t)frames[i].height >= ((int64_t)1 << 31))
-      return fail(STITCH_E_SHAPE, "frames[%d] spans 2 GiB or more (byte offsets are 32-bit)", i);
+    if (frames[i].row_pitch * (int64_t)frames[i].height >= ((int64_t)1 << 31) ||
+        frames[i].row_pitch >= ((int64_t)1 << 24))
+      return fail(STITCH_E_SHAPE, "frames[%d] spans 2 GiB or more, or its rows 16 MiB or more (offsets are "
+                  "32-bit, row offsets 24-bit products)", i);
     fa.ptr[i] = (const uint8_t*)frames[i].data;
     fa.row[i] = frames[i].row_pitch;
   }
@@ -838,32 +904,11 @@ stitch_status stitch_frame(stitch_plan* p, const stitch_image* frames, stitch_im
   const bool f16 = p->storage == STITCH_F16;
   const int L = p->L;
   // optional event chain: one event before the first launch and one after each launch
-  stitch_plan::Pending tm;
-  auto mark = [&](int kind) -> stitch_status {
-    if (!p->timing) return STITCH_OK;
-    hipEvent_t ev;
-    if (!p->ev_free.empty()) {
-      ev = p->ev_free.back();
-      p->ev_free.pop_back();
-    } else {
-      const hipError_t ce = hipEventCreate(&ev);
-      if (ce != hipSuccess) return hip_fail(ce, "timing event create");
-    }
-    const hipError_t re = hipEventRecord(ev, s);
-    if (re != hipSuccess) { p->ev_free.push_back(ev); return hip_fail(re, "timing event record"); }
-    tm.ev.push_back(ev);
-    if (kind >= 0) tm.kind.push_back(kind);
-    return STITCH_OK;
-  };
-  struct Flush {
-    stitch_plan* p; stitch_plan::Pending* tm;
-    ~Flush() {
-      if (p->timing && !tm->ev.empty()) {
-        if (tm->kind.size() + 1 == tm->ev.size()) p->pending.push_back(std::move(*tm));
-        else for (hipEvent_t e : tm->ev) p->ev_free.push_back(e);
-      }
-    }
-  } flush{p, &tm};
+  auto mark = [&](int kind) { return p->timing.mark(s, kind); };
+  struct EndCall {
+    EventLog& log;
+    ~EndCall() { log.end_call(); }
+  } end_call{p->timing};
   hipError_t e;
   if ((st = mark(-1))) return st;
   if (L == 1) {
@@ -898,34 +943,15 @@ stitch_status stitch_frame(stitch_plan* p, const stitch_image* frames, stitch_im
 
 stitch_status stitch_plan_set_timing(stitch_plan* p, int32_t enable) {
   if (!p) return fail(STITCH_E_NULL, "plan is NULL");
-  p->timing = enable != 0;
-  for (auto& q : p->pending)
-    for (hipEvent_t e : q.ev) p->ev_free.push_back(e);
-  p->pending.clear();
-  for (int i = 0; i < STITCH_TIMING_KINDS; ++i) { p->kind_ms[i] = 0.0; p->kind_n[i] = 0; }
+  p->timing.reset(enable != 0);
   return STITCH_OK;
 }
 
 stitch_status stitch_plan_read_timing(stitch_plan* p, double ms[STITCH_TIMING_KINDS],
                                       int32_t launches[STITCH_TIMING_KINDS]) {
   if (!p || !ms || !launches) return fail(STITCH_E_NULL, "plan, ms or launches is NULL");
-  stitch_status st = STITCH_OK;
-  for (auto& q : p->pending) {
-    if (!st) {
-      const hipError_t e = hipEventSynchronize(q.ev.back());
-      if (e != hipSuccess) st = hip_fail(e, "timing event synchronise");
-    }
-    for (size_t i = 0; !st && i < q.kind.size(); ++i) {
-      float t = 0.0f;
-      const hipError_t e = hipEventElapsedTime(&t, q.ev[i], q.ev[i + 1]);
-      if (e != hipSuccess) { st = hip_fail(e, "timing elapsed"); break; }
-      p->kind_ms[q.kind[i]] += t;
-      p->kind_n[q.kind[i]] += 1;
-    }
-    for (hipEvent_t e : q.ev) p->ev_free.push_back(e);
-  }
-  p->pending.clear();
-  for (int i = 0; i < STITCH_TIMING_KINDS; ++i) { ms[i] = p->kind_ms[i]; launches[i] = p->kind_n[i]; }
+  const stitch_status st = p->timing.collect();
+  for (int i = 0; i < STITCH_TIMING_KINDS; ++i) { ms[i] = p->timing.ms[i]; launches[i] = p->timing.n[i]; }
   return st;
 }
 
@@ -1027,6 +1053,7 @@ struct stitch_batch {
   bool uploaded = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  EventLog timing;   // per-launch timing; while on, runs are launched eagerly
   ~stitch_batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -1047,19 +1074,26 @@ void drop_graph(stitch_batch* b) {
 stitch_status enqueue_batch(stitch_batch* b, hipStream_t s) {
   FrameArgs fa;
   std::memset(&fa, 0, sizeof fa);   // n = 0: frames come from the item tables
-  for (int k = 0; k + 1 < b->maxL; ++k) {
+  struct EndCall {
+    EventLog& log;
+    ~EndCall() { log.end_call(); }
+  } end_call{b->timing};
+  stitch_status st = b->timing.mark(s, -1);
+  for (int k = 0; !st && k + 1 < b->maxL; ++k) {
     if (b->pyr_tiles[k] <= 0) continue;
     const hipError_t e = launch_pyr(b->f16, true, k == 0, (const PyrItem*)(b->ws + b->off_pyr[k]),
                                     (int)b->pyr[k].size(), b->pyr_tiles[k], fa, s, b->wg_cap[k]);
     if (e != hipSuccess) return hip_fail(e, "batch pyramid launch");
+    st = b->timing.mark(s, k);
   }
-  for (int k = b->maxL - 1; k >= 0; --k) {
+  for (int k = b->maxL - 1; !st && k >= 0; --k) {
     if (b->blend_tiles[k] <= 0) continue;
     const hipError_t e = launch_blend(b->f16, k == 0, (const BlendItem*)(b->ws + b->off_blend[k]),
                                       (int)b->blend[k].size(), b->blend_tiles[k], PanoArg{nullptr, 0}, s);
     if (e != hipSuccess) return hip_fail(e, "batch blend launch");
+    st = b->timing.mark(s, kMaxLevels + k);
   }
-  return STITCH_OK;
+  return st;
 }
 
 // Check the run's frames and panoramas, write their pointers into the tables and upload
@@ -1083,8 +1117,9 @@ stitch_status batch_prepare(stitch_batch* b, const stitch_image* const* frames, 
       if (st) return st;
       if (frames[j][i].width != p->cam[i].fw || frames[j][i].height != p->cam[i].fh)
         return fail(STITCH_E_SHAPE, "%s does not match the planned frame size", name);
-      if (frames[j][i].row_pitch * (int64_t)frames[j][i].height >= ((int64_t)1 << 31))
-        return fail(STITCH_E_SHAPE, "%s spans 2 GiB or more", name);
+      if (frames[j][i].row_pitch * (int64_t)frames[j][i].height >= ((int64_t)1 << 31) ||
+          frames[j][i].row_pitch >= ((int64_t)1 << 24))
+        return fail(STITCH_E_SHAPE, "%s spans 2 GiB or more, or its rows 16 MiB or more", name);
     }
   }
   for (size_t q = 0; q < b->frame_item.size(); ++q) {
@@ -1205,7 +1240,8 @@ stitch_status stitch_batch_run(stitch_batch* b, const stitch_image* const* frame
   const hipStream_t s = (hipStream_t)stream;
   stitch_status st = batch_prepare(b, frames, panos, s);
   if (st) return st;
-  if (!s) return enqueue_batch(b, s);   // the null stream cannot be captured: launch eagerly
+  // the null stream cannot be captured, and timing events stay out of graphs: launch eagerly
+  if (!s || b->timing.on) return enqueue_batch(b, s);
   if (!b->exec) {
     prepare_launches();
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
@@ -1320,6 +1356,20 @@ stitch_status stitch_batch_config(const stitch_batch* b, int32_t wg_per_cu[STITC
   if (!b || !wg_per_cu) return fail(STITCH_E_NULL, "batch or wg_per_cu is NULL");
   for (int k = 0; k < kMaxLevels; ++k) wg_per_cu[k] = b->wg_cap[k];
   return STITCH_OK;
+}
+
+stitch_status stitch_batch_set_timing(stitch_batch* b, int32_t enable) {
+  if (!b) return fail(STITCH_E_NULL, "batch is NULL");
+  b->timing.reset(enable != 0);
+  return STITCH_OK;
+}
+
+stitch_status stitch_batch_read_timing(stitch_batch* b, double ms[STITCH_BATCH_TIMING_KINDS],
+                                       int32_t launches[STITCH_BATCH_TIMING_KINDS]) {
+  if (!b || !ms || !launches) return fail(STITCH_E_NULL, "batch, ms or launches is NULL");
+  const stitch_status st = b->timing.collect();
+  for (int i = 0; i < STITCH_BATCH_TIMING_KINDS; ++i) { ms[i] = b->timing.ms[i]; launches[i] = b->timing.n[i]; }
+  return st;
 }
 
 void stitch_batch_destroy(stitch_batch* b) { delete b; }

@@ -77,6 +77,8 @@ SIGNATURES = {
     "stitch_batch_autotune": (c_int32, [c_void_p, POINTER(POINTER(StitchImage)), POINTER(StitchImage), c_void_p,
                                         c_char_p]),
     "stitch_batch_config": (c_int32, [c_void_p, POINTER(c_int32)]),
+    "stitch_batch_set_timing": (c_int32, [c_void_p, c_int32]),
+    "stitch_batch_read_timing": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int32)]),
     "stitch_batch_destroy": (None, [c_void_p]),
     "stitch_grad_create": (c_int32, [POINTER(c_int32), POINTER(c_int32), POINTER(POINTER(c_uint8)), c_int32,
                                      c_int32, c_int32, POINTER(c_void_p)]),
@@ -391,6 +393,20 @@ class Batch:
         check(lib().stitch_batch_autotune(self._h, a[1], a[2], _stream(stream),
                                           None if cache_path is None else str(cache_path).encode()))
         return self.config()
+
+    def set_timing(self, enable: bool) -> None:
+        check(lib().stitch_batch_set_timing(self._h, 1 if enable else 0))
+
+    def read_timing(self) -> dict:
+        """{("pyr", k) or ("blend", k): (total_ms, launches)} accumulated since set_timing(True)."""
+        ms = (c_double * (2 * MAX_LEVELS))()
+        n = (c_int32 * (2 * MAX_LEVELS))()
+        check(lib().stitch_batch_read_timing(self._h, ms, n))
+        out = {}
+        for i in range(2 * MAX_LEVELS):
+            if n[i]:
+                out[("pyr", i) if i < MAX_LEVELS else ("blend", i - MAX_LEVELS)] = (ms[i], n[i])
+        return out
 
     def config(self):
         out = (c_int32 * MAX_LEVELS)()
