@@ -154,7 +154,8 @@ stitch_status stitch_blend(int32_t n, const stitch_levels* bands, const stitch_l
 
 #define STITCH_PLAN_KEEP_R0 1   /* flags bit: also store R_0 (float) in the workspace */
 
-/* Validate a fixed rig and plan the per-frame work: n cameras of frame_w[i] x frame_h[i],
+/* Validate a fixed rig and plan the per-frame work: n cameras of frame_w[i] x frame_h[i]
+ * (width >= 3),
  * H (n*9 doubles, source -> canvas, row-major per camera), seam weights masks[i]
  * (host, canvas_h x canvas_w uint8, row-major, summing to 255 at every pixel),
  * levels L (1..16, every canvas level side >= 3), storage STITCH_F32 or STITCH_F16 for

@@ -116,6 +116,35 @@ __device__ __forceinline__ void warp_coords_z(const float* __restrict__ h, float
   y = v / z;
 }
 
+// x = u/z and y = v/z, correctly rounded, for operands in the range where the hardware
+// division sequence scales nothing and fixes nothing up: z in [2^-10, 2^20] and |u|, |v|
+// in [2^-12, 2^44] (exponent gaps far below 96, no denormal reciprocal, numerator or
+// quotient).  In that range the IEEE divide of the
+// compiler is exactly: r = rcp(z) refined by one Newton step, q = u r, two residual
+// corrections; the refined reciprocal is shared by both quotients.
+__device__ __forceinline__ void div2_in_range(float u, float v, float z, float& x, float& y) {
+  float r = __builtin_amdgcn_rcpf(z);
+  r = __builtin_fmaf(__builtin_fmaf(-z, r, 1.0f), r, r);
+  float qx = u * r, qy = v * r;
+  qx = __builtin_fmaf(__builtin_fmaf(-z, qx, u), r, qx);
+  qy = __builtin_fmaf(__builtin_fmaf(-z, qy, v), r, qy);
+  x = __builtin_fmaf(__builtin_fmaf(-z, qx, u), r, qx);
+  y = __builtin_fmaf(__builtin_fmaf(-z, qy, v), r, qy);
+}
+
+// The coordinate sequence with that division (callers guarantee the range).
+__device__ __forceinline__ void warp_coords_in_range(const float* __restrict__ h, float Xf, float Yf, float& x,
+                                                     float& y) {
+  float u, v, z;
+  {
+#pragma clang fp contract(off)
+    u = (h[0] * Xf + h[1] * Yf) + h[2];
+    v = (h[3] * Xf + h[4] * Yf) + h[5];
+    z = (h[6] * Xf + h[7] * Yf) + h[8];
+  }
+  div2_in_range(u, v, z, x, y);
+}
+
 // Eight bytes at any byte address (global memory accepts unaligned dword accesses).
 typedef unsigned long long __attribute__((aligned(1))) u64_unaligned;
 __device__ __forceinline__ unsigned long long ld8(const GLB uint8_t* p) { return *(const GLB u64_unaligned*)p; }
@@ -190,7 +219,7 @@ __device__ __forceinline__ PyrTile decode_tile(const PyrItem* __restrict__ items
 }
 
 template <typename T, bool EMIT_LAP, bool WARP>
-__global__ void __launch_bounds__(kThreads) k_pyr(const PyrItem* __restrict__ items, int nitems, int ntiles,
+__global__ void __launch_bounds__(kThreads, 3) k_pyr(const PyrItem* __restrict__ items, int nitems, int ntiles,
                                                   FrameArgs fa) {
   constexpr int TX = kPyrTX, TY = kPyrTY;
   constexpr int EW = TX + 7, EH = TY + 7;            // staged fine samples: 4 before, 3 after
@@ -354,31 +383,55 @@ __global__ void __launch_bounds__(kThreads) k_pyr(const PyrItem* __restrict__ it
       // is projective there, so every staged sample lies in the convex hull of the corner
       // images (up to FP32 rounding, far below the one-sample margin): its four taps are in
       // the frame and the pair of taps of a row is one 8-byte read that ends inside the row.
-      bool fast = false;
+      // Source-exterior tile: z > 0 at the corners and all four corner images at least
+      // one sample beyond the same side of the frame (x <= -2, x >= w + 1, y <= -2 or
+      // y >= h + 1): every staged sample's taps are outside and its G_0 is exactly 0.
+      bool fast = false, outside = false;
       if (interior) {
-        bool bad = false;
+        bool bad = false, zok = false, lft = false, rgt = false, top = false, bot = false;
         const int lane = tid & 63;
         if (lane < 4) {
           float xc, yc, zc;
           warp_coords_z(hv, X0m4 + (float)((lane & 1) ? EW - 1 : 0), Y0m4 + (float)((lane & 2) ? EH - 1 : 0), xc,
                         yc, zc);
-          bad = !(zc >= 0x1p-10f && xc >= 1.0f && xc < (float)(w - 3) && yc >= 1.0f && yc < (float)(h - 2));
+          zok = zc >= 0x1p-10f && zc <= 0x1p20f;
+          bad = !(zok && xc >= 1.0f && xc < (float)(w - 3) && yc >= 1.0f && yc < (float)(h - 2));
+          lft = xc <= -2.0f;
+          rgt = xc >= (float)(w + 1);
+          top = yc <= -2.0f;
+          bot = yc >= (float)(h + 1);
         }
-        fast = __ballot(bad) == 0ull;   // the same in every wave of the workgroup
+        // ballots are the same in every wave of the workgroup
+        fast = __ballot(bad) == 0ull;
+        outside = __ballot(zok) == 15ull &&
+                  (__ballot(lft) == 15ull || __ballot(rgt) == 15ull || __ballot(top) == 15ull ||
+                   __ballot(bot) == 15ull);
       }
-      if (fast) {
+      if (outside) {
+#pragma unroll
+        for (int q = 0; q < NIT; ++q) {
+          if (rc[q] >= 0) {
+            const int r = rc[q] >> 8, c = rc[q] & 255;
+            sIn[0][r][c] = 0.0f;
+            sIn[1][r][c] = 0.0f;
+            sIn[2][r][c] = 0.0f;
+            sIn[3][r][c] = (float)mreg[q] * kInv255;
+          }
+        }
+      } else if (fast) {
         // every sample: coordinates and both row reads issued first, so a wave keeps
         // 2 * NIT reads in flight; then the bilinear combination
         unsigned long long ra[NIT], rb[NIT];
         float fxq[NIT], fyq[NIT];
 #pragma unroll
         for (int q = 0; q < NIT; ++q) {
-          float x, y, z;
-          warp_coords_z(hv, X0m4 + cfq[q], Y0m4 + rfq[q], x, y, z);
-          const float x0f = floorf(x), y0f = floorf(y);
-          fxq[q] = x - x0f;
-          fyq[q] = y - y0f;
-          const uint32_t off = __umul24((uint32_t)(int)y0f, srow32) + 3u * (uint32_t)(int)x0f;
+          // z lies between its corner values and x, y in [1, w) x [1, h): the in-range
+          // division is the IEEE one, x - floor(x) is exact and truncation is floor
+          float x, y;
+          warp_coords_in_range(hv, X0m4 + cfq[q], Y0m4 + rfq[q], x, y);
+          fxq[q] = __builtin_amdgcn_fractf(x);
+          fyq[q] = __builtin_amdgcn_fractf(y);
+          const uint32_t off = __umul24((uint32_t)(int)y, srow32) + 3u * (uint32_t)(int)x;
           ra[q] = ld8(src + off);
           rb[q] = ld8(src + off + srow32);
         }
@@ -401,53 +454,68 @@ __global__ void __launch_bounds__(kThreads) k_pyr(const PyrItem* __restrict__ it
             sIn[3][r][c] = (float)mreg[q] * kInv255;
           }
         }
-      } else
+      } else {
+        // General tile (frame borders, canvas edges): taps outside the frame weigh 0.  Each
+        // row pair is still one 8-byte read, from a start clamped into [0, 3w - 8] of a row
+        // clamped into the frame (w >= 3), so no read leaves its row; the pair is shifted
+        // into place afterwards.  All reads are issued before any is used.
+        unsigned long long ra[NIT], rb[NIT];
+        float fxq[NIT], fyq[NIT];
+        uint32_t tapq[NIT];                       // bits: 00 01 10 11 inside, << 4: byte shift + 3
+        const uint32_t lastc = 3u * (uint32_t)w - 8u;
 #pragma unroll
-      for (int q = 0; q < NIT; ++q) {
-        float Xf, Yf;
-        if (interior) {
-          Xf = X0m4 + cfq[q];
-          Yf = Y0m4 + rfq[q];
-        } else {
-          int Xc, Yc;
-          sample_pos(q, X0, Y0, interior, fw, fh, Xc, Yc);
-          Xf = (float)Xc;
-          Yf = (float)Yc;
+        for (int q = 0; q < NIT; ++q) {
+          float Xf, Yf;
+          if (interior) {
+            Xf = X0m4 + cfq[q];
+            Yf = Y0m4 + rfq[q];
+          } else {
+            int Xc, Yc;
+            sample_pos(q, X0, Y0, interior, fw, fh, Xc, Yc);
+            Xf = (float)Xc;
+            Yf = (float)Yc;
+          }
+          float x, y;
+          bool zpos;
+          warp_coords_f(hv, Xf, Yf, x, y, zpos);
+          const bool ok = zpos && x >= -1.0f && x < fwf && y >= -1.0f && y < fhf;
+          const float xs = ok ? x : 0.0f, ys = ok ? y : 0.0f;
+          const float x0f = floorf(xs), y0f = floorf(ys);
+          fxq[q] = xs - x0f;
+          fyq[q] = ys - y0f;
+          const bool xa = ok && x0f >= 0.0f, xb = ok && x0f < fwm1, ya = y0f >= 0.0f, yb = y0f < fhm1;
+          const int x0 = (int)x0f, y0 = (int)y0f;                 // x0 >= -1, y0 >= -1
+          const int c3 = 3 * x0;
+          const uint32_t start = (uint32_t)min(max(c3, 0), (int)lastc);
+          const uint32_t r0 = (uint32_t)max(y0, 0), r1 = (uint32_t)min(y0 + 1, h - 1);
+          tapq[q] = (uint32_t)(ya && xa) | ((uint32_t)(ya && xb) << 1) | ((uint32_t)(yb && xa) << 2) |
+                    ((uint32_t)(yb && xb) << 3) | ((uint32_t)(c3 - (int)start + 3) << 4);
+          ra[q] = ld8(src + (__umul24(r0, srow32) + start));
+          rb[q] = ld8(src + (__umul24(r1, srow32) + start));
         }
-        float x, y;
-        bool zpos;
-        warp_coords_f(hv, Xf, Yf, x, y, zpos);
-        const bool ok = zpos && x >= -1.0f && x < fwf && y >= -1.0f && y < fhf;
-        const float xs = ok ? x : 0.0f, ys = ok ? y : 0.0f;
-        const float x0f = floorf(xs), y0f = floorf(ys);
-        const float fx = xs - x0f, fy = ys - y0f, gx = 1.0f - fx, gy = 1.0f - fy;
-        const bool xa = ok && x0f >= 0.0f, xb = ok && x0f < fwm1, ya = y0f >= 0.0f, yb = y0f < fhm1;
-        // bilinear weights with 1/255 folded in; taps outside the frame weigh 0
-        const float gyi = gy * kInv255, fyi = fy * kInv255;
-        const float w00 = (ya && xa) ? gyi * gx : 0.0f, w01 = (ya && xb) ? gyi * fx : 0.0f;
-        const float w10 = (yb && xa) ? fyi * gx : 0.0f, w11 = (yb && xb) ? fyi * fx : 0.0f;
-        const uint32_t x0 = (uint32_t)(int)x0f, y0 = (uint32_t)(int)y0f;
-        const uint32_t o0 = ya ? __umul24(y0, srow32) : 0u, o1 = yb ? __umul24(y0 + 1u, srow32) : 0u;
-        const uint32_t c0 = xa ? 3u * x0 : 0u, c1 = xb ? 3u * x0 + 3u : 0u;
-        const GLB uint8_t* t00 = src + (o0 + c0);
-        const GLB uint8_t* t01 = src + (o0 + c1);
-        const GLB uint8_t* t10 = src + (o1 + c0);
-        const GLB uint8_t* t11 = src + (o1 + c1);
-        uint32_t p[12];
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-          p[ch] = t00[ch];
-          p[3 + ch] = t01[ch];
-          p[6 + ch] = t10[ch];
-          p[9 + ch] = t11[ch];
-        }
-        if (rc[q] >= 0) {
-          const int r = rc[q] >> 8, c = rc[q] & 255;
+        for (int q = 0; q < NIT; ++q) {
+          const int sh = (int)(tapq[q] >> 4) - 3;                 // byte offset of tap 0: -3 .. 5
+          const unsigned long long a = sh >= 0 ? ra[q] >> (8 * sh) : ra[q] << 24;
+          const unsigned long long b = sh >= 0 ? rb[q] >> (8 * sh) : rb[q] << 24;
+          const float fx = fxq[q], fy = fyq[q], gx = 1.0f - fx, gy = 1.0f - fy;
+          const float gyi = gy * kInv255, fyi = fy * kInv255;
+          const uint32_t tp = tapq[q];
+          const float w00 = (tp & 1u) ? gyi * gx : 0.0f, w01 = (tp & 2u) ? gyi * fx : 0.0f;
+          const float w10 = (tp & 4u) ? fyi * gx : 0.0f, w11 = (tp & 8u) ? fyi * fx : 0.0f;
+          const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+          const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+          const float p00[3] = {(float)(a0 & 255u), (float)((a0 >> 8) & 255u), (float)((a0 >> 16) & 255u)};
+          const float p01[3] = {(float)(a0 >> 24), (float)(a1 & 255u), (float)((a1 >> 8) & 255u)};
+          const float p10[3] = {(float)(b0 & 255u), (float)((b0 >> 8) & 255u), (float)((b0 >> 16) & 255u)};
+          const float p11[3] = {(float)(b0 >> 24), (float)(b1 & 255u), (float)((b1 >> 8) & 255u)};
+          if (rc[q] >= 0) {
+            const int r = rc[q] >> 8, c = rc[q] & 255;
 #pragma unroll
-          for (int ch = 0; ch < 3; ++ch)
-            sIn[ch][r][c] = w00 * (float)p[ch] + w01 * (float)p[3 + ch] + w10 * (float)p[6 + ch] +
-                            w11 * (float)p[9 + ch];
-          sIn[3][r][c] = (float)mreg[q] * kInv255;
+            for (int ch = 0; ch < 3; ++ch)
+              sIn[ch][r][c] = w00 * p00[ch] + w01 * p01[ch] + w10 * p10[ch] + w11 * p11[ch];
+            sIn[3][r][c] = (float)mreg[q] * kInv255;
+          }
         }
       }
     } else {
@@ -781,9 +849,26 @@ __global__ void __launch_bounds__(kThreads) k_warp_coords(Hinv9 hi, int rx, int 
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
   const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (x >= dw || y >= dh) return;
+  // the warp pass's arithmetic: the shared-reciprocal division where its range holds
+  // (z in [2^-10, 2^20], |u|, |v| in [2^-12, 2^44]), the compiler's IEEE divide elsewhere
+  const float* h = hi.h;
+  const float Xf = (float)(rx + x), Yf = (float)(ry + y);
+  float u, v, z;
+  {
+#pragma clang fp contract(off)
+    u = (h[0] * Xf + h[1] * Yf) + h[2];
+    v = (h[3] * Xf + h[4] * Yf) + h[5];
+    z = (h[6] * Xf + h[7] * Yf) + h[8];
+  }
+  const bool zpos = z > 0.0f;
+  const float au = fabsf(u), av = fabsf(v);
   float sx, sy;
-  bool zpos;
-  warp_coords(hi.h, rx + x, ry + y, sx, sy, zpos);
+  if (z >= 0x1p-10f && z <= 0x1p20f && au >= 0x1p-12f && au <= 0x1p44f && av >= 0x1p-12f && av <= 0x1p44f) {
+    div2_in_range(u, v, z, sx, sy);
+  } else {
+    sx = u / z;
+    sy = v / z;
+  }
   const int64_t off = (int64_t)y * drow + x;
   dst[off] = zpos ? sx : __builtin_nanf("");
   dst[dplane + off] = zpos ? sy : __builtin_nanf("");

@@ -727,8 +727,9 @@ stitch_status stitch_plan_create(int32_t n, const int32_t* frame_w, const int32_
   const int64_t A = (int64_t)1 << (L - 1);   // every ROI origin is a multiple of 2^(L-1)
   for (int i = 0; i < n; ++i) {
     CamPlan& c = p->cam[i];
-    if (frame_w[i] <= 0 || frame_h[i] <= 0 || frame_w[i] > (1 << 20) || frame_h[i] > (1 << 20))
-      return fail(STITCH_E_SHAPE, "frame %d has size %dx%d", i, frame_w[i], frame_h[i]);
+    if (frame_w[i] < 3 || frame_h[i] <= 0 || frame_w[i] > (1 << 20) || frame_h[i] > (1 << 20))
+      return fail(STITCH_E_SHAPE, "frame %d has size %dx%d (width 3 .. 2^20, height 1 .. 2^20)", i, frame_w[i],
+                  frame_h[i]);
     c.fw = frame_w[i];
     c.fh = frame_h[i];
     const double* Hi = H + 9 * i;

@@ -43,6 +43,29 @@ def test_warp_coordinates_random_homographies_bitwise():
         assert np.all(np.isnan(xy[0][~ok]))
 
 
+def test_warp_coordinates_bitwise_across_the_division_range():
+    """Canvas -> source maps whose z sweeps through 0 and over many binades and whose u, v
+    run from tiny to ~2^30: samples take both the shared-reciprocal division (where its
+    range holds) and the plain IEEE divide, and every finite result must be the IEEE one."""
+    rng = np.random.default_rng(11)
+    near_horizon = 0
+    for _ in range(6):
+        M = np.array([[rng.uniform(-2e3, 2e3), rng.uniform(-2e3, 2e3), rng.uniform(-1e4, 1e4)],
+                      [rng.uniform(-2e3, 2e3), rng.uniform(-2e3, 2e3), rng.uniform(-1e4, 1e4)],
+                      [rng.uniform(-1e-2, 1e-2), rng.uniform(-1e-2, 1e-2), 1.0]])
+        H = np.linalg.inv(M)
+        xy = P.warp_coords(H, -350, -150, 700, 300).cpu().numpy()
+        x, y, zpos = o.warp_coords(o.hinv_spec(H), np.arange(-150, 150), np.arange(-350, 350))
+        hs = o.hinv_spec(H).ravel().astype(np.float32)
+        Xs, Ys = np.arange(-350, 350, dtype=np.float32)[None, :], np.arange(-150, 150, dtype=np.float32)[:, None]
+        z = (hs[6] * Xs + hs[7] * Ys) + hs[8]
+        near_horizon += int(np.count_nonzero((z > 0) & (z < 2.0 ** -10)))
+        assert np.array_equal(xy[0][zpos].view(np.uint32), x[zpos].astype(np.float32).view(np.uint32))
+        assert np.array_equal(xy[1][zpos].view(np.uint32), y[zpos].astype(np.float32).view(np.uint32))
+        assert np.all(np.isnan(xy[0][~zpos]))
+    assert near_horizon > 50       # the IEEE fallback was exercised too
+
+
 @pytest.mark.parametrize("case", ["c1b", "proj", "identity", "translate", "f16"])
 def test_warp_matches_oracle(case):
     r = wl.rig_c1()
