@@ -187,24 +187,26 @@ __device__ __forceinline__ int find_item(const PyrItem* __restrict__ items, int 
 }
 
 // ------------------------------------------------------------------------------------
-// Fused pyramid pass over 64x16 level-k tiles (256 threads, four waves per workgroup).
+// Fused pyramid pass from level k to k+1 (256 threads, four waves per workgroup).
 //
-// Persistent, XCD-aware schedule: the tiles are split into eight contiguous ranges, one
-// per XCD (workgroup b runs on XCD b % 8), and the workgroups of an XCD stride through
-// its range, so neighbouring tiles -- which share halos -- share that XCD's L2.  While a
-// tile is being computed, the global loads of the workgroup's next tile are already in
-// flight (they land in registers), so each tile costs its compute, not its latency.
+// A tile is 64 level-k columns by 16 * sub rows; the workgroup walks down it in sub-steps
+// of 16 rows.  Persistent, XCD-aware schedule: the tiles are split into eight contiguous
+// ranges, one per XCD (workgroup b runs on XCD b % 8), and the workgroups of an XCD stride
+// through its range, so neighbouring tiles -- which share halos -- share that XCD's L2.
 //
-// Stages of one tile, each ended by one barrier:
-//   A  stage the fine tile + halo (71x23) of every channel in LDS: three image channels
-//      (bilinear warp of the source frame at level 0 -- taps read from an LDS copy of the
-//      tile's source footprint -- or stored G_k above) and the seam weight;
-//   B  horizontal REDUCE (two coarse outputs per thread from two b128 LDS reads);
+// Stages of one sub-step, each ended by one barrier:
+//   A  stage the 71-column window of the sub-step's 23 rows (its 16 rows plus 4 above and
+//      3 below) of every channel in LDS: three image channels (the bilinear warp of the
+//      source frame at level 0, the stored G_k above) and the seam weight.  LDS rows form
+//      a ring of 23: the 7 rows a sub-step shares with the previous one stay where they
+//      are, so only its 16 new rows are staged (all 23 on a tile's first sub-step);
+//   B  horizontal REDUCE of the newly staged rows (two coarse outputs per thread from
+//      two b128 LDS reads);
 //   C  vertical REDUCE -> extended 34x10 coarse tile; its interior is G_{k+1} / Gm_{k+1};
 //   D  horizontal EXPAND of the coarse tile (four fine columns per thread);
 //   E  vertical EXPAND and L_k = G_k - EXPAND(G_{k+1}), stored on the band window.
 struct PyrTile {
-  int item, X0, Y0;
+  int item, X0, Y0, nsub;
 };
 
 __device__ __forceinline__ PyrTile decode_tile(const PyrItem* __restrict__ items, int nitems, int t) {
@@ -214,25 +216,28 @@ __device__ __forceinline__ PyrTile decode_tile(const PyrItem* __restrict__ items
   const int lt = t - it.tile_begin;
   const int tyi = lt / it.tiles_x, txi = lt - tyi * it.tiles_x;
   d.X0 = it.tile_x0 + txi * kPyrTX;
-  d.Y0 = it.tile_y0 + tyi * kPyrTY;
+  d.Y0 = it.tile_y0 + tyi * (kPyrTY * it.sub);
+  d.nsub = min(it.sub, it.rows16 - tyi * it.sub);
   return d;
 }
 
+template <int N>
+struct Rows {
+  static constexpr int value = N;
+};
+
 template <typename T, bool EMIT_LAP, bool WARP>
 __global__ void __launch_bounds__(kThreads, 3) k_pyr(const PyrItem* __restrict__ items, int nitems, int ntiles,
-                                                  FrameArgs fa) {
+                                                     FrameArgs fa) {
   constexpr int TX = kPyrTX, TY = kPyrTY;
-  constexpr int EW = TX + 7, EH = TY + 7;            // staged fine samples: 4 before, 3 after
+  constexpr int EW = TX + 7, EH = TY + 7;            // staged window: 4 before, 3 after
   constexpr int SW = 72;                             // LDS row strides are 16-byte multiples
   constexpr int CW = TX / 2 + 2, CH = TY / 2 + 2;    // coarse tile + one-sample halo
   constexpr int HS = 36, ES = TX + 4;
-  constexpr int NE = EH * EW;
-  constexpr int NIT = (NE + kThreads - 1) / kThreads;
-  static_assert(3 * CH * ES <= 4 * EH * HS, "sE must fit in sH");
-  __shared__ __attribute__((aligned(16))) float sIn[4][EH][SW];
-  __shared__ __attribute__((aligned(16))) float sH[4][EH][HS];
+  __shared__ __attribute__((aligned(16))) float sIn[4][EH][SW];   // rows: ring
+  __shared__ __attribute__((aligned(16))) float sH[4][EH][HS];    // rows: ring
   __shared__ __attribute__((aligned(16))) float sC[3][CH][HS];
-  float(*sE)[CH][ES] = reinterpret_cast<float(*)[CH][ES]>(&sH[0][0][0]);   // sH is dead once sC is built
+  __shared__ __attribute__((aligned(16))) float sE[3][CH][ES];
 
   const int tid = threadIdx.x;
   // ---- schedule ----
@@ -251,43 +256,10 @@ __global__ void __launch_bounds__(kThreads, 3) k_pyr(const PyrItem* __restrict__
     stride = G;
   }
 
-  // ---- prefetched global data of the next tile (registers) ----
-  uint32_t pm[WARP ? NIT : 1];         // warp: seam weights (uint8)
-  float pg[WARP ? 1 : NIT][4];         // planes: G_k channels and Gm_k
-
-  // tile-independent sample positions of this thread: (row << 8) | column, -1 past the end
-  int rc[NIT];
-#pragma unroll
-  for (int q = 0; q < NIT; ++q) {
-    const int e = tid + q * kThreads;
-    rc[q] = e < NE ? ((e / EW) << 8) | (e % EW) : -1;
-  }
-  float cfq[NIT], rfq[NIT];             // the same positions as floats (exact)
-#pragma unroll
-  for (int q = 0; q < NIT; ++q) {
-    cfq[q] = (float)(rc[q] < 0 ? 0 : rc[q] & 255);
-    rfq[q] = (float)(rc[q] < 0 ? 0 : rc[q] >> 8);
-  }
-  // canvas position of staged sample q (folded at canvas edges unless the tile is interior)
-  auto sample_pos = [&](int q, int X0, int Y0, bool interior, int fw, int fh, int& X, int& Y) {
-    const int r = rc[q] < 0 ? 0 : rc[q] >> 8, c = rc[q] < 0 ? 0 : rc[q] & 255;
-    X = X0 - 4 + c;
-    Y = Y0 - 4 + r;
-    if (!interior) {
-      X = fold(X, fw);
-      Y = fold(Y, fh);
-    }
-  };
-  // tile-independent work items of stages B, C, D: (channel slot << 16) | (row << 8) | column group
-  constexpr int PB = EH * (CW / 2), NB = (4 * PB + kThreads - 1) / kThreads;
+  // tile-independent work items of stages C and D: (channel slot << 16) | (row << 8) | column group
   constexpr int PC = (CH / 2) * (CW / 2), NCI = (4 * PC + kThreads - 1) / kThreads;
   constexpr int PD = CH * (TX / 4), ND = (3 * PD + kThreads - 1) / kThreads;
-  int itB[NB], itC[NCI], itD[ND];
-#pragma unroll
-  for (int q = 0; q < NB; ++q) {
-    const int e = tid + q * kThreads, ci = e / PB, rem = e - ci * PB;
-    itB[q] = (ci << 16) | ((rem / (CW / 2)) << 8) | (rem % (CW / 2));
-  }
+  int itC[NCI], itD[ND];
 #pragma unroll
   for (int q = 0; q < NCI; ++q) {
     const int e = tid + q * kThreads, ci = e / PC, rem = e - ci * PC;
@@ -299,347 +271,368 @@ __global__ void __launch_bounds__(kThreads, 3) k_pyr(const PyrItem* __restrict__
     itD[q] = (ci << 16) | ((rem / (TX / 4)) << 8) | (rem % (TX / 4));
   }
 
-  auto prefetch = [&](int tt) {
-    const PyrTile d = decode_tile(items, nitems, tt);
-    const CST PyrItem& it = cst(items)[d.item];
-    const int fw = it.fine_w, fh = it.fine_h;
-    const int rx = it.roi_x, ry = it.roi_y, rw = it.roi_w, rh = it.roi_h;
-    const bool interior = d.X0 >= 4 && d.X0 + TX + 3 <= fw && d.Y0 >= 4 && d.Y0 + TY + 3 <= fh;
-    if (WARP) {
-      const GLB uint8_t* msk = cg<uint8_t>(it.msk);
-      const bool has_mask = it.msk_kind != kSrcNone;
-      const bool inside = interior && d.X0 - 4 >= rx && d.X0 + TX + 3 <= rx + rw && d.Y0 - 4 >= ry &&
-                          d.Y0 + TY + 3 <= ry + rh;
-      if (has_mask && inside) {   // every sample of the tile lies in the stored weight rectangle
-        const GLB uint8_t* m0 = msk + (int64_t)(d.Y0 - 4 - ry) * it.msk_row + (d.X0 - 4 - rx);
-        const uint32_t mrow = (uint32_t)it.msk_row;
-#pragma unroll
-        for (int q = 0; q < NIT; ++q) {
-          const int r = rc[q] < 0 ? 0 : rc[q] >> 8, c = rc[q] < 0 ? 0 : rc[q] & 255;
-          pm[q] = m0[__umul24((uint32_t)r, mrow) + (uint32_t)c];
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < NIT; ++q) {
-          int X, Y;
-          sample_pos(q, d.X0, d.Y0, interior, fw, fh, X, Y);
-          const int my = Y - ry, mx = X - rx;
-          const bool in = has_mask && my >= 0 && my < rh && mx >= 0 && mx < rw;
-          const uint32_t m = has_mask ? (uint32_t)msk[in ? (int64_t)my * it.msk_row + mx : 0] : 0u;
-          pm[q] = in ? m : 0u;
-        }
-      }
-    } else {
-      const GLB T* g = cg<T>(it.img);
-      const GLB T* m = cg<T>(it.msk);
-      const int nimg = it.img_kind == kSrcNone ? 0 : it.nch;
-      const bool has_mask = it.msk_kind != kSrcNone;
-#pragma unroll
-      for (int q = 0; q < NIT; ++q) {
-        int X, Y;
-        sample_pos(q, d.X0, d.Y0, interior, fw, fh, X, Y);
-        Y -= ry;
-        X -= rx;
-        const bool in = X >= 0 && X < rw && Y >= 0 && Y < rh;
-        const int64_t off = in ? (int64_t)Y * it.img_row + X : 0;
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) pg[q][ch] = ch < nimg ? ldg(g, ch * it.img_plane + off) : 0.0f;
-        pg[q][3] = has_mask ? ldg(m, in ? (int64_t)Y * it.msk_row + X : 0) : 0.0f;
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch) pg[q][ch] = in ? pg[q][ch] : 0.0f;
-      }
-    }
-  };
-
-  if (t < t_end) prefetch(t);
   for (; t < t_end; t += stride) {
-    const int tn = t + stride;
     const PyrTile d = decode_tile(items, nitems, t);
     const CST PyrItem& it = cst(items)[d.item];
-    const int X0 = d.X0, Y0 = d.Y0;
+    const int X0 = d.X0;
     const int fw = it.fine_w, fh = it.fine_h;
     const int nimg = it.img_kind == kSrcNone ? 0 : it.nch;
     const bool has_mask = it.msk_kind != kSrcNone;
-    __syncthreads();   // the previous tile's readers of LDS are done
-
-    // ---- A: stage ----
-    const bool interior = X0 >= 4 && X0 + TX + 3 <= fw && Y0 >= 4 && Y0 + TY + 3 <= fh;
-    if (WARP) {
-      const GLB uint8_t* src = cg<uint8_t>(fa.n ? (const void*)fa.ptr[it.frame_slot] : it.img);
-      const int64_t srow = fa.n ? fa.row[it.frame_slot] : it.img_row;
-      const int w = it.frame_w, h = it.frame_h;
-      float hv[9];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) hv[i] = it.hinv[i];
-      uint32_t mreg[NIT];
-#pragma unroll
-      for (int q = 0; q < NIT; ++q) mreg[q] = pm[q];
-      if (tn < t_end) prefetch(tn);    // next tile's seam weights fly while this one computes
-      const float fwf = (float)w, fhf = (float)h, fwm1 = (float)(w - 1), fhm1 = (float)(h - 1);
-      const uint32_t srow32 = (uint32_t)srow;
-      const float X0m4 = (float)(X0 - 4), Y0m4 = (float)(Y0 - 4);
-      // Source-interior tile: z > 0 at the four corners of the staged rectangle (so on all
-      // of it: z is affine) and their source positions inside [1, w-3) x [1, h-2).  The map
-      // is projective there, so every staged sample lies in the convex hull of the corner
-      // images (up to FP32 rounding, far below the one-sample margin): its four taps are in
-      // the frame and the pair of taps of a row is one 8-byte read that ends inside the row.
-      // Source-exterior tile: z > 0 at the corners and all four corner images at least
-      // one sample beyond the same side of the frame (x <= -2, x >= w + 1, y <= -2 or
-      // y >= h + 1): every staged sample's taps are outside and its G_0 is exactly 0.
-      bool fast = false, outside = false;
-      if (interior) {
-        bool bad = false, zok = false, lft = false, rgt = false, top = false, bot = false;
-        const int lane = tid & 63;
-        if (lane < 4) {
-          float xc, yc, zc;
-          warp_coords_z(hv, X0m4 + (float)((lane & 1) ? EW - 1 : 0), Y0m4 + (float)((lane & 2) ? EH - 1 : 0), xc,
-                        yc, zc);
-          zok = zc >= 0x1p-10f && zc <= 0x1p20f;
-          bad = !(zok && xc >= 1.0f && xc < (float)(w - 3) && yc >= 1.0f && yc < (float)(h - 2));
-          lft = xc <= -2.0f;
-          rgt = xc >= (float)(w + 1);
-          top = yc <= -2.0f;
-          bot = yc >= (float)(h + 1);
-        }
-        // ballots are the same in every wave of the workgroup
-        fast = __ballot(bad) == 0ull;
-        outside = __ballot(zok) == 15ull &&
-                  (__ballot(lft) == 15ull || __ballot(rgt) == 15ull || __ballot(top) == 15ull ||
-                   __ballot(bot) == 15ull);
-      }
-      if (outside) {
-#pragma unroll
-        for (int q = 0; q < NIT; ++q) {
-          if (rc[q] >= 0) {
-            const int r = rc[q] >> 8, c = rc[q] & 255;
-            sIn[0][r][c] = 0.0f;
-            sIn[1][r][c] = 0.0f;
-            sIn[2][r][c] = 0.0f;
-            sIn[3][r][c] = (float)mreg[q] * kInv255;
-          }
-        }
-      } else if (fast) {
-        // every sample: coordinates and both row reads issued first, so a wave keeps
-        // 2 * NIT reads in flight; then the bilinear combination
-        unsigned long long ra[NIT], rb[NIT];
-        float fxq[NIT], fyq[NIT];
-#pragma unroll
-        for (int q = 0; q < NIT; ++q) {
-          // z lies between its corner values and x, y in [1, w) x [1, h): the in-range
-          // division is the IEEE one, x - floor(x) is exact and truncation is floor
-          float x, y;
-          warp_coords_in_range(hv, X0m4 + cfq[q], Y0m4 + rfq[q], x, y);
-          fxq[q] = __builtin_amdgcn_fractf(x);
-          fyq[q] = __builtin_amdgcn_fractf(y);
-          const uint32_t off = __umul24((uint32_t)(int)y, srow32) + 3u * (uint32_t)(int)x;
-          ra[q] = ld8(src + off);
-          rb[q] = ld8(src + off + srow32);
-        }
-#pragma unroll
-        for (int q = 0; q < NIT; ++q) {
-          const float fx = fxq[q], fy = fyq[q], gx = 1.0f - fx, gy = 1.0f - fy;
-          const float gyi = gy * kInv255, fyi = fy * kInv255;
-          const float w00 = gyi * gx, w01 = gyi * fx, w10 = fyi * gx, w11 = fyi * fx;
-          const uint32_t a0 = (uint32_t)ra[q], a1 = (uint32_t)(ra[q] >> 32);
-          const uint32_t b0 = (uint32_t)rb[q], b1 = (uint32_t)(rb[q] >> 32);
-          const float p00[3] = {(float)(a0 & 255u), (float)((a0 >> 8) & 255u), (float)((a0 >> 16) & 255u)};
-          const float p01[3] = {(float)(a0 >> 24), (float)(a1 & 255u), (float)((a1 >> 8) & 255u)};
-          const float p10[3] = {(float)(b0 & 255u), (float)((b0 >> 8) & 255u), (float)((b0 >> 16) & 255u)};
-          const float p11[3] = {(float)(b0 >> 24), (float)(b1 & 255u), (float)((b1 >> 8) & 255u)};
-          if (rc[q] >= 0) {
-            const int r = rc[q] >> 8, c = rc[q] & 255;
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch)
-              sIn[ch][r][c] = w00 * p00[ch] + w01 * p01[ch] + w10 * p10[ch] + w11 * p11[ch];
-            sIn[3][r][c] = (float)mreg[q] * kInv255;
-          }
-        }
-      } else {
-        // General tile (frame borders, canvas edges): taps outside the frame weigh 0.  Each
-        // row pair is still one 8-byte read, from a start clamped into [0, 3w - 8] of a row
-        // clamped into the frame (w >= 3), so no read leaves its row; the pair is shifted
-        // into place afterwards.  All reads are issued before any is used.
-        unsigned long long ra[NIT], rb[NIT];
-        float fxq[NIT], fyq[NIT];
-        uint32_t tapq[NIT];                       // bits: 00 01 10 11 inside, << 4: byte shift + 3
-        const uint32_t lastc = 3u * (uint32_t)w - 8u;
-#pragma unroll
-        for (int q = 0; q < NIT; ++q) {
-          float Xf, Yf;
-          if (interior) {
-            Xf = X0m4 + cfq[q];
-            Yf = Y0m4 + rfq[q];
-          } else {
-            int Xc, Yc;
-            sample_pos(q, X0, Y0, interior, fw, fh, Xc, Yc);
-            Xf = (float)Xc;
-            Yf = (float)Yc;
-          }
-          float x, y;
-          bool zpos;
-          warp_coords_f(hv, Xf, Yf, x, y, zpos);
-          const bool ok = zpos && x >= -1.0f && x < fwf && y >= -1.0f && y < fhf;
-          const float xs = ok ? x : 0.0f, ys = ok ? y : 0.0f;
-          const float x0f = floorf(xs), y0f = floorf(ys);
-          fxq[q] = xs - x0f;
-          fyq[q] = ys - y0f;
-          const bool xa = ok && x0f >= 0.0f, xb = ok && x0f < fwm1, ya = y0f >= 0.0f, yb = y0f < fhm1;
-          const int x0 = (int)x0f, y0 = (int)y0f;                 // x0 >= -1, y0 >= -1
-          const int c3 = 3 * x0;
-          const uint32_t start = (uint32_t)min(max(c3, 0), (int)lastc);
-          const uint32_t r0 = (uint32_t)max(y0, 0), r1 = (uint32_t)min(y0 + 1, h - 1);
-          tapq[q] = (uint32_t)(ya && xa) | ((uint32_t)(ya && xb) << 1) | ((uint32_t)(yb && xa) << 2) |
-                    ((uint32_t)(yb && xb) << 3) | ((uint32_t)(c3 - (int)start + 3) << 4);
-          ra[q] = ld8(src + (__umul24(r0, srow32) + start));
-          rb[q] = ld8(src + (__umul24(r1, srow32) + start));
-        }
-#pragma unroll
-        for (int q = 0; q < NIT; ++q) {
-          const int sh = (int)(tapq[q] >> 4) - 3;                 // byte offset of tap 0: -3 .. 5
-          const unsigned long long a = sh >= 0 ? ra[q] >> (8 * sh) : ra[q] << 24;
-          const unsigned long long b = sh >= 0 ? rb[q] >> (8 * sh) : rb[q] << 24;
-          const float fx = fxq[q], fy = fyq[q], gx = 1.0f - fx, gy = 1.0f - fy;
-          const float gyi = gy * kInv255, fyi = fy * kInv255;
-          const uint32_t tp = tapq[q];
-          const float w00 = (tp & 1u) ? gyi * gx : 0.0f, w01 = (tp & 2u) ? gyi * fx : 0.0f;
-          const float w10 = (tp & 4u) ? fyi * gx : 0.0f, w11 = (tp & 8u) ? fyi * fx : 0.0f;
-          const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
-          const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
-          const float p00[3] = {(float)(a0 & 255u), (float)((a0 >> 8) & 255u), (float)((a0 >> 16) & 255u)};
-          const float p01[3] = {(float)(a0 >> 24), (float)(a1 & 255u), (float)((a1 >> 8) & 255u)};
-          const float p10[3] = {(float)(b0 & 255u), (float)((b0 >> 8) & 255u), (float)((b0 >> 16) & 255u)};
-          const float p11[3] = {(float)(b0 >> 24), (float)(b1 & 255u), (float)((b1 >> 8) & 255u)};
-          if (rc[q] >= 0) {
-            const int r = rc[q] >> 8, c = rc[q] & 255;
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch)
-              sIn[ch][r][c] = w00 * p00[ch] + w01 * p01[ch] + w10 * p10[ch] + w11 * p11[ch];
-            sIn[3][r][c] = (float)mreg[q] * kInv255;
-          }
-        }
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < NIT; ++q) {
-        if (rc[q] >= 0) {
-          const int r = rc[q] >> 8, c = rc[q] & 255;
-#pragma unroll
-          for (int ch = 0; ch < 4; ++ch) sIn[ch][r][c] = pg[q][ch];
-        }
-      }
-      if (tn < t_end) prefetch(tn);
-    }
-    __syncthreads();
-
     const int nact = nimg + (has_mask ? 1 : 0);
-    // ---- B: horizontal REDUCE, coarse columns cx0 .. cx0+CW-1 of every staged row ----
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int ci = itB[q] >> 16;
-      if (ci < nact) {
-        const int ch = ci < nimg ? ci : 3;
-        const int r = (itB[q] >> 8) & 255, m = itB[q] & 255;
-        const float4 a = *reinterpret_cast<const float4*>(&sIn[ch][r][4 * m]);
-        const float4 bq = *reinterpret_cast<const float4*>(&sIn[ch][r][4 * m + 4]);
-        float2 o;
-        o.x = kW0 * (a.x + bq.x) + kW1 * (a.y + a.w) + kW2 * a.z;
-        o.y = kW0 * (a.z + bq.z) + kW1 * (a.w + bq.y) + kW2 * bq.x;
-        *reinterpret_cast<float2*>(&sH[ch][r][2 * m]) = o;
-      }
-    }
-    __syncthreads();
+    const int rx = it.roi_x, ry = it.roi_y, rw = it.roi_w, rh = it.roi_h;
 
-    // ---- C: vertical REDUCE -> extended coarse tile (2x2 outputs per item); store its interior ----
-    const int cx0 = X0 / 2 - 1, cy0 = Y0 / 2 - 1;      // coarse canvas coordinates of sC[.][0][0]
+    for (int s = 0; s < d.nsub; ++s) {
+      const int Y0 = d.Y0 + s * TY;
+      const int off = (s * TY) % EH;   // logical row r of the window lives in ring row (r + off) mod EH
+      auto ring = [off](int r) {
+        const int p = r + off;
+        return p >= EH ? p - EH : p;
+      };
+      const bool interior = X0 >= 4 && X0 + TX + 3 <= fw && Y0 >= 4 && Y0 + TY + 3 <= fh;
+      __syncthreads();   // the previous sub-step's readers of LDS are done
+
+      // ---- A: stage logical rows R0 .. R0+NR-1 ----
+      auto stage_a = [&](auto rows_c, auto r0_c) __attribute__((always_inline)) {
+        constexpr int NR = decltype(rows_c)::value;
+        constexpr int R0 = decltype(r0_c)::value;
+        constexpr int NE = NR * EW;
+        constexpr int NQ = (NE + kThreads - 1) / kThreads;
+        // recomputed per sub-step (cheap) rather than held in registers across the loop
+        int tid_l = tid;
+        asm volatile("" : "+v"(tid_l));
+        int rr[NQ], cc[NQ];                       // logical row (-1: idle slot) and column
 #pragma unroll
-    for (int q = 0; q < NCI; ++q) {
-      const int ci = itC[q] >> 16;
-      if (ci < nact) {
-        const int ch = ci < nimg ? ci : 3;
-        const int pp = (itC[q] >> 8) & 255, jp = itC[q] & 255;
-        float2 sv[7];
-#pragma unroll
-        for (int u = 0; u < 7; ++u) sv[u] = *reinterpret_cast<const float2*>(&sH[ch][4 * pp + u][2 * jp]);
-        float2 o0, o1;
-        o0.x = kW0 * (sv[0].x + sv[4].x) + kW1 * (sv[1].x + sv[3].x) + kW2 * sv[2].x;
-        o0.y = kW0 * (sv[0].y + sv[4].y) + kW1 * (sv[1].y + sv[3].y) + kW2 * sv[2].y;
-        o1.x = kW0 * (sv[2].x + sv[6].x) + kW1 * (sv[3].x + sv[5].x) + kW2 * sv[4].x;
-        o1.y = kW0 * (sv[2].y + sv[6].y) + kW1 * (sv[3].y + sv[5].y) + kW2 * sv[4].y;
-        if (ch < 3) {
-          *reinterpret_cast<float2*>(&sC[ch][2 * pp][2 * jp]) = o0;
-          *reinterpret_cast<float2*>(&sC[ch][2 * pp + 1][2 * jp]) = o1;
+        for (int q = 0; q < NQ; ++q) {
+          const int e = tid_l + q * kThreads;
+          rr[q] = e < NE ? R0 + e / EW : -1;
+          cc[q] = e < NE ? e % EW : 0;
         }
-        GLB T* out = ch < 3 ? mg<T>(it.g_out) : mg<T>(it.gm_out);
-        const int64_t orow = ch < 3 ? it.g_row : it.gm_row;
-        const int64_t obase = ch < 3 ? ch * it.g_plane : 0;
+        // canvas position of a slot (idle slots take the window's first sample)
+        auto canvas = [&](int q, int& X, int& Y) {
+          X = X0 - 4 + cc[q];
+          Y = Y0 - 4 + (rr[q] < 0 ? R0 : rr[q]);
+          if (!interior) {
+            X = fold(X, fw);
+            Y = fold(Y, fh);
+          }
+        };
+        if (WARP) {
+          const GLB uint8_t* src = cg<uint8_t>(fa.n ? (const void*)fa.ptr[it.frame_slot] : it.img);
+          const int64_t srow = fa.n ? fa.row[it.frame_slot] : it.img_row;
+          const int w = it.frame_w, h = it.frame_h;
+          float hv[9];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int i = 2 * pp + u;
-          const int cy = cy0 + i - it.croi_y;
-          const bool rowin = i >= 1 && i <= TY / 2 && cy >= 0 && cy < it.croi_h;
+          for (int i = 0; i < 9; ++i) hv[i] = it.hinv[i];
+          const uint32_t srow32 = (uint32_t)srow;
+          // seam weights (uint8 on the ROI, 0 outside): read first, used last
+          const GLB uint8_t* msk = cg<uint8_t>(it.msk);
+          uint32_t mv[NQ];
+          const bool inside = interior && X0 - 4 >= rx && X0 + TX + 3 <= rx + rw && Y0 - 4 + R0 >= ry &&
+                              Y0 - 4 + R0 + NR <= ry + rh;
+          if (has_mask && inside) {
+            const GLB uint8_t* m0 = msk + (int64_t)(Y0 - 4 + R0 - ry) * it.msk_row + (X0 - 4 - rx);
+            const uint32_t mrow = (uint32_t)it.msk_row;
 #pragma unroll
-          for (int v = 0; v < 2; ++v) {
-            const int j = 2 * jp + v;
-            const int cx = cx0 + j - it.croi_x;
-            if (rowin && j >= 1 && j <= TX / 2 && cx >= 0 && cx < it.croi_w)
-              stg(out, obase + (int64_t)cy * orow + cx, u ? (v ? o1.y : o1.x) : (v ? o0.y : o0.x));
+            for (int q = 0; q < NQ; ++q)
+              mv[q] = m0[__umul24((uint32_t)(rr[q] < 0 ? 0 : rr[q] - R0), mrow) + (uint32_t)cc[q]];
+          } else {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+              int X, Y;
+              canvas(q, X, Y);
+              const int my = Y - ry, mx = X - rx;
+              const bool in = has_mask && my >= 0 && my < rh && mx >= 0 && mx < rw;
+              const uint32_t m = has_mask ? (uint32_t)msk[in ? (int64_t)my * it.msk_row + mx : 0] : 0u;
+              mv[q] = in ? m : 0u;
+            }
+          }
+          const float fwf = (float)w, fhf = (float)h, fwm1 = (float)(w - 1), fhm1 = (float)(h - 1);
+          const float X0m4 = (float)(X0 - 4), Y0m4 = (float)(Y0 - 4);
+          // Source-interior window: z > 0 at its four corners (so on all of it: z is affine)
+          // and their source positions inside [1, w-3) x [1, h-2).  The map is projective
+          // there, so every staged sample lies in the convex hull of the corner images (up
+          // to FP32 rounding, far below the one-sample margin): its four taps are in the
+          // frame and the pair of taps of a row is one 8-byte read that ends inside the row.
+          // Source-exterior window: z > 0 at the corners and all four corner images at
+          // least one sample beyond the same side of the frame (x <= -2, x >= w + 1,
+          // y <= -2 or y >= h + 1): every staged sample's taps are outside, its G_0 is 0.
+          bool fast = false, outside = false;
+          if (interior) {
+            bool bad = false, zok = false, lft = false, rgt = false, top = false, bot = false;
+            const int lane = tid & 63;
+            if (lane < 4) {
+              float xc, yc, zc;
+              warp_coords_z(hv, X0m4 + (float)((lane & 1) ? EW - 1 : 0),
+                            Y0m4 + (float)((lane & 2) ? R0 + NR - 1 : R0), xc, yc, zc);
+              zok = zc >= 0x1p-10f && zc <= 0x1p20f;
+              bad = !(zok && xc >= 1.0f && xc < (float)(w - 3) && yc >= 1.0f && yc < (float)(h - 2));
+              lft = xc <= -2.0f;
+              rgt = xc >= (float)(w + 1);
+              top = yc <= -2.0f;
+              bot = yc >= (float)(h + 1);
+            }
+            // ballots are the same in every wave of the workgroup
+            fast = __ballot(bad) == 0ull;
+            outside = __ballot(zok) == 15ull &&
+                      (__ballot(lft) == 15ull || __ballot(rgt) == 15ull || __ballot(top) == 15ull ||
+                       __ballot(bot) == 15ull);
+          }
+          if (outside) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+              if (rr[q] >= 0) {
+                const int r = ring(rr[q]), c = cc[q];
+                sIn[0][r][c] = 0.0f;
+                sIn[1][r][c] = 0.0f;
+                sIn[2][r][c] = 0.0f;
+                sIn[3][r][c] = (float)mv[q] * kInv255;
+              }
+            }
+          } else if (fast) {
+            // every sample: coordinates and both row reads issued first, so a wave keeps
+            // 2 * NQ reads in flight; then the bilinear combination
+            unsigned long long ra[NQ], rb[NQ];
+            float fxq[NQ], fyq[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+              // z lies between its corner values and x, y in [1, w) x [1, h): the in-range
+              // division is the IEEE one, x - floor(x) is exact and truncation is floor
+              float x, y;
+              warp_coords_in_range(hv, X0m4 + (float)cc[q], Y0m4 + (float)(rr[q] < 0 ? R0 : rr[q]), x, y);
+              fxq[q] = __builtin_amdgcn_fractf(x);
+              fyq[q] = __builtin_amdgcn_fractf(y);
+              const uint32_t o = __umul24((uint32_t)(int)y, srow32) + 3u * (uint32_t)(int)x;
+              ra[q] = ld8(src + o);
+              rb[q] = ld8(src + o + srow32);
+            }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+              const float fx = fxq[q], fy = fyq[q], gx = 1.0f - fx, gy = 1.0f - fy;
+              const float gyi = gy * kInv255, fyi = fy * kInv255;
+              const float w00 = gyi * gx, w01 = gyi * fx, w10 = fyi * gx, w11 = fyi * fx;
+              const uint32_t a0 = (uint32_t)ra[q], a1 = (uint32_t)(ra[q] >> 32);
+              const uint32_t b0 = (uint32_t)rb[q], b1 = (uint32_t)(rb[q] >> 32);
+              const float p00[3] = {(float)(a0 & 255u), (float)((a0 >> 8) & 255u), (float)((a0 >> 16) & 255u)};
+              const float p01[3] = {(float)(a0 >> 24), (float)(a1 & 255u), (float)((a1 >> 8) & 255u)};
+              const float p10[3] = {(float)(b0 & 255u), (float)((b0 >> 8) & 255u), (float)((b0 >> 16) & 255u)};
+              const float p11[3] = {(float)(b0 >> 24), (float)(b1 & 255u), (float)((b1 >> 8) & 255u)};
+              if (rr[q] >= 0) {
+                const int r = ring(rr[q]), c = cc[q];
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch)
+                  sIn[ch][r][c] = w00 * p00[ch] + w01 * p01[ch] + w10 * p10[ch] + w11 * p11[ch];
+                sIn[3][r][c] = (float)mv[q] * kInv255;
+              }
+            }
+          } else {
+            // General window (frame borders, canvas edges): taps outside the frame weigh
+            // 0.  Each row pair is still one 8-byte read, from a start clamped into
+            // [0, 3w - 8] of a row clamped into the frame (w >= 3), so no read leaves its
+            // row; the pair is shifted into place afterwards.
+            unsigned long long ra[NQ], rb[NQ];
+            float fxq[NQ], fyq[NQ];
+            uint32_t tapq[NQ];                   // bits: 00 01 10 11 inside, << 4: byte shift + 3
+            const uint32_t lastc = 3u * (uint32_t)w - 8u;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+              int Xc, Yc;
+              canvas(q, Xc, Yc);
+              float x, y;
+              bool zpos;
+              warp_coords_f(hv, (float)Xc, (float)Yc, x, y, zpos);
+              const bool ok = zpos && x >= -1.0f && x < fwf && y >= -1.0f && y < fhf;
+              const float xs = ok ? x : 0.0f, ys = ok ? y : 0.0f;
+              const float x0f = floorf(xs), y0f = floorf(ys);
+              fxq[q] = xs - x0f;
+              fyq[q] = ys - y0f;
+              const bool xa = ok && x0f >= 0.0f, xb = ok && x0f < fwm1, ya = y0f >= 0.0f, yb = y0f < fhm1;
+              const int x0 = (int)x0f, y0 = (int)y0f;              // x0 >= -1, y0 >= -1
+              const int c3 = 3 * x0;
+              const uint32_t start = (uint32_t)min(max(c3, 0), (int)lastc);
+              const uint32_t r0 = (uint32_t)max(y0, 0), r1 = (uint32_t)min(y0 + 1, h - 1);
+              tapq[q] = (uint32_t)(ya && xa) | ((uint32_t)(ya && xb) << 1) | ((uint32_t)(yb && xa) << 2) |
+                        ((uint32_t)(yb && xb) << 3) | ((uint32_t)(c3 - (int)start + 3) << 4);
+              ra[q] = ld8(src + (__umul24(r0, srow32) + start));
+              rb[q] = ld8(src + (__umul24(r1, srow32) + start));
+            }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+              const int sh = (int)(tapq[q] >> 4) - 3;              // byte offset of tap 0: -3 .. 5
+              const unsigned long long a = sh >= 0 ? ra[q] >> (8 * sh) : ra[q] << 24;
+              const unsigned long long bq = sh >= 0 ? rb[q] >> (8 * sh) : rb[q] << 24;
+              const float fx = fxq[q], fy = fyq[q], gx = 1.0f - fx, gy = 1.0f - fy;
+              const float gyi = gy * kInv255, fyi = fy * kInv255;
+              const uint32_t tp = tapq[q];
+              const float w00 = (tp & 1u) ? gyi * gx : 0.0f, w01 = (tp & 2u) ? gyi * fx : 0.0f;
+              const float w10 = (tp & 4u) ? fyi * gx : 0.0f, w11 = (tp & 8u) ? fyi * fx : 0.0f;
+              const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+              const uint32_t b0 = (uint32_t)bq, b1 = (uint32_t)(bq >> 32);
+              const float p00[3] = {(float)(a0 & 255u), (float)((a0 >> 8) & 255u), (float)((a0 >> 16) & 255u)};
+              const float p01[3] = {(float)(a0 >> 24), (float)(a1 & 255u), (float)((a1 >> 8) & 255u)};
+              const float p10[3] = {(float)(b0 & 255u), (float)((b0 >> 8) & 255u), (float)((b0 >> 16) & 255u)};
+              const float p11[3] = {(float)(b0 >> 24), (float)(b1 & 255u), (float)((b1 >> 8) & 255u)};
+              if (rr[q] >= 0) {
+                const int r = ring(rr[q]), c = cc[q];
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch)
+                  sIn[ch][r][c] = w00 * p00[ch] + w01 * p01[ch] + w10 * p10[ch] + w11 * p11[ch];
+                sIn[3][r][c] = (float)mv[q] * kInv255;
+              }
+            }
+          }
+        } else {
+          // stored G_k planes and Gm_k on the ROI (0 outside): all reads first
+          const GLB T* g = cg<T>(it.img);
+          const GLB T* m = cg<T>(it.msk);
+          float v[NQ][4];
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            int X, Y;
+            canvas(q, X, Y);
+            Y -= ry;
+            X -= rx;
+            const bool in = X >= 0 && X < rw && Y >= 0 && Y < rh;
+            const int64_t o = in ? (int64_t)Y * it.img_row + X : 0;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) v[q][ch] = ch < nimg ? ldg(g, ch * it.img_plane + o) : 0.0f;
+            v[q][3] = has_mask ? ldg(m, in ? (int64_t)Y * it.msk_row + X : 0) : 0.0f;
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) v[q][ch] = in ? v[q][ch] : 0.0f;
+          }
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            if (rr[q] >= 0) {
+              const int r = ring(rr[q]), c = cc[q];
+#pragma unroll
+              for (int ch = 0; ch < 4; ++ch) sIn[ch][r][c] = v[q][ch];
+            }
+          }
+        }
+      };
+      // ---- B: horizontal REDUCE of logical rows R0 .. R0+NR-1, coarse columns cx0 .. cx0+CW-1 ----
+      auto stage_b = [&](auto rows_c, auto r0_c) __attribute__((always_inline)) {
+        constexpr int NR = decltype(rows_c)::value;
+        constexpr int R0 = decltype(r0_c)::value;
+        constexpr int PB = NR * (CW / 2), NB = (4 * PB + kThreads - 1) / kThreads;
+        int tid_l = tid;
+        asm volatile("" : "+v"(tid_l));
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          const int e = tid_l + q * kThreads, ci = e / PB;
+          if (ci < nact) {
+            const int rem = e - ci * PB;
+            const int ch = ci < nimg ? ci : 3;
+            const int r = ring(R0 + rem / (CW / 2)), mm = rem % (CW / 2);
+            const float4 a = *reinterpret_cast<const float4*>(&sIn[ch][r][4 * mm]);
+            const float4 bq = *reinterpret_cast<const float4*>(&sIn[ch][r][4 * mm + 4]);
+            float2 o;
+            o.x = kW0 * (a.x + bq.x) + kW1 * (a.y + a.w) + kW2 * a.z;
+            o.y = kW0 * (a.z + bq.z) + kW1 * (a.w + bq.y) + kW2 * bq.x;
+            *reinterpret_cast<float2*>(&sH[ch][r][2 * mm]) = o;
+          }
+        }
+      };
+      // a tile's first sub-step also stages the 7 rows the ring would otherwise carry over
+      if (s == 0) stage_a(Rows<EH - TY>(), Rows<0>());
+      stage_a(Rows<TY>(), Rows<EH - TY>());
+      __syncthreads();
+      if (s == 0) stage_b(Rows<EH - TY>(), Rows<0>());
+      stage_b(Rows<TY>(), Rows<EH - TY>());
+      __syncthreads();
+
+      // ---- C: vertical REDUCE -> extended coarse tile (2x2 outputs per item); store its interior ----
+      const int cx0 = X0 / 2 - 1, cy0 = Y0 / 2 - 1;      // coarse canvas coordinates of sC[.][0][0]
+#pragma unroll
+      for (int q = 0; q < NCI; ++q) {
+        const int ci = itC[q] >> 16;
+        if (ci < nact) {
+          const int ch = ci < nimg ? ci : 3;
+          const int pp = (itC[q] >> 8) & 255, jp = itC[q] & 255;
+          float2 sv[7];
+#pragma unroll
+          for (int u = 0; u < 7; ++u) sv[u] = *reinterpret_cast<const float2*>(&sH[ch][ring(4 * pp + u)][2 * jp]);
+          float2 o0, o1;
+          o0.x = kW0 * (sv[0].x + sv[4].x) + kW1 * (sv[1].x + sv[3].x) + kW2 * sv[2].x;
+          o0.y = kW0 * (sv[0].y + sv[4].y) + kW1 * (sv[1].y + sv[3].y) + kW2 * sv[2].y;
+          o1.x = kW0 * (sv[2].x + sv[6].x) + kW1 * (sv[3].x + sv[5].x) + kW2 * sv[4].x;
+          o1.y = kW0 * (sv[2].y + sv[6].y) + kW1 * (sv[3].y + sv[5].y) + kW2 * sv[4].y;
+          if (ch < 3) {
+            *reinterpret_cast<float2*>(&sC[ch][2 * pp][2 * jp]) = o0;
+            *reinterpret_cast<float2*>(&sC[ch][2 * pp + 1][2 * jp]) = o1;
+          }
+          GLB T* out = ch < 3 ? mg<T>(it.g_out) : mg<T>(it.gm_out);
+          const int64_t orow = ch < 3 ? it.g_row : it.gm_row;
+          const int64_t obase = ch < 3 ? ch * it.g_plane : 0;
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int i = 2 * pp + u;
+            const int cy = cy0 + i - it.croi_y;
+            const bool rowin = i >= 1 && i <= TY / 2 && cy >= 0 && cy < it.croi_h;
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+              const int j = 2 * jp + v;
+              const int cx = cx0 + j - it.croi_x;
+              if (rowin && j >= 1 && j <= TX / 2 && cx >= 0 && cx < it.croi_w)
+                stg(out, obase + (int64_t)cy * orow + cx, u ? (v ? o1.y : o1.x) : (v ? o0.y : o0.x));
+            }
           }
         }
       }
-    }
-    if (!EMIT_LAP) continue;
-    const bool lap_tile = it.lw_w > 0 && X0 < it.lw_x + it.lw_w && X0 + TX > it.lw_x && Y0 < it.lw_y + it.lw_h &&
-                          Y0 + TY > it.lw_y;
-    if (!lap_tile) continue;
-    __syncthreads();
+      if (!EMIT_LAP) continue;
+      const bool lap_tile = it.lw_w > 0 && X0 < it.lw_x + it.lw_w && X0 + TX > it.lw_x &&
+                            Y0 < it.lw_y + it.lw_h && Y0 + TY > it.lw_y;
+      if (!lap_tile) continue;
+      __syncthreads();
 
-    // ---- D: horizontal EXPAND, four fine columns per item ----
+      // ---- D: horizontal EXPAND, four fine columns per item ----
 #pragma unroll
-    for (int q = 0; q < ND; ++q) {
-      const int ch = itD[q] >> 16;
-      if (ch < nimg) {
-        const int i = (itD[q] >> 8) & 255, m = itD[q] & 255;
-        const float2 lo = *reinterpret_cast<const float2*>(&sC[ch][i][2 * m]);
-        const float2 hi = *reinterpret_cast<const float2*>(&sC[ch][i][2 * m + 2]);
-        float4 o;
-        o.x = 0.125f * (lo.x + hi.x) + 0.75f * lo.y;
-        o.y = 0.5f * (lo.y + hi.x);
-        o.z = 0.125f * (lo.y + hi.y) + 0.75f * hi.x;
-        o.w = 0.5f * (hi.x + hi.y);
-        *reinterpret_cast<float4*>(&sE[ch][i][4 * m]) = o;
-      }
-    }
-    __syncthreads();
-
-    // ---- E: vertical EXPAND and the band L_k = G_k - EXPAND(G_{k+1}), four columns per thread ----
-    {
-      const int y = tid >> 4, x = 4 * (tid & 15), yh = y >> 1;
-      const int Y = Y0 + y - it.lw_y, X = X0 + x - it.lw_x;
-      const bool rowin = Y >= 0 && Y < it.lw_h;
-      const bool full = rowin && X >= 0 && X + 3 < it.lw_w;
-      GLB T* lout = mg<T>(it.l_out);
-      for (int ch = 0; ch < nimg; ++ch) {
-        const float4 s1 = *reinterpret_cast<const float4*>(&sE[ch][yh + 1][x]);
-        const float4 s2 = *reinterpret_cast<const float4*>(&sE[ch][yh + 2][x]);
-        float4 ev;
-        if (y & 1) {
-          ev.x = 0.5f * (s1.x + s2.x); ev.y = 0.5f * (s1.y + s2.y);
-          ev.z = 0.5f * (s1.z + s2.z); ev.w = 0.5f * (s1.w + s2.w);
-        } else {
-          const float4 s0 = *reinterpret_cast<const float4*>(&sE[ch][yh][x]);
-          ev.x = 0.125f * (s0.x + s2.x) + 0.75f * s1.x; ev.y = 0.125f * (s0.y + s2.y) + 0.75f * s1.y;
-          ev.z = 0.125f * (s0.z + s2.z) + 0.75f * s1.z; ev.w = 0.125f * (s0.w + s2.w) + 0.75f * s1.w;
+      for (int q = 0; q < ND; ++q) {
+        const int ch = itD[q] >> 16;
+        if (ch < nimg) {
+          const int i = (itD[q] >> 8) & 255, mm = itD[q] & 255;
+          const float2 lo = *reinterpret_cast<const float2*>(&sC[ch][i][2 * mm]);
+          const float2 hi = *reinterpret_cast<const float2*>(&sC[ch][i][2 * mm + 2]);
+          float4 o;
+          o.x = 0.125f * (lo.x + hi.x) + 0.75f * lo.y;
+          o.y = 0.5f * (lo.y + hi.x);
+          o.z = 0.125f * (lo.y + hi.y) + 0.75f * hi.x;
+          o.w = 0.5f * (hi.x + hi.y);
+          *reinterpret_cast<float4*>(&sE[ch][i][4 * mm]) = o;
         }
-        const float4 g = *reinterpret_cast<const float4*>(&sIn[ch][y + 4][x + 4]);
-        const float l[4] = {g.x - ev.x, g.y - ev.y, g.z - ev.z, g.w - ev.w};
-        const int64_t base = ch * it.l_plane + (int64_t)Y * it.l_row + X;
-        if (full) {
+      }
+      __syncthreads();
+
+      // ---- E: vertical EXPAND and the band L_k = G_k - EXPAND(G_{k+1}), four columns per thread ----
+      {
+        const int y = tid >> 4, x = 4 * (tid & 15), yh = y >> 1;
+        const int Y = Y0 + y - it.lw_y, X = X0 + x - it.lw_x;
+        const bool rowin = Y >= 0 && Y < it.lw_h;
+        const bool full = rowin && X >= 0 && X + 3 < it.lw_w;
+        const int gr = ring(y + 4);
+        GLB T* lout = mg<T>(it.l_out);
+        for (int ch = 0; ch < nimg; ++ch) {
+          const float4 s1 = *reinterpret_cast<const float4*>(&sE[ch][yh + 1][x]);
+          const float4 s2 = *reinterpret_cast<const float4*>(&sE[ch][yh + 2][x]);
+          float4 ev;
+          if (y & 1) {
+            ev.x = 0.5f * (s1.x + s2.x); ev.y = 0.5f * (s1.y + s2.y);
+            ev.z = 0.5f * (s1.z + s2.z); ev.w = 0.5f * (s1.w + s2.w);
+          } else {
+            const float4 s0 = *reinterpret_cast<const float4*>(&sE[ch][yh][x]);
+            ev.x = 0.125f * (s0.x + s2.x) + 0.75f * s1.x; ev.y = 0.125f * (s0.y + s2.y) + 0.75f * s1.y;
+            ev.z = 0.125f * (s0.z + s2.z) + 0.75f * s1.z; ev.w = 0.125f * (s0.w + s2.w) + 0.75f * s1.w;
+          }
+          const float4 g = *reinterpret_cast<const float4*>(&sIn[ch][gr][x + 4]);
+          const float l[4] = {g.x - ev.x, g.y - ev.y, g.z - ev.z, g.w - ev.w};
+          const int64_t base = ch * it.l_plane + (int64_t)Y * it.l_row + X;
+          if (full) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u) stg(lout, base + u, l[u]);
-        } else if (rowin) {
+            for (int u = 0; u < 4; ++u) stg(lout, base + u, l[u]);
+          } else if (rowin) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (X + u >= 0 && X + u < it.lw_w) stg(lout, base + u, l[u]);
+            for (int u = 0; u < 4; ++u)
+              if (X + u >= 0 && X + u < it.lw_w) stg(lout, base + u, l[u]);
+          }
         }
       }
     }

@@ -305,6 +305,24 @@ stitch_status upload(void* dst, const void* src, size_t bytes, hipStream_t s, co
   return e == hipSuccess ? STITCH_OK : hip_fail(e, what);
 }
 
+// Sub-steps per pyramid tile (tile height 16 * sub) for a launch of t16 16-row tiles: the
+// tallest (fewest staged halo rows) that still leaves about eight tiles per compute unit.
+int choose_sub(int64_t t16) {
+  for (int sub = 8; sub > 1; sub >>= 1)
+    if (t16 / sub >= 2048) return sub;
+  return 1;
+}
+
+void set_sub(std::vector<PyrItem>& items, int sub, int& tiles) {
+  tiles = 0;
+  for (PyrItem& it : items) {
+    it.sub = sub;
+    it.tiles_y = (it.rows16 + sub - 1) / sub;
+    it.tile_begin = tiles;
+    tiles += it.tiles_x * it.tiles_y;
+  }
+}
+
 // Fill the pyramid-pass and blend tables of a plan whose workspace base is ws.
 void build_tables(stitch_plan* p) {
   uint8_t* ws = p->ws;
@@ -320,7 +338,9 @@ void build_tables(stitch_plan* p) {
       std::memset(&it, 0, sizeof it);
       it.tile_begin = tiles;
       it.tiles_x = (r.w + kPyrTX - 1) / kPyrTX;
-      it.tiles_y = (r.h + kPyrTY - 1) / kPyrTY;
+      it.rows16 = (r.h + kPyrTY - 1) / kPyrTY;
+      it.sub = 1;
+      it.tiles_y = it.rows16;
       it.tile_x0 = r.x;
       it.tile_y0 = r.y;
       it.fine_w = p->dw[k];
@@ -362,6 +382,7 @@ void build_tables(stitch_plan* p) {
       tiles += it.tiles_x * it.tiles_y;
       p->items[k].push_back(it);
     }
+    set_sub(p->items[k], choose_sub(tiles), tiles);
     p->tiles[k] = tiles;
   }
   for (int k = 0; k < L; ++k) {
@@ -543,6 +564,8 @@ stitch_status stitch_pyramid(const stitch_image* g0, int32_t kind, stitch_levels
     const int x1 = std::max(fx + f.width, 2 * (cx + c.width)), y1 = std::max(fy + f.height, 2 * (cy + c.height));
     it.tiles_x = (x1 - x0 + kPyrTX - 1) / kPyrTX;
     it.tiles_y = (y1 - y0 + kPyrTY - 1) / kPyrTY;
+    it.rows16 = it.tiles_y;
+    it.sub = 1;
     it.tile_x0 = x0;
     it.tile_y0 = y0;
     it.fine_w = dw[k];
@@ -1201,6 +1224,12 @@ stitch_status stitch_batch_create(int32_t njobs, stitch_plan* const* plans, stit
         }
         b->pyr[k].push_back(it);
       }
+  }
+  // one sub-step choice per pass, from the batch's own 16-row tile count
+  for (int k = 0; k + 1 < b->maxL; ++k) {
+    int64_t t16 = 0;
+    for (const PyrItem& it : b->pyr[k]) t16 += (int64_t)it.tiles_x * it.rows16;
+    set_sub(b->pyr[k], choose_sub(t16), b->pyr_tiles[k]);
   }
   // blends: level-0 items in job order, so blend[0][j] belongs to job j
   for (int k = 0; k < b->maxL; ++k)

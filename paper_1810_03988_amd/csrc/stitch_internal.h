@@ -46,6 +46,8 @@ struct PyrItem {
   // Laplacian band at level k on the window lw (w == 0: not written)
   int32_t lw_x, lw_y, lw_w, lw_h;
   void* l_out;  int64_t l_row, l_plane;
+  // a tile is kPyrTX columns by sub * kPyrTY rows; rows16 = 16-row blocks of the item
+  int32_t sub, rows16;
 };
 
 // Per-call frame pointers of the fused level-0 pass (kernel argument).
