@@ -307,6 +307,13 @@ __global__ void __launch_bounds__(kThreads, 3) k_pyr(const PyrItem* __restrict__
           rr[q] = e < NE ? R0 + e / EW : -1;
           cc[q] = e < NE ? e % EW : 0;
         }
+        // LDS position of a slot: idle slots write the padding column EW (read by stage B's
+        // last float4 but never used), so stores need no branch and loads are never sunk
+        // into one
+        auto lds_pos = [&](int q, int& r, int& c) {
+          r = ring(rr[q] < 0 ? R0 : rr[q]);
+          c = rr[q] < 0 ? EW : cc[q];
+        };
         // canvas position of a slot (idle slots take the window's first sample)
         auto canvas = [&](int q, int& X, int& Y) {
           X = X0 - 4 + cc[q];
@@ -380,8 +387,9 @@ __global__ void __launch_bounds__(kThreads, 3) k_pyr(const PyrItem* __restrict__
           if (outside) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-              if (rr[q] >= 0) {
-                const int r = ring(rr[q]), c = cc[q];
+              {
+                int r, c;
+                lds_pos(q, r, c);
                 sIn[0][r][c] = 0.0f;
                 sIn[1][r][c] = 0.0f;
                 sIn[2][r][c] = 0.0f;
@@ -403,7 +411,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_pyr(const PyrItem* __restrict__
               fyq[q] = __builtin_amdgcn_fractf(y);
               const uint32_t o = __umul24((uint32_t)(int)y, srow32) + 3u * (uint32_t)(int)x;
               ra[q] = ld8(src + o);
-              rb[q] = ld8(src + o + srow32);
+              rb[q] = ld8(src + (o + srow32));
             }
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
@@ -416,8 +424,9 @@ __global__ void __launch_bounds__(kThreads, 3) k_pyr(const PyrItem* __restrict__
               const float p01[3] = {(float)(a0 >> 24), (float)(a1 & 255u), (float)((a1 >> 8) & 255u)};
               const float p10[3] = {(float)(b0 & 255u), (float)((b0 >> 8) & 255u), (float)((b0 >> 16) & 255u)};
               const float p11[3] = {(float)(b0 >> 24), (float)(b1 & 255u), (float)((b1 >> 8) & 255u)};
-              if (rr[q] >= 0) {
-                const int r = ring(rr[q]), c = cc[q];
+              {
+                int r, c;
+                lds_pos(q, r, c);
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch)
                   sIn[ch][r][c] = w00 * p00[ch] + w01 * p01[ch] + w10 * p10[ch] + w11 * p11[ch];
@@ -471,8 +480,9 @@ __global__ void __launch_bounds__(kThreads, 3) k_pyr(const PyrItem* __restrict__
               const float p01[3] = {(float)(a0 >> 24), (float)(a1 & 255u), (float)((a1 >> 8) & 255u)};
               const float p10[3] = {(float)(b0 & 255u), (float)((b0 >> 8) & 255u), (float)((b0 >> 16) & 255u)};
               const float p11[3] = {(float)(b0 >> 24), (float)(b1 & 255u), (float)((b1 >> 8) & 255u)};
-              if (rr[q] >= 0) {
-                const int r = ring(rr[q]), c = cc[q];
+              {
+                int r, c;
+                lds_pos(q, r, c);
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch)
                   sIn[ch][r][c] = w00 * p00[ch] + w01 * p01[ch] + w10 * p10[ch] + w11 * p11[ch];
@@ -501,8 +511,9 @@ __global__ void __launch_bounds__(kThreads, 3) k_pyr(const PyrItem* __restrict__
           }
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
-            if (rr[q] >= 0) {
-              const int r = ring(rr[q]), c = cc[q];
+            {
+              int r, c;
+              lds_pos(q, r, c);
 #pragma unroll
               for (int ch = 0; ch < 4; ++ch) sIn[ch][r][c] = v[q][ch];
             }
