@@ -200,9 +200,8 @@ __device__ __forceinline__ int find_item(const PyrItem* __restrict__ items, int 
 //      source frame at level 0, the stored G_k above) and the seam weight.  LDS rows form
 //      a ring of 23: the 7 rows a sub-step shares with the previous one stay where they
 //      are, so only its 16 new rows are staged (all 23 on a tile's first sub-step);
-//   B  horizontal REDUCE of the newly staged rows (two coarse outputs per thread from
-//      two b128 LDS reads);
-//   C  vertical REDUCE -> extended 34x10 coarse tile; its interior is G_{k+1} / Gm_{k+1};
+//   B+C  REDUCE -> extended 34x10 coarse tile (horizontal then vertical, in registers);
+//      its interior is G_{k+1} / Gm_{k+1};
 //   D  horizontal EXPAND of the coarse tile (four fine columns per thread);
 //   E  vertical EXPAND and L_k = G_k - EXPAND(G_{k+1}), stored on the band window.
 struct PyrTile {
@@ -227,7 +226,7 @@ struct Rows {
 };
 
 template <typename T, bool EMIT_LAP, bool WARP>
-__global__ void __launch_bounds__(kThreads, 3) k_pyr(const PyrItem* __restrict__ items, int nitems, int ntiles,
+__global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__ items, int nitems, int ntiles,
                                                      FrameArgs fa) {
   constexpr int TX = kPyrTX, TY = kPyrTY;
   constexpr int EW = TX + 7, EH = TY + 7;            // staged window: 4 before, 3 after
@@ -235,7 +234,6 @@ __global__ void __launch_bounds__(kThreads, 3) k_pyr(const PyrItem* __restrict__
   constexpr int CW = TX / 2 + 2, CH = TY / 2 + 2;    // coarse tile + one-sample halo
   constexpr int HS = 36, ES = TX + 4;
   __shared__ __attribute__((aligned(16))) float sIn[4][EH][SW];   // rows: ring
-  __shared__ __attribute__((aligned(16))) float sH[4][EH][HS];    // rows: ring
   __shared__ __attribute__((aligned(16))) float sC[3][CH][HS];
   __shared__ __attribute__((aligned(16))) float sE[3][CH][ES];
 
@@ -520,38 +518,13 @@ __global__ void __launch_bounds__(kThreads, 3) k_pyr(const PyrItem* __restrict__
           }
         }
       };
-      // ---- B: horizontal REDUCE of logical rows R0 .. R0+NR-1, coarse columns cx0 .. cx0+CW-1 ----
-      auto stage_b = [&](auto rows_c, auto r0_c) __attribute__((always_inline)) {
-        constexpr int NR = decltype(rows_c)::value;
-        constexpr int R0 = decltype(r0_c)::value;
-        constexpr int PB = NR * (CW / 2), NB = (4 * PB + kThreads - 1) / kThreads;
-        int tid_l = tid;
-        asm volatile("" : "+v"(tid_l));
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-          const int e = tid_l + q * kThreads, ci = e / PB;
-          if (ci < nact) {
-            const int rem = e - ci * PB;
-            const int ch = ci < nimg ? ci : 3;
-            const int r = ring(R0 + rem / (CW / 2)), mm = rem % (CW / 2);
-            const float4 a = *reinterpret_cast<const float4*>(&sIn[ch][r][4 * mm]);
-            const float4 bq = *reinterpret_cast<const float4*>(&sIn[ch][r][4 * mm + 4]);
-            float2 o;
-            o.x = kW0 * (a.x + bq.x) + kW1 * (a.y + a.w) + kW2 * a.z;
-            o.y = kW0 * (a.z + bq.z) + kW1 * (a.w + bq.y) + kW2 * bq.x;
-            *reinterpret_cast<float2*>(&sH[ch][r][2 * mm]) = o;
-          }
-        }
-      };
       // a tile's first sub-step also stages the 7 rows the ring would otherwise carry over
       if (s == 0) stage_a(Rows<EH - TY>(), Rows<0>());
       stage_a(Rows<TY>(), Rows<EH - TY>());
       __syncthreads();
-      if (s == 0) stage_b(Rows<EH - TY>(), Rows<0>());
-      stage_b(Rows<TY>(), Rows<EH - TY>());
-      __syncthreads();
 
-      // ---- C: vertical REDUCE -> extended coarse tile (2x2 outputs per item); store its interior ----
+      // ---- B+C: REDUCE -> extended coarse tile, 2x2 outputs per item (seven fine rows, each
+      //      reduced horizontally from two b128 LDS reads, then vertically); store its interior ----
       const int cx0 = X0 / 2 - 1, cy0 = Y0 / 2 - 1;      // coarse canvas coordinates of sC[.][0][0]
 #pragma unroll
       for (int q = 0; q < NCI; ++q) {
@@ -561,7 +534,13 @@ __global__ void __launch_bounds__(kThreads, 3) k_pyr(const PyrItem* __restrict__
           const int pp = (itC[q] >> 8) & 255, jp = itC[q] & 255;
           float2 sv[7];
 #pragma unroll
-          for (int u = 0; u < 7; ++u) sv[u] = *reinterpret_cast<const float2*>(&sH[ch][ring(4 * pp + u)][2 * jp]);
+          for (int u = 0; u < 7; ++u) {
+            const float* row = &sIn[ch][ring(4 * pp + u)][4 * jp];
+            const float4 a = *reinterpret_cast<const float4*>(row);
+            const float4 bq = *reinterpret_cast<const float4*>(row + 4);
+            sv[u].x = kW0 * (a.x + bq.x) + kW1 * (a.y + a.w) + kW2 * a.z;
+            sv[u].y = kW0 * (a.z + bq.z) + kW1 * (a.w + bq.y) + kW2 * bq.x;
+          }
           float2 o0, o1;
           o0.x = kW0 * (sv[0].x + sv[4].x) + kW1 * (sv[1].x + sv[3].x) + kW2 * sv[2].x;
           o0.y = kW0 * (sv[0].y + sv[4].y) + kW1 * (sv[1].y + sv[3].y) + kW2 * sv[2].y;
