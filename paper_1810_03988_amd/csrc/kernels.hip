@@ -58,6 +58,27 @@ __device__ __forceinline__ float ldg(const GLB _Float16* p, int64_t i) { return 
 __device__ __forceinline__ void stg(GLB float* p, int64_t i, float v) { p[i] = v; }
 __device__ __forceinline__ void stg(GLB _Float16* p, int64_t i, float v) { p[i] = (_Float16)v; }
 
+// Raw bits of a stored sample (zero-extended), converted separately: loads can then all be
+// issued before the first conversion.
+template <typename T> struct RawOf;
+template <> struct RawOf<float> { using type = uint32_t; };
+template <> struct RawOf<_Float16> { using type = uint16_t; };
+template <typename T>
+__device__ __forceinline__ typename RawOf<T>::type ld_raw(const GLB T* p, int64_t i) {
+  return *(const GLB typename RawOf<T>::type*)(p + i);
+}
+__device__ __forceinline__ float from_raw(uint32_t b) { return __builtin_bit_cast(float, b); }
+__device__ __forceinline__ float from_raw(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
+// Four consecutive samples with one store (caller checks the alignment).
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef _Float16 vh4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void stg4(GLB float* p, const float v[4]) {
+  *reinterpret_cast<GLB vf4*>(p) = vf4{v[0], v[1], v[2], v[3]};
+}
+__device__ __forceinline__ void stg4(GLB _Float16* p, const float v[4]) {
+  *reinterpret_cast<GLB vh4*>(p) = vh4{(_Float16)v[0], (_Float16)v[1], (_Float16)v[2], (_Float16)v[3]};
+}
+
 __device__ __forceinline__ float ldv(const float* p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float ldv(const _Float16* p, int64_t i) { return (float)p[i]; }
 __device__ __forceinline__ void stv(float* p, int64_t i, float v) { p[i] = v; }
@@ -489,32 +510,35 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
             }
           }
         } else {
-          // stored G_k planes and Gm_k on the ROI (0 outside): all reads first
-          const GLB T* g = cg<T>(it.img);
-          const GLB T* m = cg<T>(it.msk);
-          float v[NQ][4];
+          // stored G_k planes and Gm_k on the ROI (0 outside): every read is issued first, as
+          // raw bits from an address inside the planes (channel clamped to the last plane,
+          // offset 0 outside the ROI); conversion and zeroing come afterwards
+          const GLB T* g = cg<T>(nimg > 0 ? it.img : it.msk);
+          const int64_t grow = nimg > 0 ? it.img_row : it.msk_row, gplane = nimg > 0 ? it.img_plane : 0;
+          const GLB T* m = has_mask ? cg<T>(it.msk) : g;
+          const int64_t mrow = has_mask ? it.msk_row : grow;
+          const int cmax = nimg > 0 ? nimg - 1 : 0;
+          typename RawOf<T>::type raw[NQ][4];
+          bool inq[NQ];
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
             int X, Y;
             canvas(q, X, Y);
             Y -= ry;
             X -= rx;
-            const bool in = X >= 0 && X < rw && Y >= 0 && Y < rh;
-            const int64_t o = in ? (int64_t)Y * it.img_row + X : 0;
+            inq[q] = X >= 0 && X < rw && Y >= 0 && Y < rh;
+            const int64_t og = inq[q] ? (int64_t)Y * grow + X : 0, om = inq[q] ? (int64_t)Y * mrow + X : 0;
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) v[q][ch] = ch < nimg ? ldg(g, ch * it.img_plane + o) : 0.0f;
-            v[q][3] = has_mask ? ldg(m, in ? (int64_t)Y * it.msk_row + X : 0) : 0.0f;
-#pragma unroll
-            for (int ch = 0; ch < 4; ++ch) v[q][ch] = in ? v[q][ch] : 0.0f;
+            for (int ch = 0; ch < 3; ++ch) raw[q][ch] = ld_raw(g, min(ch, cmax) * gplane + og);
+            raw[q][3] = ld_raw(m, om);
           }
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
-            {
-              int r, c;
-              lds_pos(q, r, c);
+            int r, c;
+            lds_pos(q, r, c);
 #pragma unroll
-              for (int ch = 0; ch < 4; ++ch) sIn[ch][r][c] = v[q][ch];
-            }
+            for (int ch = 0; ch < 3; ++ch) sIn[ch][r][c] = (inq[q] && ch < nimg) ? from_raw(raw[q][ch]) : 0.0f;
+            sIn[3][r][c] = (inq[q] && has_mask) ? from_raw(raw[q][3]) : 0.0f;
           }
         }
       };
@@ -615,7 +639,9 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
           const float4 g = *reinterpret_cast<const float4*>(&sIn[ch][gr][x + 4]);
           const float l[4] = {g.x - ev.x, g.y - ev.y, g.z - ev.z, g.w - ev.w};
           const int64_t base = ch * it.l_plane + (int64_t)Y * it.l_row + X;
-          if (full) {
+          if (full && ((uintptr_t)(lout + base) & (4 * sizeof(T) - 1)) == 0) {
+            stg4(lout + base, l);
+          } else if (full) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) stg(lout, base + u, l[u]);
           } else if (rowin) {
