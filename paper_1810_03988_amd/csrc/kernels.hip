@@ -677,8 +677,6 @@ __global__ void __launch_bounds__(kThreads) k_blend(const BlendItem* __restrict_
   __shared__ __attribute__((aligned(16))) float sC[3][CH][HS];
   __shared__ __attribute__((aligned(16))) float sE[3][CH][ES];
   __shared__ __attribute__((aligned(16))) uint32_t sP[TY][TX * 3 / 4];
-  __shared__ int sCam[kMaxCameras];
-  __shared__ int sNCam;
 
   const int tid = threadIdx.x;
   const int t = xcd_remap(blockIdx.x, gridDim.x);
@@ -688,8 +686,10 @@ __global__ void __launch_bounds__(kThreads) k_blend(const BlendItem* __restrict_
   const int X0 = txi * TX, Y0 = tyi * TY;
   const bool has_coarse = a.has_coarse != 0;
 
-  if (tid < 64) {   // one wave builds the tile's camera list in order
-    const int i = tid;
+  // every wave builds the tile's camera set itself (lane i tests camera i): no LDS, no barrier
+  uint64_t cams;
+  {
+    const int i = tid & 63;
     bool hit = false;
     if (i < a.ncam) {
       const CST BlendCam& c = cst(a.cams)[i];
@@ -697,10 +697,53 @@ __global__ void __launch_bounds__(kThreads) k_blend(const BlendItem* __restrict_
       const int y0 = max(c.ly, c.wy), y1 = min(c.ly + c.lh, c.wy + c.wh);
       hit = x0 < x1 && y0 < y1 && x0 < X0 + TX && x1 > X0 && y0 < Y0 + TY && y1 > Y0;
     }
-    const uint64_t mask = __ballot(hit);
-    if (hit) sCam[__popcll(mask & ((1ull << i) - 1ull))] = i;
-    if (tid == 0) sNCam = __popcll(mask);
+    cams = __ballot(hit);
   }
+
+  // one camera's band and weight samples of this thread's four pixels, as raw bits from
+  // always-valid addresses (offset 0 outside the windows); used after the coarse stage
+  const int x = tid & 63, ybase = tid >> 6;
+  const int X = X0 + x;
+  using RawT = typename RawOf<T>::type;
+  struct CamSamples {
+    RawT l[4][3];
+    uint32_t w[4];
+    bool in[4];
+  };
+  auto fetch = [&](int ci, CamSamples& cs) __attribute__((always_inline)) {
+    const CST BlendCam& c = cst(a.cams)[ci];
+    const GLB T* l = cg<T>(c.lap);
+    const int lx = X - c.lx, wx = X - c.wx;
+    const bool xin = lx >= 0 && lx < c.lw && wx >= 0 && wx < c.ww;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int Y = Y0 + ybase + 4 * j;
+      const int ly = Y - c.ly, wy = Y - c.wy;
+      cs.in[j] = xin && ly >= 0 && ly < c.lh && wy >= 0 && wy < c.wh;
+      const int64_t loff = cs.in[j] ? (int64_t)ly * c.lap_row + lx : 0;
+      const int64_t woff = cs.in[j] ? (int64_t)wy * c.wgt_row + wx : 0;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) cs.l[j][ch] = ld_raw(l, ch * c.lap_plane + loff);
+      cs.w[j] = c.wgt_u8 ? (uint32_t)cg<uint8_t>(c.wgt)[woff] : (uint32_t)ld_raw(cg<T>(c.wgt), woff);
+    }
+  };
+  float acc[4][3];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0f;
+  auto accumulate = [&](int ci, const CamSamples& cs) __attribute__((always_inline)) {
+    const bool u8 = cst(a.cams)[ci].wgt_u8 != 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float wv = !cs.in[j] ? 0.0f : (u8 ? (float)cs.w[j] * kInv255 : from_raw((RawT)cs.w[j]));
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) acc[j][ch] = acc[j][ch] + wv * from_raw(cs.l[j][ch]);
+    }
+  };
+  // the first camera's reads fly together with the coarse level's
+  const int first = cams ? (int)__builtin_ctzll(cams) : -1;
+  CamSamples cs0;
+  if (first >= 0) fetch(first, cs0);
+
   if (has_coarse) {
     const GLB T* r = cg<T>(a.r_in);
     const int cx0 = X0 / 2 - 1, cy0 = Y0 / 2 - 1;
@@ -740,49 +783,17 @@ __global__ void __launch_bounds__(kThreads) k_blend(const BlendItem* __restrict_
       o.w = 0.5f * (hi.x + hi.y);
       *reinterpret_cast<float4*>(&sE[ch][i][4 * m]) = o;
     }
+    __syncthreads();
   }
-  __syncthreads();
-  const int ncam = sNCam;
-  const int x = tid & 63, ybase = tid >> 6;
-  const int X = X0 + x;
-  float acc[4][3];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0f;
-  for (int q = 0; q < ncam; ++q) {
-    // the camera index is the same in every lane: read it as such, so the descriptor
-    // comes through scalar loads instead of one dependent vector load per field
-    const CST BlendCam& c = cst(a.cams)[__builtin_amdgcn_readfirstlane(sCam[q])];
-    const GLB T* l = cg<T>(c.lap);
-    const int lx = X - c.lx, wx = X - c.wx;
-    const bool xin = lx >= 0 && lx < c.lw && wx >= 0 && wx < c.ww;
-    float wv[4], lv[4][3];
-    int64_t woff[4];
-    bool in[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int Y = Y0 + ybase + 4 * j;
-      const int ly = Y - c.ly, wy = Y - c.wy;
-      in[j] = xin && ly >= 0 && ly < c.lh && wy >= 0 && wy < c.wh;
-      woff[j] = in[j] ? (int64_t)wy * c.wgt_row + wx : 0;
-      const int64_t loff = in[j] ? (int64_t)ly * c.lap_row + lx : 0;
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) lv[j][ch] = ldg(l, ch * c.lap_plane + loff);
+  // cameras in ascending index order
+  if (first >= 0) {
+    accumulate(first, cs0);
+    for (uint64_t rest = cams & (cams - 1); rest; rest &= rest - 1) {
+      const int ci = (int)__builtin_ctzll(rest);
+      CamSamples cs;
+      fetch(ci, cs);
+      accumulate(ci, cs);
     }
-    if (c.wgt_u8) {   // uniform: the weight buffer is either uint8 or storage type
-      const GLB uint8_t* wg = cg<uint8_t>(c.wgt);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) wv[j] = (float)wg[woff[j]] * kInv255;
-    } else {
-      const GLB T* wg = cg<T>(c.wgt);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) wv[j] = ldg(wg, woff[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) wv[j] = in[j] ? wv[j] : 0.0f;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) acc[j][ch] = acc[j][ch] + wv[j] * lv[j][ch];
   }
   GLB T* ro = mg<T>(a.r_out);
 #pragma unroll
