@@ -332,19 +332,28 @@ def phase_name(key):
     return f"blend_level{k}"
 
 
+def source_hash() -> str:
+    """SHA-256 over the sources that decide what a launch does: the kernels and the planner
+    (regions, tiles, tables)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "stitch_api.cpp"):
+        h.update((ROOT / "paper_1810_03988_amd" / "csrc" / name).read_bytes())
+    return h.hexdigest()
+
+
 def profiled_traffic(config: str, form: str, storage: str, kind: str):
     """HBM bytes per launch of one kernel kind from the committed rocprofv3 counter summary
     of this workload (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration), or
-    None when there is none or the kernel source has changed since it was taken."""
+    None when there is none or the kernel or planner source has changed since it was taken."""
     import hashlib
     import re
     f = ROOT / "profiles" / f"hbm_traffic_{config}_{form}_{storage}.txt"
     if not f.exists():
         return None
     text = f.read_text()
-    m = re.search(r"kernels\.hip sha256: ([0-9a-f]{64})", text)
-    src = ROOT / "paper_1810_03988_amd" / "csrc" / "kernels.hip"
-    if not m or hashlib.sha256(src.read_bytes()).hexdigest() != m.group(1):
+    m = re.search(r"source sha256: ([0-9a-f]{64})", text)
+    if not m or source_hash() != m.group(1):
         return None
     m = re.search(rf"^traffic {re.escape(kind)}\s+.*?\s(\d+)$", text, re.M)
     return int(m.group(1)) if m else None

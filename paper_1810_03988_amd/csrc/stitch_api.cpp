@@ -818,6 +818,60 @@ stitch_status stitch_plan_create(int32_t n, const int32_t* frame_w, const int32_
       }
       c.band[k] = intersect(nk, c.roi[k]);
     }
+    // --- shrink the ROIs to what the blend reads ---
+    // The blend reads L_k on band_k only.  L_k there needs G_k on band_k and G_{k+1} on
+    // EXPAND's support of band_k; G_k needs G_{k-1} on REDUCE's support; the weights Gm_k on
+    // band_k need Gm_{k-1} on REDUCE's support down to the uint8 map.  Every such value is
+    // computed from values inside these needed sets only, so an ROI that covers them (aligned
+    // as before) keeps every value the blend reads exact; the rest of the footprint is skipped.
+    if (!c.roi[0].empty()) {
+      int64_t nx0 = INT64_MAX, nx1 = INT64_MIN, ny0 = INT64_MAX, ny1 = INT64_MIN;   // level-0 need, inclusive
+      for (int ax = 0; ax < 2; ++ax) {
+        Interval need[kMaxLevels], mneed[kMaxLevels];
+        for (int k = 0; k < L; ++k) need[k] = mneed[k] = Interval{1, 0};
+        auto band_iv = [&](int k) {
+          const Rect b = c.band[k];
+          if (b.empty()) return Interval{1, 0};
+          return ax == 0 ? Interval{b.x, b.x + b.w - 1} : Interval{b.y, b.y + b.h - 1};
+        };
+        auto unite = [](Interval a, Interval b) {
+          if (a.a > a.b) return b;
+          if (b.a > b.b) return a;
+          return Interval{std::min(a.a, b.a), std::max(a.b, b.b)};
+        };
+        auto rsup = [](Interval a) { return a.a > a.b ? a : Interval{2 * a.a - 2, 2 * a.b + 2}; };
+        auto esup = [](Interval a) { return a.a > a.b ? a : Interval{ceil_div(a.a - 2, 2), floor_div(a.b + 2, 2)}; };
+        need[L - 1] = band_iv(L - 1);
+        for (int k = L - 2; k >= 0; --k) {
+          const Interval b = band_iv(k);
+          need[k + 1] = unite(need[k + 1], esup(b));
+          need[k] = unite(b, rsup(need[k + 1]));
+        }
+        for (int k = L - 1; k >= 0; --k) {
+          mneed[k] = unite(mneed[k], band_iv(k));
+          if (k > 0) mneed[k - 1] = unite(mneed[k - 1], rsup(mneed[k]));
+        }
+        const Interval n0 = unite(need[0], mneed[0]);
+        if (ax == 0) { nx0 = n0.a; nx1 = n0.b; } else { ny0 = n0.a; ny1 = n0.b; }
+      }
+      const Rect r0 = c.roi[0];
+      Rect shrunk{};
+      if (nx0 <= nx1 && ny0 <= ny1) {
+        const int64_t x0 = std::max<int64_t>(r0.x, floor_div(nx0, A) * A);
+        const int64_t y0 = std::max<int64_t>(r0.y, floor_div(ny0, A) * A);
+        const int64_t x1 = std::min<int64_t>(r0.x + r0.w, ceil_div(nx1 + 1, A) * A);
+        const int64_t y1 = std::min<int64_t>(r0.y + r0.h, ceil_div(ny1 + 1, A) * A);
+        if (x0 < x1 && y0 < y1) shrunk = Rect{(int)x0, (int)y0, (int)(x1 - x0), (int)(y1 - y0)};
+      }
+      for (int k = 0; k < L; ++k) {
+        if (shrunk.empty()) { c.roi[k] = Rect{}; c.band[k] = Rect{}; continue; }
+        const int xa = shrunk.x >> k, ya = shrunk.y >> k;
+        const int xb = std::min<int>(p->dw[k], (int)ceil_div(shrunk.x + shrunk.w, (int64_t)1 << k));
+        const int yb = std::min<int>(p->dh[k], (int)ceil_div(shrunk.y + shrunk.h, (int64_t)1 << k));
+        c.roi[k] = Rect{xa, ya, xb - xa, yb - ya};
+        c.band[k] = intersect(c.band[k], c.roi[k]);
+      }
+    }
     // --- keep the seam weights on roi[0] ---
     const Rect r0 = c.roi[0];
     if (!r0.empty()) {

@@ -67,9 +67,11 @@ def test_plan_create_and_regions_are_aligned():
                 # the band window lies inside the roi
                 assert band[0] >= roi[0] and band[0] + band[2] <= roi[0] + roi[2]
                 assert band[1] >= roi[1] and band[1] + band[3] <= roi[1] + roi[3]
-        # camera B (x from ~392) gets a roi that does not start at the canvas edge
+        # camera B's footprint starts near x = 392 and its seam weights at x = 520: its roi
+        # covers what the blend reads of it (the band plus the pyramid's reach), not the
+        # whole footprint and not the canvas edge
         assert P.lib().stitch_plan_regions(h, 1, 0, roi, band) == 0
-        assert 0 < roi[0] < 392 - 32
+        assert 392 - 32 < roi[0] <= band[0] - 32 and band[0] == 520
     finally:
         P.lib().stitch_plan_destroy(h)
 
