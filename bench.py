@@ -521,10 +521,10 @@ def batch_kernel_table(plan, rig, timing, steps, s, njobs):
 
 def cpu_baseline(rig, frames0):
     """The oracle as it stands, on a bounded sample: the full-height column window
-    [1248, 1888) of frame 0 (spans the first seam), all levels through their cones."""
+    [1248, 3168) of frame 0 (spans the first seam), all levels through their cones."""
     import oracle
     fr = [f.cpu().numpy() for f in frames0]
-    x0, x1 = 1248, 1888
+    x0, x1 = 1248, 3168
     if rig.canvas_w < x1:
         x0, x1 = 0, rig.canvas_w
     so = oracle.StitchOracle(fr, rig.H, rig.masks(), rig.canvas_w, rig.canvas_h, rig.levels)
