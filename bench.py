@@ -481,7 +481,7 @@ def run_c3(a):
                    "form": "batched: one launch per level over all jobs, one HIP graph replay per step"},
         "forms": res, "speedup_batched_vs_one_by_one": round(res["one_by_one"]["ms_per_step"] /
                                                             res["batched"]["ms_per_step"], 3),
-        "wg_per_cu_by_level": cfg, "device": torch.cuda.get_device_name(0),
+        "tuned_by_level": {k: v[:max(r.levels for r in rigs) - 1] for k, v in cfg.items()}, "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(line), flush=True)
 
@@ -579,7 +579,7 @@ def main():
                                                "ms_per_step": round(res["graph"][0], 4),
                                                "how": "one HIP graph replay per step"}
         form_desc = (f"batched, {a.storage} storage: the {a.frames} frames as {a.frames} jobs of one batch, one "
-                     f"launch per pyramid level and per blend level (tuned workgroups/CU {cfg[:rig.levels - 1]})")
+                     f"launch per pyramid level and per blend level (tuned workgroups/CU {cfg['wg_per_cu'][:rig.levels - 1]}, tile rows {cfg['tile_rows'][:rig.levels - 1]})")
         del _b, _p
     else:
         plan0, ms, timing, _ = time_form(rig, frames, a.storage, a.steps, a.warmup, events)

@@ -239,9 +239,10 @@ stitch_status stitch_batch_bind(stitch_batch* batch, void* workspace, size_t byt
  * DEVICE. */
 stitch_status stitch_batch_run(stitch_batch* batch, const stitch_image* const* frames, stitch_image* panos,
                                void* stream);
-/* Pick, for every pyramid level of the batch, how many persistent workgroups per compute
- * unit its pass launches (as many as fit, 1, 2, or one per tile) by timing the candidates
- * on these inputs (synchronises the stream).  cache_path (optional): a text file of
+/* Pick, for every pyramid level of the batch, the tile height of its pass (16, 32, 64 or
+ * 128 rows, the taller ones only while the level still has a tile per compute unit) and
+ * how many persistent workgroups per compute unit it launches (as many as fit, 1, 2, or
+ * one per tile) by timing the pairs on these inputs (synchronises the stream).  cache_path (optional): a text file of
  * earlier choices keyed by device and batch geometry; a hit skips the timing and a miss
  * appends the new choice.  Errors: NULL, SHAPE, STATE, DEVICE. */
 stitch_status stitch_batch_autotune(stitch_batch* batch, const stitch_image* const* frames, stitch_image* panos,
@@ -256,8 +257,10 @@ stitch_status stitch_batch_autotune(stitch_batch* batch, const stitch_image* con
 stitch_status stitch_batch_set_timing(stitch_batch* batch, int32_t enable);
 stitch_status stitch_batch_read_timing(stitch_batch* batch, double ms[STITCH_BATCH_TIMING_KINDS],
                                        int32_t launches[STITCH_BATCH_TIMING_KINDS]);
-/* The per-level workgroups-per-CU setting in use (0: as many as fit, -1: one per tile). */
-stitch_status stitch_batch_config(const stitch_batch* batch, int32_t wg_per_cu[STITCH_MAX_LEVELS]);
+/* The per-level settings in use: workgroups per CU (0: as many as fit, -1: one per tile)
+ * and the pass's tile height in rows (0 for levels with no pass from them).  Errors: NULL. */
+stitch_status stitch_batch_config(const stitch_batch* batch, int32_t wg_per_cu[STITCH_MAX_LEVELS],
+                                  int32_t tile_rows[STITCH_MAX_LEVELS]);
 void          stitch_batch_destroy(stitch_batch* batch);
 
 /* ---- differentiable form: refining a pair's transformation -------------------- */

@@ -1121,6 +1121,8 @@ struct stitch_batch {
   int pyr_tiles[kMaxLevels] = {};
   size_t off_pyr[kMaxLevels] = {};
   int wg_cap[kMaxLevels] = {};                // tuned persistent workgroups per CU per phase
+  int sub[kMaxLevels] = {};                   // tuned 16-row sub-steps per pyramid tile per phase
+  int64_t t16[kMaxLevels] = {};               // 16-row tiles per phase (independent of sub)
   std::vector<BlendItem> blend[kMaxLevels];
   int blend_tiles[kMaxLevels] = {};
   size_t off_blend[kMaxLevels] = {};
@@ -1281,9 +1283,9 @@ stitch_status stitch_batch_create(int32_t njobs, stitch_plan* const* plans, stit
   }
   // one sub-step choice per pass, from the batch's own 16-row tile count
   for (int k = 0; k + 1 < b->maxL; ++k) {
-    int64_t t16 = 0;
-    for (const PyrItem& it : b->pyr[k]) t16 += (int64_t)it.tiles_x * it.rows16;
-    set_sub(b->pyr[k], choose_sub(t16), b->pyr_tiles[k]);
+    for (const PyrItem& it : b->pyr[k]) b->t16[k] += (int64_t)it.tiles_x * it.rows16;
+    b->sub[k] = choose_sub(b->t16[k]);
+    set_sub(b->pyr[k], b->sub[k], b->pyr_tiles[k]);
   }
   // blends: level-0 items in job order, so blend[0][j] belongs to job j
   for (int k = 0; k < b->maxL; ++k)
@@ -1360,65 +1362,93 @@ stitch_status stitch_batch_autotune(stitch_batch* b, const stitch_image* const* 
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
     return fail(STITCH_E_DEVICE, "cannot query the device");
-  // cache key: device, storage type and each phase's tile count
+  // cache key: device, storage type and each phase's 16-row tile count
   uint64_t key = fnv1a(1469598103934665603ull, prop.gcnArchName, strlen(prop.gcnArchName));
   key = fnv1a(key, &b->f16, sizeof b->f16);
-  key = fnv1a(key, b->pyr_tiles, sizeof b->pyr_tiles);
-  int cached[kMaxLevels];
+  key = fnv1a(key, b->t16, sizeof b->t16);
+  constexpr int kFields = 2 * kMaxLevels;   // per phase: sub-steps per tile, workgroups per CU
+  int cached[kFields];
   bool hit = false;
   if (cache_path) {
     FILE* f = fopen(cache_path, "r");
     if (f) {
-      char line[512];
+      char line[1024];
       while (!hit && fgets(line, sizeof line, f)) {
         unsigned long long k2 = 0;
         int n = 0, off = 0;
-        if (sscanf(line, "%llx %d%n", &k2, &n, &off) == 2 && k2 == key && n == kMaxLevels) {
+        if (sscanf(line, "%llx %d%n", &k2, &n, &off) == 2 && k2 == key && n == kFields) {
           hit = true;
           const char* q = line + off;
-          for (int i = 0; i < kMaxLevels && hit; ++i) {
+          for (int i = 0; i < kFields && hit; ++i) {
             int used = 0;
             if (sscanf(q, "%d%n", &cached[i], &used) != 1) hit = false;
             q += used;
           }
+          for (int k = 0; k < kMaxLevels && hit; ++k)
+            if (cached[2 * k] < 1 || cached[2 * k] > 8 || (cached[2 * k] & (cached[2 * k] - 1)) != 0) hit = false;
         }
       }
       fclose(f);
     }
   }
+  // the host table is rewritten by the next choice, so each upload is waited for
+  auto use = [&](int k, int sub_k) {
+    b->sub[k] = sub_k;
+    set_sub(b->pyr[k], sub_k, b->pyr_tiles[k]);
+    stitch_status r = upload(b->ws + b->off_pyr[k], b->pyr[k].data(), b->pyr[k].size() * sizeof(PyrItem), s,
+                             "batch table upload");
+    if (r) return r;
+    const hipError_t e = hipStreamSynchronize(s);
+    return e == hipSuccess ? STITCH_OK : hip_fail(e, "batch table upload");
+  };
+  drop_graph(b);
   if (hit) {
-    for (int k = 0; k < kMaxLevels; ++k) b->wg_cap[k] = cached[k];
-    drop_graph(b);
-    return STITCH_OK;
+    for (int k = 0; k + 1 < b->maxL && !st; ++k) {
+      b->wg_cap[k] = cached[2 * k + 1];
+      st = use(k, cached[2 * k]);
+    }
+    return st;
   }
-  // time each candidate cap per pyramid phase (the other phases keep their settings)
-  const int cands[] = {0, 1, 2, -1};
+  // per pyramid phase, time every (sub-steps per tile, workgroups per CU) pair; the other
+  // phases keep their settings
+  const int subs[] = {1, 2, 4, 8};
+  const int caps[] = {0, 1, 2, -1};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(STITCH_E_DEVICE, "event create failed");
   FrameArgs fa;
   std::memset(&fa, 0, sizeof fa);
   for (int k = 0; k + 1 < b->maxL && !st; ++k) {
-    if (b->pyr_tiles[k] <= 0) continue;
+    if (b->t16[k] <= 0) continue;
     float best = 1e30f;
-    int best_c = 0;
-    for (int c : cands) {
-      float total = 0.0f;
-      for (int rep = 0; rep < 4 && !st; ++rep) {
-        hipError_t e = hipEventRecord(e0, s);
-        if (e == hipSuccess)
-          e = launch_pyr(b->f16, true, k == 0, (const PyrItem*)(b->ws + b->off_pyr[k]), (int)b->pyr[k].size(),
-                         b->pyr_tiles[k], fa, s, c);
-        if (e == hipSuccess) e = hipEventRecord(e1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) st = hip_fail(e, "autotune timing");
-        if (rep > 0) total += ms;   // the first launch warms caches
+    int best_sub = b->sub[k], best_cap = 0;
+    for (int sub_k : subs) {
+      if (sub_k > 1 && b->t16[k] / sub_k < 256) continue;   // at least a tile per compute unit
+      st = use(k, sub_k);
+      for (int c : caps) {
+        float total = 0.0f;
+        for (int rep = 0; rep < 4 && !st; ++rep) {
+          hipError_t e = hipEventRecord(e0, s);
+          if (e == hipSuccess)
+            e = launch_pyr(b->f16, true, k == 0, (const PyrItem*)(b->ws + b->off_pyr[k]), (int)b->pyr[k].size(),
+                           b->pyr_tiles[k], fa, s, c);
+          if (e == hipSuccess) e = hipEventRecord(e1, s);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.0f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e != hipSuccess) st = hip_fail(e, "autotune timing");
+          if (rep > 0) total += ms;   // the first launch warms caches
+        }
+        if (!st && total < best) {
+          best = total;
+          best_sub = sub_k;
+          best_cap = c;
+        }
       }
-      if (!st && total < best) { best = total; best_c = c; }
+      if (st) break;
     }
-    b->wg_cap[k] = best_c;
+    b->wg_cap[k] = best_cap;
+    if (!st) st = use(k, best_sub);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1426,19 +1456,22 @@ stitch_status stitch_batch_autotune(stitch_batch* b, const stitch_image* const* 
   if (cache_path) {
     FILE* f = fopen(cache_path, "a");
     if (f) {
-      fprintf(f, "%llx %d", (unsigned long long)key, kMaxLevels);
-      for (int k = 0; k < kMaxLevels; ++k) fprintf(f, " %d", b->wg_cap[k]);
+      fprintf(f, "%llx %d", (unsigned long long)key, kFields);
+      for (int k = 0; k < kMaxLevels; ++k) fprintf(f, " %d %d", b->sub[k] > 0 ? b->sub[k] : 1, b->wg_cap[k]);
       fprintf(f, "\n");
       fclose(f);
     }
   }
-  drop_graph(b);
   return STITCH_OK;
 }
 
-stitch_status stitch_batch_config(const stitch_batch* b, int32_t wg_per_cu[STITCH_MAX_LEVELS]) {
-  if (!b || !wg_per_cu) return fail(STITCH_E_NULL, "batch or wg_per_cu is NULL");
-  for (int k = 0; k < kMaxLevels; ++k) wg_per_cu[k] = b->wg_cap[k];
+stitch_status stitch_batch_config(const stitch_batch* b, int32_t wg_per_cu[STITCH_MAX_LEVELS],
+                                  int32_t tile_rows[STITCH_MAX_LEVELS]) {
+  if (!b || !wg_per_cu || !tile_rows) return fail(STITCH_E_NULL, "batch, wg_per_cu or tile_rows is NULL");
+  for (int k = 0; k < kMaxLevels; ++k) {
+    wg_per_cu[k] = b->wg_cap[k];
+    tile_rows[k] = k + 1 < b->maxL ? kPyrTY * b->sub[k] : 0;
+  }
   return STITCH_OK;
 }
 

@@ -76,7 +76,7 @@ SIGNATURES = {
     "stitch_batch_run": (c_int32, [c_void_p, POINTER(POINTER(StitchImage)), POINTER(StitchImage), c_void_p]),
     "stitch_batch_autotune": (c_int32, [c_void_p, POINTER(POINTER(StitchImage)), POINTER(StitchImage), c_void_p,
                                         c_char_p]),
-    "stitch_batch_config": (c_int32, [c_void_p, POINTER(c_int32)]),
+    "stitch_batch_config": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
     "stitch_batch_set_timing": (c_int32, [c_void_p, c_int32]),
     "stitch_batch_read_timing": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int32)]),
     "stitch_batch_destroy": (None, [c_void_p]),
@@ -408,10 +408,13 @@ class Batch:
                 out[("pyr", i) if i < MAX_LEVELS else ("blend", i - MAX_LEVELS)] = (ms[i], n[i])
         return out
 
-    def config(self):
-        out = (c_int32 * MAX_LEVELS)()
-        check(lib().stitch_batch_config(self._h, out))
-        return list(out)
+    def config(self) -> dict:
+        """{"wg_per_cu": [...], "tile_rows": [...]} per pyramid level (tile_rows 0 past the
+        last pass)."""
+        wg = (c_int32 * MAX_LEVELS)()
+        rows = (c_int32 * MAX_LEVELS)()
+        check(lib().stitch_batch_config(self._h, wg, rows))
+        return {"wg_per_cu": list(wg), "tile_rows": list(rows)}
 
     def close(self) -> None:
         if getattr(self, "_h", None):

@@ -97,7 +97,9 @@ def test_autotune_keeps_results_and_uses_its_cache(tmp_path):
     with torch.cuda.stream(s):
         cfg = b.autotune(frames, panos, stream=s, cache_path=cache)
     assert cache.exists() and len(cache.read_text().strip().splitlines()) == 1
-    assert all(c in (0, 1, 2, -1) for c in cfg)
+    nl = max(r.levels for r in rigs) - 1
+    assert all(c in (0, 1, 2, -1) for c in cfg["wg_per_cu"])
+    assert all(t in (16, 32, 64, 128) for t in cfg["tile_rows"][:nl]) and not any(cfg["tile_rows"][nl:])
     b2 = P.Batch(plans)
     with torch.cuda.stream(s):
         cfg2 = b2.autotune(frames, panos, stream=s, cache_path=cache)
