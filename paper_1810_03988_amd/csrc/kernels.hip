@@ -2,9 +2,10 @@
 // here is a dense contraction; every kernel is bound by HBM traffic).
 //
 //   k_pyr    fused pyramid pass from level k to k+1 for many cameras at once.  A
-//            64x32 level-k tile plus a (4,3)-sample halo is staged in LDS -- at level 0
-//            it is produced by the homography warp itself (Alg. 4, step 1), so G_0 never
-//            reaches HBM -- then REDUCE gives the level-(k+1) tile with a one-sample halo,
+//            64-column level-k tile is walked in 16-row sub-steps; each is staged in LDS
+//            with a (4,3)-sample halo -- at level 0 it is produced by the homography warp
+//            itself (Alg. 4, step 1), so G_0 never reaches HBM -- then REDUCE gives the
+//            level-(k+1) tile with a one-sample halo,
 //            EXPAND of that tile is subtracted from G_k to give L_k (multi-band fusion,
 //            Sec. 1), and the seam-weight pyramid is reduced in the same pass.
 //   k_blend  one level of the synthesis side (Alg. 4, step 6): B_k = sum_i Gm_i L_i and
@@ -215,16 +216,18 @@ __device__ __forceinline__ int find_item(const PyrItem* __restrict__ items, int 
 // ranges, one per XCD (workgroup b runs on XCD b % 8), and the workgroups of an XCD stride
 // through its range, so neighbouring tiles -- which share halos -- share that XCD's L2.
 //
-// Stages of one sub-step, each ended by one barrier:
-//   A  stage the 71-column window of the sub-step's 23 rows (its 16 rows plus 4 above and
-//      3 below) of every channel in LDS: three image channels (the bilinear warp of the
-//      source frame at level 0, the stored G_k above) and the seam weight.  LDS rows form
-//      a ring of 23: the 7 rows a sub-step shares with the previous one stay where they
-//      are, so only its 16 new rows are staged (all 23 on a tile's first sub-step);
-//   B+C  REDUCE -> extended 34x10 coarse tile (horizontal then vertical, in registers);
-//      its interior is G_{k+1} / Gm_{k+1};
-//   D  horizontal EXPAND of the coarse tile (four fine columns per thread);
-//   E  vertical EXPAND and L_k = G_k - EXPAND(G_{k+1}), stored on the band window.
+// Stages of one sub-step:
+//   A  (whole workgroup, then a barrier) stage the 71-column window of the sub-step's 23
+//      rows (its 16 rows plus 4 above and 3 below) of every channel in LDS: three image
+//      channels (the bilinear warp of the source frame at level 0, the stored G_k above)
+//      and the seam weight.  LDS rows form a ring of 23: the 7 rows a sub-step shares with
+//      the previous one stay where they are, so only its 16 new rows are staged (all 23 on
+//      a tile's first sub-step);
+//   B..E  (wave w alone on channel slot w, no workgroup barrier)
+//      B+C  REDUCE -> extended 34x10 coarse tile (horizontal then vertical, in
+//           registers); its interior is G_{k+1} / Gm_{k+1};
+//      D+E  horizontal and vertical EXPAND of the coarse tile and L_k = G_k - EXPAND(G_{k+1}),
+//           stored on the band window (image channels only).
 struct PyrTile {
   int item, X0, Y0, nsub;
 };
@@ -253,10 +256,15 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
   constexpr int EW = TX + 7, EH = TY + 7;            // staged window: 4 before, 3 after
   constexpr int SW = 72;                             // LDS row strides are 16-byte multiples
   constexpr int CW = TX / 2 + 2, CH = TY / 2 + 2;    // coarse tile + one-sample halo
-  constexpr int HS = 36, ES = TX + 4;
+  constexpr int HS = 36;
   __shared__ __attribute__((aligned(16))) float sIn[4][EH][SW];   // rows: ring
   __shared__ __attribute__((aligned(16))) float sC[3][CH][HS];
-  __shared__ __attribute__((aligned(16))) float sE[3][CH][ES];
+  // warp only: the rounded products h0 X, h3 X, h6 X of every staged column and h1 Y,
+  // h4 Y, h7 Y of every window row, shared by the workgroup's samples
+  constexpr int NCT = WARP ? EW : 1, NRT = WARP ? EH : 1;
+  __shared__ __attribute__((aligned(16))) float sColT[NCT][4];
+  __shared__ __attribute__((aligned(16))) float sRowT[NRT][4];
+  constexpr uint32_t kPlaneRing = EH * SW * 4;       // bytes of one channel's ring of rows
 
   const int tid = threadIdx.x;
   // ---- schedule ----
@@ -275,21 +283,6 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
     stride = G;
   }
 
-  // tile-independent work items of stages C and D: (channel slot << 16) | (row << 8) | column group
-  constexpr int PC = (CH / 2) * (CW / 2), NCI = (4 * PC + kThreads - 1) / kThreads;
-  constexpr int PD = CH * (TX / 4), ND = (3 * PD + kThreads - 1) / kThreads;
-  int itC[NCI], itD[ND];
-#pragma unroll
-  for (int q = 0; q < NCI; ++q) {
-    const int e = tid + q * kThreads, ci = e / PC, rem = e - ci * PC;
-    itC[q] = (ci << 16) | ((rem / (CW / 2)) << 8) | (rem % (CW / 2));
-  }
-#pragma unroll
-  for (int q = 0; q < ND; ++q) {
-    const int e = tid + q * kThreads, ci = e / PD, rem = e - ci * PD;
-    itD[q] = (ci << 16) | ((rem / (TX / 4)) << 8) | (rem % (TX / 4));
-  }
-
   for (; t < t_end; t += stride) {
     const PyrTile d = decode_tile(items, nitems, t);
     const CST PyrItem& it = cst(items)[d.item];
@@ -303,11 +296,21 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
     for (int s = 0; s < d.nsub; ++s) {
       const int Y0 = d.Y0 + s * TY;
       const int off = (s * TY) % EH;   // logical row r of the window lives in ring row (r + off) mod EH
-      auto ring = [off](int r) {
-        const int p = r + off;
-        return p >= EH ? p - EH : p;
-      };
+      const uint32_t off4 = (uint32_t)off * (SW * 4);
       const bool interior = X0 >= 4 && X0 + TX + 3 <= fw && Y0 >= 4 && Y0 + TY + 3 <= fh;
+      if (WARP) {
+        // this sub-step's coordinate tables; their last readers (the previous sub-step's
+        // stage A) finished before its closing barrier
+        if (tid < EW) {
+          const float Xf = (float)(X0 - 4 + tid);
+          const float4 c = {it.hinv[0] * Xf, it.hinv[3] * Xf, it.hinv[6] * Xf, 0.0f};
+          *reinterpret_cast<float4*>(sColT[tid]) = c;
+        } else if (tid >= 128 && tid < 128 + EH) {
+          const float Yf = (float)(Y0 - 4 + (tid - 128));
+          const float4 r = {it.hinv[1] * Yf, it.hinv[4] * Yf, it.hinv[7] * Yf, 0.0f};
+          *reinterpret_cast<float4*>(sRowT[tid - 128]) = r;
+        }
+      }
       __syncthreads();   // the previous sub-step's readers of LDS are done
 
       // ---- A: stage logical rows R0 .. R0+NR-1 ----
@@ -320,18 +323,20 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
         int tid_l = tid;
         asm volatile("" : "+v"(tid_l));
         int rr[NQ], cc[NQ];                       // logical row (-1: idle slot) and column
+        uint32_t lo[NQ];                          // byte offset of the slot in a channel's rows, unrotated
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           const int e = tid_l + q * kThreads;
           rr[q] = e < NE ? R0 + e / EW : -1;
           cc[q] = e < NE ? e % EW : 0;
+          // idle slots write the padding column EW (read by stage B's last float4 but never
+          // used), so stores need no branch and loads are never sunk into one
+          lo[q] = (uint32_t)((rr[q] < 0 ? R0 : rr[q]) * SW + (rr[q] < 0 ? EW : cc[q])) * 4u;
         }
-        // LDS position of a slot: idle slots write the padding column EW (read by stage B's
-        // last float4 but never used), so stores need no branch and loads are never sunk
-        // into one
-        auto lds_pos = [&](int q, int& r, int& c) {
-          r = ring(rr[q] < 0 ? R0 : rr[q]);
-          c = rr[q] < 0 ? EW : cc[q];
+        // the slot's cell in channel plane ch, rotated into the ring
+        auto cell = [&](int ch, int q) -> float& {
+          const uint32_t a = lo[q] + off4;
+          return *reinterpret_cast<float*>(reinterpret_cast<char*>(&sIn[ch][0][0]) + min(a, a - kPlaneRing));
         };
         // canvas position of a slot (idle slots take the window's first sample)
         auto canvas = [&](int q, int& X, int& Y) {
@@ -406,14 +411,10 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
           if (outside) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-              {
-                int r, c;
-                lds_pos(q, r, c);
-                sIn[0][r][c] = 0.0f;
-                sIn[1][r][c] = 0.0f;
-                sIn[2][r][c] = 0.0f;
-                sIn[3][r][c] = (float)mv[q] * kInv255;
-              }
+              cell(0, q) = 0.0f;
+              cell(1, q) = 0.0f;
+              cell(2, q) = 0.0f;
+              cell(3, q) = (float)mv[q] * kInv255;
             }
           } else if (fast) {
             // every sample: coordinates and both row reads issued first, so a wave keeps
@@ -424,8 +425,17 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
             for (int q = 0; q < NQ; ++q) {
               // z lies between its corner values and x, y in [1, w) x [1, h): the in-range
               // division is the IEEE one, x - floor(x) is exact and truncation is floor
-              float x, y;
-              warp_coords_in_range(hv, X0m4 + (float)cc[q], Y0m4 + (float)(rr[q] < 0 ? R0 : rr[q]), x, y);
+              // the coordinate sequence from the tabled products (the same roundings)
+              const float4 ct = *reinterpret_cast<const float4*>(sColT[cc[q]]);
+              const float4 rt = *reinterpret_cast<const float4*>(sRowT[rr[q] < 0 ? R0 : rr[q]]);
+              float u, v, z, x, y;
+              {
+#pragma clang fp contract(off)
+                u = (ct.x + rt.x) + hv[2];
+                v = (ct.y + rt.y) + hv[5];
+                z = (ct.z + rt.z) + hv[8];
+              }
+              div2_in_range(u, v, z, x, y);
               fxq[q] = __builtin_amdgcn_fractf(x);
               fyq[q] = __builtin_amdgcn_fractf(y);
               const uint32_t o = __umul24((uint32_t)(int)y, srow32) + 3u * (uint32_t)(int)x;
@@ -443,14 +453,10 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
               const float p01[3] = {(float)(a0 >> 24), (float)(a1 & 255u), (float)((a1 >> 8) & 255u)};
               const float p10[3] = {(float)(b0 & 255u), (float)((b0 >> 8) & 255u), (float)((b0 >> 16) & 255u)};
               const float p11[3] = {(float)(b0 >> 24), (float)(b1 & 255u), (float)((b1 >> 8) & 255u)};
-              {
-                int r, c;
-                lds_pos(q, r, c);
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch)
-                  sIn[ch][r][c] = w00 * p00[ch] + w01 * p01[ch] + w10 * p10[ch] + w11 * p11[ch];
-                sIn[3][r][c] = (float)mv[q] * kInv255;
-              }
+              for (int ch = 0; ch < 3; ++ch)
+                cell(ch, q) = w00 * p00[ch] + w01 * p01[ch] + w10 * p10[ch] + w11 * p11[ch];
+              cell(3, q) = (float)mv[q] * kInv255;
             }
           } else {
             // General window (frame borders, canvas edges): taps outside the frame weigh
@@ -499,14 +505,10 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
               const float p01[3] = {(float)(a0 >> 24), (float)(a1 & 255u), (float)((a1 >> 8) & 255u)};
               const float p10[3] = {(float)(b0 & 255u), (float)((b0 >> 8) & 255u), (float)((b0 >> 16) & 255u)};
               const float p11[3] = {(float)(b0 >> 24), (float)(b1 & 255u), (float)((b1 >> 8) & 255u)};
-              {
-                int r, c;
-                lds_pos(q, r, c);
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch)
-                  sIn[ch][r][c] = w00 * p00[ch] + w01 * p01[ch] + w10 * p10[ch] + w11 * p11[ch];
-                sIn[3][r][c] = (float)mv[q] * kInv255;
-              }
+              for (int ch = 0; ch < 3; ++ch)
+                cell(ch, q) = w00 * p00[ch] + w01 * p01[ch] + w10 * p10[ch] + w11 * p11[ch];
+              cell(3, q) = (float)mv[q] * kInv255;
             }
           }
         } else {
@@ -534,11 +536,9 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
           }
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
-            int r, c;
-            lds_pos(q, r, c);
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) sIn[ch][r][c] = (inq[q] && ch < nimg) ? from_raw(raw[q][ch]) : 0.0f;
-            sIn[3][r][c] = (inq[q] && has_mask) ? from_raw(raw[q][3]) : 0.0f;
+            for (int ch = 0; ch < 3; ++ch) cell(ch, q) = (inq[q] && ch < nimg) ? from_raw(raw[q][ch]) : 0.0f;
+            cell(3, q) = (inq[q] && has_mask) ? from_raw(raw[q][3]) : 0.0f;
           }
         }
       };
@@ -547,97 +547,102 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
       stage_a(Rows<TY>(), Rows<EH - TY>());
       __syncthreads();
 
-      // ---- B+C: REDUCE -> extended coarse tile, 2x2 outputs per item (seven fine rows, each
-      //      reduced horizontally from two b128 LDS reads, then vertically); store its interior ----
-      const int cx0 = X0 / 2 - 1, cy0 = Y0 / 2 - 1;      // coarse canvas coordinates of sC[.][0][0]
+      // ---- B..E: wave w works on channel slot w alone, and exchanges data only through
+      //      its own LDS rows (sC[ch]), so the next workgroup barrier is the next sub-step's ----
+      const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+      const int lane = tid & 63;
+      if (wv >= nact) continue;
+      const int ch = wv < nimg ? wv : 3;
+      // logical row r of the channel's ring (byte offsets keep the arithmetic 32-bit)
+      const char* plane = reinterpret_cast<const char*>(&sIn[ch][0][0]);
+      auto rowp = [&](int r) -> const float* {
+        const uint32_t a = (uint32_t)r * (SW * 4) + off4;
+        return reinterpret_cast<const float*>(plane + min(a, a - kPlaneRing));
+      };
+      // B+C: REDUCE -> extended coarse tile (CH x CW with a one-sample halo).  Lane
+      // (g, jp), g < 3: coarse columns 2jp, 2jp+1 of coarse rows 3g .. 3g+3, from the eleven
+      // fine rows 6g .. 6g+10, each reduced horizontally from two b128 reads; rows 3 and 6
+      // are stored by the group that starts there.  Its interior is G_{k+1} / Gm_{k+1}.
+      if (lane < 3 * (CW / 2)) {
+        const int g = lane / (CW / 2), jp = lane - (CW / 2) * g, rs = 3 * g;
+        float2 hr[11];
 #pragma unroll
-      for (int q = 0; q < NCI; ++q) {
-        const int ci = itC[q] >> 16;
-        if (ci < nact) {
-          const int ch = ci < nimg ? ci : 3;
-          const int pp = (itC[q] >> 8) & 255, jp = itC[q] & 255;
-          float2 sv[7];
+        for (int u = 0; u < 11; ++u) {
+          const float* row = rowp(2 * rs + u) + 4 * jp;
+          const float4 a = *reinterpret_cast<const float4*>(row);
+          const float4 bq = *reinterpret_cast<const float4*>(row + 4);
+          hr[u].x = kW0 * (a.x + bq.x) + kW1 * (a.y + a.w) + kW2 * a.z;
+          hr[u].y = kW0 * (a.z + bq.z) + kW1 * (a.w + bq.y) + kW2 * bq.x;
+        }
+        const int cx0 = X0 / 2 - 1, cy0 = Y0 / 2 - 1;   // coarse canvas coordinates of sC[.][0][0]
+        GLB T* out = ch < 3 ? mg<T>(it.g_out) : mg<T>(it.gm_out);
+        const int64_t orow = ch < 3 ? it.g_row : it.gm_row;
+        const int64_t obase = ch < 3 ? ch * it.g_plane : 0;
+        const int j = 2 * jp, cx = cx0 + j - it.croi_x;
+        const bool c0in = j >= 1 && j <= TX / 2 && cx >= 0 && cx < it.croi_w;
+        const bool c1in = j + 1 <= TX / 2 && cx + 1 >= 0 && cx + 1 < it.croi_w;
 #pragma unroll
-          for (int u = 0; u < 7; ++u) {
-            const float* row = &sIn[ch][ring(4 * pp + u)][4 * jp];
-            const float4 a = *reinterpret_cast<const float4*>(row);
-            const float4 bq = *reinterpret_cast<const float4*>(row + 4);
-            sv[u].x = kW0 * (a.x + bq.x) + kW1 * (a.y + a.w) + kW2 * a.z;
-            sv[u].y = kW0 * (a.z + bq.z) + kW1 * (a.w + bq.y) + kW2 * bq.x;
-          }
-          float2 o0, o1;
-          o0.x = kW0 * (sv[0].x + sv[4].x) + kW1 * (sv[1].x + sv[3].x) + kW2 * sv[2].x;
-          o0.y = kW0 * (sv[0].y + sv[4].y) + kW1 * (sv[1].y + sv[3].y) + kW2 * sv[2].y;
-          o1.x = kW0 * (sv[2].x + sv[6].x) + kW1 * (sv[3].x + sv[5].x) + kW2 * sv[4].x;
-          o1.y = kW0 * (sv[2].y + sv[6].y) + kW1 * (sv[3].y + sv[5].y) + kW2 * sv[4].y;
-          if (ch < 3) {
-            *reinterpret_cast<float2*>(&sC[ch][2 * pp][2 * jp]) = o0;
-            *reinterpret_cast<float2*>(&sC[ch][2 * pp + 1][2 * jp]) = o1;
-          }
-          GLB T* out = ch < 3 ? mg<T>(it.g_out) : mg<T>(it.gm_out);
-          const int64_t orow = ch < 3 ? it.g_row : it.gm_row;
-          const int64_t obase = ch < 3 ? ch * it.g_plane : 0;
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            const int i = 2 * pp + u;
-            const int cy = cy0 + i - it.croi_y;
-            const bool rowin = i >= 1 && i <= TY / 2 && cy >= 0 && cy < it.croi_h;
-#pragma unroll
-            for (int v = 0; v < 2; ++v) {
-              const int j = 2 * jp + v;
-              const int cx = cx0 + j - it.croi_x;
-              if (rowin && j >= 1 && j <= TX / 2 && cx >= 0 && cx < it.croi_w)
-                stg(out, obase + (int64_t)cy * orow + cx, u ? (v ? o1.y : o1.x) : (v ? o0.y : o0.x));
-            }
+        for (int m = 0; m < 4; ++m) {
+          if (m == 0 && g > 0) continue;
+          float2 o;
+          o.x = kW0 * (hr[2 * m].x + hr[2 * m + 4].x) + kW1 * (hr[2 * m + 1].x + hr[2 * m + 3].x) +
+                kW2 * hr[2 * m + 2].x;
+          o.y = kW0 * (hr[2 * m].y + hr[2 * m + 4].y) + kW1 * (hr[2 * m + 1].y + hr[2 * m + 3].y) +
+                kW2 * hr[2 * m + 2].y;
+          const int i = rs + m;
+          if (ch < 3) *reinterpret_cast<float2*>(&sC[ch][i][j]) = o;
+          const int cy = cy0 + i - it.croi_y;
+          if (i >= 1 && i <= TY / 2 && cy >= 0 && cy < it.croi_h) {
+            const int64_t ob = obase + (int64_t)cy * orow + cx;
+            if (c0in) stg(out, ob, o.x);
+            if (c1in) stg(out, ob + 1, o.y);
           }
         }
       }
-      if (!EMIT_LAP) continue;
+      if (!EMIT_LAP || ch == 3) continue;
       const bool lap_tile = it.lw_w > 0 && X0 < it.lw_x + it.lw_w && X0 + TX > it.lw_x &&
                             Y0 < it.lw_y + it.lw_h && Y0 + TY > it.lw_y;
       if (!lap_tile) continue;
-      __syncthreads();
+      // the wave's own sC[ch] rows: LDS accesses of one wave complete in order
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-      // ---- D: horizontal EXPAND, four fine columns per item ----
-#pragma unroll
-      for (int q = 0; q < ND; ++q) {
-        const int ch = itD[q] >> 16;
-        if (ch < nimg) {
-          const int i = (itD[q] >> 8) & 255, mm = itD[q] & 255;
-          const float2 lo = *reinterpret_cast<const float2*>(&sC[ch][i][2 * mm]);
-          const float2 hi = *reinterpret_cast<const float2*>(&sC[ch][i][2 * mm + 2]);
-          float4 o;
-          o.x = 0.125f * (lo.x + hi.x) + 0.75f * lo.y;
-          o.y = 0.5f * (lo.y + hi.x);
-          o.z = 0.125f * (lo.y + hi.y) + 0.75f * hi.x;
-          o.w = 0.5f * (hi.x + hi.y);
-          *reinterpret_cast<float4*>(&sE[ch][i][4 * mm]) = o;
-        }
-      }
-      __syncthreads();
-
-      // ---- E: vertical EXPAND and the band L_k = G_k - EXPAND(G_{k+1}), four columns per thread ----
+      // D+E: lane (rq, mm): fine columns 4mm .. 4mm+3 of fine rows 4rq .. 4rq+3.  Horizontal
+      // EXPAND of coarse rows 2rq .. 2rq+3, then vertical EXPAND and the band
+      // L_k = G_k - EXPAND(G_{k+1}), stored on the band window.
       {
-        const int y = tid >> 4, x = 4 * (tid & 15), yh = y >> 1;
-        const int Y = Y0 + y - it.lw_y, X = X0 + x - it.lw_x;
-        const bool rowin = Y >= 0 && Y < it.lw_h;
-        const bool full = rowin && X >= 0 && X + 3 < it.lw_w;
-        const int gr = ring(y + 4);
+        const int mm = lane & 15, rq = lane >> 4, x = 4 * mm;
+        float4 eh[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float2 lo = *reinterpret_cast<const float2*>(&sC[ch][2 * rq + k][2 * mm]);
+          const float2 hi = *reinterpret_cast<const float2*>(&sC[ch][2 * rq + k][2 * mm + 2]);
+          eh[k].x = 0.125f * (lo.x + hi.x) + 0.75f * lo.y;
+          eh[k].y = 0.5f * (lo.y + hi.x);
+          eh[k].z = 0.125f * (lo.y + hi.y) + 0.75f * hi.x;
+          eh[k].w = 0.5f * (hi.x + hi.y);
+        }
+        const int X = X0 + x - it.lw_x;
         GLB T* lout = mg<T>(it.l_out);
-        for (int ch = 0; ch < nimg; ++ch) {
-          const float4 s1 = *reinterpret_cast<const float4*>(&sE[ch][yh + 1][x]);
-          const float4 s2 = *reinterpret_cast<const float4*>(&sE[ch][yh + 2][x]);
+#pragma unroll
+        for (int yy = 0; yy < 4; ++yy) {
+          const int y = 4 * rq + yy, k = yy >> 1;
           float4 ev;
-          if (y & 1) {
-            ev.x = 0.5f * (s1.x + s2.x); ev.y = 0.5f * (s1.y + s2.y);
-            ev.z = 0.5f * (s1.z + s2.z); ev.w = 0.5f * (s1.w + s2.w);
+          if (yy & 1) {
+            ev.x = 0.5f * (eh[k + 1].x + eh[k + 2].x); ev.y = 0.5f * (eh[k + 1].y + eh[k + 2].y);
+            ev.z = 0.5f * (eh[k + 1].z + eh[k + 2].z); ev.w = 0.5f * (eh[k + 1].w + eh[k + 2].w);
           } else {
-            const float4 s0 = *reinterpret_cast<const float4*>(&sE[ch][yh][x]);
-            ev.x = 0.125f * (s0.x + s2.x) + 0.75f * s1.x; ev.y = 0.125f * (s0.y + s2.y) + 0.75f * s1.y;
-            ev.z = 0.125f * (s0.z + s2.z) + 0.75f * s1.z; ev.w = 0.125f * (s0.w + s2.w) + 0.75f * s1.w;
+            ev.x = 0.125f * (eh[k].x + eh[k + 2].x) + 0.75f * eh[k + 1].x;
+            ev.y = 0.125f * (eh[k].y + eh[k + 2].y) + 0.75f * eh[k + 1].y;
+            ev.z = 0.125f * (eh[k].z + eh[k + 2].z) + 0.75f * eh[k + 1].z;
+            ev.w = 0.125f * (eh[k].w + eh[k + 2].w) + 0.75f * eh[k + 1].w;
           }
-          const float4 g = *reinterpret_cast<const float4*>(&sIn[ch][gr][x + 4]);
-          const float l[4] = {g.x - ev.x, g.y - ev.y, g.z - ev.z, g.w - ev.w};
+          const float4 gv = *reinterpret_cast<const float4*>(rowp(y + 4) + x + 4);
+          const float l[4] = {gv.x - ev.x, gv.y - ev.y, gv.z - ev.z, gv.w - ev.w};
+          const int Y = Y0 + y - it.lw_y;
+          const bool rowin = Y >= 0 && Y < it.lw_h;
+          const bool full = rowin && X >= 0 && X + 3 < it.lw_w;
           const int64_t base = ch * it.l_plane + (int64_t)Y * it.l_row + X;
           if (full && ((uintptr_t)(lout + base) & (4 * sizeof(T) - 1)) == 0) {
             stg4(lout + base, l);
