@@ -80,6 +80,28 @@ __device__ __forceinline__ void stg4(GLB _Float16* p, const float v[4]) {
   *reinterpret_cast<GLB vh4*>(p) = vh4{(_Float16)v[0], (_Float16)v[1], (_Float16)v[2], (_Float16)v[3]};
 }
 
+// Streaming stores for the pyramid levels: written once, read by a later kernel long after
+// the lines would have left L2.
+typedef float vf2 __attribute__((ext_vector_type(2)));
+typedef _Float16 vh2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void stgnt(GLB float* p, int64_t i, float v) { __builtin_nontemporal_store(v, p + i); }
+__device__ __forceinline__ void stgnt(GLB _Float16* p, int64_t i, float v) {
+  __builtin_nontemporal_store((_Float16)v, p + i);
+}
+__device__ __forceinline__ void stg2nt(GLB float* p, float a, float b) {
+  __builtin_nontemporal_store(vf2{a, b}, reinterpret_cast<GLB vf2*>(p));
+}
+__device__ __forceinline__ void stg2nt(GLB _Float16* p, float a, float b) {
+  __builtin_nontemporal_store(vh2{(_Float16)a, (_Float16)b}, reinterpret_cast<GLB vh2*>(p));
+}
+__device__ __forceinline__ void stg4nt(GLB float* p, const float v[4]) {
+  __builtin_nontemporal_store(vf4{v[0], v[1], v[2], v[3]}, reinterpret_cast<GLB vf4*>(p));
+}
+__device__ __forceinline__ void stg4nt(GLB _Float16* p, const float v[4]) {
+  __builtin_nontemporal_store(vh4{(_Float16)v[0], (_Float16)v[1], (_Float16)v[2], (_Float16)v[3]},
+                              reinterpret_cast<GLB vh4*>(p));
+}
+
 __device__ __forceinline__ float ldv(const float* p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float ldv(const _Float16* p, int64_t i) { return (float)p[i]; }
 __device__ __forceinline__ void stv(float* p, int64_t i, float v) { p[i] = v; }
@@ -579,8 +601,13 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
         const int64_t orow = ch < 3 ? it.g_row : it.gm_row;
         const int64_t obase = ch < 3 ? ch * it.g_plane : 0;
         const int j = 2 * jp, cx = cx0 + j - it.croi_x;
-        const bool c0in = j >= 1 && j <= TX / 2 && cx >= 0 && cx < it.croi_w;
-        const bool c1in = j + 1 <= TX / 2 && cx + 1 >= 0 && cx + 1 < it.croi_w;
+        // global stores go out as pairs that start at an even element of the output row
+        // (aligned when the row is): (2jp, 2jp+1), or (2jp+1, 2jp+2) with the second value
+        // from the next lane
+        const bool odd = ((cx0 - it.croi_x) & 1) != 0;
+        const int js = odd ? j + 1 : j, cxs = cx0 + js - it.croi_x;
+        const bool s0in = js >= 1 && js <= TX / 2 && cxs >= 0 && cxs < it.croi_w;
+        const bool s1in = js + 1 >= 1 && js + 1 <= TX / 2 && cxs + 1 >= 0 && cxs + 1 < it.croi_w;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           if (m == 0 && g > 0) continue;
@@ -592,10 +619,16 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
           const int i = rs + m;
           if (ch < 3) *reinterpret_cast<float2*>(&sC[ch][i][j]) = o;
           const int cy = cy0 + i - it.croi_y;
+          const float nx = __shfl_down(o.x, 1);
           if (i >= 1 && i <= TY / 2 && cy >= 0 && cy < it.croi_h) {
-            const int64_t ob = obase + (int64_t)cy * orow + cx;
-            if (c0in) stg(out, ob, o.x);
-            if (c1in) stg(out, ob + 1, o.y);
+            const float v0 = odd ? o.y : o.x, v1 = odd ? nx : o.y;
+            const int64_t ob = obase + (int64_t)cy * orow + cxs;
+            if (s0in && s1in) {
+              stg2nt(out + ob, v0, v1);
+            } else {
+              if (s0in) stgnt(out, ob, v0);
+              if (s1in) stgnt(out, ob + 1, v1);
+            }
           }
         }
       }
@@ -645,14 +678,14 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
           const bool full = rowin && X >= 0 && X + 3 < it.lw_w;
           const int64_t base = ch * it.l_plane + (int64_t)Y * it.l_row + X;
           if (full && ((uintptr_t)(lout + base) & (4 * sizeof(T) - 1)) == 0) {
-            stg4(lout + base, l);
+            stg4nt(lout + base, l);
           } else if (full) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) stg(lout, base + u, l[u]);
+            for (int u = 0; u < 4; ++u) stgnt(lout, base + u, l[u]);
           } else if (rowin) {
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-              if (X + u >= 0 && X + u < it.lw_w) stg(lout, base + u, l[u]);
+              if (X + u >= 0 && X + u < it.lw_w) stgnt(lout, base + u, l[u]);
           }
         }
       }

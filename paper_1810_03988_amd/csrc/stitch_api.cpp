@@ -1426,8 +1426,8 @@ stitch_status stitch_batch_autotune(stitch_batch* b, const stitch_image* const* 
       if (sub_k > 1 && b->t16[k] / sub_k < 256) continue;   // at least a tile per compute unit
       st = use(k, sub_k);
       for (int c : caps) {
-        float total = 0.0f;
-        for (int rep = 0; rep < 4 && !st; ++rep) {
+        float score = 1e30f;   // fastest of five launches after a warm-up one
+        for (int rep = 0; rep < 6 && !st; ++rep) {
           hipError_t e = hipEventRecord(e0, s);
           if (e == hipSuccess)
             e = launch_pyr(b->f16, true, k == 0, (const PyrItem*)(b->ws + b->off_pyr[k]), (int)b->pyr[k].size(),
@@ -1437,10 +1437,10 @@ stitch_status stitch_batch_autotune(stitch_batch* b, const stitch_image* const* 
           float ms = 0.0f;
           if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
           if (e != hipSuccess) st = hip_fail(e, "autotune timing");
-          if (rep > 0) total += ms;   // the first launch warms caches
+          if (rep > 0) score = std::min(score, ms);
         }
-        if (!st && total < best) {
-          best = total;
+        if (!st && score < best) {
+          best = score;
           best_sub = sub_k;
           best_cap = c;
         }
