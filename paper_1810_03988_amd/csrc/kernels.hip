@@ -82,17 +82,9 @@ __device__ __forceinline__ void stg4(GLB _Float16* p, const float v[4]) {
 
 // Streaming stores for the pyramid levels: written once, read by a later kernel long after
 // the lines would have left L2.
-typedef float vf2 __attribute__((ext_vector_type(2)));
-typedef _Float16 vh2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void stgnt(GLB float* p, int64_t i, float v) { __builtin_nontemporal_store(v, p + i); }
 __device__ __forceinline__ void stgnt(GLB _Float16* p, int64_t i, float v) {
   __builtin_nontemporal_store((_Float16)v, p + i);
-}
-__device__ __forceinline__ void stg2nt(GLB float* p, float a, float b) {
-  __builtin_nontemporal_store(vf2{a, b}, reinterpret_cast<GLB vf2*>(p));
-}
-__device__ __forceinline__ void stg2nt(GLB _Float16* p, float a, float b) {
-  __builtin_nontemporal_store(vh2{(_Float16)a, (_Float16)b}, reinterpret_cast<GLB vh2*>(p));
 }
 __device__ __forceinline__ void stg4nt(GLB float* p, const float v[4]) {
   __builtin_nontemporal_store(vf4{v[0], v[1], v[2], v[3]}, reinterpret_cast<GLB vf4*>(p));
@@ -278,14 +270,17 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
   constexpr int EW = TX + 7, EH = TY + 7;            // staged window: 4 before, 3 after
   constexpr int SW = 72;                             // LDS row strides are 16-byte multiples
   constexpr int CW = TX / 2 + 2, CH = TY / 2 + 2;    // coarse tile + one-sample halo
-  constexpr int HS = 36;
+  // coarse tile of every channel: coarse column j at index j + 3, so the interior columns
+  // 1 .. 32 start on a 16-byte boundary
+  constexpr int HS = 40, CO = 3;
   __shared__ __attribute__((aligned(16))) float sIn[4][EH][SW];   // rows: ring
-  __shared__ __attribute__((aligned(16))) float sC[3][CH][HS];
+  __shared__ __attribute__((aligned(16))) float sC[4][CH][HS];
   // warp only: the rounded products h0 X, h3 X, h6 X of every staged column and h1 Y,
   // h4 Y, h7 Y of every window row, shared by the workgroup's samples
   constexpr int NCT = WARP ? EW : 1, NRT = WARP ? EH : 1;
   __shared__ __attribute__((aligned(16))) float sColT[NCT][4];
   __shared__ __attribute__((aligned(16))) float sRowT[NRT][4];
+  __shared__ int sCls[2];   // warp only: window classes of the 16-row and the 7-row stage
   constexpr uint32_t kPlaneRing = EH * SW * 4;       // bytes of one channel's ring of rows
 
   const int tid = threadIdx.x;
@@ -331,6 +326,46 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
           const float Yf = (float)(Y0 - 4 + (tid - 128));
           const float4 r = {it.hinv[1] * Yf, it.hinv[4] * Yf, it.hinv[7] * Yf, 0.0f};
           *reinterpret_cast<float4*>(sRowT[tid - 128]) = r;
+        } else if (tid >= 192) {
+          // Window classes, once for the workgroup (wave 3; lanes 0-3: the corners of the
+          // 16 new rows, lanes 4-7: of the 7 rows a tile's first sub-step also stages).
+          // Source-interior (bit 0): z > 0 at the four corners (so on all of the window: z
+          // is affine) and their source positions inside [1, w-3) x [1, h-2).  The map is
+          // projective there, so every staged sample lies in the convex hull of the corner
+          // images (up to FP32 rounding, far below the one-sample margin): its four taps
+          // are in the frame and the pair of taps of a row is one 8-byte read that ends
+          // inside the row.  Source-exterior (bit 1): z > 0 at the corners and all four
+          // corner images at least one sample beyond the same side of the frame (x <= -2,
+          // x >= w + 1, y <= -2 or y >= h + 1): every staged sample's taps are outside,
+          // its G_0 is 0.  Either also needs the window inside the canvas (checked by the
+          // stage).
+          const int lane = tid - 192;
+          bool bad = false, zok = false, lft = false, rgt = false, top = false, bot = false;
+          if (lane < 8) {
+            float hv[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) hv[i] = it.hinv[i];
+            const int w = it.frame_w, h = it.frame_h;
+            const int r0 = lane < 4 ? EH - TY : 0, r1 = lane < 4 ? EH - 1 : EH - TY - 1;
+            float xc, yc, zc;
+            warp_coords_z(hv, (float)(X0 - 4 + ((lane & 1) ? EW - 1 : 0)),
+                          (float)(Y0 - 4 + ((lane & 2) ? r1 : r0)), xc, yc, zc);
+            zok = zc >= 0x1p-10f && zc <= 0x1p20f;
+            bad = !(zok && xc >= 1.0f && xc < (float)(w - 3) && yc >= 1.0f && yc < (float)(h - 2));
+            lft = xc <= -2.0f;
+            rgt = xc >= (float)(w + 1);
+            top = yc <= -2.0f;
+            bot = yc >= (float)(h + 1);
+          }
+          const uint64_t mb = __ballot(bad), mz = __ballot(zok), ml = __ballot(lft), mr = __ballot(rgt),
+                         mt = __ballot(top), mo = __ballot(bot);
+          if (lane < 2) {
+            const int sh = 4 * lane;
+            auto all4 = [sh](uint64_t m) { return ((m >> sh) & 15ull) == 15ull; };
+            const bool fast = ((mb >> sh) & 15ull) == 0ull;
+            const bool outside = all4(mz) && (all4(ml) || all4(mr) || all4(mt) || all4(mo));
+            sCls[lane] = (fast ? 1 : 0) | (outside ? 2 : 0);
+          }
         }
       }
       __syncthreads();   // the previous sub-step's readers of LDS are done
@@ -400,36 +435,9 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
             }
           }
           const float fwf = (float)w, fhf = (float)h, fwm1 = (float)(w - 1), fhm1 = (float)(h - 1);
-          const float X0m4 = (float)(X0 - 4), Y0m4 = (float)(Y0 - 4);
-          // Source-interior window: z > 0 at its four corners (so on all of it: z is affine)
-          // and their source positions inside [1, w-3) x [1, h-2).  The map is projective
-          // there, so every staged sample lies in the convex hull of the corner images (up
-          // to FP32 rounding, far below the one-sample margin): its four taps are in the
-          // frame and the pair of taps of a row is one 8-byte read that ends inside the row.
-          // Source-exterior window: z > 0 at the corners and all four corner images at
-          // least one sample beyond the same side of the frame (x <= -2, x >= w + 1,
-          // y <= -2 or y >= h + 1): every staged sample's taps are outside, its G_0 is 0.
-          bool fast = false, outside = false;
-          if (interior) {
-            bool bad = false, zok = false, lft = false, rgt = false, top = false, bot = false;
-            const int lane = tid & 63;
-            if (lane < 4) {
-              float xc, yc, zc;
-              warp_coords_z(hv, X0m4 + (float)((lane & 1) ? EW - 1 : 0),
-                            Y0m4 + (float)((lane & 2) ? R0 + NR - 1 : R0), xc, yc, zc);
-              zok = zc >= 0x1p-10f && zc <= 0x1p20f;
-              bad = !(zok && xc >= 1.0f && xc < (float)(w - 3) && yc >= 1.0f && yc < (float)(h - 2));
-              lft = xc <= -2.0f;
-              rgt = xc >= (float)(w + 1);
-              top = yc <= -2.0f;
-              bot = yc >= (float)(h + 1);
-            }
-            // ballots are the same in every wave of the workgroup
-            fast = __ballot(bad) == 0ull;
-            outside = __ballot(zok) == 15ull &&
-                      (__ballot(lft) == 15ull || __ballot(rgt) == 15ull || __ballot(top) == 15ull ||
-                       __ballot(bot) == 15ull);
-          }
+          // the window's class, computed before the sub-step's barrier
+          const int cls = interior ? sCls[R0 == 0 ? 1 : 0] : 0;
+          const bool fast = (cls & 1) != 0, outside = (cls & 2) != 0;
           if (outside) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
@@ -551,9 +559,10 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
             Y -= ry;
             X -= rx;
             inq[q] = X >= 0 && X < rw && Y >= 0 && Y < rh;
-            const int64_t og = inq[q] ? (int64_t)Y * grow + X : 0, om = inq[q] ? (int64_t)Y * mrow + X : 0;
+            const uint32_t og = inq[q] ? __umul24((uint32_t)Y, (uint32_t)grow) + (uint32_t)X : 0u;
+            const uint32_t om = inq[q] ? __umul24((uint32_t)Y, (uint32_t)mrow) + (uint32_t)X : 0u;
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) raw[q][ch] = ld_raw(g, min(ch, cmax) * gplane + og);
+            for (int ch = 0; ch < 3; ++ch) raw[q][ch] = ld_raw(g, (uint32_t)min(ch, cmax) * (uint32_t)gplane + og);
             raw[q][3] = ld_raw(m, om);
           }
 #pragma unroll
@@ -581,10 +590,10 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
         const uint32_t a = (uint32_t)r * (SW * 4) + off4;
         return reinterpret_cast<const float*>(plane + min(a, a - kPlaneRing));
       };
-      // B+C: REDUCE -> extended coarse tile (CH x CW with a one-sample halo).  Lane
-      // (g, jp), g < 3: coarse columns 2jp, 2jp+1 of coarse rows 3g .. 3g+3, from the eleven
-      // fine rows 6g .. 6g+10, each reduced horizontally from two b128 reads; rows 3 and 6
-      // are stored by the group that starts there.  Its interior is G_{k+1} / Gm_{k+1}.
+      // B+C: REDUCE -> extended coarse tile (CH x CW with a one-sample halo) in sC[ch].
+      // Lane (g, jp), g < 3: coarse columns 2jp, 2jp+1 of coarse rows 3g .. 3g+3, from the
+      // eleven fine rows 6g .. 6g+10, each reduced horizontally from two b128 reads; rows 3
+      // and 6 are written by the group that starts there.
       if (lane < 3 * (CW / 2)) {
         const int g = lane / (CW / 2), jp = lane - (CW / 2) * g, rs = 3 * g;
         float2 hr[11];
@@ -596,18 +605,6 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
           hr[u].x = kW0 * (a.x + bq.x) + kW1 * (a.y + a.w) + kW2 * a.z;
           hr[u].y = kW0 * (a.z + bq.z) + kW1 * (a.w + bq.y) + kW2 * bq.x;
         }
-        const int cx0 = X0 / 2 - 1, cy0 = Y0 / 2 - 1;   // coarse canvas coordinates of sC[.][0][0]
-        GLB T* out = ch < 3 ? mg<T>(it.g_out) : mg<T>(it.gm_out);
-        const int64_t orow = ch < 3 ? it.g_row : it.gm_row;
-        const int64_t obase = ch < 3 ? ch * it.g_plane : 0;
-        const int j = 2 * jp, cx = cx0 + j - it.croi_x;
-        // global stores go out as pairs that start at an even element of the output row
-        // (aligned when the row is): (2jp, 2jp+1), or (2jp+1, 2jp+2) with the second value
-        // from the next lane
-        const bool odd = ((cx0 - it.croi_x) & 1) != 0;
-        const int js = odd ? j + 1 : j, cxs = cx0 + js - it.croi_x;
-        const bool s0in = js >= 1 && js <= TX / 2 && cxs >= 0 && cxs < it.croi_w;
-        const bool s1in = js + 1 >= 1 && js + 1 <= TX / 2 && cxs + 1 >= 0 && cxs + 1 < it.croi_w;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           if (m == 0 && g > 0) continue;
@@ -616,19 +613,35 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
                 kW2 * hr[2 * m + 2].x;
           o.y = kW0 * (hr[2 * m].y + hr[2 * m + 4].y) + kW1 * (hr[2 * m + 1].y + hr[2 * m + 3].y) +
                 kW2 * hr[2 * m + 2].y;
-          const int i = rs + m;
-          if (ch < 3) *reinterpret_cast<float2*>(&sC[ch][i][j]) = o;
-          const int cy = cy0 + i - it.croi_y;
-          const float nx = __shfl_down(o.x, 1);
-          if (i >= 1 && i <= TY / 2 && cy >= 0 && cy < it.croi_h) {
-            const float v0 = odd ? o.y : o.x, v1 = odd ? nx : o.y;
-            const int64_t ob = obase + (int64_t)cy * orow + cxs;
-            if (s0in && s1in) {
-              stg2nt(out + ob, v0, v1);
-            } else {
-              if (s0in) stgnt(out, ob, v0);
-              if (s1in) stgnt(out, ob + 1, v1);
-            }
+          float* c = &sC[ch][rs + m][CO + 2 * jp];
+          c[0] = o.x;
+          c[1] = o.y;
+        }
+      }
+      // the wave's own sC[ch] rows: LDS accesses of one wave complete in order
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // the interior (8 x 32) is G_{k+1} / Gm_{k+1}: lane (i, m) stores coarse row 1 + i,
+      // columns 1 + 4m .. 4 + 4m, one 16-byte store where the four are inside the coarse ROI
+      {
+        const int i = 1 + (lane >> 3), j = 1 + 4 * (lane & 7);
+        const float4 v4 = *reinterpret_cast<const float4*>(&sC[ch][i][CO + j]);
+        const float v[4] = {v4.x, v4.y, v4.z, v4.w};
+        const int cy = Y0 / 2 - 1 + i - it.croi_y, cx = X0 / 2 - 1 + j - it.croi_x;
+        if (cy >= 0 && cy < it.croi_h) {
+          GLB T* out = ch < 3 ? mg<T>(it.g_out) : mg<T>(it.gm_out);
+          // 32-bit element offsets (the host keeps every level's planes under 2^31
+          // elements and its rows under 2^23)
+          const uint32_t orow = (uint32_t)(ch < 3 ? it.g_row : it.gm_row);
+          const uint32_t obase = ch < 3 ? (uint32_t)ch * (uint32_t)it.g_plane : 0u;
+          const int ob = (int)(obase + __umul24((uint32_t)cy, orow)) + cx;
+          if (cx >= 0 && cx + 3 < it.croi_w && ((uintptr_t)(out + ob) & (4 * sizeof(T) - 1)) == 0) {
+            stg4nt(out + ob, v);
+          } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (cx + u >= 0 && cx + u < it.croi_w) stgnt(out, ob + u, v[u]);
           }
         }
       }
@@ -636,10 +649,6 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
       const bool lap_tile = it.lw_w > 0 && X0 < it.lw_x + it.lw_w && X0 + TX > it.lw_x &&
                             Y0 < it.lw_y + it.lw_h && Y0 + TY > it.lw_y;
       if (!lap_tile) continue;
-      // the wave's own sC[ch] rows: LDS accesses of one wave complete in order
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
       // D+E: lane (rq, mm): fine columns 4mm .. 4mm+3 of fine rows 4rq .. 4rq+3.  Horizontal
       // EXPAND of coarse rows 2rq .. 2rq+3, then vertical EXPAND and the band
@@ -649,8 +658,8 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
         float4 eh[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          const float2 lo = *reinterpret_cast<const float2*>(&sC[ch][2 * rq + k][2 * mm]);
-          const float2 hi = *reinterpret_cast<const float2*>(&sC[ch][2 * rq + k][2 * mm + 2]);
+          const float* c = &sC[ch][2 * rq + k][CO + 2 * mm];
+          const float2 lo = {c[0], c[1]}, hi = {c[2], c[3]};
           eh[k].x = 0.125f * (lo.x + hi.x) + 0.75f * lo.y;
           eh[k].y = 0.5f * (lo.y + hi.x);
           eh[k].z = 0.125f * (lo.y + hi.y) + 0.75f * hi.x;
@@ -676,7 +685,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
           const int Y = Y0 + y - it.lw_y;
           const bool rowin = Y >= 0 && Y < it.lw_h;
           const bool full = rowin && X >= 0 && X + 3 < it.lw_w;
-          const int64_t base = ch * it.l_plane + (int64_t)Y * it.l_row + X;
+          const int base = ch * (int)it.l_plane + __mul24(Y, (int)it.l_row) + X;
           if (full && ((uintptr_t)(lout + base) & (4 * sizeof(T) - 1)) == 0) {
             stg4nt(lout + base, l);
           } else if (full) {

@@ -307,6 +307,12 @@ stitch_status upload(void* dst, const void* src, size_t bytes, hipStream_t s, co
 
 // Sub-steps per pyramid tile (tile height 16 * sub) for a launch of t16 16-row tiles: the
 // tallest (fewest staged halo rows) that still leaves about eight tiles per compute unit.
+// The pyramid pass addresses a level with 32-bit element offsets and 24-bit row products:
+// every plane set must span fewer than 2^31 elements and every row fewer than 2^23.
+bool fits_offsets(int64_t row, int64_t plane, int64_t rows, int nplanes) {
+  return row < ((int64_t)1 << 23) && (int64_t)(nplanes - 1) * plane + rows * row < ((int64_t)1 << 31);
+}
+
 int choose_sub(int64_t t16) {
   for (int sub = 8; sub > 1; sub >>= 1)
     if (t16 / sub >= 2048) return sub;
@@ -532,6 +538,9 @@ stitch_status stitch_pyramid(const stitch_image* g0, int32_t kind, stitch_levels
     const Rect lr{out->origin_x[k], out->origin_y[k], out->level[k].width, out->level[k].height};
     if (lr.x < 0 || lr.y < 0 || lr.x + lr.w > dw[k] || lr.y + lr.h > dh[k])
       return fail(STITCH_E_SHAPE, "level %d rectangle leaves the %dx%d level canvas", k, dw[k], dh[k]);
+    const int oes = elem_size(odt);
+    if (!fits_offsets(out->level[k].row_pitch / oes, out->level[k].plane_pitch / oes, out->level[k].height, nch))
+      return fail(STITCH_E_SHAPE, "%s spans 2^31 elements or more, or its rows 2^23 or more", name);
   }
   if (g0->width != out->level[0].width || g0->height != out->level[0].height)
     return fail(STITCH_E_SHAPE, "g0 and out->level[0] differ in size");
@@ -916,6 +925,15 @@ stitch_status stitch_plan_create(int32_t n, const int32_t* frame_w, const int32_
   for (int k = 0; k + 1 < L; ++k) p->off_items[k] = lay.take((size_t)n * sizeof(PyrItem));
   for (int k = 0; k < L; ++k) p->off_bcams[k] = lay.take((size_t)n * sizeof(BlendCam));
   p->off_bitems = lay.take((size_t)L * sizeof(BlendItem));
+  for (int i = 0; i < n; ++i) {
+    const CamPlan& c = p->cam[i];
+    for (int k = 0; k < L; ++k) {
+      const bool ok = (k > 0 || fits_offsets(c.mask_row, 0, c.roi[0].h, 1)) &&
+                      fits_offsets(c.g_row[k], c.g_plane[k], c.roi[k].h, 3) &&
+                      fits_offsets(c.gm_row[k], 0, c.roi[k].h, 1) && fits_offsets(c.l_row[k], c.l_plane[k], c.band[k].h, 3);
+      if (!ok) return fail(STITCH_E_SHAPE, "camera %d's level-%d planes span 2^31 elements or more", i, k);
+    }
+  }
   p->ws_bytes = lay.top;
   *out = p;
   p = nullptr;   // disarm the guard
