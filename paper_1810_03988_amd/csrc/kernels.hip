@@ -756,32 +756,38 @@ __global__ void __launch_bounds__(kThreads) k_blend(const BlendItem* __restrict_
     RawT l[4][3];
     uint32_t w[4];
     bool in[4];
+    bool u8;
   };
+  // The camera's descriptor is read once (scalar loads issued together); bounds tests are
+  // evaluated without branches and offsets are 32-bit (the host keeps every band and
+  // weight plane under 2^31 elements and its rows under 2^23).
   auto fetch = [&](int ci, CamSamples& cs) __attribute__((always_inline)) {
-    const CST BlendCam& c = cst(a.cams)[ci];
+    const BlendCam c = ld_cst(cst(a.cams) + ci);
     const GLB T* l = cg<T>(c.lap);
     const int lx = X - c.lx, wx = X - c.wx;
-    const bool xin = lx >= 0 && lx < c.lw && wx >= 0 && wx < c.ww;
+    const bool xin = (lx >= 0) & (lx < c.lw) & (wx >= 0) & (wx < c.ww);
+    const uint32_t lrow = (uint32_t)c.lap_row, lplane = (uint32_t)c.lap_plane, wrow = (uint32_t)c.wgt_row;
+    cs.u8 = c.wgt_u8 != 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int Y = Y0 + ybase + 4 * j;
       const int ly = Y - c.ly, wy = Y - c.wy;
-      cs.in[j] = xin && ly >= 0 && ly < c.lh && wy >= 0 && wy < c.wh;
-      const int64_t loff = cs.in[j] ? (int64_t)ly * c.lap_row + lx : 0;
-      const int64_t woff = cs.in[j] ? (int64_t)wy * c.wgt_row + wx : 0;
+      cs.in[j] = xin & (ly >= 0) & (ly < c.lh) & (wy >= 0) & (wy < c.wh);
+      const uint32_t loff = cs.in[j] ? __umul24((uint32_t)ly, lrow) + (uint32_t)lx : 0u;
+      const uint32_t woff = cs.in[j] ? __umul24((uint32_t)wy, wrow) + (uint32_t)wx : 0u;
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) cs.l[j][ch] = ld_raw(l, ch * c.lap_plane + loff);
-      cs.w[j] = c.wgt_u8 ? (uint32_t)cg<uint8_t>(c.wgt)[woff] : (uint32_t)ld_raw(cg<T>(c.wgt), woff);
+      for (int ch = 0; ch < 3; ++ch) cs.l[j][ch] = ld_raw(l, (uint32_t)ch * lplane + loff);
+      cs.w[j] = cs.u8 ? (uint32_t)cg<uint8_t>(c.wgt)[woff] : (uint32_t)ld_raw(cg<T>(c.wgt), woff);
     }
   };
   float acc[4][3];
 #pragma unroll
   for (int j = 0; j < 4; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0f;
   auto accumulate = [&](int ci, const CamSamples& cs) __attribute__((always_inline)) {
-    const bool u8 = cst(a.cams)[ci].wgt_u8 != 0;
+    (void)ci;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const float wv = !cs.in[j] ? 0.0f : (u8 ? (float)cs.w[j] * kInv255 : from_raw((RawT)cs.w[j]));
+      const float wv = !cs.in[j] ? 0.0f : (cs.u8 ? (float)cs.w[j] * kInv255 : from_raw((RawT)cs.w[j]));
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) acc[j][ch] = acc[j][ch] + wv * from_raw(cs.l[j][ch]);
     }

@@ -651,6 +651,11 @@ stitch_status stitch_blend(int32_t n, const stitch_levels* bands, const stitch_l
       if (st) return st;
       if (w.dtype != STITCH_U8 && w.dtype != dt)
         return fail(STITCH_E_SHAPE, "%s must be U8 or the band dtype", name);
+      const stitch_image& bl = bands[i].level[k];
+      const int wes = elem_size(w.dtype);
+      if (!fits_offsets(bl.row_pitch / es, bl.plane_pitch / es, bl.height, 3) ||
+          !fits_offsets(w.row_pitch / wes, 0, w.height, 1))
+        return fail(STITCH_E_SHAPE, "pyramid %d level %d spans 2^31 elements or more, or its rows 2^23 or more", i, k);
     }
   }
   if (L > 1 && !keep_r) return fail(STITCH_E_NULL, "keep_r is required when levels > 1 (it holds R_k)");
