@@ -281,6 +281,11 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
   __shared__ __attribute__((aligned(16))) float sColT[NCT][4];
   __shared__ __attribute__((aligned(16))) float sRowT[NRT][4];
   __shared__ int sCls[2];   // warp only: window classes of the 16-row and the 7-row stage
+  // warp only: the source rectangle under a source-interior 16-row window, one 256-byte
+  // LDS row per source row (read as aligned 16-byte chunks), and its origin
+  constexpr int FH = 24, FWB = 256;
+  __shared__ __attribute__((aligned(16))) uint32_t sSrc[WARP ? FH : 1][FWB / 4];
+  __shared__ int sBox[4];   // bx0, by0, rows, 16-byte chunks per row
   constexpr uint32_t kPlaneRing = EH * SW * 4;       // bytes of one channel's ring of rows
 
   const int tid = threadIdx.x;
@@ -341,13 +346,14 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
           // stage).
           const int lane = tid - 192;
           bool bad = false, zok = false, lft = false, rgt = false, top = false, bot = false;
+          float xc = 0.0f, yc = 0.0f;
+          const int w = it.frame_w, h = it.frame_h;
           if (lane < 8) {
             float hv[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) hv[i] = it.hinv[i];
-            const int w = it.frame_w, h = it.frame_h;
             const int r0 = lane < 4 ? EH - TY : 0, r1 = lane < 4 ? EH - 1 : EH - TY - 1;
-            float xc, yc, zc;
+            float zc;
             warp_coords_z(hv, (float)(X0 - 4 + ((lane & 1) ? EW - 1 : 0)),
                           (float)(Y0 - 4 + ((lane & 2) ? r1 : r0)), xc, yc, zc);
             zok = zc >= 0x1p-10f && zc <= 0x1p20f;
@@ -359,12 +365,39 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
           }
           const uint64_t mb = __ballot(bad), mz = __ballot(zok), ml = __ballot(lft), mr = __ballot(rgt),
                          mt = __ballot(top), mo = __ballot(bot);
+          // bounding box of the 16-row window's corner images (lanes 0-3)
+          float mnx = xc, mxx = xc, mny = yc, mxy = yc;
+#pragma unroll
+          for (int d = 1; d < 4; d <<= 1) {
+            mnx = fminf(mnx, __shfl_xor(mnx, d));
+            mxx = fmaxf(mxx, __shfl_xor(mxx, d));
+            mny = fminf(mny, __shfl_xor(mny, d));
+            mxy = fmaxf(mxy, __shfl_xor(mxy, d));
+          }
           if (lane < 2) {
             const int sh = 4 * lane;
             auto all4 = [sh](uint64_t m) { return ((m >> sh) & 15ull) == 15ull; };
             const bool fast = ((mb >> sh) & 15ull) == 0ull;
             const bool outside = all4(mz) && (all4(ml) || all4(mr) || all4(mt) || all4(mo));
-            sCls[lane] = (fast ? 1 : 0) | (outside ? 2 : 0);
+            // Staged (bit 2, 16-row window only): every tap lies in the box [bx0, bx1] x
+            // [by0, by1] (the corner images' bounding box, one sample wider on each side
+            // for rounding), which fits the LDS rows, and the 16-byte chunks covering a
+            // box row (from its start rounded down to 16 bytes, at most 15 + 3 nbx + 15
+            // bytes) stay inside the frame row: bx0 >= 5 and bx1 <= w - 11.
+            bool staged = false;
+            if (lane == 0 && fast) {
+              const int bx0 = (int)floorf(mnx) - 1, bx1 = (int)floorf(mxx) + 2;
+              const int by0 = (int)floorf(mny) - 1, by1 = (int)floorf(mxy) + 2;
+              const int nbx = bx1 - bx0 + 1, nby = by1 - by0 + 1;
+              staged = bx0 >= 5 && bx1 <= w - 11 && by0 >= 0 && by1 <= h - 1 && 15 + 3 * nbx <= FWB && nby <= FH;
+              if (staged) {
+                sBox[0] = bx0;
+                sBox[1] = by0;
+                sBox[2] = nby;
+                sBox[3] = (15 + 3 * nbx + 15) / 16;
+              }
+            }
+            sCls[lane] = (fast ? 1 : 0) | (outside ? 2 : 0) | (staged ? 4 : 0);
           }
         }
       }
@@ -444,6 +477,78 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
               cell(0, q) = 0.0f;
               cell(1, q) = 0.0f;
               cell(2, q) = 0.0f;
+              cell(3, q) = (float)mv[q] * kInv255;
+            }
+          } else if (fast && (cls & 4) != 0) {
+            // Source rectangle staged in LDS: its rows are read as aligned 16-byte chunks
+            // (the reads of the whole workgroup cover it once), each sample's coordinates
+            // are computed meanwhile, and its two 8-byte tap pairs come from LDS.
+            const int bx0 = sBox[0], by0 = sBox[1], nby = sBox[2], nck = sBox[3];
+            constexpr int NCK = (FH * (FWB / 16) + kThreads - 1) / kThreads;
+            typedef uint32_t vu4 __attribute__((ext_vector_type(4)));
+            vu4 ck[NCK];
+#pragma unroll
+            for (int k = 0; k < NCK; ++k) {
+              // spare lanes repeat a chunk of the box (the same bytes to the same place)
+              const int e = tid + k * kThreads, r = min(e / (FWB / 16), nby - 1), c = min(e % (FWB / 16), nck - 1);
+              const uintptr_t a = ((uintptr_t)src + __umul24((uint32_t)(by0 + r), srow32) + 3u * (uint32_t)bx0) & ~(uintptr_t)15;
+              ck[k] = *reinterpret_cast<const GLB vu4*>(a + 16u * (uint32_t)c);
+            }
+            // a box row starts in its LDS row at byte (frame address of the box row) mod 16
+            const uint32_t sbase = (uint32_t)(uintptr_t)src + 3u * (uint32_t)bx0;
+            float fxq[NQ], fyq[NQ];
+            uint32_t o1[NQ], o2[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+              // the coordinate sequence from the tabled products (the same roundings as
+              // the direct one; the in-range division is the IEEE one)
+              const float4 ct = *reinterpret_cast<const float4*>(sColT[cc[q]]);
+              const float4 rt = *reinterpret_cast<const float4*>(sRowT[rr[q] < 0 ? R0 : rr[q]]);
+              float u, v, z, x, y;
+              {
+#pragma clang fp contract(off)
+                u = (ct.x + rt.x) + hv[2];
+                v = (ct.y + rt.y) + hv[5];
+                z = (ct.z + rt.z) + hv[8];
+              }
+              div2_in_range(u, v, z, x, y);
+              fxq[q] = __builtin_amdgcn_fractf(x);
+              fyq[q] = __builtin_amdgcn_fractf(y);
+              const uint32_t xi = (uint32_t)(int)x, yi = (uint32_t)(int)y;
+              const uint32_t r = yi - (uint32_t)by0, dx = 3u * (xi - (uint32_t)bx0);
+              const uint32_t s1 = (sbase + __umul24(yi, srow32)) & 15u;
+              o1[q] = r * FWB + s1 + dx;
+              o2[q] = (r + 1u) * FWB + ((s1 + srow32) & 15u) + dx;
+            }
+#pragma unroll
+            for (int k = 0; k < NCK; ++k) {
+              const int e = tid + k * kThreads, r = min(e / (FWB / 16), nby - 1), c = min(e % (FWB / 16), nck - 1);
+              *reinterpret_cast<vu4*>(&sSrc[r][4 * c]) = ck[k];
+            }
+            __syncthreads();
+            const uint8_t* sb = reinterpret_cast<const uint8_t*>(&sSrc[0][0]);
+            auto ld8s = [&](uint32_t o) -> unsigned long long {
+              const uint32_t* d = reinterpret_cast<const uint32_t*>(sb + (o & ~3u));
+              const uint32_t w0 = d[0], w1 = d[1], w2 = d[2];
+              const uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, o & 3u);
+              const uint32_t hi = __builtin_amdgcn_alignbyte(w2, w1, o & 3u);
+              return (unsigned long long)lo | ((unsigned long long)hi << 32);
+            };
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+              const unsigned long long ra = ld8s(o1[q]), rb = ld8s(o2[q]);
+              const float fx = fxq[q], fy = fyq[q], gx = 1.0f - fx, gy = 1.0f - fy;
+              const float gyi = gy * kInv255, fyi = fy * kInv255;
+              const float w00 = gyi * gx, w01 = gyi * fx, w10 = fyi * gx, w11 = fyi * fx;
+              const uint32_t a0 = (uint32_t)ra, a1 = (uint32_t)(ra >> 32);
+              const uint32_t b0 = (uint32_t)rb, b1 = (uint32_t)(rb >> 32);
+              const float p00[3] = {(float)(a0 & 255u), (float)((a0 >> 8) & 255u), (float)((a0 >> 16) & 255u)};
+              const float p01[3] = {(float)(a0 >> 24), (float)(a1 & 255u), (float)((a1 >> 8) & 255u)};
+              const float p10[3] = {(float)(b0 & 255u), (float)((b0 >> 8) & 255u), (float)((b0 >> 16) & 255u)};
+              const float p11[3] = {(float)(b0 >> 24), (float)(b1 & 255u), (float)((b1 >> 8) & 255u)};
+#pragma unroll
+              for (int ch = 0; ch < 3; ++ch)
+                cell(ch, q) = w00 * p00[ch] + w01 * p01[ch] + w10 * p10[ch] + w11 * p11[ch];
               cell(3, q) = (float)mv[q] * kInv255;
             }
           } else if (fast) {
