@@ -82,6 +82,28 @@ def test_c1_is_deterministic_and_repeatable():
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("offset, pad", [(3, 7), (1, 16), (8, 1)])
+def test_frames_at_odd_addresses_and_pitches_give_the_same_panorama(offset, pad):
+    """The source rows are read as aligned 16-byte chunks (from each row's start rounded
+    down) or as unaligned 8-byte pairs: frames at odd byte addresses with odd row pitches
+    must give the panorama of packed frames bit for bit."""
+    r = wl.rig_c1()
+    frames = [f.to(DEV) for f in wl.render_rig_frames(r)]
+    plan = P.Plan(r.frame_sizes, r.H, r.masks(), r.canvas_w, r.canvas_h, r.levels)
+    want = plan.frame(frames).clone()
+    views = []
+    for f in frames:
+        h, w, _ = f.shape
+        pitch = 3 * w + pad
+        buf = torch.zeros(offset + h * pitch + 64, dtype=torch.uint8, device=DEV)
+        v = torch.as_strided(buf, (h, w, 3), (pitch, 3, 1), offset)
+        v.copy_(f)
+        views.append(v)
+    got = plan.frame(views)
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_random_small_rigs(seed):
     """Odd and even canvases spanning several tiles with ragged tails, 1-3 cameras,
