@@ -383,9 +383,12 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
             // [by0, by1] (the corner images' bounding box, one sample wider on each side
             // for rounding), which fits the LDS rows, and the 16-byte chunks covering a
             // box row (from its start rounded down to 16 bytes, at most 15 + 3 nbx + 15
-            // bytes) stay inside the frame row: bx0 >= 5 and bx1 <= w - 11.
+            // bytes) stay inside the frame row: bx0 >= 5 and bx1 <= w - 11.  The row
+            // pitch is a multiple of 16 bytes, so every box row starts at the same offset
+            // in its LDS row.
             bool staged = false;
-            if (lane == 0 && fast) {
+            const int64_t srow = fa.n ? fa.row[it.frame_slot] : it.img_row;
+            if (lane == 0 && fast && (srow & 15) == 0) {
               const int bx0 = (int)floorf(mnx) - 1, bx1 = (int)floorf(mxx) + 2;
               const int by0 = (int)floorf(mny) - 1, by1 = (int)floorf(mxy) + 2;
               const int nbx = bx1 - bx0 + 1, nby = by1 - by0 + 1;
@@ -494,10 +497,10 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
               const uintptr_t a = ((uintptr_t)src + __umul24((uint32_t)(by0 + r), srow32) + 3u * (uint32_t)bx0) & ~(uintptr_t)15;
               ck[k] = *reinterpret_cast<const GLB vu4*>(a + 16u * (uint32_t)c);
             }
-            // a box row starts in its LDS row at byte (frame address of the box row) mod 16
-            const uint32_t sbase = (uint32_t)(uintptr_t)src + 3u * (uint32_t)bx0;
+            // every box row starts in its LDS row at byte (frame address of the box row) mod 16
+            const uint32_t s1 = ((uint32_t)(uintptr_t)src + 3u * (uint32_t)bx0) & 15u;
             float fxq[NQ], fyq[NQ];
-            uint32_t o1[NQ], o2[NQ];
+            uint32_t o1[NQ];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
               // the coordinate sequence from the tabled products (the same roundings as
@@ -516,9 +519,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
               fyq[q] = __builtin_amdgcn_fractf(y);
               const uint32_t xi = (uint32_t)(int)x, yi = (uint32_t)(int)y;
               const uint32_t r = yi - (uint32_t)by0, dx = 3u * (xi - (uint32_t)bx0);
-              const uint32_t s1 = (sbase + __umul24(yi, srow32)) & 15u;
               o1[q] = r * FWB + s1 + dx;
-              o2[q] = (r + 1u) * FWB + ((s1 + srow32) & 15u) + dx;
             }
 #pragma unroll
             for (int k = 0; k < NCK; ++k) {
@@ -534,9 +535,16 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
               const uint32_t hi = __builtin_amdgcn_alignbyte(w2, w1, o & 3u);
               return (unsigned long long)lo | ((unsigned long long)hi << 32);
             };
+            // every sample's tap reads first, then the bilinear combination
+            unsigned long long ras[NQ], rbs[NQ];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-              const unsigned long long ra = ld8s(o1[q]), rb = ld8s(o2[q]);
+              ras[q] = ld8s(o1[q]);
+              rbs[q] = ld8s(o1[q] + FWB);
+            }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+              const unsigned long long ra = ras[q], rb = rbs[q];
               const float fx = fxq[q], fy = fyq[q], gx = 1.0f - fx, gy = 1.0f - fy;
               const float gyi = gy * kInv255, fyi = fy * kInv255;
               const float w00 = gyi * gx, w01 = gyi * fx, w10 = fyi * gx, w11 = fyi * fx;
