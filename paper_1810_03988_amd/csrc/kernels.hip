@@ -836,7 +836,6 @@ __global__ void __launch_bounds__(kThreads) k_blend(const BlendItem* __restrict_
   constexpr int HS = 36, ES = TX + 4;
   __shared__ __attribute__((aligned(16))) float sC[3][CH][HS];
   __shared__ __attribute__((aligned(16))) float sE[3][CH][ES];
-  __shared__ __attribute__((aligned(16))) uint32_t sP[TY][TX * 3 / 4];
 
   const int tid = threadIdx.x;
   const int t = xcd_remap(blockIdx.x, gridDim.x);
@@ -982,34 +981,30 @@ __global__ void __launch_bounds__(kThreads) k_blend(const BlendItem* __restrict_
     }
   }
   if (FINAL) {
-    // quantise, pack the 64x16 RGB tile in LDS, write it back as whole dwords when aligned
-    uint8_t* sb = reinterpret_cast<uint8_t*>(&sP[0][0]);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int y = ybase + 4 * j;
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch)
-        sb[y * (TX * 3) + x * 3 + ch] = (uint8_t)fminf(fmaxf(rintf(255.0f * acc[j][ch]), 0.0f), 255.0f);
-    }
-    __syncthreads();
+    // Quantise.  A full tile row in an aligned panorama goes out as whole dwords: each
+    // group of four lanes (four adjacent pixels, 12 bytes) packs its bytes into three
+    // dwords in its first lane; otherwise byte by byte.
     uint8_t* const pano_ptr = po.ptr ? po.ptr : a.pano;
     const int64_t pano_row = po.ptr ? po.row : a.pano_row;
-    const int nx = min(TX, a.W - X0);
-    const bool words = nx == TX && (pano_row & 3) == 0 && ((uintptr_t)pano_ptr & 3) == 0;
+    const bool words = X0 + TX <= a.W && (pano_row & 3) == 0 && ((uintptr_t)pano_ptr & 3) == 0;
     GLB uint8_t* pano = mg<uint8_t>(pano_ptr);
-    if (words) {
-      constexpr int WPR = TX * 3 / 4;   // 48 dwords per row
-      for (int e = tid; e < TY * WPR; e += kThreads) {
-        const int y = e / WPR, wi = e - y * WPR;
-        const int Y = Y0 + y;
-        if (Y < a.H)
-          *reinterpret_cast<GLB uint32_t*>(pano + (int64_t)Y * pano_row + (int64_t)X0 * 3 + wi * 4) = sP[y][wi];
-      }
-    } else {
-      for (int e = tid; e < TY * TX * 3; e += kThreads) {
-        const int y = e / (TX * 3), b = e - y * (TX * 3);
-        const int Y = Y0 + y;
-        if (Y < a.H && b < nx * 3) pano[(int64_t)Y * pano_row + (int64_t)X0 * 3 + b] = sb[y * (TX * 3) + b];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int Y = Y0 + ybase + 4 * j;
+      uint32_t q[3];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) q[ch] = (uint32_t)fminf(fmaxf(rintf(255.0f * acc[j][ch]), 0.0f), 255.0f);
+      GLB uint8_t* prow = pano + (int64_t)Y * pano_row + (int64_t)X * 3;
+      if (words) {
+        const uint32_t v = q[0] | (q[1] << 8) | (q[2] << 16);
+        const uint32_t v1 = __shfl_down(v, 1), v2 = __shfl_down(v, 2), v3 = __shfl_down(v, 3);
+        if ((x & 3) == 0 && Y < a.H) {
+          typedef uint32_t vu3 __attribute__((ext_vector_type(3)));
+          *reinterpret_cast<GLB vu3*>(prow) = vu3{v | (v1 << 24), (v1 >> 8) | (v2 << 16), (v2 >> 16) | (v3 << 8)};
+        }
+      } else if (X < a.W && Y < a.H) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) prow[ch] = (uint8_t)q[ch];
       }
     }
   }
