@@ -125,7 +125,9 @@ stitch_status stitch_warp_coords(const double H[9], int32_t roi_x, int32_t roi_y
  * result equals the full-canvas definition when g0 is zero outside its rectangle and
  * each level's rectangle holds that level's support; with origin 0 and full-canvas
  * sizes it is the plain pyramid of g0.  Level 0 of the output is overwritten with
- * G_0 (kind 0) or L_0 (kind 1) and may alias g0 when dtypes match.
+ * G_0 (kind 0) or L_0 (kind 1) and may alias g0 when dtypes match.  Each output level's
+ * planes must span fewer than 2^31 elements and its rows fewer than 2^23 (SHAPE
+ * otherwise: the kernels address levels with 32-bit offsets).
  * workspace: device memory of stitch_pyramid_workspace_bytes(levels) bytes, 256-byte
  * aligned, holding the launch tables (calls that may overlap must not share it; the
  * table upload comes from pageable host memory and may wait for the stream).
@@ -139,7 +141,9 @@ stitch_status stitch_pyramid(const stitch_image* g0, int32_t kind, stitch_levels
  * bands[i]: F32/F16 CHW 3-channel Laplacian levels; weights[i]: Gaussian weight
  * levels (F32/F16 1 channel of the band dtype, or U8 at any level read as u8/255); all
  * pyramids share levels and canvas size, and each level's samples outside its stored
- * rectangle count as 0.  pano: U8 HWC 3 channels, canvas_w x canvas_h.  keep_r: a
+ * rectangle count as 0; every band level's planes, and every weight level, must span
+ * fewer than 2^31 elements with rows under 2^23 elements (SHAPE otherwise: 32-bit offsets).
+ * pano: U8 HWC 3 channels, canvas_w x canvas_h.  keep_r: a
  * full-canvas pyramid (origins 0, band dtype, CHW, 3 channels) receiving R_k; it is
  * required when levels > 1 (the collapse reads R_{k+1} from it); its level[0].data may be
  * NULL to skip storing R_0.  workspace: stitch_blend_workspace_bytes(n, levels) bytes of
@@ -160,7 +164,8 @@ stitch_status stitch_blend(int32_t n, const stitch_levels* bands, const stitch_l
  * (host, canvas_h x canvas_w uint8, row-major, summing to 255 at every pixel),
  * levels L (1..16, every canvas level side >= 3), storage STITCH_F32 or STITCH_F16 for
  * every stored pyramid level.  Host-only: touches no GPU.  The plan keeps what it
- * needs from masks; the caller may free them after the call.
+ * needs from masks; the caller may free them after the call.  Every camera's stored
+ * level planes must span fewer than 2^31 elements with rows under 2^23 (SHAPE otherwise).
  * Errors: NULL, SHAPE, LEVELS, HOMOGRAPHY, MASK, UNSUPPORTED. */
 stitch_status stitch_plan_create(int32_t n, const int32_t* frame_w, const int32_t* frame_h,
                                  const double* H, const uint8_t* const* masks, int32_t canvas_w,

@@ -151,6 +151,10 @@ def test_single_stage_calls_validate_on_host():
     lv.levels = 2
     assert lib.stitch_pyramid(ctypes.byref(g0), 1, ctypes.byref(lv), None, 0, None) == E["E_WORKSPACE"]
     assert lib.stitch_pyramid(ctypes.byref(g0), 3, ctypes.byref(lv), fake, 4096, None) == E["E_UNSUPPORTED"]
+    # the kernels address a level with 32-bit offsets: rows of 2^23 elements or more are refused
+    lv.level[1] = S.StitchImage(fake, 4, 4, 1, S.F32, S.CHW, (1 << 23) * 4, (1 << 23) * 16)
+    assert lib.stitch_pyramid(ctypes.byref(g0), 1, ctypes.byref(lv), fake, 4096, None) == E["E_SHAPE"]
+    lv.level[1] = S.StitchImage(fake, 4, 4, 1, S.F32, S.CHW, 256, 256 * 4)
     # blend: missing R storage for a multi-level blend
     pano = S.StitchImage(fake, 8, 8, 3, S.U8, S.HWC, 24, 0)
     b = S.StitchLevels()
@@ -163,6 +167,10 @@ def test_single_stage_calls_validate_on_host():
     assert lib.stitch_blend(1, ctypes.byref(b), ctypes.byref(w), ctypes.byref(pano), None, fake, 1 << 20,
                             None) == E["E_NULL"]
     assert lib.stitch_blend(0, ctypes.byref(b), ctypes.byref(w), ctypes.byref(pano), None, fake, 1 << 20,
+                            None) == E["E_SHAPE"]
+    # three band planes spanning 2^31 elements or more are refused (32-bit offsets)
+    b.level[1] = S.StitchImage(fake, 4, 4, 3, S.F32, S.CHW, 256, (1 << 30) * 4)
+    assert lib.stitch_blend(1, ctypes.byref(b), ctypes.byref(w), ctypes.byref(pano), None, fake, 1 << 20,
                             None) == E["E_SHAPE"]
 
 
