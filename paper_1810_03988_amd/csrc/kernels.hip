@@ -70,18 +70,12 @@ __device__ __forceinline__ typename RawOf<T>::type ld_raw(const GLB T* p, int64_
 }
 __device__ __forceinline__ float from_raw(uint32_t b) { return __builtin_bit_cast(float, b); }
 __device__ __forceinline__ float from_raw(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
-// Four consecutive samples with one store (caller checks the alignment).
 typedef float vf4 __attribute__((ext_vector_type(4)));
 typedef _Float16 vh4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ void stg4(GLB float* p, const float v[4]) {
-  *reinterpret_cast<GLB vf4*>(p) = vf4{v[0], v[1], v[2], v[3]};
-}
-__device__ __forceinline__ void stg4(GLB _Float16* p, const float v[4]) {
-  *reinterpret_cast<GLB vh4*>(p) = vh4{(_Float16)v[0], (_Float16)v[1], (_Float16)v[2], (_Float16)v[3]};
-}
 
-// Streaming stores for the pyramid levels: written once, read by a later kernel long after
-// the lines would have left L2.
+// Streaming stores for the pyramid levels (written once, read by a later kernel long after
+// the lines would have left L2); the four-sample forms need 4-sample alignment (checked by
+// the caller).
 __device__ __forceinline__ void stgnt(GLB float* p, int64_t i, float v) { __builtin_nontemporal_store(v, p + i); }
 __device__ __forceinline__ void stgnt(GLB _Float16* p, int64_t i, float v) {
   __builtin_nontemporal_store((_Float16)v, p + i);
@@ -166,19 +160,6 @@ __device__ __forceinline__ void div2_in_range(float u, float v, float z, float& 
   qy = __builtin_fmaf(__builtin_fmaf(-z, qy, v), r, qy);
   x = __builtin_fmaf(__builtin_fmaf(-z, qx, u), r, qx);
   y = __builtin_fmaf(__builtin_fmaf(-z, qy, v), r, qy);
-}
-
-// The coordinate sequence with that division (callers guarantee the range).
-__device__ __forceinline__ void warp_coords_in_range(const float* __restrict__ h, float Xf, float Yf, float& x,
-                                                     float& y) {
-  float u, v, z;
-  {
-#pragma clang fp contract(off)
-    u = (h[0] * Xf + h[1] * Yf) + h[2];
-    v = (h[3] * Xf + h[4] * Yf) + h[5];
-    z = (h[6] * Xf + h[7] * Yf) + h[8];
-  }
-  div2_in_range(u, v, z, x, y);
 }
 
 // Eight bytes at any byte address (global memory accepts unaligned dword accesses).
