@@ -333,12 +333,17 @@ def phase_name(key):
 
 
 def source_hash() -> str:
-    """SHA-256 over the sources that decide what a launch does: the kernels and the planner
-    (regions, tiles, tables)."""
+    """SHA-256 over the code that decides what a launch does: the kernels and the planner
+    (regions, tiles, tables), with comments and whitespace removed (neither source holds a
+    comment marker inside a string literal)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in ("kernels.hip", "stitch_api.cpp"):
-        h.update((ROOT / "paper_1810_03988_amd" / "csrc" / name).read_bytes())
+        text = (ROOT / "paper_1810_03988_amd" / "csrc" / name).read_text()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

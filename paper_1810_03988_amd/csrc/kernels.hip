@@ -217,10 +217,13 @@ __device__ __forceinline__ int find_item(const PyrItem* __restrict__ items, int 
 //      channels (the bilinear warp of the source frame at level 0, the stored G_k above)
 //      and the seam weight.  LDS rows form a ring of 23: the 7 rows a sub-step shares with
 //      the previous one stay where they are, so only its 16 new rows are staged (all 23 on
-//      a tile's first sub-step);
+//      a tile's first sub-step).  At level 0 the source rectangle under a source-interior
+//      window is first read into LDS as aligned 16-byte chunks (one more barrier) and the
+//      bilinear taps come from there;
 //   B..E  (wave w alone on channel slot w, no workgroup barrier)
-//      B+C  REDUCE -> extended 34x10 coarse tile (horizontal then vertical, in
-//           registers); its interior is G_{k+1} / Gm_{k+1};
+//      B+C  REDUCE -> extended 34x10 coarse tile (horizontal then vertical in registers,
+//           then into the wave's LDS rows); its interior, G_{k+1} / Gm_{k+1}, is stored
+//           from LDS with one 16-byte store per lane;
 //      D+E  horizontal and vertical EXPAND of the coarse tile and L_k = G_k - EXPAND(G_{k+1}),
 //           stored on the band window (image channels only).
 struct PyrTile {
