@@ -44,8 +44,9 @@ def parse():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16"])
     ap.add_argument("--form", default="batched", choices=["batched", "plain"],
                     help="the headline form: all frames of the step as one batch, or one stitch_frame per frame")
-    ap.add_argument("--forms", default="batched_graph_f16,plain_f32,plain_f16",
-                    help="extra forms timed after the headline (comma list of batched_graph_<s> / plain_<s>, "
+    ap.add_argument("--forms", default="batched_graph_f16,plain_f32,plain_f16,pipe_f32",
+                    help="extra forms timed after the headline (comma list of batched_graph_<s> / plain_<s> / "
+                         "pipe_<s>, the last end to end through PCIe, "
                          "or 'none')")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-events", action="store_true",
@@ -401,6 +402,27 @@ def time_form(rig, frames, storage, steps, warmup, kernel_events=True):
     return plan, ms, timing, panos
 
 
+def time_pipe(rig, frames, storage, steps, warmup, depth=3):
+    """End to end through the pipelined sequence form: the step's frame sets start in
+    pinned host memory and its panoramas end there (PCIe both ways, overlapped with the
+    stitching on separate streams).  Wall-clock ms per step."""
+    import paper_1810_03988_amd as P
+    plan = P.Plan(rig.frame_sizes, rig.H, rig.masks(), rig.canvas_w, rig.canvas_h, rig.levels, storage=storage)
+    host = [[f.cpu().pin_memory() for f in fs] for fs in frames]
+    panos = [torch.empty((rig.canvas_h, rig.canvas_w, 3), dtype=torch.uint8, pin_memory=True) for _ in frames]
+    pipe = P.Pipe(plan, depth)
+    for _ in range(warmup):
+        pipe.run(host, panos)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pipe.run(host, panos)
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    pipe.close()
+    in_bytes = sum(f.numel() for fs in host for f in fs)
+    out_bytes = sum(p.numel() for p in panos)
+    return ms, in_bytes, out_bytes
+
+
 def time_batched(rig, frames, storage, steps, warmup, tune_cache=None, kernel_events=True):
     """All frames of the sequence as jobs of one batch (one plan per job).  Timed twice on
     one stream: with per-launch HIP events (launches issued directly, an event after each)
@@ -609,7 +631,14 @@ def main():
         if (kind == a.form and st == a.storage) or (kind == "batched_graph" and a.form == "batched" and
                                                     st == a.storage):
             continue
-        if kind in ("batched", "batched_graph"):
+        if kind == "pipe":
+            pms, in_b, out_b = time_pipe(rig, frames, st, a.steps, a.warmup)
+            forms[f"pipe_{st}"] = {"Mpx_s": mpx(pms), "ms_per_step": round(pms, 4),
+                                   "how": "end to end: pinned host frames in, host panoramas out, uploads, "
+                                          "stitch_frame and downloads on three streams (3 slots); wall clock",
+                                   "pcie_bytes_per_step": [in_b, out_b],
+                                   "pcie_GBs": round((in_b + out_b) / (pms / 1e3) / 1e9, 1)}
+        elif kind in ("batched", "batched_graph"):
             res, cfg, _pl, _b, _p = time_batched(rig, frames, st, a.steps, a.warmup, tune, False)
             forms[f"batched_graph_{st}"] = {"Mpx_s": mpx(res["graph"][0]), "ms_per_step": round(res["graph"][0], 4),
                                             "how": "one HIP graph replay per step"}

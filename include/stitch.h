@@ -268,6 +268,32 @@ stitch_status stitch_batch_config(const stitch_batch* batch, int32_t wg_per_cu[S
                                   int32_t tile_rows[STITCH_MAX_LEVELS]);
 void          stitch_batch_destroy(stitch_batch* batch);
 
+/* ---- stream-pipelined frame sequences: host frames in, host panoramas out -------- */
+
+/* The paper keeps the upload of the next frames, the stitching of the current ones and
+ * the download of the previous panorama in flight together on stream queues (Sec. 4.3.2,
+ * Fig. 3).  A pipe owns `depth` (1..8) device slots, each holding one frame set and one
+ * panorama of a bound plan, and three streams of default priority: copies in,
+ * stitch_frame, copies out.  Events order the reuse of a slot: its frames are overwritten
+ * only after the stitch that read them, its panorama only after the copy that read it.
+ * The plan must stay bound and unused by other calls while a pipe runs on it.
+ * Errors: NULL, SHAPE (depth), STATE (plan without workspace), DEVICE. */
+typedef struct stitch_pipe stitch_pipe;
+stitch_status stitch_pipe_create(stitch_plan* plan, int32_t depth, stitch_pipe** out);
+/* Stitch nframes frame sets: frames[t * n + i] is camera i's frame of set t (host memory,
+ * U8 HWC with packed rows: frame_w x frame_h x 3 bytes), panos[t] its panorama (host, U8
+ * HWC packed, canvas_w x canvas_h x 3 bytes).  Returns when every panorama is on the host.
+ * Memory from stitch_host_alloc (pinned) lets the copies overlap the stitching; pageable
+ * memory gives the same results with serialised copies.  Errors: NULL, SHAPE (nframes < 0),
+ * DEVICE, and those of stitch_frame. */
+stitch_status stitch_pipe_run(stitch_pipe* pipe, int32_t nframes, const uint8_t* const* frames,
+                              uint8_t* const* panos);
+void          stitch_pipe_destroy(stitch_pipe* pipe);
+/* Pinned host memory for pipe inputs and outputs (hipHostMalloc); release it with
+ * stitch_host_free.  Errors: NULL, DEVICE. */
+stitch_status stitch_host_alloc(size_t bytes, void** out);
+void          stitch_host_free(void* p);
+
 /* ---- differentiable form: refining a pair's transformation -------------------- */
 
 /* The paper fixes each frame's transformation by feature matching and PROSAC (Alg. 3,

@@ -237,6 +237,18 @@ struct stitch_plan {
   EventLog timing;   // optional per-launch event timing (diagnostics)
 };
 
+void stitch::plan_geometry(const stitch_plan* p, int* n, int* frame_w, int* frame_h, int* canvas_w, int* canvas_h,
+                           bool* bound) {
+  *n = p->n;
+  for (int i = 0; i < p->n; ++i) {
+    frame_w[i] = p->cam[i].fw;
+    frame_h[i] = p->cam[i].fh;
+  }
+  *canvas_w = p->W;
+  *canvas_h = p->H;
+  *bound = p->ws != nullptr;
+}
+
 namespace {
 
 // Bump allocator over the workspace (offsets only, 256-byte aligned).

@@ -111,6 +111,11 @@ hipError_t launch_expand_sub(bool f16, int nch, void* fine, int64_t f_row, int64
 hipError_t launch_convert(bool f16_out, int nch, bool src_u8, const void* src, int64_t s_row, int64_t s_plane,
                           void* dst, int64_t d_row, int64_t d_plane, int w, int h, hipStream_t s);
 
+// Geometry of a plan for the other host files: cameras, their frame sizes (arrays of at
+// least kMaxCameras), the canvas, and whether a workspace is bound.
+void plan_geometry(const stitch_plan* p, int* n, int* frame_w, int* frame_h, int* canvas_w, int* canvas_h,
+                   bool* bound);
+
 // Host helpers shared by the API files (stitch_api.cpp).
 stitch_status fail(stitch_status s, const char* fmt, ...);
 stitch_status hip_fail(hipError_t e, const char* what);

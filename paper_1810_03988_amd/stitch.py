@@ -89,6 +89,11 @@ SIGNATURES = {
                                       c_void_p]),
     "stitch_grad_backward": (c_int32, [c_void_p, POINTER(StitchImage), POINTER(c_double), c_void_p]),
     "stitch_grad_destroy": (None, [c_void_p]),
+    "stitch_pipe_create": (c_int32, [c_void_p, c_int32, POINTER(c_void_p)]),
+    "stitch_pipe_run": (c_int32, [c_void_p, c_int32, POINTER(c_void_p), POINTER(c_void_p)]),
+    "stitch_pipe_destroy": (None, [c_void_p]),
+    "stitch_host_alloc": (c_int32, [c_size_t, POINTER(c_void_p)]),
+    "stitch_host_free": (None, [c_void_p]),
     "stitch_corners_to_h": (c_int32, [POINTER(c_double), c_int32, c_int32, POINTER(c_double)]),
     "stitch_map_grad_to_corners": (c_int32, [POINTER(c_double), c_int32, c_int32, POINTER(c_double),
                                              POINTER(c_double)]),
@@ -345,6 +350,45 @@ class Plan:
     def close(self) -> None:
         if getattr(self, "_h", None):
             lib().stitch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------- pipelined sequences
+class Pipe:
+    """Stream-pipelined frame sequences over a bound plan (Sec. 4.3.2, Fig. 3): host frame
+    sets in, host panoramas out, with uploads, stitching and downloads on three streams."""
+
+    def __init__(self, plan: "Plan", depth: int = 2):
+        handle = c_void_p()
+        check(lib().stitch_pipe_create(plan._h, depth, ctypes.byref(handle)))
+        self._h = handle
+        self.plan = plan
+        self.depth = depth
+
+    def run(self, frames, panos) -> None:
+        """frames: one list of n host uint8 (h, w, 3) tensors per frame set (pinned memory
+        lets the copies overlap); panos: one host uint8 (H, W, 3) tensor per frame set.
+        Returns when every panorama is on the host."""
+        n = self.plan.n
+        flat = [f for fs in frames for f in fs]
+        if len(flat) != n * len(panos):
+            raise ValueError("frames must hold n frames per panorama")
+        for t in flat + list(panos):
+            if t.device.type != "cpu" or t.dtype != torch.uint8 or not t.is_contiguous():
+                raise ValueError("pipe frames and panoramas are contiguous host uint8 tensors")
+        fp = (c_void_p * len(flat))(*[t.data_ptr() for t in flat])
+        pp = (c_void_p * len(panos))(*[t.data_ptr() for t in panos])
+        check(lib().stitch_pipe_run(self._h, len(panos), fp, pp))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().stitch_pipe_destroy(self._h)
             self._h = None
 
     def __del__(self):

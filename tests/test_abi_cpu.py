@@ -174,6 +174,26 @@ def test_single_stage_calls_validate_on_host():
                             None) == E["E_SHAPE"]
 
 
+def test_pipe_validates_on_host():
+    lib = P.lib()
+    args, keep = _plan_args()
+    st, h = _create(*args)
+    assert st == 0
+    try:
+        out = ctypes.c_void_p()
+        assert lib.stitch_pipe_create(None, 2, ctypes.byref(out)) == E["E_NULL"]
+        assert lib.stitch_pipe_create(h, 0, ctypes.byref(out)) == E["E_SHAPE"]
+        assert lib.stitch_pipe_create(h, 9, ctypes.byref(out)) == E["E_SHAPE"]
+        assert lib.stitch_pipe_create(h, 2, ctypes.byref(out)) == E["E_STATE"]   # no workspace bound
+        assert out.value is None
+        assert lib.stitch_pipe_run(None, 1, None, None) == E["E_NULL"]
+        assert lib.stitch_host_alloc(16, None) == E["E_NULL"]
+        lib.stitch_pipe_destroy(None)
+        lib.stitch_host_free(None)
+    finally:
+        lib.stitch_plan_destroy(h)
+
+
 def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(S, "LIB_PATH", tmp_path / "missing.so")
     monkeypatch.setattr(S, "_lib", None)
