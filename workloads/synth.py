@@ -273,3 +273,42 @@ def render_rig_sequence(rig: Rig, frames, device="cpu") -> list[list[torch.Tenso
             out[t][i] = quantise_with_noise(scene, _key32(rig.config, rig.job, i, f, TAG_NOISE))
         del scene
     return out
+
+
+# ----------------------------------------------------------------------------- feature-extraction inputs
+def brief_pattern(nd: int = 256, seed: int = 0) -> np.ndarray:
+    """n_d point pairs for a BRIEF descriptor as an (nd, 4) int32 array of offsets
+    (dx1, dy1, dx2, dy2), each drawn from an isotropic Gaussian of sigma 31/5 around the
+    point, rounded and clipped to the 31x31 patch (|d| <= 15).  Input data only."""
+    rng = np.random.default_rng(np.random.SeedSequence([ROOT_SEED, 90, seed]))
+    d = np.rint(rng.normal(0.0, 31.0 / 5.0, size=(nd, 4)))
+    return np.clip(d, -15, 15).astype(np.int32)
+
+
+def overlap_areas(rig: Rig, margin: int = 24) -> list[list[tuple[int, int, int, int]]]:
+    """Per camera, the frame rectangles (x, y, w, h) that the pre-aligned neighbours overlap
+    (Alg. 2, step 1): the canvas overlap of adjacent footprints, widened by margin canvas
+    pixels, mapped back through the camera's H and clipped to its frame.  Input data only."""
+    n = rig.n
+    boxes = []
+    for i in range(n):
+        w, h = rig.frame_sizes[i]
+        c = np.array([[0, 0, 1], [w, 0, 1], [0, h, 1], [w, h, 1]], float) @ np.asarray(rig.H[i]).T
+        c = c[:, :2] / c[:, 2:]
+        boxes.append((c[:, 0].min(), c[:, 0].max()))
+    out = [[] for _ in range(n)]
+    for i in range(n - 1):
+        x0 = max(boxes[i][0], boxes[i + 1][0]) - margin
+        x1 = min(boxes[i][1], boxes[i + 1][1]) + margin
+        if x1 <= x0:
+            continue
+        for cam in (i, i + 1):
+            w, h = rig.frame_sizes[cam]
+            Hi = np.linalg.inv(np.asarray(rig.H[cam]))
+            pts = np.array([[x0, 0, 1], [x1, 0, 1], [x0, rig.canvas_h, 1], [x1, rig.canvas_h, 1]], float) @ Hi.T
+            pts = pts[:, :2] / pts[:, 2:]
+            fx0 = int(max(0, np.floor(pts[:, 0].min())))
+            fx1 = int(min(w, np.ceil(pts[:, 0].max())))
+            if fx1 > fx0:
+                out[cam].append((fx0, 0, fx1 - fx0, h))
+    return out
