@@ -174,5 +174,6 @@ def lorb(rgb: np.ndarray, areas, tf: int, t: int, n: int, pattern: np.ndarray):
         for x, y, _ in pts:
             gt, lt = brief(S, x, y, pattern)
             desc.append(np.concatenate([pack_bits(gt), pack_bits(lt)]))
-        out.append((pts, np.array(desc, dtype=np.uint32).reshape(len(pts), -1)))
+        words = 2 * ((len(pattern) + 31) // 32)
+        out.append((pts, np.array(desc, dtype=np.uint32).reshape(len(pts), words)))
     return out

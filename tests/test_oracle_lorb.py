@@ -109,3 +109,6 @@ def test_lorb_output_shapes_and_margin():
         for x, y, _ in pts:
             assert 17 <= x < 160 - 17 and 17 <= y < 120 - 17
     assert len(out[0][0]) == 25
+    # an area past the frame clips to nothing and yields an empty, well-shaped result
+    (pts, desc), = lo.lorb(frame, [(150, 10, 40, 40)], 20, 0, 25, pat)
+    assert pts == [] and desc.shape == (0, 16)
