@@ -347,6 +347,47 @@ stitch_status stitch_corners_to_h(const double q[8], int32_t w, int32_t h, doubl
 stitch_status stitch_map_grad_to_corners(const double q[8], int32_t w, int32_t h, const double d_map[9],
                                          double d_q[8]);
 
+/* ---- L-ORB features in the detection areas (registration front end) ------------ */
+
+/* L-ORB (Sec. 4.1, Alg. 1 and Alg. 2): in each of m feature detection areas of a frame
+ * (Alg. 2, step 1: the pre-aligned overlap of neighbouring cameras), FAST corners scored
+ * by the Harris response, non-maximal suppression, the n_max strongest, and a BRIEF
+ * descriptor for each.  The paper leaves the operators and constants open; this call
+ * fixes them so that every decision is exact integer arithmetic:
+ *   - gray level g = (77 R + 150 G + 29 B + 128) >> 8;
+ *   - FAST: at least 9 cyclically contiguous pixels of the radius-3, 16-pixel circle all
+ *     brighter than g + fast_threshold or all darker than g - fast_threshold;
+ *   - gradients Ix = g(x+1,y) - g(x-1,y), Iy = g(x,y+1) - g(x,y-1); the Gaussian weighting
+ *     (sigma = 1) is the 5x5 binomial window b b^T, b = [1,4,6,4,1], unnormalised, giving
+ *     A, B, C; the response (alpha = 3/64, scaled by 64) R = 64 (A B - C^2) - 3 (A + B)^2;
+ *   - candidates: FAST corners with R > harris_threshold; a candidate survives when every
+ *     candidate among its 8 neighbours has a smaller R, or an equal R and a later raster
+ *     position; the n_max survivors of largest R are kept, equal R in raster order;
+ *   - BRIEF (Sec. 4.1.2) on S = b b^T * g: pair k of the pattern (dx1, dy1, dx2, dy2, each
+ *     clamped to -15..15) gives bit k of the "greater" string when S(p + d1) > S(p + d2)
+ *     and of the "less" string when S(p + d1) < S(p + d2) (the paper's three-valued test).
+ * Only points 17 or more samples from every frame edge are considered (the descriptor
+ * support); areas are clipped to that range, and an area clipped to nothing yields none.
+ *
+ * frame: U8 HWC, 3 channels, device, spanning under 2 GiB; sides >= 35.
+ * areas: HOST array of m (1..64) rectangles (x, y, width, height) in frame coordinates,
+ *   width, height >= 0; each clipped area holds under 2^30 samples.
+ * pattern: DEVICE array of nd x 4 int32 offsets; nd a multiple of 32 in 32..512.
+ * Outputs (DEVICE, area i at offset i times the per-area size): counts[m] the number kept
+ *   (<= n_max, 1..2^20), points[m][n_max][2] their (x, y) in frame coordinates,
+ *   responses[m][n_max] their R, descriptors[m][n_max][2 nd/32] words of the "greater"
+ *   string then of the "less" string, bit k in bit k%32 of word k/32.  Entries past
+ *   counts[i] are not written.
+ * workspace: device, 256-byte aligned, at least stitch_lorb_workspace_bytes for the same
+ *   frame size and areas; reused area by area.  Work is queued on `stream`; not for graph
+ *   capture (the sort may record memory sets).
+ * Errors: NULL, SHAPE, WORKSPACE, DEVICE. */
+size_t        stitch_lorb_workspace_bytes(int32_t frame_w, int32_t frame_h, int32_t m, const int32_t* areas);
+stitch_status stitch_lorb(const stitch_image* frame, int32_t m, const int32_t* areas, int32_t fast_threshold,
+                          int64_t harris_threshold, int32_t n_max, int32_t nd, const int32_t* pattern,
+                          int32_t* counts, int32_t* points, int64_t* responses, uint32_t* descriptors,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

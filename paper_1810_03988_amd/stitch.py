@@ -97,6 +97,9 @@ SIGNATURES = {
     "stitch_corners_to_h": (c_int32, [POINTER(c_double), c_int32, c_int32, POINTER(c_double)]),
     "stitch_map_grad_to_corners": (c_int32, [POINTER(c_double), c_int32, c_int32, POINTER(c_double),
                                              POINTER(c_double)]),
+    "stitch_lorb_workspace_bytes": (c_size_t, [c_int32, c_int32, c_int32, POINTER(c_int32)]),
+    "stitch_lorb": (c_int32, [POINTER(StitchImage), c_int32, POINTER(c_int32), c_int32, c_int64, c_int32, c_int32,
+                              c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
 }
 
 TIMING_KINDS = ["warp_level0_pass", "level_pass", "blend_level0", "blend_middle", "blend_top",
@@ -615,3 +618,53 @@ def refine_pair(grad: Grad, frame_a, frame_b, H_a, q0, steps: int = 50, lr: floa
         loss.backward()
         opt.step()
     return (qt * scale).detach().numpy(), log
+
+
+# ----------------------------------------------------------------------------- L-ORB features
+class Lorb:
+    """L-ORB feature extraction (Sec. 4.1, Alg. 1 and Alg. 2) in fixed detection areas of
+    frames of one size: device outputs and workspace are allocated once and reused."""
+
+    def __init__(self, frame_w: int, frame_h: int, areas, n_max: int = 500, nd: int = 256,
+                 fast_threshold: int = 20, harris_threshold: int = 0, device="cuda"):
+        self.frame_w, self.frame_h = int(frame_w), int(frame_h)
+        flat = [int(v) for r in areas for v in r]
+        self.m = len(flat) // 4
+        self.areas = (c_int32 * max(len(flat), 1))(*flat)
+        self.n_max, self.nd = int(n_max), int(nd)
+        self.tf, self.t = int(fast_threshold), int(harris_threshold)
+        nbytes = lib().stitch_lorb_workspace_bytes(self.frame_w, self.frame_h, self.m, self.areas)
+        if nbytes == 0:
+            raise StitchError(2, "no workspace size for these areas")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws = self.workspace[off:off + nbytes]
+        m, n, words = self.m, self.n_max, 2 * self.nd // 32
+        self.counts = torch.zeros(m, dtype=torch.int32, device=device)
+        self.points = torch.zeros(m, n, 2, dtype=torch.int32, device=device)
+        self.responses = torch.zeros(m, n, dtype=torch.int64, device=device)
+        self.descriptors = torch.zeros(m, n, words, dtype=torch.int32, device=device)
+
+    def run_raw(self, frame: torch.Tensor, pattern: torch.Tensor, stream_handle: int) -> None:
+        """Queue the extraction of `frame` (H, W, 3 uint8 device) with `pattern` (nd, 4 int32
+        device) on a raw stream handle; outputs land in counts/points/responses/descriptors."""
+        img = image_hwc(frame)
+        check(lib().stitch_lorb(ctypes.byref(img), self.m, self.areas, self.tf, self.t, self.n_max, self.nd,
+                                pattern.data_ptr(), self.counts.data_ptr(), self.points.data_ptr(),
+                                self.responses.data_ptr(), self.descriptors.data_ptr(), self._ws.data_ptr(),
+                                self._ws.numel(), stream_handle))
+
+    def run(self, frame: torch.Tensor, pattern: torch.Tensor, stream=None) -> list:
+        """Extract and return, per area, (points (k, 2) int32, responses (k,) int64,
+        descriptors (k, 2 nd/32) uint32 as int32 bits), k = that area's count."""
+        if pattern.dtype != torch.int32 or tuple(pattern.shape) != (self.nd, 4) or not pattern.is_contiguous():
+            raise ValueError(f"pattern must be a contiguous ({self.nd}, 4) int32 tensor")
+        if frame.dtype != torch.uint8 or frame.dim() != 3 or frame.shape[2] != 3:
+            raise ValueError("frame must be an (H, W, 3) uint8 tensor")
+        if frame.shape[0] != self.frame_h or frame.shape[1] != self.frame_w:
+            raise ValueError("frame size differs from the one the areas were sized for")
+        self.run_raw(frame, pattern, _stream(stream))
+        torch.cuda.synchronize()
+        counts = self.counts.cpu().tolist()
+        return [(self.points[i, :k].cpu(), self.responses[i, :k].cpu(), self.descriptors[i, :k].cpu())
+                for i, k in enumerate(counts)]

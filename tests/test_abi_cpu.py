@@ -194,6 +194,35 @@ def test_pipe_validates_on_host():
         lib.stitch_plan_destroy(h)
 
 
+def test_lorb_validates_on_host():
+    lib = P.lib()
+    fake = 0x10000
+    frame = S.StitchImage(fake, 640, 480, 3, S.U8, S.HWC, 1920, 0)
+    areas = (ctypes.c_int32 * 8)(0, 0, 300, 200, 100, 50, 80, 80)
+    bad_areas = (ctypes.c_int32 * 8)(0, 0, 300, 200, 100, 50, -1, 80)
+    outs = [fake] * 4
+
+    def call(fr=ctypes.byref(frame), m=2, ar=areas, tf=20, t=0, n=500, nd=256, pat=fake, o=outs):
+        return lib.stitch_lorb(fr, m, ar, tf, t, n, nd, pat, *o, fake, 1 << 30, None)
+
+    assert call(fr=None) == E["E_NULL"]
+    assert call(pat=None) == E["E_NULL"]
+    assert call(o=[fake, None, fake, fake]) == E["E_NULL"]
+    assert call(m=0) == E["E_SHAPE"] and call(m=65) == E["E_SHAPE"]
+    for nd in (0, 16, 48, 544):
+        assert call(nd=nd) == E["E_SHAPE"], nd
+    assert call(n=0) == E["E_SHAPE"] and call(n=(1 << 20) + 1) == E["E_SHAPE"]
+    assert call(tf=-1) == E["E_SHAPE"] and call(tf=256) == E["E_SHAPE"]
+    assert call(ar=bad_areas) == E["E_SHAPE"]
+    tiny = S.StitchImage(fake, 34, 480, 3, S.U8, S.HWC, 102, 0)
+    assert call(fr=ctypes.byref(tiny)) == E["E_SHAPE"]           # no sample 17 from both sides
+    chw = S.StitchImage(fake, 640, 480, 3, S.U8, S.CHW, 640, 640 * 480)
+    assert call(fr=ctypes.byref(chw)) != 0
+    gray = S.StitchImage(fake, 640, 480, 1, S.U8, S.HWC, 640, 0)
+    assert call(fr=ctypes.byref(gray)) == E["E_SHAPE"]
+    assert lib.stitch_lorb_workspace_bytes(640, 480, 0, areas) == 0
+
+
 def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(S, "LIB_PATH", tmp_path / "missing.so")
     monkeypatch.setattr(S, "_lib", None)

@@ -1,0 +1,128 @@
+"""L-ORB feature extraction (Sec. 4.1, Alg. 1 and Alg. 2) on the GPU against the oracle:
+points, responses and descriptors bit for bit (all of it is integer arithmetic), on rig
+frames and their detection areas, synthetic rotations, exact ties, ragged and clipped
+areas, and descriptor lengths from one to sixteen words."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1810_03988_amd as P
+import workloads as wl
+from oracle import lorb_oracle as lo
+from helpers import gpu_available
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def _check(frame: np.ndarray, areas, tf=20, t=0, n=500, nd=256, pattern=None, dev_frame=None, want_pattern=None):
+    h, w = frame.shape[:2]
+    pat = wl.brief_pattern(nd, seed=nd) if pattern is None else pattern
+    lorb = P.Lorb(w, h, areas, n_max=n, nd=nd, fast_threshold=tf, harris_threshold=t)
+    f = torch.from_numpy(np.ascontiguousarray(frame)).cuda() if dev_frame is None else dev_frame
+    got = lorb.run(f, torch.from_numpy(np.ascontiguousarray(pat)).cuda())
+    want = lo.lorb(frame, areas, tf, t, n, pat if want_pattern is None else want_pattern)
+    assert len(got) == len(want) == len(areas)
+    total = 0
+    for i, ((pts, resp, desc), (wp, wd)) in enumerate(zip(got, want)):
+        assert pts.tolist() == [[x, y] for x, y, _ in wp], f"area {i}: points"
+        assert resp.tolist() == [r for _, _, r in wp], f"area {i}: responses"
+        d = desc.numpy().view(np.uint32)
+        assert d.shape == (len(wp), 2 * nd // 32)
+        assert np.array_equal(d, wd.reshape(d.shape)), f"area {i}: descriptors"
+        total += len(wp)
+    return total
+
+
+def test_rig_frames_in_their_overlap_areas():
+    """Both cameras of the 640x480 pair, each in its pre-aligned overlap (Alg. 2, step 1),
+    500 points of 256-pair descriptors: more survivors than kept, so the cut is exercised."""
+    rig = wl.rig_c1()
+    frames = wl.render_rig_frames(rig)
+    for cam, areas in enumerate(wl.overlap_areas(rig)):
+        assert _check(frames[cam].numpy(), areas) == 500 * len(areas), cam
+
+
+def test_full_hd_frame_with_two_areas():
+    """A 1920x1080 camera of the four-camera rig with its two overlap areas (both sides)."""
+    rig = wl.rig_c2()
+    frame = wl.render_rig_frames(rig)[1].numpy()
+    areas = wl.overlap_areas(rig)[1]
+    assert len(areas) == 2
+    assert _check(frame, areas, n=1000) > 0
+
+
+@pytest.mark.parametrize("deg", [5.0, 15.0, 45.0])
+def test_synthetic_rotations(deg):
+    """Rotated rig frames (the rotations BRIEF is probed with): zero fill and nearest-sample
+    staircases give new corners and ties."""
+    rig = wl.rig_c1()
+    frame = wl.rotated_frame(wl.render_rig_frames(rig)[0].numpy(), deg)
+    _check(frame, [(0, 0, 640, 480)], n=800)
+
+
+def test_exact_ties_in_suppression_and_selection():
+    """Identical 2x2 blobs on a flat ground: the four pixels of a blob are candidates of
+    equal response (mirror images), so only the first in raster order survives, and every
+    blob gives the same response, so the cut at n falls inside one class of equal R and
+    is decided by raster order."""
+    g = np.full((160, 224), 40, dtype=np.uint8)
+    for y in range(24, 136, 12):
+        for x in range(24, 200, 10):
+            g[y:y + 2, x:x + 2] = 200
+    frame = np.repeat(g[..., None], 3, axis=2)
+    want = lo.lorb(frame, [(0, 0, 224, 160)], 20, 0, 1000, wl.brief_pattern(256))
+    rs = [r for _, _, r in want[0][0]]
+    assert len(rs) == 10 * 18 and len(set(rs)) == 1   # one survivor per blob, all equal
+    assert _check(frame, [(0, 0, 224, 160)], n=37) == 37
+
+
+@pytest.mark.parametrize("nd", [32, 96, 512])
+def test_descriptor_lengths(nd):
+    rig = wl.rig_c1()
+    frame = wl.render_rig_frames(rig)[1].numpy()
+    _check(frame, [(40, 30, 200, 150)], nd=nd, n=300)
+
+
+def test_ragged_clipped_and_empty_areas():
+    """Areas that are not whole tiles, reach past the frame or the 17-sample margin, hold a
+    single sample, or clip to nothing; thresholds that keep few points (counts below n)."""
+    rig = wl.rig_c1()
+    frame = wl.render_rig_frames(rig)[0].numpy()
+    areas = [(0, 0, 65, 17 + 17), (600, 450, 100, 100), (100, 100, 1, 1), (700, 10, 20, 20),
+             (-50, -20, 130, 77), (17, 17, 64, 16), (300, 200, 0, 40), (250, 60, 129, 33)]
+    _check(frame, areas, n=50)
+    _check(frame, areas, tf=60, t=10 ** 9, n=50)
+    _check(frame, [(0, 0, 640, 480)], n=1)
+
+
+def test_noise_frame_and_strided_view():
+    """Uniform noise (a dense field of candidates) read through a frame view whose rows are
+    longer than the frame (row pitch 3 * 700 bytes)."""
+    rng = np.random.default_rng(5)
+    big = rng.integers(0, 256, (200, 700, 3)).astype(np.uint8)
+    frame = np.ascontiguousarray(big[:, :333])
+    dev = torch.from_numpy(big).cuda()[:, :333]
+    assert dev.stride(0) == 700 * 3
+    _check(frame, [(0, 0, 333, 200), (150, 20, 90, 140)], n=400, dev_frame=dev)
+
+
+def test_pattern_offsets_are_clamped_to_the_patch():
+    rig = wl.rig_c1()
+    frame = wl.render_rig_frames(rig)[0].numpy()
+    rng = np.random.default_rng(9)
+    wild = rng.integers(-40, 41, (64, 4)).astype(np.int32)
+    _check(frame, [(200, 100, 150, 120)], nd=64, n=100, pattern=wild, want_pattern=np.clip(wild, -15, 15))
+
+
+def test_outputs_are_reused_across_frames():
+    """One Lorb object, two different frames: the second run's outputs are its own."""
+    rig = wl.rig_c1()
+    frames = wl.render_rig_frames(rig)
+    areas = [(0, 0, 640, 480)]
+    pat = wl.brief_pattern(256)
+    lorb = P.Lorb(640, 480, areas, n_max=200)
+    first = lorb.run(frames[0].cuda(), torch.from_numpy(pat).cuda())
+    second = lorb.run(frames[1].cuda(), torch.from_numpy(pat).cuda())
+    want = lo.lorb(frames[1].numpy(), areas, 20, 0, 200, pat)
+    assert second[0][0].tolist() == [[x, y] for x, y, _ in want[0][0]]
+    assert first[0][0].tolist() != second[0][0].tolist()

@@ -312,3 +312,18 @@ def overlap_areas(rig: Rig, margin: int = 24) -> list[list[tuple[int, int, int, 
             if fx1 > fx0:
                 out[cam].append((fx0, 0, fx1 - fx0, h))
     return out
+
+
+def rotated_frame(frame: np.ndarray, deg: float) -> np.ndarray:
+    """The (h, w, 3) uint8 frame turned by deg about its centre, nearest sample, 0 outside:
+    the synthetic rotations the BRIEF descriptor is probed with (Fig. 2).  Input data only."""
+    h, w = frame.shape[:2]
+    y, x = np.mgrid[0:h, 0:w].astype(np.float64)
+    c, s = np.cos(np.radians(deg)), np.sin(np.radians(deg))
+    cx, cy = (w - 1) / 2.0, (h - 1) / 2.0
+    sx = np.rint(c * (x - cx) + s * (y - cy) + cx).astype(np.int64)
+    sy = np.rint(-s * (x - cx) + c * (y - cy) + cy).astype(np.int64)
+    ok = (sx >= 0) & (sx < w) & (sy >= 0) & (sy < h)
+    out = np.zeros_like(frame)
+    out[ok] = frame[sy[ok], sx[ok]]
+    return out
