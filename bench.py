@@ -46,8 +46,8 @@ def parse():
                     help="the headline form: all frames of the step as one batch, or one stitch_frame per frame")
     ap.add_argument("--forms", default="batched_graph_f16,plain_f32,plain_f16,pipe_f32",
                     help="extra forms timed after the headline (comma list of batched_graph_<s> / plain_<s> / "
-                         "pipe_<s>, the last end to end through PCIe, "
-                         "or 'none')")
+                         "pipe_<s>, the last end to end through PCIe, lorb (the feature-extraction front "
+                         "end on the same frames), or 'none')")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the step without per-launch events (roofline then omitted)")
@@ -423,6 +423,64 @@ def time_pipe(rig, frames, storage, steps, warmup, depth=3):
     return ms, in_bytes, out_bytes
 
 
+def time_lorb(rig, frames, steps, warmup, n_max=500, nd=256):
+    """L-ORB feature extraction (Alg. 1-2) of every camera of a frame set in its pre-aligned
+    overlap areas: one stitch_lorb call per camera on the current stream, frames already
+    in HBM.  Returns ms per frame set, the detection-area samples per frame set and the
+    areas."""
+    import paper_1810_03988_amd as P
+    import workloads as wl
+    areas = wl.overlap_areas(rig)
+    pattern = torch.from_numpy(wl.brief_pattern(nd)).cuda()
+    lorbs = [P.Lorb(w, h, areas[i], n_max=n_max, nd=nd) if areas[i] else None
+             for i, (w, h) in enumerate(rig.frame_sizes)]
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def step(t):
+        for i, lb in enumerate(lorbs):
+            if lb is not None:
+                lb.run_raw(frames[t % len(frames)][i], pattern, stream)
+
+    for t in range(warmup):
+        step(t)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for t in range(steps):
+        step(t)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    px = sum(_scanned(r, w, h) for (w, h), ar in zip(rig.frame_sizes, areas) for r in ar)
+    counts = [lb.counts.cpu().tolist() for lb in lorbs if lb is not None]
+    return ms, px, areas, counts
+
+
+def _scanned(rect, w, h, margin=17):
+    """Samples of a detection area that are scanned: those 17 or more from every frame
+    edge (the descriptor support)."""
+    x0, y0, rw, rh = rect
+    cw = min(x0 + rw, w - margin) - max(x0, margin)
+    ch = min(y0 + rh, h - margin) - max(y0, margin)
+    return max(0, cw) * max(0, ch)
+
+
+def lorb_cpu_baseline(rig, frames0, n_max=500, nd=256):
+    """The L-ORB oracle on one detection area of camera 0 (exact integer numpy and Python
+    loops, one thread): area samples per second."""
+    from oracle import lorb_oracle as lo
+    import workloads as wl
+    area = wl.overlap_areas(rig)[0][0]
+    w, h = rig.frame_sizes[0]
+    frame = frames0[0].cpu().numpy()
+    t = time.perf_counter()
+    lo.lorb(frame, [area], 20, 0, n_max, wl.brief_pattern(nd))
+    dt = time.perf_counter() - t
+    px = _scanned(area, w, h)
+    return {"value": round(px / dt / 1e6, 5), "unit": "Mpx/s (detection-area samples)", "cores": 1,
+            "kind": "oracle", "sample": f"camera 0, area {tuple(area)}: {px} samples scanned, frame 0, {dt:.1f} s"}
+
+
 def time_batched(rig, frames, storage, steps, warmup, tune_cache=None, kernel_events=True):
     """All frames of the sequence as jobs of one batch (one plan per job).  Timed twice on
     one stream: with per-launch HIP events (launches issued directly, an event after each)
@@ -627,9 +685,21 @@ def main():
                 "traffic": profiled_traffic(a.config, a.form, a.storage, dom), "kernel": dom,
                 "alg_bytes": kd["alg_bytes_per_launch"], "avg_us": kd["avg_us"]}
     for form in [f for f in a.forms.split(",") if f and f != "none"]:
-        kind, st = form.rsplit("_", 1)
+        kind, st = form.rsplit("_", 1) if "_" in form else (form, "")
         if (kind == a.form and st == a.storage) or (kind == "batched_graph" and a.form == "batched" and
                                                     st == a.storage):
+            continue
+        if form == "lorb":
+            lms, lpx, lareas, lcounts = time_lorb(rig, frames, a.steps, a.warmup)
+            forms["lorb"] = {"ms_per_frame_set": round(lms, 4), "frame_sets_per_s": round(1e3 / lms, 1),
+                             "area_Mpx_s": round(lpx / (lms / 1e3) / 1e6, 1), "area_px_per_frame_set": lpx,
+                             "how": "L-ORB (Alg. 1-2) of every camera in its overlap areas, tf 20, t 0, "
+                                    "500 points, 256 pairs; one stitch_lorb per camera, frames in HBM",
+                             "areas": lareas, "points_kept": lcounts}
+            if not a.no_cpu_baseline:
+                forms["lorb"]["cpu_baseline"] = lorb_cpu_baseline(rig, frames[0])
+            print(f"# lorb: {json.dumps({k: v for k, v in forms['lorb'].items() if k not in ('areas',)})}",
+                  file=sys.stderr, flush=True)
             continue
         if kind == "pipe":
             pms, in_b, out_b = time_pipe(rig, frames, st, a.steps, a.warmup)

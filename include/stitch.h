@@ -379,9 +379,14 @@ stitch_status stitch_map_grad_to_corners(const double q[8], int32_t w, int32_t h
  *   string then of the "less" string, bit k in bit k%32 of word k/32.  Entries past
  *   counts[i] are not written.
  * workspace: device, 256-byte aligned, at least stitch_lorb_workspace_bytes for the same
- *   frame size and areas; reused area by area.  Work is queued on `stream`; not for graph
- *   capture (the sort may record memory sets).
- * Errors: NULL, SHAPE, WORKSPACE, DEVICE. */
+ *   frame size and areas (24 bytes per area sample; a host-only query, 0 on bad
+ *   arguments).
+ * Work is queued on `stream` as five kernel launches covering all areas (no allocation,
+ * no memory set, no synchronisation).  Selection histograms the survivors' responses and
+ * ranks only the survivors in the histogram buckets that hold the n_max strongest, by
+ * comparing every pair of them: its cost grows with the square of that set (n_max plus
+ * one bucket's share).
+ * Errors: NULL, SHAPE (also a pattern not 16-byte aligned), WORKSPACE, DEVICE. */
 size_t        stitch_lorb_workspace_bytes(int32_t frame_w, int32_t frame_h, int32_t m, const int32_t* areas);
 stitch_status stitch_lorb(const stitch_image* frame, int32_t m, const int32_t* areas, int32_t fast_threshold,
                           int64_t harris_threshold, int32_t n_max, int32_t nd, const int32_t* pattern,

@@ -221,6 +221,16 @@ def test_lorb_validates_on_host():
     gray = S.StitchImage(fake, 640, 480, 1, S.U8, S.HWC, 640, 0)
     assert call(fr=ctypes.byref(gray)) == E["E_SHAPE"]
     assert lib.stitch_lorb_workspace_bytes(640, 480, 0, areas) == 0
+    assert lib.stitch_lorb_workspace_bytes(640, 480, 2, bad_areas) == 0
+    # 24 bytes per sample of the clipped areas (283 x 183 and 80 x 80), counters and padding
+    need = lib.stitch_lorb_workspace_bytes(640, 480, 2, areas)
+    base = 24 * (283 * 183 + 80 * 80)
+    assert base <= need < base + 4096
+    assert call(pat=fake + 4) == E["E_SHAPE"]                    # pattern not 16-byte aligned
+    assert lib.stitch_lorb(ctypes.byref(frame), 2, areas, 20, 0, 500, 256, fake, *outs, fake, need - 1,
+                           None) == E["E_WORKSPACE"]
+    assert lib.stitch_lorb(ctypes.byref(frame), 2, areas, 20, 0, 500, 256, fake, *outs, fake + 64, need,
+                           None) == E["E_WORKSPACE"]
 
 
 def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
