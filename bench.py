@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16"])
     ap.add_argument("--form", default="batched", choices=["batched", "plain"],
                     help="the headline form: all frames of the step as one batch, or one stitch_frame per frame")
-    ap.add_argument("--forms", default="batched_graph_f16,plain_f32,plain_f16,pipe_f32",
+    ap.add_argument("--forms", default="batched_graph_f16,plain_f32,plain_f16,pipe_f32,lorb",
                     help="extra forms timed after the headline (comma list of batched_graph_<s> / plain_<s> / "
                          "pipe_<s>, the last end to end through PCIe, lorb (the feature-extraction front "
                          "end on the same frames), or 'none')")
@@ -73,15 +73,19 @@ KERNEL_KINDS = {
     "k_blend<_Float16, true, true>": "blend_level0 (f16)", "k_blend<_Float16, false, true>": "blend_middle/top (f16)",
     "k_blend<float, true, false>": "blend_level0, batched (f32)",
     "k_blend<float, false, false>": "blend_middle/top, batched (f32)",
+    "k_lorb_clear": "L-ORB clear", "k_lorb_detect": "L-ORB detect (FAST, R, suppression)",
+    "k_lorb_select": "L-ORB select (histogram threshold)", "k_lorb_rank": "L-ORB rank",
+    "k_lorb_brief": "L-ORB BRIEF",
 }
 COPY_KERNEL_HINT = "neg"
 
 
 def _short_kernel(name: str) -> str:
     import re
+    name = name.replace("(anonymous namespace)::", "")
     m = re.search(r"(k_[a-z_]+)<([^()]*)>", name)
     if m:
-        return m.group(1) + "<" + m.group(2).replace("(anonymous namespace)::", "") + ">"
+        return m.group(1) + "<" + m.group(2) + ">"
     return name.split("(")[0][-90:]
 
 
@@ -425,35 +429,65 @@ def time_pipe(rig, frames, storage, steps, warmup, depth=3):
 
 def time_lorb(rig, frames, steps, warmup, n_max=500, nd=256):
     """L-ORB feature extraction (Alg. 1-2) of every camera of a frame set in its pre-aligned
-    overlap areas: one stitch_lorb call per camera on the current stream, frames already
-    in HBM.  Returns ms per frame set, the detection-area samples per frame set and the
-    areas."""
+    overlap areas, frames already in HBM: one stitch_lorb call per camera, timed (a) on one
+    stream, (b) on one stream with per-launch events (kernel table), (c) with each camera on
+    its own stream (default priority), as the paper runs L-ORB on stream queues."""
     import paper_1810_03988_amd as P
+    from paper_1810_03988_amd import stitch as S
     import workloads as wl
     areas = wl.overlap_areas(rig)
     pattern = torch.from_numpy(wl.brief_pattern(nd)).cuda()
-    lorbs = [P.Lorb(w, h, areas[i], n_max=n_max, nd=nd) if areas[i] else None
-             for i, (w, h) in enumerate(rig.frame_sizes)]
-    stream = torch.cuda.current_stream().cuda_stream
+    cams = [i for i in range(rig.n) if areas[i]]
+    lorbs = {i: P.Lorb(*rig.frame_sizes[i], areas[i], n_max=n_max, nd=nd) for i in cams}
+    main = torch.cuda.current_stream()
+    streams = {i: torch.cuda.Stream() for i in cams}
 
-    def step(t):
-        for i, lb in enumerate(lorbs):
-            if lb is not None:
-                lb.run_raw(frames[t % len(frames)][i], pattern, stream)
+    def step(t, per_camera_streams=False):
+        for i in cams:
+            h = streams[i].cuda_stream if per_camera_streams else main.cuda_stream
+            lorbs[i].run_raw(frames[t % len(frames)][i], pattern, h)
 
-    for t in range(warmup):
-        step(t)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for t in range(steps):
-        step(t)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    px = sum(_scanned(r, w, h) for (w, h), ar in zip(rig.frame_sizes, areas) for r in ar)
-    counts = [lb.counts.cpu().tolist() for lb in lorbs if lb is not None]
-    return ms, px, areas, counts
+    def timed(per_camera_streams):
+        for t in range(warmup):
+            step(t, per_camera_streams)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(main)
+        if per_camera_streams:
+            for st in streams.values():
+                st.wait_event(e0)
+        for t in range(steps):
+            step(t, per_camera_streams)
+        if per_camera_streams:
+            for st in streams.values():
+                ev = torch.cuda.Event()
+                ev.record(st)
+                main.wait_event(ev)
+        e1.record(main)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_one = timed(False)
+    ms_multi = timed(True)
+    S.lorb_set_timing(True)
+    ms_events = timed(False)
+    tim = S.lorb_read_timing()
+    S.lorb_set_timing(False)
+    px = {i: sum(_scanned(r, *rig.frame_sizes[i]) for r in areas[i]) for i in cams}
+    counts = {i: lorbs[i].counts.cpu().tolist() for i in cams}
+    calls = len(cams)
+    kernels = {}
+    for k, (tot, n) in tim.items():
+        if n:
+            kernels[k] = {"avg_us": round(tot / n * 1e3, 2), "launches_per_step": calls,
+                          "ms_per_step": round(tot / n * calls, 4)}
+    # detection reads each scanned sample's 3 bytes once (halo re-reads are not algorithmic)
+    det_bytes = 3 * sum(px.values()) / calls
+    kd = kernels["detect"]
+    kd["alg_bytes_per_launch"] = int(det_bytes)
+    kd["achieved_GBs"] = round(det_bytes / (kd["avg_us"] * 1e-6) / 1e9, 1)
+    return {"ms_one_stream": ms_one, "ms_per_camera_streams": ms_multi, "ms_with_launch_events": ms_events,
+            "px": sum(px.values()), "areas": areas, "counts": counts, "kernels": kernels}
 
 
 def _scanned(rect, w, h, margin=17):
@@ -690,12 +724,24 @@ def main():
                                                     st == a.storage):
             continue
         if form == "lorb":
-            lms, lpx, lareas, lcounts = time_lorb(rig, frames, a.steps, a.warmup)
-            forms["lorb"] = {"ms_per_frame_set": round(lms, 4), "frame_sets_per_s": round(1e3 / lms, 1),
-                             "area_Mpx_s": round(lpx / (lms / 1e3) / 1e6, 1), "area_px_per_frame_set": lpx,
-                             "how": "L-ORB (Alg. 1-2) of every camera in its overlap areas, tf 20, t 0, "
-                                    "500 points, 256 pairs; one stitch_lorb per camera, frames in HBM",
-                             "areas": lareas, "points_kept": lcounts}
+            L = time_lorb(rig, frames, a.steps, a.warmup)
+            lms, lpx = L["ms_one_stream"], L["px"]
+            kd = L["kernels"]["detect"]
+            forms["lorb"] = {
+                "ms_per_frame_set": round(lms, 4), "frame_sets_per_s": round(1e3 / lms, 1),
+                "area_Mpx_s": round(lpx / (lms / 1e3) / 1e6, 1), "area_px_per_frame_set": lpx,
+                "ms_per_frame_set_camera_streams": round(L["ms_per_camera_streams"], 4),
+                "area_Mpx_s_camera_streams": round(lpx / (L["ms_per_camera_streams"] / 1e3) / 1e6, 1),
+                "ms_per_frame_set_with_launch_events": round(L["ms_with_launch_events"], 4),
+                "how": "L-ORB (Alg. 1-2) of every camera in its overlap areas, tf 20, t 0, 500 points, "
+                       "256 pairs; one stitch_lorb per camera, frames in HBM; one stream, and one "
+                       "stream per camera",
+                "kernels": L["kernels"],
+                "roofline": {"bound": "hbm", "kernel": "detect", "achieved": kd["achieved_GBs"],
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                             "alg_bytes": kd["alg_bytes_per_launch"], "avg_us": kd["avg_us"]},
+                "areas": L["areas"], "points_kept": L["counts"]}
             if not a.no_cpu_baseline:
                 forms["lorb"]["cpu_baseline"] = lorb_cpu_baseline(rig, frames[0])
             print(f"# lorb: {json.dumps({k: v for k, v in forms['lorb'].items() if k not in ('areas',)})}",

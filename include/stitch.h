@@ -393,6 +393,16 @@ stitch_status stitch_lorb(const stitch_image* frame, int32_t m, const int32_t* a
                           int32_t* counts, int32_t* points, int64_t* responses, uint32_t* descriptors,
                           void* workspace, size_t workspace_bytes, void* stream);
 
+/* Per-launch timing of stitch_lorb (diagnostics), process-wide.  While enabled, each call
+ * records a HIP event on its stream before its first launch and after each of its five
+ * launches: 0 clear the counts, 1 detection (FAST, response, suppression), 2 selection
+ * threshold, 3 ranking, 4 BRIEF.  set_timing clears the totals; read_timing waits for the
+ * recorded events and returns accumulated milliseconds and launch counts per launch.
+ * Errors: NULL, DEVICE. */
+#define STITCH_LORB_KINDS 5
+stitch_status stitch_lorb_set_timing(int32_t enable);
+stitch_status stitch_lorb_read_timing(double ms[STITCH_LORB_KINDS], int32_t launches[STITCH_LORB_KINDS]);
+
 #ifdef __cplusplus
 }
 #endif

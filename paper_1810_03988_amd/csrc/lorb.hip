@@ -36,6 +36,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <climits>
+#include <mutex>
+#include <vector>
 
 #include "stitch_internal.h"
 
@@ -525,6 +529,27 @@ bool plan_areas(int fw, int fh, int m, const int32_t* areas, AreaTable& T, Layou
   return true;
 }
 
+// Per-launch event timing of stitch_lorb (diagnostics), process-wide.  While enabled, a
+// call records an event before its first launch and one after each launch.
+constexpr int kKinds = 5;                  // clear, detect, select, rank, brief
+struct LorbTiming {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> spare;
+  std::vector<std::array<hipEvent_t, kKinds + 1>> done;
+  double ms[kKinds] = {};
+  int32_t n[kKinds] = {};
+  void recycle() {
+    for (auto& c : done)
+      for (hipEvent_t e : c) spare.push_back(e);
+    done.clear();
+  }
+};
+LorbTiming& timing() {
+  static LorbTiming* t = new LorbTiming;   // never destroyed: events outlive static teardown
+  return *t;
+}
+
 stitch_status check_areas(int32_t frame_w, int32_t frame_h, int32_t m, const int32_t* areas) {
   if (m < 1 || m > kMaxAreas) return fail(STITCH_E_SHAPE, "m = %d areas outside 1..%d", m, kMaxAreas);
   if (!areas) return fail(STITCH_E_NULL, "areas is NULL");
@@ -583,17 +608,89 @@ stitch_status stitch_lorb(const stitch_image* frame, int32_t m, const int32_t* a
   int32_t* shortI = (int32_t*)(ws + L.shortI);
   const uint8_t* src = (const uint8_t*)frame->data;
   const int tiles = T.a[m - 1].tile_begin + T.a[m - 1].ntiles;
+  // optional timing events (taken before anything is enqueued)
+  LorbTiming& tm = timing();
+  std::array<hipEvent_t, kKinds + 1> ev{};
+  bool timed = false;
+  {
+    std::lock_guard<std::mutex> lock(tm.mu);
+    if (tm.on) {
+      timed = true;
+      for (auto& e : ev) {
+        if (!tm.spare.empty()) {
+          e = tm.spare.back();
+          tm.spare.pop_back();
+        } else {
+          const hipError_t ce = hipEventCreate(&e);
+          if (ce != hipSuccess) return hip_fail(ce, "timing event create");
+        }
+      }
+    }
+  }
+  hipError_t e = hipSuccess;
+  auto mark = [&](int k) {
+    if (timed && e == hipSuccess) e = hipEventRecord(ev[k], s);
+  };
+  mark(0);
   hipLaunchKernelGGL(k_lorb_clear, dim3(1), dim3(128), 0, s, count, m);
+  mark(1);
   if (tiles > 0)
     hipLaunchKernelGGL(k_lorb_detect, dim3(tiles), dim3(256), 0, s, src, frame->row_pitch, fw, fh, T,
                        fast_threshold, harris_threshold, count, listR, listI);
+  mark(2);
   hipLaunchKernelGGL(k_lorb_select, dim3(m), dim3(1024), 0, s, T, count, listR, listI, shortR, shortI, counts);
+  mark(3);
   hipLaunchKernelGGL(k_lorb_rank, dim3(kRankGrid, m), dim3(256), 0, s, T, count, shortR, shortI, points, responses);
+  mark(4);
   hipLaunchKernelGGL(k_lorb_brief, dim3((n_max + 3) / 4, m), dim3(256), 0, s, src, frame->row_pitch, T, pattern,
                      counts, points, descriptors);
-  const hipError_t e = hipGetLastError();
+  mark(5);
+  if (timed) {
+    std::lock_guard<std::mutex> lock(tm.mu);
+    if (e == hipSuccess && tm.on) tm.done.push_back(ev);
+    else
+      for (hipEvent_t x : ev) tm.spare.push_back(x);
+  }
+  if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "feature extraction launch");
   return STITCH_OK;
+}
+
+stitch_status stitch_lorb_set_timing(int32_t enable) {
+  LorbTiming& tm = timing();
+  std::lock_guard<std::mutex> lock(tm.mu);
+  tm.on = enable != 0;
+  tm.recycle();
+  for (int k = 0; k < kKinds; ++k) {
+    tm.ms[k] = 0.0;
+    tm.n[k] = 0;
+  }
+  return STITCH_OK;
+}
+
+stitch_status stitch_lorb_read_timing(double ms[STITCH_LORB_KINDS], int32_t launches[STITCH_LORB_KINDS]) {
+  if (!ms || !launches) return fail(STITCH_E_NULL, "ms or launches is NULL");
+  LorbTiming& tm = timing();
+  std::lock_guard<std::mutex> lock(tm.mu);
+  stitch_status st = STITCH_OK;
+  for (auto& c : tm.done) {
+    hipError_t e = hipEventSynchronize(c[kKinds]);
+    for (int k = 0; e == hipSuccess && k < kKinds; ++k) {
+      float t = 0.0f;
+      e = hipEventElapsedTime(&t, c[k], c[k + 1]);
+      if (e == hipSuccess) {
+        tm.ms[k] += t;
+        tm.n[k] += 1;
+      }
+    }
+    if (e != hipSuccess && !st) st = hip_fail(e, "timing events");
+  }
+  tm.recycle();
+  for (int k = 0; k < kKinds; ++k) {
+    ms[k] = tm.ms[k];
+    launches[k] = tm.n[k];
+  }
+  return st;
 }
 
 }  // extern "C"

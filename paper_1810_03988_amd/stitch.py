@@ -100,6 +100,8 @@ SIGNATURES = {
     "stitch_lorb_workspace_bytes": (c_size_t, [c_int32, c_int32, c_int32, POINTER(c_int32)]),
     "stitch_lorb": (c_int32, [POINTER(StitchImage), c_int32, POINTER(c_int32), c_int32, c_int64, c_int32, c_int32,
                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "stitch_lorb_set_timing": (c_int32, [c_int32]),
+    "stitch_lorb_read_timing": (c_int32, [POINTER(c_double), POINTER(c_int32)]),
 }
 
 TIMING_KINDS = ["warp_level0_pass", "level_pass", "blend_level0", "blend_middle", "blend_top",
@@ -668,3 +670,19 @@ class Lorb:
         counts = self.counts.cpu().tolist()
         return [(self.points[i, :k].cpu(), self.responses[i, :k].cpu(), self.descriptors[i, :k].cpu())
                 for i, k in enumerate(counts)]
+
+
+LORB_KINDS = ["clear", "detect", "select", "rank", "brief"]
+
+
+def lorb_set_timing(enable: bool) -> None:
+    """Per-launch event timing of every stitch_lorb call in the process (clears totals)."""
+    check(lib().stitch_lorb_set_timing(int(enable)))
+
+
+def lorb_read_timing() -> dict:
+    """{launch: (total ms, launches)} over the calls since lorb_set_timing."""
+    ms = (c_double * len(LORB_KINDS))()
+    n = (c_int32 * len(LORB_KINDS))()
+    check(lib().stitch_lorb_read_timing(ms, n))
+    return {k: (ms[i], n[i]) for i, k in enumerate(LORB_KINDS)}

@@ -126,3 +126,30 @@ def test_outputs_are_reused_across_frames():
     want = lo.lorb(frames[1].numpy(), areas, 20, 0, 200, pat)
     assert second[0][0].tolist() == [[x, y] for x, y, _ in want[0][0]]
     assert first[0][0].tolist() != second[0][0].tolist()
+
+
+def test_launch_timing_and_per_camera_streams():
+    """Per-launch timing counts every launch of every call; cameras extracted concurrently on
+    their own streams give the same points as one after another."""
+    from paper_1810_03988_amd import stitch as S
+    rig = wl.rig_c1()
+    frames = [f.cuda() for f in wl.render_rig_frames(rig)]
+    areas = wl.overlap_areas(rig)
+    pat = torch.from_numpy(wl.brief_pattern(256)).cuda()
+    lorbs = [P.Lorb(640, 480, areas[i], n_max=300) for i in range(rig.n)]
+    S.lorb_set_timing(True)
+    want = [lb.run(frames[i], pat) for i, lb in enumerate(lorbs)]
+    tim = S.lorb_read_timing()
+    S.lorb_set_timing(False)
+    assert all(n == rig.n for _, n in tim.values()) and tim["detect"][0] > 0
+    assert S.lorb_read_timing()["detect"][1] == 0                 # cleared, and off
+    for lb in lorbs:
+        lb.points.zero_()
+    streams = [torch.cuda.Stream() for _ in lorbs]
+    for i, lb in enumerate(lorbs):
+        streams[i].wait_stream(torch.cuda.current_stream())
+        lb.run_raw(frames[i], pat, streams[i].cuda_stream)
+    torch.cuda.synchronize()
+    for i, lb in enumerate(lorbs):
+        k = int(lb.counts[0])
+        assert torch.equal(lb.points[0, :k].cpu(), want[i][0][0])
