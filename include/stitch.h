@@ -403,6 +403,61 @@ stitch_status stitch_lorb(const stitch_image* frame, int32_t m, const int32_t* a
 stitch_status stitch_lorb_set_timing(int32_t enable);
 stitch_status stitch_lorb_read_timing(double ms[STITCH_LORB_KINDS], int32_t launches[STITCH_LORB_KINDS]);
 
+/* ---- pairwise registration: multi-probe LSH matching and PROSAC ----------------- */
+
+/* Multi-probe LSH matching (Sec. 4.2.1; Alg. 3, step 1) of the L-ORB descriptors of area A
+ * (queries) against those of area B (references), e.g. the facing overlap areas of two
+ * neighbouring cameras.  Readings fixed here (the paper names the method only):
+ *   - distance: L1 of the ternary descriptors = popcount(gt ^ gt') + popcount(lt ^ lt');
+ *   - LSH: bit sampling of the "greater" string; table l's key has bit b equal to gt bit
+ *     positions[l * kbits + b];
+ *   - probes: in every table the query's own key and the kbits keys one bit away; the
+ *     candidates are the union over tables;
+ *   - a query's match is its nearest candidate by (distance, reference index), kept when
+ *     the distance is at most max_dist.
+ * desc_a / desc_b: DEVICE rows of 2 nd/32 uint32 (stitch_lorb's layout), 8-byte aligned;
+ * count_a / count_b: DEVICE int32, the valid rows (stitch_lorb's counts[i]), capped at
+ * cap_a / cap_b (1..65536).  tables 1..16, kbits 0..24 (0: every point is a candidate,
+ * i.e. exhaustive search); positions: HOST tables x kbits int32 in 0..nd-1.
+ * match / dist: DEVICE int32[cap_a]: reference index and distance, -1 where there is no
+ * match and for rows past count_a.  workspace: stitch_lsh_match_workspace_bytes (the keys),
+ * 256-byte aligned.  Errors: NULL, SHAPE, WORKSPACE, DEVICE. */
+size_t        stitch_lsh_match_workspace_bytes(int32_t cap_a, int32_t cap_b, int32_t tables);
+stitch_status stitch_lsh_match(int32_t nd, const uint32_t* desc_a, const int32_t* count_a, int32_t cap_a,
+                               const uint32_t* desc_b, const int32_t* count_b, int32_t cap_b, int32_t tables,
+                               int32_t kbits, const int32_t* positions, int32_t max_dist, int32_t* match,
+                               int32_t* dist, void* workspace, size_t workspace_bytes, void* stream);
+
+/* PROSAC screening of the matches and the transformation they yield (Sec. 4.2.2; Alg. 3,
+ * step 2; Alg. 4, step 5).  Readings fixed here:
+ *   - quality order: matches by (distance, query index); samples of 4;
+ *   - the growth function of Chum and Matas with T_N, evaluated in FP64 in the order
+ *     T_4 = T_N prod_{i<4} (4-i)/(M-i), T_{n+1} = T_n (n+1)/(n+1-4), T'_4 = 1,
+ *     T'_{n+1} = T'_n + ceil(T_{n+1} - T_n); hypothesis t (1-based) grows n when t = T'_n
+ *     and n < M, then samples the n-th match and 3 draws from the top n-1 unless T'_n < t
+ *     (then 4 draws from the top n);
+ *   - draws from the caller's uniforms: draw k of a range of R takes
+ *     r = min(floor(u_k (R - k)), R - k - 1) and the r-th index not drawn before;
+ *   - model: 4-point DLT with h33 = 1 (FP64); a sample with three collinear points in
+ *     either frame is skipped; inliers: w > 0 and squared reprojection error <= eps^2;
+ *   - a fixed budget of nhyp hypotheses; the best has the most inliers (ties: the earlier);
+ *     H is the least-squares DLT over its inliers on Hartley-normalised coordinates (5 or
+ *     more inliers), else the best's own model; no valid hypothesis: H = 0, 0 inliers.
+ * pts_a: DEVICE int32 [cap_a][2], pts_b: DEVICE int32 [cap_b][2] (stitch_lorb's points);
+ * match, dist, count_a: as stitch_lsh_match wrote them.  uniforms: DEVICE double
+ * [nhyp][4] in [0, 1) (the random draws are an input); nhyp 1..65536.  T_N, eps > 0.
+ * Outputs (DEVICE): H[9] double row-major (frame A -> frame B, h33 = 1), inliers (int32),
+ * inlier_mask uint8[cap_a] (1 where query i's match is an inlier of the best hypothesis),
+ * hyp_counts int32[nhyp] (each hypothesis' inlier count, 0 when skipped).
+ * workspace: stitch_prosac_workspace_bytes, 256-byte aligned.
+ * Errors: NULL, SHAPE, WORKSPACE, DEVICE. */
+size_t        stitch_prosac_workspace_bytes(int32_t cap_a, int32_t nhyp);
+stitch_status stitch_prosac(const int32_t* pts_a, const int32_t* pts_b, int32_t cap_b, const int32_t* match,
+                            const int32_t* dist, const int32_t* count_a, int32_t cap_a, int32_t nhyp,
+                            const double* uniforms, double T_N, double eps, double* H, int32_t* inliers,
+                            uint8_t* inlier_mask, int32_t* hyp_counts, void* workspace, size_t workspace_bytes,
+                            void* stream);
+
 #ifdef __cplusplus
 }
 #endif

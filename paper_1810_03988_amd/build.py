@@ -10,7 +10,8 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libstitch.so"
-SOURCES = [CSRC / "kernels.hip", CSRC / "stitch_api.cpp", CSRC / "grad.hip", CSRC / "pipe.cpp", CSRC / "lorb.hip"]
+SOURCES = [CSRC / "kernels.hip", CSRC / "stitch_api.cpp", CSRC / "grad.hip", CSRC / "pipe.cpp", CSRC / "lorb.hip",
+           CSRC / "register.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -1,0 +1,576 @@
+// Pairwise registration on gfx950 after L-ORB: multi-probe LSH matching of the descriptors
+// (Sec. 4.2.1; Alg. 3, step 1) and PROSAC screening with the transformation it yields
+// (Sec. 4.2.2; Alg. 3, step 2; Alg. 4, step 5).
+//
+//   distance   L1 of the ternary descriptors = popcount(gt ^ gt') + popcount(lt ^ lt')
+//   LSH        bit sampling of the "greater" string: table l's key has bit b = gt bit P[l][b]
+//   probes     a query's own key and the k keys one bit away, in every table; a reference
+//              point is a candidate when its key is one of them in some table
+//   match      the nearest candidate by (distance, reference index), kept when <= D
+//   PROSAC     m = 4, quality order (distance, query index), the growth function of Chum
+//              and Matas (T_N given), draws from input uniforms, 4-point DLT (h33 = 1) in
+//              FP64, degenerate samples (three collinear points) skipped, inliers by squared
+//              reprojection error <= eps^2 with w > 0, a fixed budget of hypotheses, the best
+//              by inlier count (ties to the earlier), then the least-squares DLT over its
+//              inliers on Hartley-normalised coordinates (>= 5 inliers).
+//
+// Matching evaluates the probe predicate over every (query, reference) pair instead of
+// building hash tables: the candidates, and hence the matches, are the same, and at the
+// point counts of a detection area (hundreds to a few thousand) a wave per query scanning
+// the reference keys and descriptors from L2 is faster than bucket lists.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+
+#include "stitch_internal.h"
+
+using namespace stitch;
+
+namespace {
+
+constexpr int kMaxTables = 16, kMaxKeyBits = 24;
+constexpr int kMaxPoints = 1 << 16;
+constexpr int kMaxHyp = 1 << 16;
+constexpr int kSample = 4;
+
+struct LshParams {
+  int32_t tables, kbits, words, pad;          // words: 32-bit words per bit string (nd / 32)
+  int16_t pos[kMaxTables][kMaxKeyBits];
+};
+
+__device__ __forceinline__ uint32_t key_of(const uint32_t* gt, const LshParams& P, int l) {
+  uint32_t key = 0;
+  for (int b = 0; b < P.kbits; ++b) {
+    const int p = P.pos[l][b];
+    key |= ((gt[p >> 5] >> (p & 31)) & 1u) << b;
+  }
+  return key;
+}
+
+// keys[l][i] of the first count rows of desc (rows of 2 * words uint32)
+__global__ void __launch_bounds__(256) k_lsh_keys(const uint32_t* __restrict__ desc, const int32_t* __restrict__ count,
+                                                  int cap, const LshParams P, uint32_t* __restrict__ keys) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int n = min(*count, cap);
+  if (i >= n) return;
+  const uint32_t* gt = desc + (int64_t)i * 2 * P.words;
+  for (int l = 0; l < P.tables; ++l) keys[(int64_t)l * cap + i] = key_of(gt, P, l);
+}
+
+// one wave per query: lanes stride over the reference points, then a (distance, index) min
+__global__ void __launch_bounds__(256) k_lsh_match(const uint32_t* __restrict__ desc_a,
+                                                   const int32_t* __restrict__ count_a, int cap_a,
+                                                   const uint32_t* __restrict__ desc_b,
+                                                   const int32_t* __restrict__ count_b, int cap_b, const LshParams P,
+                                                   const uint32_t* __restrict__ keys_a,
+                                                   const uint32_t* __restrict__ keys_b, int max_dist,
+                                                   int32_t* __restrict__ match, int32_t* __restrict__ dist) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= cap_a) return;                           // whole waves leave; no block barrier below
+  const int na = min(*count_a, cap_a), nb = min(*count_b, cap_b);
+  if (i >= na) {
+    if (lane == 0) {
+      match[i] = -1;
+      dist[i] = -1;
+    }
+    return;
+  }
+  const int W2 = 2 * P.words;
+  uint32_t ka[kMaxTables];
+  for (int l = 0; l < P.tables; ++l) ka[l] = keys_a[(int64_t)l * cap_a + i];
+  const uint32_t* da = desc_a + (int64_t)i * W2;
+  unsigned long long best = ~0ull;                  // (distance << 32) | index
+  for (int j = lane; j < nb; j += 64) {
+    bool cand = false;
+    for (int l = 0; l < P.tables && !cand; ++l) cand = __popc(ka[l] ^ keys_b[(int64_t)l * cap_b + j]) <= 1;
+    if (!cand) continue;
+    const uint32_t* db = desc_b + (int64_t)j * W2;
+    int d = 0;
+    for (int w = 0; w < W2; w += 2) {                 // rows hold an even number of words
+      const uint2 x = *reinterpret_cast<const uint2*>(da + w), y = *reinterpret_cast<const uint2*>(db + w);
+      d += __popc(x.x ^ y.x) + __popc(x.y ^ y.y);
+    }
+    const unsigned long long kd = ((unsigned long long)d << 32) | (uint32_t)j;
+    best = kd < best ? kd : best;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long other = __shfl_xor(best, o);
+    best = other < best ? other : best;
+  }
+  if (lane == 0) {
+    const int d = (int)(best >> 32);
+    const bool ok = best != ~0ull && d <= max_dist;
+    match[i] = ok ? (int)(uint32_t)best : -1;
+    dist[i] = ok ? d : -1;
+  }
+}
+
+// ---------------------------------------------------------------------------- PROSAC
+struct ProsacWs {            // offsets into the workspace
+  size_t misc, qa, qb, qi, tp, hyp_h, hyp_ok;
+};
+
+// misc: [0] M = number of matches
+// one block of 1024 threads: matches in quality order, and T'_n for n = 4 .. M
+__global__ void __launch_bounds__(1024) k_prosac_prepare(const int32_t* __restrict__ pts_a,
+                                                         const int32_t* __restrict__ pts_b, int cap_b,
+                                                         const int32_t* __restrict__ match,
+                                                         const int32_t* __restrict__ dist,
+                                                         const int32_t* __restrict__ count_a, int cap_a, double T_N,
+                                                         int32_t* __restrict__ misc, int2* __restrict__ qa,
+                                                         int2* __restrict__ qb, int32_t* __restrict__ qi,
+                                                         int64_t* __restrict__ tp) {
+  __shared__ int sM;
+  const int tid = threadIdx.x;
+  const int na = min(*count_a, cap_a);
+  if (tid == 0) sM = 0;
+  __syncthreads();
+  // number of valid matches
+  int local = 0;
+  for (int i = tid; i < na; i += 1024) local += match[i] >= 0 && match[i] < cap_b;
+  atomicAdd(&sM, local);
+  __syncthreads();
+  const int M = sM;
+  // rank of match i: the valid matches ordered before it by (distance, query index)
+  for (int i = tid; i < na; i += 1024) {
+    const int mi = match[i];
+    if (mi < 0 || mi >= cap_b) continue;
+    const int di = dist[i];
+    int r = 0;
+    for (int j = 0; j < na; ++j) {
+      const int mj = match[j], dj = dist[j];
+      r += (mj >= 0 && mj < cap_b) && (dj < di || (dj == di && j < i));
+    }
+    qa[r] = make_int2(pts_a[2 * i], pts_a[2 * i + 1]);
+    qb[r] = make_int2(pts_b[2 * mi], pts_b[2 * mi + 1]);
+    qi[r] = i;
+  }
+  // the growth function, sequentially in FP64 in the order of its definition
+  if (tid == 0) {
+    misc[0] = M;
+    if (M >= kSample) {
+      double T = T_N;
+      for (int i = 0; i < kSample; ++i) T = T * (double)(kSample - i) / (double)(M - i);
+      tp[kSample] = 1;
+      for (int n = kSample; n < M; ++n) {
+        const double Tn = T * (double)(n + 1) / (double)(n + 1 - kSample);
+        tp[n + 1] = tp[n] + (int64_t)ceil(Tn - T);
+        T = Tn;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ bool collinear(int2 p, int2 q, int2 r) {
+  return (int64_t)(q.x - p.x) * (r.y - p.y) - (int64_t)(q.y - p.y) * (r.x - p.x) == 0;
+}
+
+__device__ bool degenerate4(const int2* p) {
+  for (int a = 0; a < 4; ++a)
+    for (int b = a + 1; b < 4; ++b)
+      for (int c = b + 1; c < 4; ++c)
+        if (collinear(p[a], p[b], p[c])) return true;
+  return false;
+}
+
+// Solve the n x n system A x = b (row-major A, n <= 8) by Gaussian elimination with
+// partial pivoting (largest |pivot|, the first on ties); false when a pivot is zero.
+__device__ bool solve8(double A[8][8], double b[8], int n, double x[8]) {
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (fabs(A[r][c]) > fabs(A[p][c])) p = r;
+    if (A[p][c] == 0.0) return false;
+    if (p != c) {
+      for (int k = 0; k < n; ++k) {
+        const double t = A[c][k];
+        A[c][k] = A[p][k];
+        A[p][k] = t;
+      }
+      const double t = b[c];
+      b[c] = b[p];
+      b[p] = t;
+    }
+    for (int r = c + 1; r < n; ++r) {
+      const double f = A[r][c] / A[c][c];
+      for (int k = c; k < n; ++k) A[r][k] -= f * A[c][k];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    double s = b[r];
+    for (int k = r + 1; k < n; ++k) s -= A[r][k] * x[k];
+    x[r] = s / A[r][r];
+  }
+  return true;
+}
+
+// squared reprojection test in the order of its definition (no contraction)
+__device__ __forceinline__ bool is_inlier(const double* H, int2 p, int2 q, double eps2) {
+#pragma clang fp contract(off)
+  const double x = p.x, y = p.y;
+  const double X = H[0] * x + H[1] * y + H[2];
+  const double Y = H[3] * x + H[4] * y + H[5];
+  const double W = H[6] * x + H[7] * y + H[8];
+  if (!(W > 0.0)) return false;
+  const double ex = X / W - (double)q.x, ey = Y / W - (double)q.y;
+  return ex * ex + ey * ey <= eps2;
+}
+
+// r-th index of [0, R) not in chosen[0 .. nch), in increasing order
+__device__ int nth_free(int r, const int* chosen, int nch) {
+  int s[3];
+  for (int k = 0; k < nch; ++k) s[k] = chosen[k];
+  for (int a = 0; a < nch; ++a)                       // sort (at most 3)
+    for (int b = a + 1; b < nch; ++b)
+      if (s[b] < s[a]) {
+        const int t = s[a];
+        s[a] = s[b];
+        s[b] = t;
+      }
+  for (int k = 0; k < nch; ++k)
+    if (s[k] <= r) ++r;
+  return r;
+}
+
+// one wave per hypothesis t: its sample, its model and its inlier count
+__global__ void __launch_bounds__(256) k_prosac_hyp(const int32_t* __restrict__ misc, const int2* __restrict__ qa,
+                                                    const int2* __restrict__ qb, const int64_t* __restrict__ tp,
+                                                    int nhyp, const double* __restrict__ uniforms, double eps2,
+                                                    double* __restrict__ hyp_h, int32_t* __restrict__ hyp_ok,
+                                                    int32_t* __restrict__ hyp_counts) {
+  __shared__ double sH[4][9];
+  __shared__ int sOk[4];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + wv;                  // hypothesis t + 1 of the schedule
+  if (t >= nhyp) return;                              // whole waves; no block barrier below
+  const int M = misc[0];
+  if (M < kSample) {
+    if (lane == 0) {
+      hyp_ok[t] = 0;
+      hyp_counts[t] = 0;
+    }
+    return;
+  }
+  if (lane == 0) {
+    // n_t = 4 + #{n in [4, M-1] : T'_n <= t+1}: binary search over the increasing T'
+    const int64_t tt = t + 1;
+    int lo = kSample, hi = M;                         // first n in [4, M) with T'_n > tt, or M
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (tp[mid] <= tt) lo = mid + 1;
+      else hi = mid;
+    }
+    const int n = kSample + (lo - kSample);
+    const bool nth = !(tp[n] < tt);
+    const double* u = uniforms + (int64_t)t * 4;
+    int idx[4];
+    const int R = nth ? n - 1 : n, draws = nth ? 3 : 4;
+    for (int k = 0; k < draws; ++k) {
+      int r = (int)floor(u[k] * (double)(R - k));
+      r = min(r, R - k - 1);
+      idx[k] = nth_free(r, idx, k);
+    }
+    if (nth) idx[3] = n - 1;
+    int2 pa[4], pb[4];
+    for (int k = 0; k < 4; ++k) {
+      pa[k] = qa[idx[k]];
+      pb[k] = qb[idx[k]];
+    }
+    bool ok = !degenerate4(pa) && !degenerate4(pb);
+    double h[8] = {};
+    if (ok) {
+      double A[8][8], b[8];
+      for (int k = 0; k < 4; ++k) {
+        const double x = pa[k].x, y = pa[k].y, u2 = pb[k].x, v2 = pb[k].y;
+        const double r0[8] = {x, y, 1.0, 0.0, 0.0, 0.0, -u2 * x, -u2 * y};
+        const double r1[8] = {0.0, 0.0, 0.0, x, y, 1.0, -v2 * x, -v2 * y};
+        for (int c = 0; c < 8; ++c) {
+          A[2 * k][c] = r0[c];
+          A[2 * k + 1][c] = r1[c];
+        }
+        b[2 * k] = u2;
+        b[2 * k + 1] = v2;
+      }
+      ok = solve8(A, b, 8, h);
+    }
+    for (int c = 0; c < 8; ++c) sH[wv][c] = h[c];
+    sH[wv][8] = 1.0;
+    sOk[wv] = ok;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const bool ok = sOk[wv];
+  double H[9];
+  for (int c = 0; c < 9; ++c) H[c] = sH[wv][c];
+  int cnt = 0;
+  if (ok)
+    for (int k = lane; k < M; k += 64) cnt += is_inlier(H, qa[k], qb[k], eps2);
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+  if (lane == 0) {
+    hyp_ok[t] = ok;
+    hyp_counts[t] = ok ? cnt : 0;
+  }
+  if (lane < 9) hyp_h[(int64_t)t * 9 + lane] = H[lane];
+}
+
+// block-wide sum of v (1024 threads) into every thread; sRed holds 16 partials
+__device__ double block_sum(double v, double* sRed) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sRed[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int k = 0; k < 16; ++k) s += sRed[k];
+  return s;
+}
+
+// rows of the normalised DLT system for correspondence (x, y) -> (u, v):
+//   r0 = [x, y, 1, 0, 0, 0, -u x, -u y] (right side u), r1 = [0, 0, 0, x, y, 1, -v x, -v y] (v)
+__device__ __forceinline__ double row0(int i, double x, double y, double u) {
+  return i == 0 ? x : i == 1 ? y : i == 2 ? 1.0 : i == 6 ? -u * x : i == 7 ? -u * y : 0.0;
+}
+__device__ __forceinline__ double row1(int i, double x, double y, double v) {
+  return i == 3 ? x : i == 4 ? y : i == 5 ? 1.0 : i == 6 ? -v * x : i == 7 ? -v * y : 0.0;
+}
+
+constexpr int kParts = 14;                            // 72 x 14 = 1008 of the 1024 threads
+
+// one block of 1024 threads: the best hypothesis, its inliers, the least-squares refit
+__global__ void __launch_bounds__(1024) k_prosac_final(const int32_t* __restrict__ misc,
+                                                       const int2* __restrict__ qa, const int2* __restrict__ qb,
+                                                       const int32_t* __restrict__ qi, int cap_a, int nhyp,
+                                                       const double* __restrict__ hyp_h,
+                                                       const int32_t* __restrict__ hyp_ok,
+                                                       const int32_t* __restrict__ hyp_counts, double eps2,
+                                                       double* __restrict__ H_out, int32_t* __restrict__ inliers,
+                                                       uint8_t* __restrict__ mask) {
+  __shared__ unsigned long long sBest;
+  __shared__ double sRed[16];
+  __shared__ double sPart[kParts][72];
+  __shared__ double sH[9];
+  __shared__ uint32_t sFlag[kMaxPoints / 32];
+  const int tid = threadIdx.x;
+  const int M = misc[0];
+  if (tid == 0) sBest = 0ull;
+  for (int i = tid; i < cap_a; i += 1024) mask[i] = 0;
+  for (int i = tid; i < (M + 31) / 32; i += 1024) sFlag[i] = 0;
+  __syncthreads();
+  // best: most inliers, then the earliest hypothesis; key (count + 1) << 32 | (2^32-1 - t)
+  unsigned long long mine = 0ull;
+  for (int t = tid; t < nhyp; t += 1024)
+    if (hyp_ok[t]) {
+      const unsigned long long k = ((unsigned long long)(hyp_counts[t] + 1) << 32) | (0xFFFFFFFFull - (unsigned)t);
+      mine = k > mine ? k : mine;
+    }
+  atomicMax(&sBest, mine);
+  __syncthreads();
+  const unsigned long long best = sBest;
+  if (best == 0ull) {                                 // no valid hypothesis
+    if (tid < 9) H_out[tid] = 0.0;
+    if (tid == 0) *inliers = 0;
+    return;
+  }
+  const int tb = (int)(0xFFFFFFFFull - (best & 0xFFFFFFFFull));
+  if (tid < 9) sH[tid] = hyp_h[(int64_t)tb * 9 + tid];
+  __syncthreads();
+  double Hb[9];
+  for (int c = 0; c < 9; ++c) Hb[c] = sH[c];
+  // inliers of the best model (flags, mask over queries) and the sums for the normalisation
+  double sx = 0, sy = 0, su = 0, sv = 0, cn = 0;
+  for (int k = tid; k < M; k += 1024)
+    if (is_inlier(Hb, qa[k], qb[k], eps2)) {
+      atomicOr(&sFlag[k >> 5], 1u << (k & 31));
+      mask[qi[k]] = 1;
+      sx += qa[k].x;
+      sy += qa[k].y;
+      su += qb[k].x;
+      sv += qb[k].y;
+      cn += 1.0;
+    }
+  const double n_in = block_sum(cn, sRed);           // (its barriers also publish sFlag)
+  if (tid == 0) *inliers = (int)n_in;
+  if (n_in < 5.0) {
+    if (tid < 9) H_out[tid] = Hb[tid] / Hb[8];
+    return;
+  }
+  const double cx = block_sum(sx, sRed) / n_in, cy = block_sum(sy, sRed) / n_in;
+  const double cu = block_sum(su, sRed) / n_in, cv = block_sum(sv, sRed) / n_in;
+  auto flag = [&](int k) { return (sFlag[k >> 5] >> (k & 31)) & 1u; };
+  double da = 0, db = 0;
+  for (int k = tid; k < M; k += 1024)
+    if (flag(k)) {
+      da += sqrt((qa[k].x - cx) * (qa[k].x - cx) + (qa[k].y - cy) * (qa[k].y - cy));
+      db += sqrt((qb[k].x - cu) * (qb[k].x - cu) + (qb[k].y - cv) * (qb[k].y - cv));
+    }
+  const double s_a = sqrt(2.0) / (block_sum(da, sRed) / n_in);
+  const double s_b = sqrt(2.0) / (block_sum(db, sRed) / n_in);
+  // normal equations of the normalised system: entry c (64 of A^T A, 8 of A^T b) summed by
+  // kParts threads over interleaved inliers, then the parts in a fixed order
+  if (tid < 72 * kParts) {
+    const int c = tid % 72, part = tid / 72;
+    const int a = c < 64 ? c / 8 : c - 64, cc = c % 8;
+    double acc = 0.0;
+    for (int k = part; k < M; k += kParts)
+      if (flag(k)) {
+        const double x = s_a * (qa[k].x - cx), y = s_a * (qa[k].y - cy);
+        const double u = s_b * (qb[k].x - cu), v = s_b * (qb[k].y - cv);
+        if (c < 64) acc += row0(a, x, y, u) * row0(cc, x, y, u) + row1(a, x, y, v) * row1(cc, x, y, v);
+        else acc += row0(a, x, y, u) * u + row1(a, x, y, v) * v;
+      }
+    sPart[part][c] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double A[8][8], b[8], h[8];
+    for (int a = 0; a < 8; ++a) {
+      for (int c = 0; c < 8; ++c) {
+        double sum = 0.0;
+        for (int k = 0; k < kParts; ++k) sum += sPart[k][8 * a + c];
+        A[a][c] = sum;
+      }
+      double sum = 0.0;
+      for (int k = 0; k < kParts; ++k) sum += sPart[k][64 + a];
+      b[a] = sum;
+    }
+    if (solve8(A, b, 8, h)) {
+      double Hn[9];
+      for (int c = 0; c < 8; ++c) Hn[c] = h[c];
+      Hn[8] = 1.0;
+      // H = Tb^-1 Hn Ta with Ta = [s_a 0 -s_a cx; 0 s_a -s_a cy; 0 0 1], Tb likewise
+      const double Ta[9] = {s_a, 0, -s_a * cx, 0, s_a, -s_a * cy, 0, 0, 1};
+      const double Tbi[9] = {1.0 / s_b, 0, cu, 0, 1.0 / s_b, cv, 0, 0, 1};
+      double HT[9], R[9];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+          double sum = 0.0;
+          for (int k = 0; k < 3; ++k) sum += Hn[3 * r + k] * Ta[3 * k + c];
+          HT[3 * r + c] = sum;
+        }
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+          double sum = 0.0;
+          for (int k = 0; k < 3; ++k) sum += Tbi[3 * r + k] * HT[3 * k + c];
+          R[3 * r + c] = sum;
+        }
+      for (int c = 0; c < 9; ++c) H_out[c] = R[c] / R[8];
+    } else {
+      for (int c = 0; c < 9; ++c) H_out[c] = Hb[c] / Hb[8];
+    }
+  }
+}
+
+size_t up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+ProsacWs prosac_layout(int cap_a, int nhyp, size_t* total) {
+  ProsacWs L;
+  size_t o = 0;
+  L.misc = o; o += 256;
+  L.qa = o; o += up((size_t)cap_a * 8);
+  L.qb = o; o += up((size_t)cap_a * 8);
+  L.qi = o; o += up((size_t)cap_a * 4);
+  L.tp = o; o += up((size_t)(cap_a + 1) * 8);
+  L.hyp_h = o; o += up((size_t)nhyp * 9 * 8);
+  L.hyp_ok = o; o += up((size_t)nhyp * 4);
+  *total = o;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t stitch_lsh_match_workspace_bytes(int32_t cap_a, int32_t cap_b, int32_t tables) {
+  if (cap_a < 1 || cap_b < 1 || cap_a > kMaxPoints || cap_b > kMaxPoints || tables < 1 || tables > kMaxTables)
+    return 0;
+  return up((size_t)tables * cap_a * 4) + up((size_t)tables * cap_b * 4);
+}
+
+stitch_status stitch_lsh_match(int32_t nd, const uint32_t* desc_a, const int32_t* count_a, int32_t cap_a,
+                               const uint32_t* desc_b, const int32_t* count_b, int32_t cap_b, int32_t tables,
+                               int32_t kbits, const int32_t* positions, int32_t max_dist, int32_t* match,
+                               int32_t* dist, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!desc_a || !count_a || !desc_b || !count_b || !match || !dist || (kbits > 0 && !positions))
+    return fail(STITCH_E_NULL, "a descriptor, count, output or the positions is NULL");
+  if (nd < 32 || nd > 512 || nd % 32) return fail(STITCH_E_SHAPE, "nd = %d is not a multiple of 32 in 32..512", nd);
+  if (cap_a < 1 || cap_b < 1 || cap_a > kMaxPoints || cap_b > kMaxPoints)
+    return fail(STITCH_E_SHAPE, "capacities must lie in 1..%d", kMaxPoints);
+  if (tables < 1 || tables > kMaxTables || kbits < 0 || kbits > kMaxKeyBits)
+    return fail(STITCH_E_SHAPE, "tables in 1..%d and key bits in 0..%d", kMaxTables, kMaxKeyBits);
+  if ((uintptr_t)desc_a & 7 || (uintptr_t)desc_b & 7)
+    return fail(STITCH_E_SHAPE, "descriptors must be 8-byte aligned");
+  LshParams P{};
+  P.tables = tables;
+  P.kbits = kbits;
+  P.words = nd / 32;
+  for (int l = 0; l < tables; ++l)
+    for (int b = 0; b < kbits; ++b) {
+      const int p = positions[l * kbits + b];
+      if (p < 0 || p >= nd) return fail(STITCH_E_SHAPE, "bit position %d outside 0..%d", p, nd - 1);
+      P.pos[l][b] = (int16_t)p;
+    }
+  const size_t need = stitch_lsh_match_workspace_bytes(cap_a, cap_b, tables);
+  if (!workspace || workspace_bytes < need || ((uintptr_t)workspace & 255))
+    return fail(STITCH_E_WORKSPACE, "workspace missing, misaligned or smaller than %zu bytes", need);
+  uint32_t* keys_a = (uint32_t*)workspace;
+  uint32_t* keys_b = (uint32_t*)((uint8_t*)workspace + up((size_t)tables * cap_a * 4));
+  const hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_lsh_keys, dim3((cap_a + 255) / 256), dim3(256), 0, s, desc_a, count_a, cap_a, P, keys_a);
+  hipLaunchKernelGGL(k_lsh_keys, dim3((cap_b + 255) / 256), dim3(256), 0, s, desc_b, count_b, cap_b, P, keys_b);
+  hipLaunchKernelGGL(k_lsh_match, dim3((cap_a + 3) / 4), dim3(256), 0, s, desc_a, count_a, cap_a, desc_b, count_b,
+                     cap_b, P, keys_a, keys_b, max_dist, match, dist);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "matching launch");
+  return STITCH_OK;
+}
+
+size_t stitch_prosac_workspace_bytes(int32_t cap_a, int32_t nhyp) {
+  if (cap_a < 1 || cap_a > kMaxPoints || nhyp < 1 || nhyp > kMaxHyp) return 0;
+  size_t total = 0;
+  prosac_layout(cap_a, nhyp, &total);
+  return total;
+}
+
+stitch_status stitch_prosac(const int32_t* pts_a, const int32_t* pts_b, int32_t cap_b, const int32_t* match,
+                            const int32_t* dist, const int32_t* count_a, int32_t cap_a, int32_t nhyp,
+                            const double* uniforms, double T_N, double eps, double* H, int32_t* inliers,
+                            uint8_t* inlier_mask, int32_t* hyp_counts, void* workspace, size_t workspace_bytes,
+                            void* stream) {
+  if (!pts_a || !pts_b || !match || !dist || !count_a || !uniforms || !H || !inliers || !inlier_mask || !hyp_counts)
+    return fail(STITCH_E_NULL, "an input or output is NULL");
+  if (cap_a < 1 || cap_a > kMaxPoints || cap_b < 1 || cap_b > kMaxPoints)
+    return fail(STITCH_E_SHAPE, "capacities must lie in 1..%d", kMaxPoints);
+  if (nhyp < 1 || nhyp > kMaxHyp) return fail(STITCH_E_SHAPE, "nhyp = %d outside 1..%d", nhyp, kMaxHyp);
+  if (!(T_N > 0.0) || !std::isfinite(T_N) || !(eps > 0.0) || !std::isfinite(eps))
+    return fail(STITCH_E_SHAPE, "T_N and eps must be positive and finite");
+  size_t need = 0;
+  const ProsacWs L = prosac_layout(cap_a, nhyp, &need);
+  if (!workspace || workspace_bytes < need || ((uintptr_t)workspace & 255))
+    return fail(STITCH_E_WORKSPACE, "workspace missing, misaligned or smaller than %zu bytes", need);
+  uint8_t* ws = (uint8_t*)workspace;
+  int32_t* misc = (int32_t*)(ws + L.misc);
+  int2* qa = (int2*)(ws + L.qa);
+  int2* qb = (int2*)(ws + L.qb);
+  int32_t* qi = (int32_t*)(ws + L.qi);
+  int64_t* tp = (int64_t*)(ws + L.tp);
+  double* hyp_h = (double*)(ws + L.hyp_h);
+  int32_t* hyp_ok = (int32_t*)(ws + L.hyp_ok);
+  const double eps2 = eps * eps;
+  const hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_prosac_prepare, dim3(1), dim3(1024), 0, s, pts_a, pts_b, cap_b, match, dist, count_a, cap_a,
+                     T_N, misc, qa, qb, qi, tp);
+  hipLaunchKernelGGL(k_prosac_hyp, dim3((nhyp + 3) / 4), dim3(256), 0, s, misc, qa, qb, tp, nhyp, uniforms, eps2,
+                     hyp_h, hyp_ok, hyp_counts);
+  hipLaunchKernelGGL(k_prosac_final, dim3(1), dim3(1024), 0, s, misc, qa, qb, qi, cap_a, nhyp, hyp_h, hyp_ok,
+                     hyp_counts, eps2, H, inliers, inlier_mask);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "PROSAC launch");
+  return STITCH_OK;
+}
+
+}  // extern "C"

@@ -101,6 +101,14 @@ SIGNATURES = {
     "stitch_lorb": (c_int32, [POINTER(StitchImage), c_int32, POINTER(c_int32), c_int32, c_int64, c_int32, c_int32,
                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "stitch_lorb_set_timing": (c_int32, [c_int32]),
+    "stitch_lsh_match_workspace_bytes": (c_size_t, [c_int32, c_int32, c_int32]),
+    "stitch_lsh_match": (c_int32, [c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_int32,
+                                   c_int32, POINTER(c_int32), c_int32, c_void_p, c_void_p, c_void_p, c_size_t,
+                                   c_void_p]),
+    "stitch_prosac_workspace_bytes": (c_size_t, [c_int32, c_int32]),
+    "stitch_prosac": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
+                                c_void_p, c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                c_size_t, c_void_p]),
     "stitch_lorb_read_timing": (c_int32, [POINTER(c_double), POINTER(c_int32)]),
 }
 
@@ -686,3 +694,78 @@ def lorb_read_timing() -> dict:
     n = (c_int32 * len(LORB_KINDS))()
     check(lib().stitch_lorb_read_timing(ms, n))
     return {k: (ms[i], n[i]) for i, k in enumerate(LORB_KINDS)}
+
+
+# ----------------------------------------------------------------------------- registration
+def _aligned_workspace(nbytes: int, device) -> tuple:
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf[off:off + nbytes]
+
+
+class Matcher:
+    """Multi-probe LSH matching (Sec. 4.2.1; Alg. 3, step 1) of two descriptor sets with
+    capacities cap_a, cap_b: positions is a (tables, kbits) int array of gt-bit indices."""
+
+    def __init__(self, cap_a: int, cap_b: int, nd: int, positions, max_dist: int, device="cuda"):
+        pos = np.ascontiguousarray(np.asarray(positions, dtype=np.int32).reshape(len(positions), -1))
+        self.tables, self.kbits = pos.shape
+        self.positions = (c_int32 * max(pos.size, 1))(*pos.reshape(-1).tolist())
+        self.cap_a, self.cap_b, self.nd, self.max_dist = int(cap_a), int(cap_b), int(nd), int(max_dist)
+        nbytes = lib().stitch_lsh_match_workspace_bytes(self.cap_a, self.cap_b, self.tables)
+        if nbytes == 0:
+            raise StitchError(2, "no workspace size for these capacities")
+        self._buf, self._ws = _aligned_workspace(nbytes, device)
+        self.match = torch.full((self.cap_a,), -1, dtype=torch.int32, device=device)
+        self.dist = torch.full((self.cap_a,), -1, dtype=torch.int32, device=device)
+
+    def run_raw(self, desc_a, count_a, desc_b, count_b, stream_handle: int) -> None:
+        check(lib().stitch_lsh_match(self.nd, desc_a.data_ptr(), count_a.data_ptr(), self.cap_a, desc_b.data_ptr(),
+                                     count_b.data_ptr(), self.cap_b, self.tables, self.kbits, self.positions,
+                                     self.max_dist, self.match.data_ptr(), self.dist.data_ptr(),
+                                     self._ws.data_ptr(), self._ws.numel(), stream_handle))
+
+    def run(self, desc_a, count_a, desc_b, count_b, stream=None):
+        """desc_*: (cap, 2 nd/32) int32/uint32 device tensors, count_*: one-element int32
+        device tensors.  Returns (match, dist) as host tensors."""
+        for d, cap in ((desc_a, self.cap_a), (desc_b, self.cap_b)):
+            if d.shape[0] < cap or d.shape[-1] != 2 * self.nd // 32 or not d.is_contiguous():
+                raise ValueError("descriptor rows must be contiguous (cap, 2 nd/32)")
+        self.run_raw(desc_a, count_a, desc_b, count_b, _stream(stream))
+        torch.cuda.synchronize()
+        return self.match.cpu(), self.dist.cpu()
+
+
+class Prosac:
+    """PROSAC (Sec. 4.2.2; Alg. 3, step 2; Alg. 4, step 5) over the matches of one pair,
+    with nhyp hypotheses drawn from caller-supplied uniforms."""
+
+    def __init__(self, cap_a: int, cap_b: int, nhyp: int, T_N: float = 200000.0, eps: float = 3.0,
+                 device="cuda"):
+        self.cap_a, self.cap_b, self.nhyp = int(cap_a), int(cap_b), int(nhyp)
+        self.T_N, self.eps = float(T_N), float(eps)
+        nbytes = lib().stitch_prosac_workspace_bytes(self.cap_a, self.nhyp)
+        if nbytes == 0:
+            raise StitchError(2, "no workspace size for these capacities")
+        self._buf, self._ws = _aligned_workspace(nbytes, device)
+        self.H = torch.zeros(9, dtype=torch.float64, device=device)
+        self.inliers = torch.zeros(1, dtype=torch.int32, device=device)
+        self.mask = torch.zeros(self.cap_a, dtype=torch.uint8, device=device)
+        self.hyp_counts = torch.zeros(self.nhyp, dtype=torch.int32, device=device)
+
+    def run_raw(self, pts_a, pts_b, match, dist, count_a, uniforms, stream_handle: int) -> None:
+        check(lib().stitch_prosac(pts_a.data_ptr(), pts_b.data_ptr(), self.cap_b, match.data_ptr(), dist.data_ptr(),
+                                  count_a.data_ptr(), self.cap_a, self.nhyp, uniforms.data_ptr(), self.T_N, self.eps,
+                                  self.H.data_ptr(), self.inliers.data_ptr(), self.mask.data_ptr(),
+                                  self.hyp_counts.data_ptr(), self._ws.data_ptr(), self._ws.numel(),
+                                  stream_handle))
+
+    def run(self, pts_a, pts_b, match, dist, count_a, uniforms, stream=None) -> dict:
+        """pts_*: (cap, 2) int32 device, match/dist: (cap_a,) int32 device, count_a: one-element
+        int32 device, uniforms: (nhyp, 4) float64 device in [0, 1)."""
+        if uniforms.dtype != torch.float64 or tuple(uniforms.shape) != (self.nhyp, 4) or not uniforms.is_contiguous():
+            raise ValueError(f"uniforms must be a contiguous ({self.nhyp}, 4) float64 tensor")
+        self.run_raw(pts_a, pts_b, match, dist, count_a, uniforms, _stream(stream))
+        torch.cuda.synchronize()
+        return {"H": self.H.cpu().numpy().reshape(3, 3), "inliers": int(self.inliers[0]),
+                "mask": self.mask.cpu().numpy().astype(bool), "hyp_counts": self.hyp_counts.cpu().numpy()}

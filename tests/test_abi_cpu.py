@@ -233,6 +233,40 @@ def test_lorb_validates_on_host():
                            None) == E["E_WORKSPACE"]
 
 
+def test_registration_calls_validate_on_host():
+    lib = P.lib()
+    fake = 0x10000
+    pos = (ctypes.c_int32 * 24)(*range(24))
+    bad_pos = (ctypes.c_int32 * 24)(*([3] * 23 + [256]))
+
+    def match(nd=256, a=fake, cap_a=100, cap_b=100, tables=2, kbits=12, p=pos, ws=fake, nbytes=1 << 20):
+        return lib.stitch_lsh_match(nd, a, fake, cap_a, fake, fake, cap_b, tables, kbits, p, 64, fake, fake, ws,
+                                    nbytes, None)
+
+    assert match(a=None) == E["E_NULL"]
+    assert match(p=None) == E["E_NULL"] and match(p=None, kbits=0) != E["E_NULL"]
+    assert match(nd=48) == E["E_SHAPE"] and match(cap_a=0) == E["E_SHAPE"] and match(cap_b=65537) == E["E_SHAPE"]
+    assert match(tables=17) == E["E_SHAPE"] and match(kbits=25) == E["E_SHAPE"]
+    assert match(p=bad_pos) == E["E_SHAPE"]                      # a bit position past nd
+    assert match(a=fake + 4) == E["E_SHAPE"]                     # descriptors not 8-byte aligned
+    need = lib.stitch_lsh_match_workspace_bytes(100, 100, 2)
+    assert need >= 2 * 100 * 4 * 2
+    assert match(ws=fake + 16) == E["E_WORKSPACE"] and match(nbytes=need - 1) == E["E_WORKSPACE"]
+    assert lib.stitch_lsh_match_workspace_bytes(0, 100, 2) == 0
+
+    def prosac(pa=fake, cap_a=100, nhyp=512, T_N=2e5, eps=3.0, nbytes=1 << 24, ws=fake):
+        return lib.stitch_prosac(pa, fake, 100, fake, fake, fake, cap_a, nhyp, fake, T_N, eps, fake, fake, fake,
+                                 fake, ws, nbytes, None)
+
+    assert prosac(pa=None) == E["E_NULL"]
+    assert prosac(nhyp=0) == E["E_SHAPE"] and prosac(nhyp=65537) == E["E_SHAPE"]
+    assert prosac(T_N=0.0) == E["E_SHAPE"] and prosac(eps=float("nan")) == E["E_SHAPE"]
+    assert prosac(cap_a=70000) == E["E_SHAPE"]
+    need = lib.stitch_prosac_workspace_bytes(100, 512)
+    assert need >= 512 * 9 * 8
+    assert prosac(nbytes=need - 1) == E["E_WORKSPACE"] and prosac(ws=fake + 8) == E["E_WORKSPACE"]
+
+
 def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(S, "LIB_PATH", tmp_path / "missing.so")
     monkeypatch.setattr(S, "_lib", None)
