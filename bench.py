@@ -44,10 +44,11 @@ def parse():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16"])
     ap.add_argument("--form", default="batched", choices=["batched", "plain"],
                     help="the headline form: all frames of the step as one batch, or one stitch_frame per frame")
-    ap.add_argument("--forms", default="batched_graph_f16,plain_f32,plain_f16,pipe_f32,lorb",
+    ap.add_argument("--forms", default="batched_graph_f16,plain_f32,plain_f16,pipe_f32,lorb,register",
                     help="extra forms timed after the headline (comma list of batched_graph_<s> / plain_<s> / "
                          "pipe_<s>, the last end to end through PCIe, lorb (the feature-extraction front "
-                         "end on the same frames), or 'none')")
+                         "end on the same frames), register (L-ORB, matching and PROSAC of the rig's "
+                         "neighbouring pairs), or 'none')")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the step without per-launch events (roofline then omitted)")
@@ -76,6 +77,8 @@ KERNEL_KINDS = {
     "k_lorb_clear": "L-ORB clear", "k_lorb_detect": "L-ORB detect (FAST, R, suppression)",
     "k_lorb_select": "L-ORB select (histogram threshold)", "k_lorb_rank": "L-ORB rank",
     "k_lorb_brief": "L-ORB BRIEF",
+    "k_lsh_keys": "LSH keys", "k_lsh_match": "LSH matching", "k_prosac_prepare": "PROSAC order + growth",
+    "k_prosac_hyp": "PROSAC hypotheses", "k_prosac_final": "PROSAC best + refit",
 }
 COPY_KERNEL_HINT = "neg"
 
@@ -490,6 +493,87 @@ def time_lorb(rig, frames, steps, warmup, n_max=500, nd=256):
             "px": sum(px.values()), "areas": areas, "counts": counts, "kernels": kernels}
 
 
+def time_register(rig, frames, steps, warmup, n_max=500, nd=256, nhyp=1024):
+    """Registration of a rig (Alg. 3, Alg. 4 steps 2-5): L-ORB of every camera in its overlap
+    areas, then for each pair of neighbouring cameras multi-probe LSH matching of the facing
+    areas and PROSAC to the map between their frames; one stream, frames in HBM.  Timed as
+    the whole chain and as matching + PROSAC alone; accuracy against the rig's true maps."""
+    import paper_1810_03988_amd as P
+    import workloads as wl
+    areas = wl.overlap_areas(rig)
+    pattern = torch.from_numpy(wl.brief_pattern(nd)).cuda()
+    lorbs = {i: P.Lorb(*rig.frame_sizes[i], areas[i], n_max=n_max, nd=nd) for i in range(rig.n) if areas[i]}
+    pos = np.random.default_rng(42).integers(0, nd, (6, 14))
+    uni = torch.from_numpy(np.random.default_rng(7).random((nhyp, 4))).cuda()
+    pairs = [i for i in range(rig.n - 1) if areas[i] and areas[i + 1]]
+    matchers = {i: P.Matcher(n_max, n_max, nd, pos, nd // 4) for i in pairs}
+    prosacs = {i: P.Prosac(n_max, n_max, nhyp, 200000.0, 3.0) for i in pairs}
+    h = torch.cuda.current_stream().cuda_stream
+
+    def feats(i):
+        za, zb = len(areas[i]) - 1, 0
+        la, lb = lorbs[i], lorbs[i + 1]
+        return (la.points[za], la.descriptors[za], la.counts[za:za + 1],
+                lb.points[zb], lb.descriptors[zb], lb.counts[zb:zb + 1])
+
+    def match_prosac():
+        for i in pairs:
+            pa, da, ca, pb, db, cb = feats(i)
+            matchers[i].run_raw(da, ca, db, cb, h)
+            prosacs[i].run_raw(pa, pb, matchers[i].match, matchers[i].dist, ca, uni, h)
+
+    def chain(t):
+        for c, lb in lorbs.items():
+            lb.run_raw(frames[t % len(frames)][c], pattern, h)
+        match_prosac()
+
+    def timed(fn):
+        for t in range(warmup):
+            fn(t)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for t in range(steps):
+            fn(t)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_chain = timed(chain)
+    chain(0)                                        # features and maps of frame set 0
+    torch.cuda.synchronize()
+    ms_mp = timed(lambda t: match_prosac())
+    res = []
+    for i in pairs:
+        H = prosacs[i].H.cpu().numpy().reshape(3, 3)
+        H_true = np.linalg.inv(np.asarray(rig.H[i + 1])) @ np.asarray(rig.H[i])
+        x0, y0, w, hh = areas[i][-1]
+        err = 0.0
+        for (x, y) in [(x0, y0), (x0 + w, y0), (x0, y0 + hh), (x0 + w, y0 + hh)]:
+            a = H @ np.array([x, y, 1.0])
+            b = H_true @ np.array([x, y, 1.0])
+            err = max(err, float(np.hypot(*(a[:2] / a[2] - b[:2] / b[2]))))
+        res.append({"pair": [i, i + 1], "matches": int((matchers[i].match >= 0).sum()),
+                    "inliers": int(prosacs[i].inliers[0]), "max_corner_error_px": round(err, 3)})
+    return {"ms_chain": ms_chain, "ms_match_prosac": ms_mp, "pairs": res, "nhyp": nhyp,
+            "features": (feats, pos, uni)}
+
+
+def register_cpu_baseline(rig, frames0, feats, pos, uni, nd=256):
+    """The registration oracle (matching and PROSAC, Python loops, one thread) on the first
+    pair's features as the GPU found them: seconds per pair."""
+    from oracle import register_oracle as ro
+    pa, da, ca, pb, db, cb = feats(0)
+    na, nb = int(ca[0]), int(cb[0])
+    dah, dbh = da.cpu().numpy().view(np.uint32)[:na], db.cpu().numpy().view(np.uint32)[:nb]
+    t = time.perf_counter()
+    idx, dist = ro.lsh_match(dah, dbh, pos, nd // 4)
+    ro.prosac(pa.cpu().numpy()[:na], pb.cpu().numpy(), idx, dist, uni.cpu().numpy(), 200000.0, 3.0)
+    dt = time.perf_counter() - t
+    return {"value": round(1.0 / dt, 4), "unit": "pairs/s (matching + PROSAC)", "cores": 1, "kind": "oracle",
+            "sample": f"pair 0-1 of frame set 0, {na} x {nb} features, {len(uni)} hypotheses, {dt:.1f} s"}
+
+
 def _scanned(rect, w, h, margin=17):
     """Samples of a detection area that are scanned: those 17 or more from every frame
     edge (the descriptor support)."""
@@ -722,6 +806,20 @@ def main():
         kind, st = form.rsplit("_", 1) if "_" in form else (form, "")
         if (kind == a.form and st == a.storage) or (kind == "batched_graph" and a.form == "batched" and
                                                     st == a.storage):
+            continue
+        if form == "register":
+            G = time_register(rig, frames, a.steps, a.warmup)
+            feats, pos, uni = G.pop("features")
+            forms["register"] = {
+                "ms_per_rig_registration": round(G["ms_chain"], 4),
+                "ms_match_prosac_all_pairs": round(G["ms_match_prosac"], 4),
+                "how": "L-ORB of every camera in its overlap areas, then per neighbouring pair multi-probe LSH "
+                       "matching (6 tables x 14 bits, distance <= 64) and PROSAC (1024 hypotheses, T_N 2e5, "
+                       "eps 3 px, least-squares refit); one stream, frames in HBM",
+                "pairs": G["pairs"], "nhyp": G["nhyp"]}
+            if not a.no_cpu_baseline:
+                forms["register"]["cpu_baseline"] = register_cpu_baseline(rig, frames[0], feats, pos, uni)
+            print(f"# register: {json.dumps(forms['register'])}", file=sys.stderr, flush=True)
             continue
         if form == "lorb":
             L = time_lorb(rig, frames, a.steps, a.warmup)

@@ -49,14 +49,18 @@ __device__ __forceinline__ uint32_t key_of(const uint32_t* gt, const LshParams& 
   return key;
 }
 
-// keys[l][i] of the first count rows of desc (rows of 2 * words uint32)
+// keys[l][i] of the first count rows of desc (rows of 2 * words uint32); each thread copies
+// its row's "greater" words to LDS first, so the bit reads are LDS reads
 __global__ void __launch_bounds__(256) k_lsh_keys(const uint32_t* __restrict__ desc, const int32_t* __restrict__ count,
                                                   int cap, const LshParams P, uint32_t* __restrict__ keys) {
+  __shared__ uint32_t sRow[256][17];
   const int i = blockIdx.x * 256 + threadIdx.x;
   const int n = min(*count, cap);
-  if (i >= n) return;
+  if (i >= n) return;                               // no block barrier below
   const uint32_t* gt = desc + (int64_t)i * 2 * P.words;
-  for (int l = 0; l < P.tables; ++l) keys[(int64_t)l * cap + i] = key_of(gt, P, l);
+  uint32_t* row = sRow[threadIdx.x];
+  for (int w = 0; w < P.words; ++w) row[w] = gt[w];
+  for (int l = 0; l < P.tables; ++l) keys[(int64_t)l * cap + i] = key_of(row, P, l);
 }
 
 // one wave per query: lanes stride over the reference points, then a (distance, index) min
@@ -123,27 +127,51 @@ __global__ void __launch_bounds__(1024) k_prosac_prepare(const int32_t* __restri
                                                          int32_t* __restrict__ misc, int2* __restrict__ qa,
                                                          int2* __restrict__ qb, int32_t* __restrict__ qi,
                                                          int64_t* __restrict__ tp) {
+  constexpr int kStage = 16384;                      // ranking keys staged in LDS up to here
   __shared__ int sM;
+  __shared__ __attribute__((aligned(16))) int16_t sKey[kStage];
   const int tid = threadIdx.x;
   const int na = min(*count_a, cap_a);
+  // ranking key of query j: its distance (0 .. 1024) when it has a match, else 0x7FFF
+  // (which precedes nothing and equals no valid key)
+  auto key = [&](int j) -> int {
+    const int mj = match[j];
+    return (mj >= 0 && mj < cap_b) ? dist[j] : 0x7FFF;
+  };
+  const bool staged = na <= kStage;
+  const int npad = (na + 7) & ~7;
   if (tid == 0) sM = 0;
+  if (staged)
+    for (int j = tid; j < npad; j += 1024) sKey[j] = (int16_t)(j < na ? key(j) : 0x7FFF);
   __syncthreads();
   // number of valid matches
   int local = 0;
-  for (int i = tid; i < na; i += 1024) local += match[i] >= 0 && match[i] < cap_b;
+  for (int i = tid; i < na; i += 1024) local += key(i) != 0x7FFF;
   atomicAdd(&sM, local);
   __syncthreads();
   const int M = sM;
   // rank of match i: the valid matches ordered before it by (distance, query index)
   for (int i = tid; i < na; i += 1024) {
-    const int mi = match[i];
-    if (mi < 0 || mi >= cap_b) continue;
-    const int di = dist[i];
+    const int ki = key(i);
+    if (ki == 0x7FFF) continue;
     int r = 0;
-    for (int j = 0; j < na; ++j) {
-      const int mj = match[j], dj = dist[j];
-      r += (mj >= 0 && mj < cap_b) && (dj < di || (dj == di && j < i));
+    if (staged) {
+      for (int j = 0; j < npad; j += 8) {
+        const int4 v = *reinterpret_cast<const int4*>(&sKey[j]);
+        const int w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int kj = (int)(int16_t)((uint32_t)w[q >> 1] >> (16 * (q & 1)));
+          r += kj < ki || (kj == ki && j + q < i);
+        }
+      }
+    } else {
+      for (int j = 0; j < na; ++j) {
+        const int kj = key(j);
+        r += kj < ki || (kj == ki && j < i);
+      }
     }
+    const int mi = match[i];
     qa[r] = make_int2(pts_a[2 * i], pts_a[2 * i + 1]);
     qb[r] = make_int2(pts_b[2 * mi], pts_b[2 * mi + 1]);
     qi[r] = i;
@@ -176,34 +204,43 @@ __device__ bool degenerate4(const int2* p) {
   return false;
 }
 
-// Solve the n x n system A x = b (row-major A, n <= 8) by Gaussian elimination with
-// partial pivoting (largest |pivot|, the first on ties); false when a pivot is zero.
-__device__ bool solve8(double A[8][8], double b[8], int n, double x[8]) {
-  for (int c = 0; c < n; ++c) {
-    int p = c;
-    for (int r = c + 1; r < n; ++r)
-      if (fabs(A[r][c]) > fabs(A[p][c])) p = r;
-    if (A[p][c] == 0.0) return false;
-    if (p != c) {
-      for (int k = 0; k < n; ++k) {
-        const double t = A[c][k];
-        A[c][k] = A[p][k];
-        A[p][k] = t;
+// Solve the 8 x 8 system A x = b with one wave: lane l holds a = A[l / 8][l % 8] and bv =
+// b[l / 8].  Gaussian elimination with partial pivoting (largest |pivot|, the first row on
+// ties) by shuffles, then back substitution; returns x[l % 8] in every lane, and false (in
+// every lane) when a pivot is zero.
+__device__ bool wave_solve8(double a, double bv, double& x_mine) {
+  const int lane = threadIdx.x & 63, r = lane >> 3, c = lane & 7;
+  for (int k = 0; k < 8; ++k) {
+    // pivot: max |A[row][k]| over rows >= k, the first row on ties
+    double v = (c == k && r >= k) ? fabs(a) : -1.0;
+    int pr = r;
+    for (int o = 32; o > 0; o >>= 1) {
+      const double v2 = __shfl_xor(v, o);
+      const int r2 = __shfl_xor(pr, o);
+      if (v2 > v || (v2 == v && r2 < pr)) {
+        v = v2;
+        pr = r2;
       }
-      const double t = b[c];
-      b[c] = b[p];
-      b[p] = t;
     }
-    for (int r = c + 1; r < n; ++r) {
-      const double f = A[r][c] / A[c][c];
-      for (int k = c; k < n; ++k) A[r][k] -= f * A[c][k];
-      b[r] -= f * b[c];
+    if (!(v > 0.0)) return false;
+    // swap rows pr and k
+    const int src = r == k ? pr * 8 + c : r == pr ? k * 8 + c : lane;
+    a = __shfl(a, src);
+    bv = __shfl(bv, src);
+    const double piv = __shfl(a, k * 8 + k), prow = __shfl(a, k * 8 + c), bk = __shfl(bv, k * 8);
+    const double col = __shfl(a, r * 8 + k);
+    if (r > k) {
+      const double f = col / piv;
+      if (c >= k) a -= f * prow;
+      bv -= f * bk;
     }
   }
-  for (int r = n - 1; r >= 0; --r) {
-    double s = b[r];
-    for (int k = r + 1; k < n; ++k) s -= A[r][k] * x[k];
-    x[r] = s / A[r][r];
+  x_mine = 0.0;
+  for (int k = 7; k >= 0; --k) {
+    double t = (r == k && c > k) ? a * x_mine : 0.0;
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    const double xk = (__shfl(bv, k * 8) - t) / __shfl(a, k * 8 + k);
+    if (c == k) x_mine = xk;
   }
   return true;
 }
@@ -236,6 +273,21 @@ __device__ int nth_free(int r, const int* chosen, int nch) {
   return r;
 }
 
+// rows of the DLT system (h33 = 1) for a correspondence (x, y) -> (u, v):
+//   r0 = [x, y, 1, 0, 0, 0, -u x, -u y] (right side u), r1 = [0, 0, 0, x, y, 1, -v x, -v y] (v)
+__device__ __forceinline__ double row0(int i, double x, double y, double u) {
+  return i == 0 ? x : i == 1 ? y : i == 2 ? 1.0 : i == 6 ? -u * x : i == 7 ? -u * y : 0.0;
+}
+__device__ __forceinline__ double row1(int i, double x, double y, double v) {
+  return i == 3 ? x : i == 4 ? y : i == 5 ? 1.0 : i == 6 ? -v * x : i == 7 ? -v * y : 0.0;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // one wave per hypothesis t: its sample, its model and its inlier count
 __global__ void __launch_bounds__(256) k_prosac_hyp(const int32_t* __restrict__ misc, const int2* __restrict__ qa,
                                                     const int2* __restrict__ qb, const int64_t* __restrict__ tp,
@@ -244,6 +296,7 @@ __global__ void __launch_bounds__(256) k_prosac_hyp(const int32_t* __restrict__ 
                                                     int32_t* __restrict__ hyp_counts) {
   __shared__ double sH[4][9];
   __shared__ int sOk[4];
+  __shared__ int2 sPts[4][8];                         // the sample: 4 points of A, then of B
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int t = blockIdx.x * 4 + wv;                  // hypothesis t + 1 of the schedule
   if (t >= nhyp) return;                              // whole waves; no block barrier below
@@ -279,32 +332,27 @@ __global__ void __launch_bounds__(256) k_prosac_hyp(const int32_t* __restrict__ 
     for (int k = 0; k < 4; ++k) {
       pa[k] = qa[idx[k]];
       pb[k] = qb[idx[k]];
+      sPts[wv][k] = pa[k];
+      sPts[wv][4 + k] = pb[k];
     }
-    bool ok = !degenerate4(pa) && !degenerate4(pb);
-    double h[8] = {};
-    if (ok) {
-      double A[8][8], b[8];
-      for (int k = 0; k < 4; ++k) {
-        const double x = pa[k].x, y = pa[k].y, u2 = pb[k].x, v2 = pb[k].y;
-        const double r0[8] = {x, y, 1.0, 0.0, 0.0, 0.0, -u2 * x, -u2 * y};
-        const double r1[8] = {0.0, 0.0, 0.0, x, y, 1.0, -v2 * x, -v2 * y};
-        for (int c = 0; c < 8; ++c) {
-          A[2 * k][c] = r0[c];
-          A[2 * k + 1][c] = r1[c];
-        }
-        b[2 * k] = u2;
-        b[2 * k + 1] = v2;
-      }
-      ok = solve8(A, b, 8, h);
-    }
-    for (int c = 0; c < 8; ++c) sH[wv][c] = h[c];
-    sH[wv][8] = 1.0;
-    sOk[wv] = ok;
+    sOk[wv] = !degenerate4(pa) && !degenerate4(pb);
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const bool ok = sOk[wv];
+  wave_sync();
+  bool ok = sOk[wv];
+  if (ok) {
+    // lane (row, col) of the 8 x 8 DLT system: rows 2k, 2k+1 from correspondence k
+    const int r = lane >> 3, c = lane & 7, k = r >> 1;
+    const int2 p = sPts[wv][k], q = sPts[wv][4 + k];
+    const double x = p.x, y = p.y, u2 = q.x, v2 = q.y;
+    const double a = (r & 1) ? row1(c, x, y, v2) : row0(c, x, y, u2);
+    double h = 0.0;
+    ok = wave_solve8(a, (r & 1) ? v2 : u2, h);
+    if (lane < 8) sH[wv][lane] = ok ? h : 0.0;
+  } else if (lane < 8) {
+    sH[wv][lane] = 0.0;
+  }
+  if (lane == 0) sH[wv][8] = 1.0;
+  wave_sync();
   double H[9];
   for (int c = 0; c < 9; ++c) H[c] = sH[wv][c];
   int cnt = 0;
@@ -330,14 +378,6 @@ __device__ double block_sum(double v, double* sRed) {
   return s;
 }
 
-// rows of the normalised DLT system for correspondence (x, y) -> (u, v):
-//   r0 = [x, y, 1, 0, 0, 0, -u x, -u y] (right side u), r1 = [0, 0, 0, x, y, 1, -v x, -v y] (v)
-__device__ __forceinline__ double row0(int i, double x, double y, double u) {
-  return i == 0 ? x : i == 1 ? y : i == 2 ? 1.0 : i == 6 ? -u * x : i == 7 ? -u * y : 0.0;
-}
-__device__ __forceinline__ double row1(int i, double x, double y, double v) {
-  return i == 3 ? x : i == 4 ? y : i == 5 ? 1.0 : i == 6 ? -v * x : i == 7 ? -v * y : 0.0;
-}
 
 constexpr int kParts = 14;                            // 72 x 14 = 1008 of the 1024 threads
 
@@ -426,21 +466,20 @@ __global__ void __launch_bounds__(1024) k_prosac_final(const int32_t* __restrict
     sPart[part][c] = acc;
   }
   __syncthreads();
-  if (tid == 0) {
-    double A[8][8], b[8], h[8];
-    for (int a = 0; a < 8; ++a) {
-      for (int c = 0; c < 8; ++c) {
-        double sum = 0.0;
-        for (int k = 0; k < kParts; ++k) sum += sPart[k][8 * a + c];
-        A[a][c] = sum;
-      }
-      double sum = 0.0;
-      for (int k = 0; k < kParts; ++k) sum += sPart[k][64 + a];
-      b[a] = sum;
+  if (tid < 64) {                                     // wave 0 solves the normal equations
+    const int r = tid >> 3;
+    double a = 0.0, bv = 0.0;
+    for (int k = 0; k < kParts; ++k) {
+      a += sPart[k][tid];
+      bv += sPart[k][64 + r];
     }
-    if (solve8(A, b, 8, h)) {
+    double h = 0.0;
+    const bool solved = wave_solve8(a, bv, h);
+    if (tid < 8) sH[tid] = h;
+    wave_sync();
+    if (tid == 0 && solved) {
       double Hn[9];
-      for (int c = 0; c < 8; ++c) Hn[c] = h[c];
+      for (int c = 0; c < 8; ++c) Hn[c] = sH[c];
       Hn[8] = 1.0;
       // H = Tb^-1 Hn Ta with Ta = [s_a 0 -s_a cx; 0 s_a -s_a cy; 0 0 1], Tb likewise
       const double Ta[9] = {s_a, 0, -s_a * cx, 0, s_a, -s_a * cy, 0, 0, 1};
@@ -459,7 +498,7 @@ __global__ void __launch_bounds__(1024) k_prosac_final(const int32_t* __restrict
           R[3 * r + c] = sum;
         }
       for (int c = 0; c < 9; ++c) H_out[c] = R[c] / R[8];
-    } else {
+    } else if (tid == 0) {
       for (int c = 0; c < 9; ++c) H_out[c] = Hb[c] / Hb[8];
     }
   }
