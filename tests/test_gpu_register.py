@@ -162,3 +162,44 @@ def test_rig_pair_registration_matches_the_oracle_and_the_true_map(rig_name, cam
     corners = [(x0, y0), (x0 + w, y0), (x0, y0 + h), (x0 + w, y0 + h)]
     err = max(np.hypot(*(_apply(got["H"], p) - _apply(H_true, p))) for p in corners)
     assert got["inliers"] >= 30 and err < 1.5, (got["inliers"], err)
+
+
+def test_registration_feeds_the_gradient_refinement():
+    """Alg. 4 step 5 closed into the differentiable form: PROSAC's map between the frames of a
+    C5 pair places frame B's corners on the canvas, and 20 Adam steps on the stitched pair's
+    loss start there.  The map is within 1 px of the truth on the overlap area it was fitted
+    on (the far corners of B, a frame width away, amplify its perspective terms); the
+    refinement does not raise the loss and does not move the corners further off."""
+    r = wl.rig_c5_pairs(1)[0]
+    w, h = r.frame_sizes[1]
+    frames = wl.render_rig_frames(r)
+    areas = wl.overlap_areas(r)
+    pat = torch.from_numpy(wl.brief_pattern(256)).cuda()
+    feats = []
+    for c, area in ((0, areas[0][-1]), (1, areas[1][0])):
+        lb = P.Lorb(w, h, [area], n_max=500)
+        lb.run(frames[c].cuda(), pat)
+        feats.append((lb.points[0], lb.descriptors[0], lb.counts[:1]))
+    (pa, da, ca), (pb, db, cb) = feats
+    m = P.Matcher(500, 500, 256, np.random.default_rng(42).integers(0, 256, (6, 14)), 64)
+    m.run(da, ca, db, cb)
+    pr = P.Prosac(500, 500, 1024, 200000.0, 3.0)
+    got = pr.run(pa, pb, m.match, m.dist, ca, torch.from_numpy(np.random.default_rng(7).random((1024, 4))).cuda())
+    H_true = np.linalg.inv(np.asarray(r.H[1])) @ np.asarray(r.H[0])     # frame A -> frame B
+    x0, y0, aw, ah = lo.clip_area(areas[0][-1], w, h)
+    near = max(np.hypot(*(_apply(got["H"], p) - _apply(H_true, p)))
+               for p in [(x0, y0), (x0 + aw, y0), (x0, y0 + ah), (x0 + aw, y0 + ah)])
+    assert got["inliers"] >= 30 and near < 1.0, (got["inliers"], near)
+    H_b = np.linalg.inv(got["H"])                      # frame B -> frame A = canvas (H_A = I)
+    corners = np.array([[0, 0], [w - 1, 0], [w - 1, h - 1], [0, h - 1]], dtype=np.float64)
+    c = np.c_[corners, np.ones(4)] @ H_b.T
+    q0 = (c[:, :2] / c[:, 2:]).ravel()
+    ct = np.c_[corners, np.ones(4)] @ np.asarray(r.H[1]).T
+    q_true = (ct[:, :2] / ct[:, 2:]).ravel()
+    fr = [f.permute(2, 0, 1).float().div(255.0).contiguous().cuda() for f in frames]
+    g = P.Grad(r.frame_sizes, r.masks(), r.canvas_w, r.canvas_h, r.levels)
+    q, log = P.refine_pair(g, fr[0], fr[1], np.eye(3), q0, steps=20, record=(0, 20), q_true=q_true)
+    print("registered corners off by", log[0][1], "px; after 20 steps", log[20][1], "px; loss",
+          log[0][0], "->", log[20][0])
+    assert log[20][0] <= 1.02 * log[0][0]
+    assert log[20][1] < log[0][1] + 0.5
