@@ -393,7 +393,22 @@ stitch_status stitch_lorb(const stitch_image* frame, int32_t m, const int32_t* a
                           int32_t* counts, int32_t* points, int64_t* responses, uint32_t* descriptors,
                           void* workspace, size_t workspace_bytes, void* stream);
 
-/* Per-launch timing of stitch_lorb (diagnostics), process-wide.  While enabled, each call
+/* The same for the areas of several frames at once (e.g. every camera of a frame set):
+ * one call, five launches covering all of them.  frames: HOST array of nframes (1..16)
+ * frame descriptions (device data, each as for stitch_lorb); m_per_frame: HOST, the number
+ * of areas of each frame (>= 0, 1..64 in total); areas: HOST, all frames' rectangles in
+ * frame order, each in its own frame's coordinates.  Outputs and workspace as for
+ * stitch_lorb, indexed by the area's position in `areas`; the results equal one stitch_lorb
+ * per frame.  Errors as stitch_lorb. */
+size_t        stitch_lorb_multi_workspace_bytes(int32_t nframes, const int32_t* frame_w, const int32_t* frame_h,
+                                                const int32_t* m_per_frame, const int32_t* areas);
+stitch_status stitch_lorb_multi(int32_t nframes, const stitch_image* frames, const int32_t* m_per_frame,
+                                const int32_t* areas, int32_t fast_threshold, int64_t harris_threshold,
+                                int32_t n_max, int32_t nd, const int32_t* pattern, int32_t* counts, int32_t* points,
+                                int64_t* responses, uint32_t* descriptors, void* workspace, size_t workspace_bytes,
+                                void* stream);
+
+/* Per-launch timing of stitch_lorb and stitch_lorb_multi (diagnostics), process-wide.  While enabled, each call
  * records a HIP event on its stream before its first launch and after each of its five
  * launches: 0 clear the counts, 1 detection (FAST, response, suppression), 2 selection
  * threshold, 3 ranking, 4 BRIEF.  set_timing clears the totals; read_timing waits for the

@@ -14,7 +14,7 @@
 // Points must keep their descriptor support in the frame (17 samples from every edge);
 // areas are clipped to that range.
 //
-// Five launches per call, each covering every area of the frame:
+// Five launches per call, each covering every area of every frame of the call:
 //   k_lorb_clear    zero the areas' survivor counts
 //   k_lorb_detect   64x16 tiles: gray tile with a 4-sample halo, gradient products and the
 //                   separable window in LDS, the FAST test and R on the tile plus a 1-sample
@@ -59,14 +59,24 @@ constexpr int kRankGrid = 64;
 constexpr int kPatch = 35, kHalfPatch = 17;             // gray patch of a point (15 + 2)
 constexpr int64_t kNone = INT64_MIN;
 
+constexpr int kMaxFrames = 16;
+
 struct AreaDesc {
   int32_t x0, y0, w, h;        // clipped area (frame coordinates)
   int32_t tiles_x, ntiles, tile_begin, list_off;
+  int32_t frame;               // index into AreaTable::f
+};
+
+struct FrameRef {
+  const uint8_t* p;            // U8 HWC RGB
+  int64_t row;                 // bytes
+  int32_t w, h;
 };
 
 struct AreaTable {
   int32_t m, n_max, nd, pad;
   AreaDesc a[kMaxAreas];
+  FrameRef f[kMaxFrames];
 };
 
 __device__ __forceinline__ int luma3(uint32_t r, uint32_t g, uint32_t b) {
@@ -115,8 +125,7 @@ __global__ void k_lorb_clear(int32_t* __restrict__ count, int m) {
   if ((int)threadIdx.x < 2 * m) count[threadIdx.x] = 0;
 }
 
-__global__ void __launch_bounds__(256) k_lorb_detect(const uint8_t* __restrict__ frame, int64_t row, int fw, int fh,
-                                                     const AreaTable T, int tf, int64_t t,
+__global__ void __launch_bounds__(256) k_lorb_detect(const AreaTable T, int tf, int64_t t,
                                                      int32_t* __restrict__ count, int64_t* __restrict__ listR,
                                                      int32_t* __restrict__ listI) {
   __shared__ __attribute__((aligned(16))) int sG[kGH][kGW + 4];
@@ -133,6 +142,9 @@ __global__ void __launch_bounds__(256) k_lorb_detect(const uint8_t* __restrict__
   for (int i = 0; i < T.m; ++i)
     if (b >= T.a[i].tile_begin && b < T.a[i].tile_begin + T.a[i].ntiles) z = i;
   const AreaDesc a = T.a[z];
+  const uint8_t* __restrict__ frame = T.f[a.frame].p;
+  const int64_t row = T.f[a.frame].row;
+  const int fw = T.f[a.frame].w, fh = T.f[a.frame].h;
   const int tl = b - a.tile_begin;
   const int ty = tl / a.tiles_x, tx = tl - ty * a.tiles_x;
   const int ox = tx * kTX, oy = ty * kTY;                    // tile origin (area coordinates)
@@ -418,8 +430,7 @@ __global__ void __launch_bounds__(256) k_lorb_rank(const AreaTable T, const int3
 // One wave per kept point: the 35x35 gray patch around it and the horizontal pass of the
 // window in the wave's LDS; each tested sample takes the vertical pass from there.  Pattern
 // offsets are clamped to +-15 so that every read stays in the patch.
-__global__ void __launch_bounds__(256) k_lorb_brief(const uint8_t* __restrict__ frame, int64_t row,
-                                                    const AreaTable T,
+__global__ void __launch_bounds__(256) k_lorb_brief(const AreaTable T,
                                                     const int32_t* __restrict__ pattern,
                                                     const int32_t* __restrict__ counts,
                                                     const int32_t* __restrict__ pts, uint32_t* __restrict__ desc) {
@@ -431,6 +442,8 @@ __global__ void __launch_bounds__(256) k_lorb_brief(const uint8_t* __restrict__ 
   if (k >= counts[z]) return;                        // whole waves leave; no block barrier below
   const int64_t slot = (int64_t)z * n_max + k;
   const int x = pts[2 * slot], y = pts[2 * slot + 1];
+  const uint8_t* __restrict__ frame = T.f[T.a[z].frame].p;
+  const int64_t row = T.f[T.a[z].frame].row;
   const uint8_t* base = frame + (int64_t)(y - kHalfPatch) * row + 3 * (int64_t)(x - kHalfPatch);
   // per row: 8 groups of 4 pixels (12 bytes) and a tail of 3 pixels (9 bytes); every byte
   // read belongs to the patch, which lies inside the frame
@@ -503,12 +516,20 @@ struct Layout {
   size_t count = 0, listR = 0, listI = 0, shortR = 0, shortI = 0, bytes = 0;
 };
 
-// Area table and workspace layout; false when the areas are too large for 32-bit indices
-bool plan_areas(int fw, int fh, int m, const int32_t* areas, AreaTable& T, Layout& L) {
+// Area table and workspace layout for the areas of nframes frames (m_per_frame[f] areas of
+// frame f, consecutive in areas); false when they are too large for 32-bit indices
+bool plan_areas(int nframes, const int32_t* fw, const int32_t* fh, const int32_t* m_per_frame,
+                const int32_t* areas, AreaTable& T, Layout& L) {
+  int m = 0;
+  for (int f = 0; f < nframes; ++f) m += m_per_frame[f];
   T.m = m;
   int64_t tiles = 0, total = 0;
+  int frame = 0, left = m_per_frame[0];
   for (int i = 0; i < m; ++i) {
-    AreaDesc a = clip(areas + 4 * i, fw, fh);
+    while (left == 0) left = m_per_frame[++frame];
+    --left;
+    AreaDesc a = clip(areas + 4 * i, fw[frame], fh[frame]);
+    a.frame = frame;
     a.tiles_x = (a.w + kTX - 1) / kTX;
     a.ntiles = a.tiles_x * ((a.h + kTY - 1) / kTY);
     a.tile_begin = (int32_t)tiles;
@@ -550,55 +571,106 @@ LorbTiming& timing() {
   return *t;
 }
 
-stitch_status check_areas(int32_t frame_w, int32_t frame_h, int32_t m, const int32_t* areas) {
+stitch_status check_areas(int32_t nframes, const int32_t* frame_w, const int32_t* frame_h,
+                          const int32_t* m_per_frame, const int32_t* areas) {
+  if (nframes < 1 || nframes > kMaxFrames) return fail(STITCH_E_SHAPE, "%d frames outside 1..%d", nframes, kMaxFrames);
+  if (!frame_w || !frame_h || !m_per_frame || !areas) return fail(STITCH_E_NULL, "sizes, counts or areas is NULL");
+  int m = 0;
+  for (int f = 0; f < nframes; ++f) {
+    if (m_per_frame[f] < 0 || m_per_frame[f] > kMaxAreas) return fail(STITCH_E_SHAPE, "frame %d: bad area count", f);
+    m += m_per_frame[f];
+    if (frame_w[f] < 2 * kMargin + 1 || frame_h[f] < 2 * kMargin + 1)
+      return fail(STITCH_E_SHAPE, "frames need at least %d samples per side", 2 * kMargin + 1);
+  }
   if (m < 1 || m > kMaxAreas) return fail(STITCH_E_SHAPE, "m = %d areas outside 1..%d", m, kMaxAreas);
-  if (!areas) return fail(STITCH_E_NULL, "areas is NULL");
-  if (frame_w < 2 * kMargin + 1 || frame_h < 2 * kMargin + 1)
-    return fail(STITCH_E_SHAPE, "frames need at least %d samples per side", 2 * kMargin + 1);
   for (int i = 0; i < m; ++i)
     if (areas[4 * i + 2] < 0 || areas[4 * i + 3] < 0) return fail(STITCH_E_SHAPE, "area %d has a negative size", i);
   return STITCH_OK;
 }
 
+stitch_status lorb_run(int32_t nframes, const stitch_image* frames, const int32_t* m_per_frame,
+                       const int32_t* areas, int32_t fast_threshold, int64_t harris_threshold, int32_t n_max,
+                       int32_t nd, const int32_t* pattern, int32_t* counts, int32_t* points, int64_t* responses,
+                       uint32_t* descriptors, void* workspace, size_t workspace_bytes, void* stream);
+
 }  // namespace
 
 extern "C" {
 
-size_t stitch_lorb_workspace_bytes(int32_t frame_w, int32_t frame_h, int32_t m, const int32_t* areas) {
-  if (check_areas(frame_w, frame_h, m, areas)) return 0;
+size_t stitch_lorb_multi_workspace_bytes(int32_t nframes, const int32_t* frame_w, const int32_t* frame_h,
+                                         const int32_t* m_per_frame, const int32_t* areas) {
+  if (check_areas(nframes, frame_w, frame_h, m_per_frame, areas)) return 0;
   AreaTable T;
   Layout L;
-  if (!plan_areas(frame_w, frame_h, m, areas, T, L)) {
+  if (!plan_areas(nframes, frame_w, frame_h, m_per_frame, areas, T, L)) {
     fail(STITCH_E_SHAPE, "the areas hold 2^30 samples or more");
     return 0;
   }
   return L.bytes;
 }
 
+size_t stitch_lorb_workspace_bytes(int32_t frame_w, int32_t frame_h, int32_t m, const int32_t* areas) {
+  return stitch_lorb_multi_workspace_bytes(1, &frame_w, &frame_h, &m, areas);
+}
+
 stitch_status stitch_lorb(const stitch_image* frame, int32_t m, const int32_t* areas, int32_t fast_threshold,
                           int64_t harris_threshold, int32_t n_max, int32_t nd, const int32_t* pattern,
                           int32_t* counts, int32_t* points, int64_t* responses, uint32_t* descriptors,
                           void* workspace, size_t workspace_bytes, void* stream) {
-  stitch_status st = check_image(frame, "frame", STITCH_U8, STITCH_HWC, 3);
-  if (st) return st;
+  if (!frame) return fail(STITCH_E_NULL, "frame is NULL");
+  return lorb_run(1, frame, &m, areas, fast_threshold, harris_threshold, n_max, nd, pattern, counts, points,
+                  responses, descriptors, workspace, workspace_bytes, stream);
+}
+
+stitch_status stitch_lorb_multi(int32_t nframes, const stitch_image* frames, const int32_t* m_per_frame,
+                                const int32_t* areas, int32_t fast_threshold, int64_t harris_threshold,
+                                int32_t n_max, int32_t nd, const int32_t* pattern, int32_t* counts, int32_t* points,
+                                int64_t* responses, uint32_t* descriptors, void* workspace, size_t workspace_bytes,
+                                void* stream) {
+  if (!frames) return fail(STITCH_E_NULL, "frames is NULL");
+  return lorb_run(nframes, frames, m_per_frame, areas, fast_threshold, harris_threshold, n_max, nd, pattern, counts,
+                  points, responses, descriptors, workspace, workspace_bytes, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+stitch_status lorb_run(int32_t nframes, const stitch_image* frames, const int32_t* m_per_frame,
+                       const int32_t* areas, int32_t fast_threshold, int64_t harris_threshold, int32_t n_max,
+                       int32_t nd, const int32_t* pattern, int32_t* counts, int32_t* points, int64_t* responses,
+                       uint32_t* descriptors, void* workspace, size_t workspace_bytes, void* stream) {
+  if (nframes < 1 || nframes > kMaxFrames) return fail(STITCH_E_SHAPE, "%d frames outside 1..%d", nframes, kMaxFrames);
+  int32_t fw[kMaxFrames], fh[kMaxFrames];
+  for (int f = 0; f < nframes; ++f) {
+    const stitch_status st = check_image(&frames[f], "frame", STITCH_U8, STITCH_HWC, 3);
+    if (st) return st;
+    fw[f] = frames[f].width;
+    fh[f] = frames[f].height;
+    if (frames[f].row_pitch * (int64_t)fh[f] >= ((int64_t)1 << 31))
+      return fail(STITCH_E_SHAPE, "frame %d spans 2 GiB or more", f);
+  }
   if (!pattern || !counts || !points || !responses || !descriptors)
     return fail(STITCH_E_NULL, "pattern or an output is NULL");
   if (nd < 32 || nd > 512 || nd % 32) return fail(STITCH_E_SHAPE, "nd = %d is not a multiple of 32 in 32..512", nd);
   if (n_max < 1 || n_max > (1 << 20)) return fail(STITCH_E_SHAPE, "n_max = %d outside 1..2^20", n_max);
   if (fast_threshold < 0 || fast_threshold > 255) return fail(STITCH_E_SHAPE, "fast_threshold outside 0..255");
   if ((uintptr_t)pattern & 15) return fail(STITCH_E_SHAPE, "pattern is not 16-byte aligned");
-  const int fw = frame->width, fh = frame->height;
-  if ((st = check_areas(fw, fh, m, areas))) return st;
-  if (frame->row_pitch * (int64_t)fh >= ((int64_t)1 << 31))
-    return fail(STITCH_E_SHAPE, "frame spans 2 GiB or more");
+  stitch_status st = check_areas(nframes, fw, fh, m_per_frame, areas);
+  if (st) return st;
   AreaTable T;
   Layout L;
-  if (!plan_areas(fw, fh, m, areas, T, L)) return fail(STITCH_E_SHAPE, "the areas hold 2^30 samples or more");
+  if (!plan_areas(nframes, fw, fh, m_per_frame, areas, T, L))
+    return fail(STITCH_E_SHAPE, "the areas hold 2^30 samples or more");
   if (!workspace || workspace_bytes < L.bytes || ((uintptr_t)workspace & 255))
     return fail(STITCH_E_WORKSPACE, "workspace missing, misaligned or smaller than %zu bytes", L.bytes);
+  const int m = T.m;
   T.n_max = n_max;
   T.nd = nd;
   T.pad = 0;
+  for (int f = 0; f < kMaxFrames; ++f)
+    T.f[f] = f < nframes ? FrameRef{(const uint8_t*)frames[f].data, frames[f].row_pitch, fw[f], fh[f]}
+                         : FrameRef{nullptr, 0, 0, 0};
   const hipStream_t s = (hipStream_t)stream;
   uint8_t* ws = (uint8_t*)workspace;
   int32_t* count = (int32_t*)(ws + L.count);         // per area: survivors, short-list length
@@ -606,7 +678,6 @@ stitch_status stitch_lorb(const stitch_image* frame, int32_t m, const int32_t* a
   int32_t* listI = (int32_t*)(ws + L.listI);
   int64_t* shortR = (int64_t*)(ws + L.shortR);
   int32_t* shortI = (int32_t*)(ws + L.shortI);
-  const uint8_t* src = (const uint8_t*)frame->data;
   const int tiles = T.a[m - 1].tile_begin + T.a[m - 1].ntiles;
   // optional timing events (taken before anything is enqueued)
   LorbTiming& tm = timing();
@@ -635,15 +706,15 @@ stitch_status stitch_lorb(const stitch_image* frame, int32_t m, const int32_t* a
   hipLaunchKernelGGL(k_lorb_clear, dim3(1), dim3(128), 0, s, count, m);
   mark(1);
   if (tiles > 0)
-    hipLaunchKernelGGL(k_lorb_detect, dim3(tiles), dim3(256), 0, s, src, frame->row_pitch, fw, fh, T,
-                       fast_threshold, harris_threshold, count, listR, listI);
+    hipLaunchKernelGGL(k_lorb_detect, dim3(tiles), dim3(256), 0, s, T, fast_threshold, harris_threshold, count,
+                       listR, listI);
   mark(2);
   hipLaunchKernelGGL(k_lorb_select, dim3(m), dim3(1024), 0, s, T, count, listR, listI, shortR, shortI, counts);
   mark(3);
   hipLaunchKernelGGL(k_lorb_rank, dim3(kRankGrid, m), dim3(256), 0, s, T, count, shortR, shortI, points, responses);
   mark(4);
-  hipLaunchKernelGGL(k_lorb_brief, dim3((n_max + 3) / 4, m), dim3(256), 0, s, src, frame->row_pitch, T, pattern,
-                     counts, points, descriptors);
+  hipLaunchKernelGGL(k_lorb_brief, dim3((n_max + 3) / 4, m), dim3(256), 0, s, T, pattern, counts, points,
+                     descriptors);
   mark(5);
   if (timed) {
     std::lock_guard<std::mutex> lock(tm.mu);
@@ -655,6 +726,10 @@ stitch_status stitch_lorb(const stitch_image* frame, int32_t m, const int32_t* a
   if (e != hipSuccess) return hip_fail(e, "feature extraction launch");
   return STITCH_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 stitch_status stitch_lorb_set_timing(int32_t enable) {
   LorbTiming& tm = timing();

@@ -101,6 +101,11 @@ SIGNATURES = {
     "stitch_lorb": (c_int32, [POINTER(StitchImage), c_int32, POINTER(c_int32), c_int32, c_int64, c_int32, c_int32,
                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "stitch_lorb_set_timing": (c_int32, [c_int32]),
+    "stitch_lorb_multi_workspace_bytes": (c_size_t, [c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
+                                                     POINTER(c_int32)]),
+    "stitch_lorb_multi": (c_int32, [c_int32, POINTER(StitchImage), POINTER(c_int32), POINTER(c_int32), c_int32,
+                                    c_int64, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                    c_void_p, c_size_t, c_void_p]),
     "stitch_lsh_match_workspace_bytes": (c_size_t, [c_int32, c_int32, c_int32]),
     "stitch_lsh_match": (c_int32, [c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_int32,
                                    c_int32, POINTER(c_int32), c_int32, c_void_p, c_void_p, c_void_p, c_size_t,
@@ -678,6 +683,40 @@ class Lorb:
         counts = self.counts.cpu().tolist()
         return [(self.points[i, :k].cpu(), self.responses[i, :k].cpu(), self.descriptors[i, :k].cpu())
                 for i, k in enumerate(counts)]
+
+
+class LorbSet:
+    """L-ORB in the areas of several frames with one call (stitch_lorb_multi): frame_sizes
+    [(w, h)] and areas_per_frame [[(x, y, w, h), ...], ...]; outputs indexed by the areas in
+    frame order."""
+
+    def __init__(self, frame_sizes, areas_per_frame, n_max: int = 500, nd: int = 256, fast_threshold: int = 20,
+                 harris_threshold: int = 0, device="cuda"):
+        self.nframes = len(frame_sizes)
+        self.fw = (c_int32 * self.nframes)(*[int(w) for w, _ in frame_sizes])
+        self.fh = (c_int32 * self.nframes)(*[int(h) for _, h in frame_sizes])
+        self.mpf = (c_int32 * self.nframes)(*[len(a) for a in areas_per_frame])
+        flat = [int(v) for a in areas_per_frame for r in a for v in r]
+        self.m = len(flat) // 4
+        self.areas = (c_int32 * max(len(flat), 1))(*flat)
+        self.n_max, self.nd = int(n_max), int(nd)
+        self.tf, self.t = int(fast_threshold), int(harris_threshold)
+        nbytes = lib().stitch_lorb_multi_workspace_bytes(self.nframes, self.fw, self.fh, self.mpf, self.areas)
+        if nbytes == 0:
+            raise StitchError(2, "no workspace size for these areas: " + last_error())
+        self._buf, self._ws = _aligned_workspace(nbytes, device)
+        m, n, words = self.m, self.n_max, 2 * self.nd // 32
+        self.counts = torch.zeros(m, dtype=torch.int32, device=device)
+        self.points = torch.zeros(m, n, 2, dtype=torch.int32, device=device)
+        self.responses = torch.zeros(m, n, dtype=torch.int64, device=device)
+        self.descriptors = torch.zeros(m, n, words, dtype=torch.int32, device=device)
+
+    def run_raw(self, frames, pattern: torch.Tensor, stream_handle: int) -> None:
+        imgs = (StitchImage * self.nframes)(*[image_hwc(f) for f in frames])
+        check(lib().stitch_lorb_multi(self.nframes, imgs, self.mpf, self.areas, self.tf, self.t, self.n_max, self.nd,
+                                      pattern.data_ptr(), self.counts.data_ptr(), self.points.data_ptr(),
+                                      self.responses.data_ptr(), self.descriptors.data_ptr(), self._ws.data_ptr(),
+                                      self._ws.numel(), stream_handle))
 
 
 LORB_KINDS = ["clear", "detect", "select", "rank", "brief"]

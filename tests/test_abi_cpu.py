@@ -233,6 +233,30 @@ def test_lorb_validates_on_host():
                            None) == E["E_WORKSPACE"]
 
 
+def test_lorb_multi_validates_on_host():
+    lib = P.lib()
+    fake = 0x10000
+    imgs = (S.StitchImage * 2)(S.StitchImage(fake, 640, 480, 3, S.U8, S.HWC, 1920, 0),
+                               S.StitchImage(fake, 320, 240, 3, S.U8, S.HWC, 960, 0))
+    fw, fh = (ctypes.c_int32 * 2)(640, 320), (ctypes.c_int32 * 2)(480, 240)
+    areas = (ctypes.c_int32 * 12)(0, 0, 300, 200, 100, 50, 80, 80, 10, 10, 100, 100)
+    mpf = (ctypes.c_int32 * 2)(2, 1)
+    outs = [fake] * 4
+
+    def call(n=2, im=imgs, m=mpf, ar=areas):
+        return lib.stitch_lorb_multi(n, im, m, ar, 20, 0, 500, 256, fake, *outs, fake, 1 << 30, None)
+
+    assert call(im=None) == E["E_NULL"] and call(m=None) == E["E_NULL"]
+    assert call(n=0) == E["E_SHAPE"] and call(n=17) == E["E_SHAPE"]
+    assert call(m=(ctypes.c_int32 * 2)(2, -1)) == E["E_SHAPE"]
+    assert call(m=(ctypes.c_int32 * 2)(0, 0)) == E["E_SHAPE"]              # no area at all
+    # 24 bytes per scanned sample: 283 x 183 and 80 x 80 in the first frame, 93 x 93 in the second
+    need = lib.stitch_lorb_multi_workspace_bytes(2, fw, fh, mpf, areas)
+    base = 24 * (283 * 183 + 80 * 80 + 93 * 93)
+    assert base <= need < base + 4096
+    assert lib.stitch_lorb_multi_workspace_bytes(2, fw, fh, (ctypes.c_int32 * 2)(0, 0), areas) == 0
+
+
 def test_registration_calls_validate_on_host():
     lib = P.lib()
     fake = 0x10000

@@ -153,3 +153,40 @@ def test_launch_timing_and_per_camera_streams():
     for i, lb in enumerate(lorbs):
         k = int(lb.counts[0])
         assert torch.equal(lb.points[0, :k].cpu(), want[i][0][0])
+
+
+def test_one_call_for_several_frames_equals_one_call_per_frame():
+    """stitch_lorb_multi over the four 1920x1080 cameras (six areas) and over frames of two
+    sizes gives exactly the per-frame results; the per-frame results are the oracle's."""
+    rig = wl.rig_c2()
+    frames = [f.cuda() for f in wl.render_rig_frames(rig)]
+    areas = wl.overlap_areas(rig)
+    pat = torch.from_numpy(wl.brief_pattern(256)).cuda()
+    ls = P.LorbSet(rig.frame_sizes, areas, n_max=400)
+    ls.run_raw(frames, pat, torch.cuda.current_stream().cuda_stream)
+    z = 0
+    for cam in range(rig.n):
+        one = P.Lorb(*rig.frame_sizes[cam], areas[cam], n_max=400)
+        got = one.run(frames[cam], pat)
+        for k, (pts, resp, desc) in enumerate(got):
+            n = int(ls.counts[z])
+            assert n == len(pts)
+            assert torch.equal(ls.points[z, :n].cpu(), pts) and torch.equal(ls.responses[z, :n].cpu(), resp)
+            assert torch.equal(ls.descriptors[z, :n].cpu(), desc)
+            z += 1
+    assert z == ls.m == 6
+    # two frame sizes in one call, against the oracle
+    small = wl.render_rig_frames(wl.rig_c1())[0]
+    big = wl.render_rig_frames(rig)[2]
+    sets = [[(100, 60, 200, 150)], [(1500, 400, 180, 120), (40, 900, 100, 200)]]
+    ls2 = P.LorbSet([(640, 480), (1920, 1080)], sets, n_max=120)
+    ls2.run_raw([small.cuda(), big.cuda()], pat, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    z = 0
+    for fr, ar in ((small, sets[0]), (big, sets[1])):
+        want = lo.lorb(fr.numpy(), ar, 20, 0, 120, wl.brief_pattern(256))
+        for wp, wd in want:
+            n = int(ls2.counts[z])
+            assert ls2.points[z, :n].cpu().tolist() == [[x, y] for x, y, _ in wp]
+            assert np.array_equal(ls2.descriptors[z, :n].cpu().numpy().view(np.uint32), wd.reshape(n, -1))
+            z += 1
