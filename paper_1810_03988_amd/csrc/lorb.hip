@@ -16,8 +16,9 @@
 //
 // Five launches per call, each covering every area of every frame of the call:
 //   k_lorb_clear    zero the areas' survivor counts
-//   k_lorb_detect   64x16 tiles: gray tile with a 4-sample halo, gradient products and the
-//                   separable window in LDS, the FAST test and R on the tile plus a 1-sample
+//   k_lorb_detect   64x16 tiles: gray tile with a 4-sample halo in LDS, the horizontal pass
+//                   of the window over the gradient products (formed on the fly) in LDS,
+//                   the vertical pass, the FAST test and R on the tile plus a 1-sample
 //                   ring, suppression from LDS; survivors are appended to the area's list
 //                   (one atomic per block; list order is arbitrary)
 //   k_lorb_select   one block per area: a histogram of the survivors over a monotone bucket
@@ -51,7 +52,7 @@ constexpr int kMargin = 17;
 constexpr int kMaxAreas = 64;
 constexpr int kTX = 64, kTY = 16;                       // outputs per tile
 constexpr int kGW = kTX + 8, kGH = kTY + 8;             // gray: tile + 4 each side (72 x 24)
-constexpr int kPW = kTX + 6, kPH = kTY + 6;             // gradient products: tile + 3 (70 x 22)
+constexpr int kPH = kTY + 6;                            // gradient-product rows: tile + 3 (22)
 constexpr int kHW = kTX + 2;                            // horizontal pass: tile + 1 (66 x 22)
 constexpr int kRW = kTX + 2, kRH = kTY + 2;             // responses: tile + 1 (66 x 18)
 constexpr int kBins = 4096;                             // response histogram per area
@@ -132,10 +133,7 @@ __global__ void __launch_bounds__(256) k_lorb_detect(const AreaTable T, int tf, 
   __shared__ int sWave[4];
   __shared__ int sBase;
   __shared__ int sH[3][kPH][kHW];
-  __shared__ union {
-    int p[3][kPH][kPW];           // gradient products (dead once sH is formed)
-    int64_t r[kRH][kRW];          // responses, kNone where no candidate
-  } u;
+  __shared__ int64_t sR[kRH][kRW];                   // responses, kNone where no candidate
   const int tid = threadIdx.x;
   const int b = blockIdx.x;
   int z = 0;
@@ -162,21 +160,22 @@ __global__ void __launch_bounds__(256) k_lorb_detect(const AreaTable T, int tf, 
     }
   }
   __syncthreads();
-  // gradient products on columns ox-3 .. ox+66, rows oy-3 .. oy+18
-  for (int e = tid; e < kPH * kPW; e += 256) {
-    const int r = e / kPW, c = e - r * kPW;
-    const int ix = sG[r + 1][c + 2] - sG[r + 1][c], iy = sG[r + 2][c + 1] - sG[r][c + 1];
-    u.p[0][r][c] = ix * ix;
-    u.p[1][r][c] = iy * iy;
-    u.p[2][r][c] = ix * iy;
-  }
-  __syncthreads();
-  // binomial window [1 4 6 4 1] horizontally: columns ox-1 .. ox+64
-  for (int e = tid; e < 3 * kPH * kHW; e += 256) {
-    const int q = e / (kPH * kHW), rem = e - q * (kPH * kHW);
-    const int r = rem / kHW, c = rem - r * kHW;
-    const int* p = &u.p[q][r][c];
-    sH[q][r][c] = (p[0] + p[4]) + 4 * (p[1] + p[3]) + 6 * p[2];
+  // gradient products (on columns ox-3 .. ox+66, rows oy-3 .. oy+18) and the binomial
+  // window [1 4 6 4 1] horizontally (columns ox-1 .. ox+64): each output forms the gradients
+  // of its five taps from the gray levels and weights their three products
+  for (int e = tid; e < kPH * kHW; e += 256) {
+    const int r = e / kHW, c = e - r * kHW;
+    int pxx[5], pyy[5], pxy[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {                  // product column c + i (gray column c + i + 1)
+      const int ix = sG[r + 1][c + i + 2] - sG[r + 1][c + i], iy = sG[r + 2][c + i + 1] - sG[r][c + i + 1];
+      pxx[i] = ix * ix;
+      pyy[i] = iy * iy;
+      pxy[i] = ix * iy;
+    }
+    sH[0][r][c] = (pxx[0] + pxx[4]) + 4 * (pxx[1] + pxx[3]) + 6 * pxx[2];
+    sH[1][r][c] = (pyy[0] + pyy[4]) + 4 * (pyy[1] + pyy[3]) + 6 * pyy[2];
+    sH[2][r][c] = (pxy[0] + pxy[4]) + 4 * (pxy[1] + pxy[3]) + 6 * pxy[2];
   }
   __syncthreads();
   // vertically, the response and the segment test on the tile and a 1-sample ring
@@ -221,11 +220,10 @@ __global__ void __launch_bounds__(256) k_lorb_detect(const AreaTable T, int tf, 
     }
     resp[k] = out;
   }
-  __syncthreads();                                   // sH and u.p reads done
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     const int e = tid + 256 * k;
-    if (e < kRH * kRW) u.r[e / kRW][e % kRW] = resp[k];
+    if (e < kRH * kRW) sR[e / kRW][e % kRW] = resp[k];
   }
   __syncthreads();
   // suppression on the tile: a candidate survives when every neighbouring candidate has a
@@ -239,7 +237,7 @@ __global__ void __launch_bounds__(256) k_lorb_detect(const AreaTable T, int tf, 
   for (int k = 0; k < kPer; ++k) {
     const int e = tid + 256 * k;
     const int r = e / kTX, c = e - r * kTX;
-    const int64_t R = u.r[r + 1][c + 1];
+    const int64_t R = sR[r + 1][c + 1];
     bool keep = R != kNone;
     if (keep) {
 #pragma unroll
@@ -247,7 +245,7 @@ __global__ void __launch_bounds__(256) k_lorb_detect(const AreaTable T, int tf, 
 #pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
           if (!dx && !dy) continue;
-          const int64_t q = u.r[r + 1 + dy][c + 1 + dx];
+          const int64_t q = sR[r + 1 + dy][c + 1 + dx];
           const bool earlier = dy < 0 || (dy == 0 && dx < 0);
           if (q != kNone && (q > R || (q == R && earlier))) keep = false;
         }
