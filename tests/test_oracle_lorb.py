@@ -112,3 +112,20 @@ def test_lorb_output_shapes_and_margin():
     # an area past the frame clips to nothing and yields an empty, well-shaped result
     (pts, desc), = lo.lorb(frame, [(150, 10, 40, 40)], 20, 0, 25, pat)
     assert pts == [] and desc.shape == (0, 16)
+
+
+def test_equal_responses_go_to_the_first_in_raster_order():
+    """R23/R24 tie rules on hand-made candidates: of two adjacent candidates with equal R the
+    earlier in raster order survives (also across a row boundary), and the cut at n takes
+    equal responses in raster order."""
+    w = 100
+    cand = {(10, 5): 7, (11, 5): 7,            # same row: (10, 5) first
+            (20, 8): 9, (19, 9): 9,            # (20, 8) is earlier than (19, 9) though further right
+            (40, 2): 5, (60, 2): 5, (50, 1): 5, (30, 3): 5}
+    keep = {(x, y) for x, y, _ in lo.suppress(cand, w)}
+    assert (10, 5) in keep and (11, 5) not in keep
+    assert (20, 8) in keep and (19, 9) not in keep
+    sel = lo.select(lo.suppress(cand, w), 3, w)
+    assert [(x, y) for x, y, _ in sel] == [(20, 8), (10, 5), (50, 1)]   # R 9, 7, then the first R 5
+    sel = lo.select(lo.suppress(cand, w), 6, w)
+    assert [(x, y) for x, y, _ in sel][2:] == [(50, 1), (40, 2), (60, 2), (30, 3)]

@@ -178,3 +178,18 @@ def test_prosac_recovers_the_map_and_rejects_outliers():
     # too few matches: no hypothesis
     Hz, fz, cz, bz = ro.prosac(pa[:3], pb, np.arange(3), dist[:3], us, 200000.0, 2.0)
     assert bz == -1 and not fz.any() and np.all(Hz == 0)
+
+
+def test_quality_order_and_match_ties_follow_the_lower_index():
+    """R30/R31 tie rules: equal distances order queries by index; a query whose two nearest
+    references are at equal distance takes the lower reference index."""
+    order = ro.quality_order(np.array([3, -1, 0, 2, 5]), np.array([4, -1, 2, 4, 2]))
+    assert order == [2, 4, 0, 3]
+    rng = np.random.default_rng(8)
+    a = rng.integers(-1, 2, (1, 64))
+    b = np.repeat(a, 3, axis=0)
+    b[0, :5] = -b[0, :5] + (b[0, :5] == 0)      # a different reference, farther away
+    b[1, 0] = 1 if a[0, 0] != 1 else 0           # two references one step away
+    b[2, 0] = b[1, 0]
+    idx, d = ro.lsh_match(_pack(a), _pack(b), np.zeros((1, 0), dtype=np.int64), 64)
+    assert idx[0] == 1 and d[0] == ro.distance(_pack(a)[0], _pack(b)[1])
