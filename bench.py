@@ -491,6 +491,27 @@ def time_lorb(rig, frames, steps, warmup, n_max=500, nd=256):
         return e0.elapsed_time(e1) / steps
 
     ms_set = timed_set()
+    # the same call captured once per frame set of the cycle and replayed from HIP graphs
+    graphs = []
+    side = torch.cuda.Stream()
+    side.wait_stream(main)
+    for t in range(min(len(frames), warmup + steps)):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            lset.run_raw([frames[t][i] for i in cams], pattern, side.cuda_stream)
+        graphs.append(g)
+    torch.cuda.synchronize()
+    for t in range(warmup):
+        graphs[t % len(graphs)].replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(main)
+    for t in range(steps):
+        graphs[t % len(graphs)].replay()
+    e1.record(main)
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1) / steps
+    del graphs
     S.lorb_set_timing(True)
     ms_events = timed_set()
     tim = S.lorb_read_timing()
@@ -508,7 +529,7 @@ def time_lorb(rig, frames, steps, warmup, n_max=500, nd=256):
     kd["alg_bytes_per_launch"] = int(det_bytes)
     kd["achieved_GBs"] = round(det_bytes / (kd["avg_us"] * 1e-6) / 1e9, 1)
     return {"ms_one_stream": ms_one, "ms_per_camera_streams": ms_multi, "ms_with_launch_events": ms_events,
-            "ms_one_call": ms_set,
+            "ms_one_call": ms_set, "ms_graph": ms_graph,
             "px": sum(px.values()), "areas": areas, "counts": counts, "kernels": kernels}
 
 
@@ -851,12 +872,14 @@ def main():
                 "ms_per_frame_set": round(lms, 4), "frame_sets_per_s": round(1e3 / lms, 1),
                 "area_Mpx_s": round(lpx / (lms / 1e3) / 1e6, 1), "area_px_per_frame_set": lpx,
                 "ms_per_frame_set_with_launch_events": round(L["ms_with_launch_events"], 4),
+                "ms_per_frame_set_graph_replay": round(L["ms_graph"], 4),
+                "area_Mpx_s_graph_replay": round(lpx / (L["ms_graph"] / 1e3) / 1e6, 1),
                 "ms_per_frame_set_call_per_camera": round(L["ms_one_stream"], 4),
                 "ms_per_frame_set_call_per_camera_own_streams": round(L["ms_per_camera_streams"], 4),
                 "how": "L-ORB (Alg. 1-2) of every camera in its overlap areas, tf 20, t 0, 500 points, "
                        "256 pairs; frames in HBM; all cameras in one stitch_lorb_multi call (the "
-                       "form's headline and kernel table), and one stitch_lorb per camera on one "
-                       "stream or on a stream each",
+                       "form's headline and kernel table), the same call replayed from HIP graphs, "
+                       "and one stitch_lorb per camera on one stream or on a stream each",
                 "kernels": L["kernels"],
                 "roofline": {"bound": "hbm", "kernel": "detect", "achieved": kd["achieved_GBs"],
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",

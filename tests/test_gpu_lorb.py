@@ -190,3 +190,30 @@ def test_one_call_for_several_frames_equals_one_call_per_frame():
             assert ls2.points[z, :n].cpu().tolist() == [[x, y] for x, y, _ in wp]
             assert np.array_equal(ls2.descriptors[z, :n].cpu().numpy().view(np.uint32), wd.reshape(n, -1))
             z += 1
+
+
+def test_frame_set_call_replays_from_a_hip_graph():
+    """stitch_lorb_multi allocates, sets and synchronises nothing, so the call can be captured
+    into a graph: three replays, with eager work (zeroed outputs) and a synchronisation
+    between them, each equal to the eager call."""
+    rig = wl.rig_c2()
+    frames = [f.cuda() for f in wl.render_rig_frames(rig)]
+    areas = wl.overlap_areas(rig)
+    pat = torch.from_numpy(wl.brief_pattern(256)).cuda()
+    ls = P.LorbSet(rig.frame_sizes, areas, n_max=300)
+    ls.run_raw(frames, pat, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    want = [t.clone() for t in (ls.counts, ls.points, ls.responses, ls.descriptors)]
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=side):
+        ls.run_raw(frames, pat, torch.cuda.current_stream().cuda_stream)
+    for _ in range(3):
+        for t in (ls.counts, ls.points, ls.responses, ls.descriptors):
+            t.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for got, ref in zip((ls.counts, ls.points, ls.responses, ls.descriptors), want):
+            assert torch.equal(got, ref)
