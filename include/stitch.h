@@ -452,14 +452,15 @@ stitch_status stitch_lsh_match(int32_t nd, const uint32_t* desc_a, const int32_t
  *     and n < M, then samples the n-th match and 3 draws from the top n-1 unless T'_n < t
  *     (then 4 draws from the top n);
  *   - draws from the caller's uniforms: draw k of a range of R takes
- *     r = min(floor(u_k (R - k)), R - k - 1) and the r-th index not drawn before;
+ *     r = min(floor(u_k (R - k)), R - k - 1) and the r-th index not drawn before (values
+ *     outside [0, 1) are clamped into the range);
  *   - model: 4-point DLT with h33 = 1 (FP64); a sample with three collinear points in
  *     either frame is skipped; inliers: w > 0 and squared reprojection error <= eps^2;
  *   - a fixed budget of nhyp hypotheses; the best has the most inliers (ties: the earlier);
  *     H is the least-squares DLT over its inliers on Hartley-normalised coordinates (5 or
  *     more inliers), else the best's own model; no valid hypothesis: H = 0, 0 inliers.
  * pts_a: DEVICE int32 [cap_a][2], pts_b: DEVICE int32 [cap_b][2] (stitch_lorb's points);
- * match, dist, count_a: as stitch_lsh_match wrote them.  uniforms: DEVICE double
+ * match, dist, count_a: as stitch_lsh_match wrote them (any distances below INT32_MAX).  uniforms: DEVICE double
  * [nhyp][4] in [0, 1) (the random draws are an input); nhyp 1..65536.  T_N, eps > 0.
  * Outputs (DEVICE): H[9] double row-major (frame A -> frame B, h33 = 1), inliers (int32),
  * inlier_mask uint8[cap_a] (1 where query i's match is an inlier of the best hypothesis),

@@ -29,8 +29,9 @@ none of their parameters, the distance, the match rule or the stopping rule.  Re
       the sample is m draws from the top n, else the n-th match and m - 1 draws from the top
       n - 1.
   R33 the draws of hypothesis t come from four input uniforms u in [0, 1): draw k takes
-      r = min(floor(u_k (R - k)), R - k - 1) in FP64 (R the size of the range) and picks the
-      r-th index of the range not drawn before, in increasing order.
+      r = min(floor(u_k (R - k)), R - k - 1) in FP64 (R the size of the range; clamped at 0
+      too, for inputs outside [0, 1)) and picks the r-th index of the range not drawn before,
+      in increasing order.
   R34 model: the direct linear transform with h33 = 1 through the four correspondences (an
       8 x 8 linear solve in FP64).  A sample in which three points of either image are
       collinear (integer cross product 0; the points are integer pixel positions) is
@@ -138,7 +139,7 @@ def draw(us, R: int, count: int):
     """R33: `count` distinct indices of range(R) from the uniforms us."""
     chosen = []
     for k in range(count):
-        r = min(int(math.floor(float(us[k]) * float(R - k))), R - k - 1)
+        r = max(0, min(int(math.floor(float(us[k]) * float(R - k))), R - k - 1))
         # the r-th index of range(R) not chosen before, in increasing order
         free = [x for x in range(R) if x not in chosen]
         chosen.append(free[r])

@@ -129,41 +129,37 @@ __global__ void __launch_bounds__(1024) k_prosac_prepare(const int32_t* __restri
                                                          int64_t* __restrict__ tp) {
   constexpr int kStage = 16384;                      // ranking keys staged in LDS up to here
   __shared__ int sM;
-  __shared__ __attribute__((aligned(16))) int16_t sKey[kStage];
+  __shared__ __attribute__((aligned(16))) int32_t sKey[kStage];
   const int tid = threadIdx.x;
   const int na = min(*count_a, cap_a);
-  // ranking key of query j: its distance (0 .. 1024) when it has a match, else 0x7FFF
-  // (which precedes nothing and equals no valid key)
+  // ranking key of query j: its distance when it has a match (below INT32_MAX), else
+  // INT32_MAX, which precedes nothing and equals no valid key
   auto key = [&](int j) -> int {
     const int mj = match[j];
-    return (mj >= 0 && mj < cap_b) ? dist[j] : 0x7FFF;
+    return (mj >= 0 && mj < cap_b) ? min(dist[j], INT32_MAX - 1) : INT32_MAX;
   };
   const bool staged = na <= kStage;
-  const int npad = (na + 7) & ~7;
+  const int npad = (na + 3) & ~3;
   if (tid == 0) sM = 0;
   if (staged)
-    for (int j = tid; j < npad; j += 1024) sKey[j] = (int16_t)(j < na ? key(j) : 0x7FFF);
+    for (int j = tid; j < npad; j += 1024) sKey[j] = j < na ? key(j) : INT32_MAX;
   __syncthreads();
   // number of valid matches
   int local = 0;
-  for (int i = tid; i < na; i += 1024) local += key(i) != 0x7FFF;
+  for (int i = tid; i < na; i += 1024) local += key(i) != INT32_MAX;
   atomicAdd(&sM, local);
   __syncthreads();
   const int M = sM;
   // rank of match i: the valid matches ordered before it by (distance, query index)
   for (int i = tid; i < na; i += 1024) {
     const int ki = key(i);
-    if (ki == 0x7FFF) continue;
+    if (ki == INT32_MAX) continue;
     int r = 0;
     if (staged) {
-      for (int j = 0; j < npad; j += 8) {
+      for (int j = 0; j < npad; j += 4) {
         const int4 v = *reinterpret_cast<const int4*>(&sKey[j]);
-        const int w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int kj = (int)(int16_t)((uint32_t)w[q >> 1] >> (16 * (q & 1)));
-          r += kj < ki || (kj == ki && j + q < i);
-        }
+        r += (v.x < ki || (v.x == ki && j < i)) + (v.y < ki || (v.y == ki && j + 1 < i)) +
+             (v.z < ki || (v.z == ki && j + 2 < i)) + (v.w < ki || (v.w == ki && j + 3 < i));
       }
     } else {
       for (int j = 0; j < na; ++j) {
@@ -323,8 +319,9 @@ __global__ void __launch_bounds__(256) k_prosac_hyp(const int32_t* __restrict__ 
     int idx[4];
     const int R = nth ? n - 1 : n, draws = nth ? 3 : 4;
     for (int k = 0; k < draws; ++k) {
-      int r = (int)floor(u[k] * (double)(R - k));
-      r = min(r, R - k - 1);
+      // clamped into the range (uniforms outside [0, 1), even NaN, cannot index outside it)
+      const double f = floor(u[k] * (double)(R - k));
+      const int r = f >= 0.0 ? (int)fmin(f, (double)(R - k - 1)) : 0;
       idx[k] = nth_free(r, idx, k);
     }
     if (nth) idx[3] = n - 1;

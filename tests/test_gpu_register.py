@@ -203,3 +203,21 @@ def test_registration_feeds_the_gradient_refinement():
           log[0][0], "->", log[20][0])
     assert log[20][0] <= 1.02 * log[0][0]
     assert log[20][1] < log[0][1] + 0.5
+
+
+def test_prosac_with_uniforms_outside_the_unit_interval_and_large_distances():
+    """Uniforms below 0 and at or above 1 are clamped into the draw's range on both sides;
+    distances past 16 bits order the matches like small ones; NaN uniforms stay in range."""
+    H = _H()
+    rng = np.random.default_rng(12)
+    pa = rng.integers(0, 600, (90, 2))
+    pb = np.array([np.rint(_apply(H, p)) for p in pa]).astype(np.int64)
+    pb[60:] = rng.integers(0, 800, (30, 2))
+    dist = rng.integers(40000, 1 << 30, 90)
+    us = np.random.default_rng(13).random((256, 4)) * 1.6 - 0.3
+    got = _check_prosac(pa, pb, np.arange(90), dist, 90, us)
+    assert got["inliers"] >= 55
+    nan = np.full((64, 4), np.nan)
+    pr = P.Prosac(90, 90, 64, 200000.0, 2.0)
+    out = pr.run(_dev(pa), _dev(pb), _dev(np.arange(90)), _dev(dist), _dev([90]), _dev(nan, torch.float64))
+    assert 0 <= out["inliers"] <= 90 and (out["hyp_counts"] >= 0).all()

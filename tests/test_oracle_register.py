@@ -193,3 +193,7 @@ def test_quality_order_and_match_ties_follow_the_lower_index():
     b[2, 0] = b[1, 0]
     idx, d = ro.lsh_match(_pack(a), _pack(b), np.zeros((1, 0), dtype=np.int64), 64)
     assert idx[0] == 1 and d[0] == ro.distance(_pack(a)[0], _pack(b)[1])
+
+
+def test_draws_clamp_uniforms_outside_the_unit_interval():
+    assert ro.draw([-0.5, 2.0, 0.0, 0.0], 10, 2) == [0, 9]
