@@ -768,8 +768,12 @@ class Matcher:
         """desc_*: (cap, 2 nd/32) int32/uint32 device tensors, count_*: one-element int32
         device tensors.  Returns (match, dist) as host tensors."""
         for d, cap in ((desc_a, self.cap_a), (desc_b, self.cap_b)):
-            if d.shape[0] < cap or d.shape[-1] != 2 * self.nd // 32 or not d.is_contiguous():
-                raise ValueError("descriptor rows must be contiguous (cap, 2 nd/32)")
+            if d.dtype != torch.int32 or d.dim() != 2 or d.shape[0] < cap or d.shape[1] != 2 * self.nd // 32 \
+                    or not d.is_contiguous() or not d.is_cuda:
+                raise ValueError("descriptors must be contiguous int32 device tensors of (cap, 2 nd/32)")
+        for c in (count_a, count_b):
+            if c.dtype != torch.int32 or not c.is_cuda or c.numel() < 1:
+                raise ValueError("counts must be int32 device tensors")
         self.run_raw(desc_a, count_a, desc_b, count_b, _stream(stream))
         torch.cuda.synchronize()
         return self.match.cpu(), self.dist.cpu()
@@ -804,6 +808,10 @@ class Prosac:
         int32 device, uniforms: (nhyp, 4) float64 device in [0, 1)."""
         if uniforms.dtype != torch.float64 or tuple(uniforms.shape) != (self.nhyp, 4) or not uniforms.is_contiguous():
             raise ValueError(f"uniforms must be a contiguous ({self.nhyp}, 4) float64 tensor")
+        for t, n, name in ((pts_a, 2 * self.cap_a, "pts_a"), (pts_b, 2 * self.cap_b, "pts_b"),
+                           (match, self.cap_a, "match"), (dist, self.cap_a, "dist"), (count_a, 1, "count_a")):
+            if t.dtype != torch.int32 or not t.is_contiguous() or t.numel() < n or not t.is_cuda:
+                raise ValueError(f"{name} must be a contiguous int32 device tensor of at least {n} elements")
         self.run_raw(pts_a, pts_b, match, dist, count_a, uniforms, _stream(stream))
         torch.cuda.synchronize()
         return {"H": self.H.cpu().numpy().reshape(3, 3), "inliers": int(self.inliers[0]),
