@@ -150,6 +150,19 @@ __global__ void __launch_bounds__(1024) k_prosac_prepare(const int32_t* __restri
   atomicAdd(&sM, local);
   __syncthreads();
   const int M = sM;
+  // the growth function, sequentially in FP64 in the order of its definition, on the last
+  // wave's last lane while the others rank the matches
+  if (tid == 1023 && M >= kSample) {
+    double T = T_N;
+    for (int i = 0; i < kSample; ++i) T = T * (double)(kSample - i) / (double)(M - i);
+    tp[kSample] = 1;
+    for (int n = kSample; n < M; ++n) {
+      const double Tn = T * (double)(n + 1) / (double)(n + 1 - kSample);
+      tp[n + 1] = tp[n] + (int64_t)ceil(Tn - T);
+      T = Tn;
+    }
+  }
+  if (tid == 0) misc[0] = M;
   // rank of match i: the valid matches ordered before it by (distance, query index)
   for (int i = tid; i < na; i += 1024) {
     const int ki = key(i);
@@ -171,20 +184,6 @@ __global__ void __launch_bounds__(1024) k_prosac_prepare(const int32_t* __restri
     qa[r] = make_int2(pts_a[2 * i], pts_a[2 * i + 1]);
     qb[r] = make_int2(pts_b[2 * mi], pts_b[2 * mi + 1]);
     qi[r] = i;
-  }
-  // the growth function, sequentially in FP64 in the order of its definition
-  if (tid == 0) {
-    misc[0] = M;
-    if (M >= kSample) {
-      double T = T_N;
-      for (int i = 0; i < kSample; ++i) T = T * (double)(kSample - i) / (double)(M - i);
-      tp[kSample] = 1;
-      for (int n = kSample; n < M; ++n) {
-        const double Tn = T * (double)(n + 1) / (double)(n + 1 - kSample);
-        tp[n + 1] = tp[n] + (int64_t)ceil(Tn - T);
-        T = Tn;
-      }
-    }
   }
 }
 
@@ -363,23 +362,46 @@ __global__ void __launch_bounds__(256) k_prosac_hyp(const int32_t* __restrict__ 
   if (lane < 9) hyp_h[(int64_t)t * 9 + lane] = H[lane];
 }
 
-// block-wide sum of v (1024 threads) into every thread; sRed holds 16 partials
-__device__ double block_sum(double v, double* sRed) {
+__device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// block-wide sums (kWaves waves) of up to five values into every thread; sRed holds
+// kWaves x 5 partials, added in a fixed order
+template <int kWaves>
+__device__ __forceinline__ void block_sums(double* sRed, double& a, double& b, double& c, double& d, double& e) {
   const int w = threadIdx.x >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  d = wave_sum(d);
+  e = wave_sum(e);
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) sRed[w] = v;
+  if ((threadIdx.x & 63) == 0) {
+    sRed[w * 5 + 0] = a;
+    sRed[w * 5 + 1] = b;
+    sRed[w * 5 + 2] = c;
+    sRed[w * 5 + 3] = d;
+    sRed[w * 5 + 4] = e;
+  }
   __syncthreads();
-  double s = 0.0;
-  for (int k = 0; k < 16; ++k) s += sRed[k];
-  return s;
+  a = b = c = d = e = 0.0;
+  for (int k = 0; k < kWaves; ++k) {
+    a += sRed[k * 5 + 0];
+    b += sRed[k * 5 + 1];
+    c += sRed[k * 5 + 2];
+    d += sRed[k * 5 + 3];
+    e += sRed[k * 5 + 4];
+  }
 }
 
 
-constexpr int kParts = 14;                            // 72 x 14 = 1008 of the 1024 threads
+constexpr int kFinalThreads = 512, kFinalWaves = kFinalThreads / 64;
+constexpr int kParts = 7;                             // 72 x 7 = 504 of the 512 threads
 
-// one block of 1024 threads: the best hypothesis, its inliers, the least-squares refit
-__global__ void __launch_bounds__(1024) k_prosac_final(const int32_t* __restrict__ misc,
+// one block of kFinalThreads: the best hypothesis, its inliers, the least-squares refit
+__global__ void __launch_bounds__(kFinalThreads) k_prosac_final(const int32_t* __restrict__ misc,
                                                        const int2* __restrict__ qa, const int2* __restrict__ qb,
                                                        const int32_t* __restrict__ qi, int cap_a, int nhyp,
                                                        const double* __restrict__ hyp_h,
@@ -388,19 +410,19 @@ __global__ void __launch_bounds__(1024) k_prosac_final(const int32_t* __restrict
                                                        double* __restrict__ H_out, int32_t* __restrict__ inliers,
                                                        uint8_t* __restrict__ mask) {
   __shared__ unsigned long long sBest;
-  __shared__ double sRed[16];
+  __shared__ double sRed[kFinalWaves * 5];
   __shared__ double sPart[kParts][72];
   __shared__ double sH[9];
   __shared__ uint32_t sFlag[kMaxPoints / 32];
   const int tid = threadIdx.x;
   const int M = misc[0];
   if (tid == 0) sBest = 0ull;
-  for (int i = tid; i < cap_a; i += 1024) mask[i] = 0;
-  for (int i = tid; i < (M + 31) / 32; i += 1024) sFlag[i] = 0;
+  for (int i = tid; i < cap_a; i += kFinalThreads) mask[i] = 0;
+  for (int i = tid; i < (M + 31) / 32; i += kFinalThreads) sFlag[i] = 0;
   __syncthreads();
   // best: most inliers, then the earliest hypothesis; key (count + 1) << 32 | (2^32-1 - t)
   unsigned long long mine = 0ull;
-  for (int t = tid; t < nhyp; t += 1024)
+  for (int t = tid; t < nhyp; t += kFinalThreads)
     if (hyp_ok[t]) {
       const unsigned long long k = ((unsigned long long)(hyp_counts[t] + 1) << 32) | (0xFFFFFFFFull - (unsigned)t);
       mine = k > mine ? k : mine;
@@ -420,7 +442,7 @@ __global__ void __launch_bounds__(1024) k_prosac_final(const int32_t* __restrict
   for (int c = 0; c < 9; ++c) Hb[c] = sH[c];
   // inliers of the best model (flags, mask over queries) and the sums for the normalisation
   double sx = 0, sy = 0, su = 0, sv = 0, cn = 0;
-  for (int k = tid; k < M; k += 1024)
+  for (int k = tid; k < M; k += kFinalThreads)
     if (is_inlier(Hb, qa[k], qb[k], eps2)) {
       atomicOr(&sFlag[k >> 5], 1u << (k & 31));
       mask[qi[k]] = 1;
@@ -430,23 +452,25 @@ __global__ void __launch_bounds__(1024) k_prosac_final(const int32_t* __restrict
       sv += qb[k].y;
       cn += 1.0;
     }
-  const double n_in = block_sum(cn, sRed);           // (its barriers also publish sFlag)
+  block_sums<kFinalWaves>(sRed, cn, sx, sy, su, sv);              // (its barriers also publish sFlag)
+  const double n_in = cn;
   if (tid == 0) *inliers = (int)n_in;
   if (n_in < 5.0) {
     if (tid < 9) H_out[tid] = Hb[tid] / Hb[8];
     return;
   }
-  const double cx = block_sum(sx, sRed) / n_in, cy = block_sum(sy, sRed) / n_in;
-  const double cu = block_sum(su, sRed) / n_in, cv = block_sum(sv, sRed) / n_in;
+  const double cx = sx / n_in, cy = sy / n_in, cu = su / n_in, cv = sv / n_in;
   auto flag = [&](int k) { return (sFlag[k >> 5] >> (k & 31)) & 1u; };
   double da = 0, db = 0;
-  for (int k = tid; k < M; k += 1024)
+  for (int k = tid; k < M; k += kFinalThreads)
     if (flag(k)) {
       da += sqrt((qa[k].x - cx) * (qa[k].x - cx) + (qa[k].y - cy) * (qa[k].y - cy));
       db += sqrt((qb[k].x - cu) * (qb[k].x - cu) + (qb[k].y - cv) * (qb[k].y - cv));
     }
-  const double s_a = sqrt(2.0) / (block_sum(da, sRed) / n_in);
-  const double s_b = sqrt(2.0) / (block_sum(db, sRed) / n_in);
+  double z0 = 0.0, z1 = 0.0, z2 = 0.0;
+  block_sums<kFinalWaves>(sRed, da, db, z0, z1, z2);
+  const double s_a = sqrt(2.0) / (da / n_in);
+  const double s_b = sqrt(2.0) / (db / n_in);
   // normal equations of the normalised system: entry c (64 of A^T A, 8 of A^T b) summed by
   // kParts threads over interleaved inliers, then the parts in a fixed order
   if (tid < 72 * kParts) {
@@ -602,7 +626,7 @@ stitch_status stitch_prosac(const int32_t* pts_a, const int32_t* pts_b, int32_t 
                      T_N, misc, qa, qb, qi, tp);
   hipLaunchKernelGGL(k_prosac_hyp, dim3((nhyp + 3) / 4), dim3(256), 0, s, misc, qa, qb, tp, nhyp, uniforms, eps2,
                      hyp_h, hyp_ok, hyp_counts);
-  hipLaunchKernelGGL(k_prosac_final, dim3(1), dim3(1024), 0, s, misc, qa, qb, qi, cap_a, nhyp, hyp_h, hyp_ok,
+  hipLaunchKernelGGL(k_prosac_final, dim3(1), dim3(kFinalThreads), 0, s, misc, qa, qb, qi, cap_a, nhyp, hyp_h, hyp_ok,
                      hyp_counts, eps2, H, inliers, inlier_mask);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "PROSAC launch");
