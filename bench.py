@@ -585,6 +585,24 @@ def time_register(rig, frames, steps, warmup, n_max=500, nd=256, nhyp=1024):
     chain(0)                                        # features and maps of frame set 0
     torch.cuda.synchronize()
     ms_mp = timed(lambda t: match_prosac())
+    # the pairs are independent (own workspaces and outputs): one stream per pair
+    main = torch.cuda.current_stream()
+    pstreams = {i: torch.cuda.Stream() for i in pairs}
+
+    def match_prosac_streams(t):
+        ev0 = torch.cuda.Event()
+        ev0.record(main)
+        for i in pairs:
+            st = pstreams[i]
+            st.wait_event(ev0)
+            pa, da, ca, pb, db, cb = feats(i)
+            matchers[i].run_raw(da, ca, db, cb, st.cuda_stream)
+            prosacs[i].run_raw(pa, pb, matchers[i].match, matchers[i].dist, ca, uni, st.cuda_stream)
+            ev = torch.cuda.Event()
+            ev.record(st)
+            main.wait_event(ev)
+
+    ms_mp_streams = timed(match_prosac_streams)
     res = []
     for i in pairs:
         H = prosacs[i].H.cpu().numpy().reshape(3, 3)
@@ -597,7 +615,8 @@ def time_register(rig, frames, steps, warmup, n_max=500, nd=256, nhyp=1024):
             err = max(err, float(np.hypot(*(a[:2] / a[2] - b[:2] / b[2]))))
         res.append({"pair": [i, i + 1], "matches": int((matchers[i].match >= 0).sum()),
                     "inliers": int(prosacs[i].inliers[0]), "max_corner_error_px": round(err, 3)})
-    return {"ms_chain": ms_chain, "ms_match_prosac": ms_mp, "pairs": res, "nhyp": nhyp,
+    return {"ms_chain": ms_chain, "ms_match_prosac": ms_mp, "ms_match_prosac_streams": ms_mp_streams,
+            "pairs": res, "nhyp": nhyp,
             "features": (feats, pos, uni)}
 
 
@@ -855,6 +874,7 @@ def main():
             forms["register"] = {
                 "ms_per_rig_registration": round(G["ms_chain"], 4),
                 "ms_match_prosac_all_pairs": round(G["ms_match_prosac"], 4),
+                "ms_match_prosac_all_pairs_stream_per_pair": round(G["ms_match_prosac_streams"], 4),
                 "how": "L-ORB of every camera in its overlap areas (one stitch_lorb_multi call), then per "
                        "neighbouring pair multi-probe LSH "
                        "matching (6 tables x 14 bits, distance <= 64) and PROSAC (1024 hypotheses, T_N 2e5, "
