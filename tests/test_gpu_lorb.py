@@ -188,7 +188,7 @@ def test_one_call_for_several_frames_equals_one_call_per_frame():
         for wp, wd in want:
             n = int(ls2.counts[z])
             assert ls2.points[z, :n].cpu().tolist() == [[x, y] for x, y, _ in wp]
-            assert np.array_equal(ls2.descriptors[z, :n].cpu().numpy().view(np.uint32), wd.reshape(n, -1))
+            assert np.array_equal(ls2.descriptors[z, :n].cpu().numpy().view(np.uint32), wd.reshape(n, 16))
             z += 1
 
 
@@ -217,3 +217,32 @@ def test_frame_set_call_replays_from_a_hip_graph():
         torch.cuda.synchronize()
         for got, ref in zip((ls.counts, ls.points, ls.responses, ls.descriptors), want):
             assert torch.equal(got, ref)
+
+
+def test_sixteen_frames_and_sixty_four_areas_in_one_call():
+    """The call's maximum sizes: 16 frames of a few sizes, 4 areas each (64 in all), against
+    the oracle per frame."""
+    rng = np.random.default_rng(21)
+    base = wl.render_rig_frames(wl.rig_c1())[0].numpy()
+    frames, sizes, areas = [], [], []
+    for f in range(16):
+        h, w = int(rng.integers(60, 140)), int(rng.integers(70, 200))
+        y0, x0 = int(rng.integers(0, 480 - h)), int(rng.integers(0, 640 - w))
+        frames.append(np.ascontiguousarray(base[y0:y0 + h, x0:x0 + w]))
+        sizes.append((w, h))
+        areas.append([(int(rng.integers(-5, w // 2)), int(rng.integers(-5, h // 2)), int(rng.integers(0, w)),
+                       int(rng.integers(0, h))) for _ in range(4)])
+    pat = wl.brief_pattern(64, seed=3)
+    ls = P.LorbSet(sizes, areas, n_max=40, nd=64)
+    assert ls.m == 64
+    ls.run_raw([torch.from_numpy(f).cuda() for f in frames], torch.from_numpy(pat).cuda(),
+               torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    z = 0
+    for f, ar in zip(frames, areas):
+        for wp, wd in lo.lorb(f, ar, 20, 0, 40, pat):
+            n = int(ls.counts[z])
+            assert ls.points[z, :n].cpu().tolist() == [[x, y] for x, y, _ in wp], z
+            assert ls.responses[z, :n].cpu().tolist() == [r for _, _, r in wp], z
+            assert np.array_equal(ls.descriptors[z, :n].cpu().numpy().view(np.uint32), wd.reshape(n, 4)), z
+            z += 1

@@ -221,3 +221,31 @@ def test_prosac_with_uniforms_outside_the_unit_interval_and_large_distances():
     pr = P.Prosac(90, 90, 64, 200000.0, 2.0)
     out = pr.run(_dev(pa), _dev(pb), _dev(np.arange(90)), _dev(dist), _dev([90]), _dev(nan, torch.float64))
     assert 0 <= out["inliers"] <= 90 and (out["hyp_counts"] >= 0).all()
+
+
+def test_matching_with_the_most_tables_and_key_bits():
+    rng = np.random.default_rng(31)
+    da, db = _descriptor_sets(rng, 150, 170, 256)
+    pos = rng.integers(0, 256, (16, 24))
+    want_idx, want_d = ro.lsh_match(da, db, pos, 100)
+    m = P.Matcher(150, 170, 256, pos, 100)
+    got_idx, got_d = m.run(_dev(da.view(np.int32)), _dev([150]), _dev(db.view(np.int32)), _dev([170]))
+    assert got_idx.tolist() == want_idx.tolist() and got_d.tolist() == want_d.tolist()
+
+
+def test_the_largest_hypothesis_budget_extends_a_smaller_one():
+    """65536 hypotheses (the maximum): the first 1024 are the same hypotheses as a budget of
+    1024 (the schedule depends on t only, the uniforms are a prefix), so their inlier counts
+    agree and the larger budget's best is at least as good."""
+    H = _H()
+    rng = np.random.default_rng(41)
+    pa = rng.integers(0, 600, (150, 2))
+    pb = np.array([np.rint(_apply(H, p)) for p in pa]).astype(np.int64)
+    pb[70:] = rng.integers(0, 800, (80, 2))
+    dist = rng.integers(0, 100, 150)
+    us = np.random.default_rng(42).random((65536, 4))
+    args = (_dev(pa), _dev(pb), _dev(np.arange(150)), _dev(dist), _dev([150]))
+    small = P.Prosac(150, 150, 1024, 200000.0, 2.0).run(*args, _dev(us[:1024], torch.float64))
+    big = P.Prosac(150, 150, 65536, 200000.0, 2.0).run(*args, _dev(us, torch.float64))
+    assert np.array_equal(big["hyp_counts"][:1024], small["hyp_counts"])
+    assert big["hyp_counts"].max() >= small["hyp_counts"].max() and big["inliers"] >= 60
