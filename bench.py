@@ -38,8 +38,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--frames", type=int, default=30, help="frames per step (the sequence length)")
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"],
-                    help="c3: 64 jobs of 2-6 cameras, one frame each, batched against one by one")
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4"],
+                    help="c3 (default): 64 jobs of 2-6 cameras, one frame set each, batched against one by one; "
+                         "c2/c4: one rig's frame sequence")
     ap.add_argument("--jobs", type=int, default=64, help="jobs of the c3 batch")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16"])
     ap.add_argument("--form", default="batched", choices=["batched", "plain"],
@@ -271,8 +272,18 @@ def workload_name(rig, frames):
             f"{rig.levels} levels, {frames}-frame sequence")
 
 
+_SRC_PX = {}
+
+
 def source_pixels_in(rig, i, roi):
     """Source pixels of camera i whose canvas position lies inside roi (x, y, w, h)."""
+    key = (rig.name, i, tuple(roi))
+    if key not in _SRC_PX:
+        _SRC_PX[key] = _source_pixels_in(rig, i, roi)
+    return _SRC_PX[key]
+
+
+def _source_pixels_in(rig, i, roi):
     (w, h), H = rig.frame_sizes[i], rig.H[i]
     n = 0
     for y0 in range(0, h, 256):
@@ -693,61 +704,206 @@ def time_batched(rig, frames, storage, steps, warmup, tune_cache=None, kernel_ev
     return res, cfg, plans[0], batch, panos
 
 
+def cpu_model() -> str:
+    try:
+        for line in Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def _oracle_strip(unit):
+    """One cpu_baseline unit: the oracle (FP64 numpy, as it stands) on a full-height column
+    strip of a job's canvas, evaluated through the strip's dependency cones (ROI mode).
+    Returns (canvas samples, seconds)."""
+    import oracle
+    rig, frames, x0, x1 = unit
+    t = time.perf_counter()
+    so = oracle.StitchOracle(frames, rig.H, rig.masks(), rig.canvas_w, rig.canvas_h, rig.levels)
+    so.panorama(np.arange(rig.canvas_h), np.arange(x0, x1))
+    return (x1 - x0) * rig.canvas_h, time.perf_counter() - t
+
+
+def c3_cpu_baseline(rigs, frames, single_units=4, strip=256):
+    """The oracle on the batching workload's own jobs: units are full-height strips of
+    `strip` columns centred on each job's first seam.  Timed in one process on the first
+    `single_units` jobs, then over a process pool of every usable core (at most 16, the
+    box's CPU share) on two units per worker.  value = the pool's canvas Mpx/s."""
+    import multiprocessing as mp
+
+    def unit(j):
+        r = rigs[j]
+        c = r.seams[0] if r.seams else r.canvas_w // 2
+        x0 = max(0, min(r.canvas_w - strip, c - strip // 2))
+        return (r, [f.cpu().numpy() for f in frames[j]], x0, min(r.canvas_w, x0 + strip))
+
+    px = dt = 0.0
+    for j in range(min(single_units, len(rigs))):
+        n, t = _oracle_strip(unit(j))
+        px, dt = px + n, dt + t
+    single = px / dt / 1e6
+    workers = max(1, min(len(os.sched_getaffinity(0)), 16))
+    units = [unit(j % len(rigs)) for j in range(2 * workers)]
+    ctx = mp.get_context("spawn")
+    t = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_strip, units, chunksize=1)
+    wall = time.perf_counter() - t
+    ppx = sum(n for n, _ in res)
+    return {"value": round(ppx / wall / 1e6, 5), "unit": "Mpx/s", "cores": workers, "kind": "oracle",
+            "sample": f"full-height {strip}-column strips of the jobs' canvases centred on each job's first seam, "
+                      f"through every level (FP64 numpy oracle in ROI mode): {len(units)} strips of jobs "
+                      f"0-{len(units) - 1} ({ppx / 1e6:.2f} Mpx) over a pool of {workers} processes in "
+                      f"{wall:.1f} s wall (process start included)",
+            "single_process": {"value": round(single, 5), "cores": 1,
+                               "sample": f"strips of jobs 0-{min(single_units, len(rigs)) - 1} "
+                                         f"({px / 1e6:.2f} Mpx) in {dt:.1f} s"},
+            "cpu": cpu_model(), "logical_cpus_visible": os.cpu_count(), "numpy": np.__version__}
+
+
+def time_graph_and_events(batch, bargs, stream, steps, warmup, events=True):
+    """A batch timed as HIP graph replays (one per step) and, separately, launched eagerly
+    with a HIP event after every launch (the per-kernel table)."""
+    sh = stream.cuda_stream
+    out = {}
+    for mode in ["graph"] + (["events"] if events else []):
+        batch.set_timing(mode == "events")
+        for _ in range(warmup):
+            batch.run_raw(bargs, sh)
+        stream.synchronize()
+        batch.set_timing(mode == "events")    # clears the warm-up's events
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(steps):
+            batch.run_raw(bargs, sh)
+        t1.record(stream)
+        stream.synchronize()
+        out[mode] = (t0.elapsed_time(t1) / steps, batch.read_timing() if mode == "events" else {})
+    batch.set_timing(False)
+    return out
+
+
 def run_c3(a):
-    """The batching workload: njobs stitch jobs of uneven camera counts, resolutions and
-    level counts, one frame each; the same plans stitched one by one (one stitch_frame
-    per job, eager launches) and as one batch (one HIP graph replay per step)."""
+    """The batching workload (the largest single-GPU configuration): njobs stitch jobs of
+    2-6 cameras at 640x480 .. 3840x2160 and 4-7 levels, one frame set each.  Forms: the
+    batch (one launch per level over all jobs, captured into a HIP graph, autotuned tiles)
+    in FP16 and FP32 storage, and the same jobs stitched one by one (one stitch_frame per
+    job, eager launches, the planner's default tiles).  value = batched FP16."""
     import paper_1810_03988_amd as P
     import workloads as wl
     rigs = wl.rig_c3_jobs(a.jobs)
     t = time.perf_counter()
     frames = [wl.render_rig_frames(r, 0, "cuda") for r in rigs]
-    plans = [P.Plan(r.frame_sizes, r.H, r.masks(), r.canvas_w, r.canvas_h, r.levels, storage=a.storage)
-             for r in rigs]
-    panos = [torch.empty((r.canvas_h, r.canvas_w, 3), dtype=torch.uint8, device="cuda") for r in rigs]
     torch.cuda.synchronize()
-    print(f"# {len(rigs)} jobs planned and rendered in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
     px = sum(r.canvas_pixels() for r in rigs)
+    in_px = sum(w * h for r in rigs for (w, h) in r.frame_sizes)
+    print(f"# {len(rigs)} jobs rendered in {time.perf_counter() - t:.1f} s: {px / 1e6:.1f} Mpx canvas, "
+          f"{in_px / 1e6:.1f} Mpx input", file=sys.stderr, flush=True)
     stream = torch.cuda.Stream()
     sh = stream.cuda_stream
-    args = [p.frame_args(f, o) for p, f, o in zip(plans, frames, panos)]
+    tune = os.environ.get("STITCH_TUNE_CACHE")
+    forms, ref_panos, tables, configs, plans0 = {}, {}, {}, {}, {}
+    mpx = lambda ms_: round(px / (ms_ / 1e3) / 1e6, 1)
+    for st in ("f16", "f32"):
+        t = time.perf_counter()
+        plans = [P.Plan(r.frame_sizes, r.H, r.masks(), r.canvas_w, r.canvas_h, r.levels, storage=st) for r in rigs]
+        panos = [torch.empty((r.canvas_h, r.canvas_w, 3), dtype=torch.uint8, device="cuda") for r in rigs]
+        one = [torch.empty_like(p) for p in panos]
+        torch.cuda.synchronize()
+        print(f"# {st}: {len(plans)} plans in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+        args = [p.frame_args(f, o) for p, f, o in zip(plans, frames, one)]
 
-    def one_by_one():
-        for p, ar in zip(plans, args):
-            p.frame_raw(ar, sh)
+        def one_by_one():
+            for p, ar in zip(plans, args):
+                p.frame_raw(ar, sh)
 
-    batch = P.Batch(plans)
-    with torch.cuda.stream(stream):
-        cfg = batch.autotune(frames, panos, stream=stream, cache_path=os.environ.get("STITCH_TUNE_CACHE"))
-        bargs = batch.args(frames, panos)
-        res = {}
-        for name, fn in (("one_by_one", one_by_one), ("batched", lambda: batch.run_raw(bargs, sh))):
+        with torch.cuda.stream(stream):
             for _ in range(a.warmup):
-                fn()
+                one_by_one()
             stream.synchronize()
             t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             t0.record(stream)
             for _ in range(a.steps):
-                fn()
+                one_by_one()
             t1.record(stream)
             stream.synchronize()
-            ms = t0.elapsed_time(t1) / a.steps
-            res[name] = {"Mpx_s": round(px / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms, 4)}
-            print(f"# c3 {name}: {ms:.3f} ms/step, {res[name]['Mpx_s']:.0f} Mpx/s", file=sys.stderr, flush=True)
+            ms1 = t0.elapsed_time(t1) / a.steps
+            forms[f"plain_{st}"] = {"Mpx_s": mpx(ms1), "ms_per_step": round(ms1, 4),
+                                    "how": "one stitch_frame per job, eager launches, default tiles"}
+            print(f"# plain_{st}: {ms1:.3f} ms/step, {mpx(ms1):.0f} Mpx/s", file=sys.stderr, flush=True)
+            batch = P.Batch(plans)
+            cfg = batch.autotune(frames, panos, stream=stream, cache_path=tune)
+            bargs = batch.args(frames, panos)
+            res = time_graph_and_events(batch, bargs, stream, a.steps, a.warmup, events=not a.no_kernel_events)
+        torch.cuda.synchronize()
+        same = all(torch.equal(x, y) for x, y in zip(panos, one))
+        ms = res["graph"][0]
+        forms[f"batched_graph_{st}"] = {
+            "Mpx_s": mpx(ms), "ms_per_step": round(ms, 4), "how": "one HIP graph replay per step",
+            "speedup_vs_one_by_one": round(ms1 / ms, 3), "equals_one_by_one_bitwise": same,
+            "tuned": {k: v[:max(r.levels for r in rigs) - 1] for k, v in cfg.items()}}
+        if "events" in res:
+            forms[f"batched_graph_{st}"]["ms_per_step_eager_with_launch_events"] = round(res["events"][0], 4)
+            s_b = 2 if st == "f16" else 4
+            tables[st] = c3_kernel_table(plans, rigs, res["events"][1], a.steps, s_b)
+            forms[f"batched_graph_{st}"]["kernels"] = tables[st]
+        print(f"# batched_graph_{st}: {ms:.3f} ms/step, {mpx(ms):.0f} Mpx/s, x{ms1 / ms:.2f} vs one by one, "
+              f"bitwise equal: {same}", file=sys.stderr, flush=True)
+        for k, v in tables.get(st, {}).items():
+            print(f"#   {k:18s} {v['avg_us']:9.2f} us/launch  {v['alg_bytes_per_launch'] / 1e6:9.2f} MB  "
+                  f"{v['achieved_GBs']:8.1f} GB/s", file=sys.stderr, flush=True)
+        del batch, plans, panos, one, args
+        torch.cuda.empty_cache()
+    head = forms["batched_graph_f16"]
+    roof = None
+    if "f16" in tables:
+        kt = tables["f16"]
+        dom = max(kt, key=lambda k: kt[k]["ms_per_step"])
+        kd = kt[dom]
+        roof = {"bound": "hbm", "achieved": kd["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                "traffic": profiled_traffic("c3", "batched", "f16", dom), "kernel": dom,
+                "alg_bytes": kd["alg_bytes_per_launch"], "avg_us": kd["avg_us"],
+                "step_alg_bytes": int(sum(v["alg_bytes_per_launch"] * v["launches_per_step"] for v in kt.values())),
+                "step_frac": round(sum(v["alg_bytes_per_launch"] * v["launches_per_step"] for v in kt.values())
+                                   / (head["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if a.copy_calibration_mib > 0:
+        copy_calibration(a.copy_calibration_mib)
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = c3_cpu_baseline(rigs, frames)
+        print(f"# cpu oracle: {cpu['value']} Mpx/s on {cpu['cores']} processes, "
+              f"{cpu['single_process']['value']} Mpx/s on one", file=sys.stderr, flush=True)
     cams = [r.n for r in rigs]
     line = {
-        "metric": METRIC, "value": res["batched"]["Mpx_s"], "unit": "Mpx/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": res["batched"]["ms_per_step"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if a.storage == "f32" else "f32 (f16 storage)",
-        "data": "synthetic",
-        "config": {"workload": f"C3: {len(rigs)} stitch jobs, {min(cams)}-{max(cams)} cameras of 640x480 to "
-                   f"3840x2160, {px / 1e6:.1f} Mpx of canvas per step, one frame per job",
-                   "form": "batched: one launch per level over all jobs, one HIP graph replay per step"},
-        "forms": res, "speedup_batched_vs_one_by_one": round(res["one_by_one"]["ms_per_step"] /
-                                                            res["batched"]["ms_per_step"], 3),
-        "tuned_by_level": {k: v[:max(r.levels for r in rigs) - 1] for k, v in cfg.items()}, "device": torch.cuda.get_device_name(0),
+        "metric": METRIC, "value": head["Mpx_s"], "unit": "Mpx/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (f16 storage)", "data": "synthetic",
+        "config": {"workload": f"C3: {len(rigs)} stitch jobs of {min(cams)}-{max(cams)} cameras at 640x480 to "
+                               f"3840x2160, 4-7 levels, {px / 1e6:.1f} Mpx of canvas and {in_px / 1e6:.1f} Mpx "
+                               f"of input per step, one frame set per job",
+                   "form": "batched, FP16 storage: one launch per pyramid level and per blend level over all "
+                           "jobs, captured into one HIP graph (one replay per step), autotuned tiles",
+                   "jobs": len(rigs)},
+        "batched_f16_vs_plain_f32": round(forms["plain_f32"]["ms_per_step"] / head["ms_per_step"], 3),
+        "roofline": roof, "cpu_baseline": cpu, "forms": forms, "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(line), flush=True)
+
+
+def c3_kernel_table(plans, rigs, timing, steps, s):
+    """Batched form on the jobs: per launch kind, average launch time and the algorithmic
+    bytes of the jobs that launch covers (each job's phase bytes from its own regions)."""
+    per_job = [phase_bytes(p, r, s) for p, r in zip(plans, rigs)]
+    table = {}
+    for key, (tot_ms, launches) in sorted(timing.items()):
+        pk = f"{key[0]}{key[1]}"
+        nbytes = sum(b.get(pk, 0) for b in per_job)
+        if nbytes:
+            table[phase_name(key)] = _row(tot_ms, launches, steps, nbytes)
+    return table
 
 
 def _row(tot_ms, launches, steps, nbytes):

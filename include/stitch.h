@@ -216,6 +216,28 @@ stitch_status stitch_plan_set_timing(stitch_plan* plan, int32_t enable);
 stitch_status stitch_plan_read_timing(stitch_plan* plan, double ms[STITCH_TIMING_KINDS],
                                       int32_t launches[STITCH_TIMING_KINDS]);
 
+/* Settings of the plan's pyramid passes (the plain form, stitch_frame), as for batches:
+ * pass k from level k (k = 0: warp + level 0) runs tiles of tile_rows[k] rows (16, 32, 64
+ * or 128) on wg_per_cu[k] persistent workgroups per compute unit (-1: one per tile, 0: as
+ * many as fit, 1, 2).  Until set or tuned, the planner picks the tallest tile that leaves
+ * about eight tiles per compute unit and as many workgroups as fit.  The results do not
+ * depend on the settings.  stitch_plan_config reads them (0 for levels with no pass).
+ * stitch_plan_set_config sets them (tile_rows[k] = 0 keeps pass k's height); on a bound plan
+ * it uploads the changed tables on the stream and waits for them.  Errors: NULL, SHAPE,
+ * DEVICE. */
+stitch_status stitch_plan_config(const stitch_plan* plan, int32_t wg_per_cu[STITCH_MAX_LEVELS],
+                                 int32_t tile_rows[STITCH_MAX_LEVELS]);
+stitch_status stitch_plan_set_config(stitch_plan* plan, const int32_t wg_per_cu[STITCH_MAX_LEVELS],
+                                     const int32_t tile_rows[STITCH_MAX_LEVELS], void* stream);
+/* Autotuner of the plain form (the paper sizes its thread grids by analysing the resources
+ * an image needs, Sec. 4.3.2; here they are measured): times every (tile height, workgroups
+ * per compute unit) pair of each pyramid pass of stitch_frame on these frames (U8 HWC, as for
+ * stitch_frame) and keeps the fastest; synchronises the stream.  cache_path (optional): a
+ * text file of earlier choices keyed by the device, the storage type and the plan's tile
+ * counts; a hit skips the timing, a miss appends the new choice.  The choice survives a
+ * rebind.  Errors: NULL, SHAPE, STATE (not bound), DEVICE. */
+stitch_status stitch_autotune(stitch_plan* plan, const stitch_image* frames, void* stream, const char* cache_path);
+
 void stitch_plan_destroy(stitch_plan* plan);
 
 /* ---- many jobs in one captured launch sequence --------------------------------- */
@@ -266,20 +288,33 @@ stitch_status stitch_batch_read_timing(stitch_batch* batch, double ms[STITCH_BAT
  * and the pass's tile height in rows (0 for levels with no pass from them).  Errors: NULL. */
 stitch_status stitch_batch_config(const stitch_batch* batch, int32_t wg_per_cu[STITCH_MAX_LEVELS],
                                   int32_t tile_rows[STITCH_MAX_LEVELS]);
+/* Set the per-level settings directly instead of timing them: for every pass k (levels
+ * 0 .. max levels - 2) tile_rows[k] in {16, 32, 64, 128} (0 keeps the current height) and
+ * wg_per_cu[k] in {-1 (one workgroup per tile), 0 (as many as fit), 1, 2}.  The results do
+ * not depend on the settings.  Host-only; the next run uploads the tables and captures a
+ * new graph.  Errors: NULL, SHAPE. */
+stitch_status stitch_batch_set_config(stitch_batch* batch, const int32_t wg_per_cu[STITCH_MAX_LEVELS],
+                                      const int32_t tile_rows[STITCH_MAX_LEVELS]);
 void          stitch_batch_destroy(stitch_batch* batch);
 
 /* ---- stream-pipelined frame sequences: host frames in, host panoramas out -------- */
 
 /* The paper keeps the upload of the next frames, the stitching of the current ones and
  * the download of the previous panorama in flight together on stream queues (Sec. 4.3.2,
- * Fig. 3).  A pipe owns `depth` (1..8) device slots, each holding one frame set and one
- * panorama of a bound plan, and three streams of default priority: copies in,
- * stitch_frame, copies out.  Events order the reuse of a slot: its frames are overwritten
- * only after the stitch that read them, its panorama only after the copy that read it.
- * The plan must stay bound and unused by other calls while a pipe runs on it.
- * Errors: NULL, SHAPE (depth), STATE (plan without workspace), DEVICE. */
+ * Fig. 3).  A pipe uses `depth` (1..8) device slots, each holding one frame set and one
+ * panorama of a bound plan, in a caller-owned device workspace of
+ * stitch_pipe_workspace_bytes(plan, depth) bytes (256-byte aligned; the paper's start-up
+ * pre-allocation, Sec. 4.3.2; 0 on bad arguments), and owns three streams of default
+ * priority: copies in, stitch_frame, copies out.  Events order the reuse of a slot: its
+ * frames are overwritten only after the stitch that read them, its panorama only after the
+ * copy that read it.  The plan and the workspace must stay alive, and the plan bound and
+ * unused by other calls, while a pipe runs on it.
+ * Errors: NULL, SHAPE (depth), WORKSPACE (NULL, misaligned or too small), STATE (plan
+ * without workspace), DEVICE. */
 typedef struct stitch_pipe stitch_pipe;
-stitch_status stitch_pipe_create(stitch_plan* plan, int32_t depth, stitch_pipe** out);
+size_t        stitch_pipe_workspace_bytes(const stitch_plan* plan, int32_t depth);
+stitch_status stitch_pipe_create(stitch_plan* plan, int32_t depth, void* workspace, size_t bytes,
+                                 stitch_pipe** out);
 /* Stitch nframes frame sets: frames[t * n + i] is camera i's frame of set t (host memory,
  * U8 HWC with packed rows: frame_w x frame_h x 3 bytes), panos[t] its panorama (host, U8
  * HWC packed, canvas_w x canvas_h x 3 bytes).  Returns when every panorama is on the host.
@@ -360,7 +395,7 @@ stitch_status stitch_map_grad_to_corners(const double q[8], int32_t w, int32_t h
  *   - gradients Ix = g(x+1,y) - g(x-1,y), Iy = g(x,y+1) - g(x,y-1); the Gaussian weighting
  *     (sigma = 1) is the 5x5 binomial window b b^T, b = [1,4,6,4,1], unnormalised, giving
  *     A, B, C; the response (alpha = 3/64, scaled by 64) R = 64 (A B - C^2) - 3 (A + B)^2;
- *   - candidates: FAST corners with R > harris_threshold; a candidate survives when every
+ *   - candidates: FAST corners with R >= harris_threshold (Alg. 1 step 5 deletes those below it); a candidate survives when every
  *     candidate among its 8 neighbours has a smaller R, or an equal R and a later raster
  *     position; the n_max survivors of largest R are kept, equal R in raster order;
  *   - BRIEF (Sec. 4.1.2) on S = b b^T * g: pair k of the pattern (dx1, dy1, dx2, dy2, each
@@ -461,7 +496,8 @@ stitch_status stitch_lsh_match(int32_t nd, const uint32_t* desc_a, const int32_t
  *     more inliers), else the best's own model; no valid hypothesis: H = 0, 0 inliers.
  * pts_a: DEVICE int32 [cap_a][2], pts_b: DEVICE int32 [cap_b][2] (stitch_lorb's points);
  * match, dist, count_a: as stitch_lsh_match wrote them (any distances below INT32_MAX).  uniforms: DEVICE double
- * [nhyp][4] in [0, 1) (the random draws are an input); nhyp 1..65536.  T_N, eps > 0.
+ * [nhyp][4] in [0, 1) (the random draws are an input); nhyp 1..65536.  eps > 0 and
+ * 0 < T_N <= 2^53 (the schedule is integer-valued; SHAPE otherwise).
  * Outputs (DEVICE): H[9] double row-major (frame A -> frame B, h33 = 1), inliers (int32),
  * inlier_mask uint8[cap_a] (1 where query i's match is an inlier of the best hypothesis),
  * hyp_counts int32[nhyp] (each hypothesis' inlier count, 0 when skipped).

@@ -6,7 +6,7 @@ does, and the two share no code, header, table or helper.
 What is computed.  Within each feature detection area of a frame (Alg. 2, step 1), FAST
 corners (Alg. 1, step 4) are scored with the Harris response R = det M - alpha (trace M)^2
 of the Gaussian-weighted (sigma = 1) gradient products (Alg. 1, steps 1-3, 5), those with
-R not above a threshold t are dropped, non-maximal suppression keeps the local maxima
+R below a threshold t are dropped, non-maximal suppression keeps the local maxima
 (Alg. 1, step 6) and the N of largest response remain (Alg. 1, step 7; Alg. 2, step 3).
 Each kept point gets a BRIEF descriptor from n_d point pairs of the smoothed image
 (Sec. 4.1.2; Alg. 2, step 4).  The paper fixes none of the operators or constants; the
@@ -24,7 +24,8 @@ integer one, so a GPU implementation can match it bit for bit:
       C = sum b b^T Ix Iy (integers).
   R21 alpha = 3/64 (inside the customary 0.04 - 0.06) and the response scaled by 64, so it
       is an integer: R = 64 (A B - C^2) - 3 (A + B)^2.
-  R22 a candidate is a FAST corner of the area with R > t.
+  R22 a candidate is a FAST corner of the area with R >= t (Alg. 1, step 5 deletes the
+      points whose response is less than t).
   R23 non-maximal suppression over the 3x3 neighbourhood among candidates: p survives
       when every neighbouring candidate q has R(q) < R(p), or R(q) = R(p) and q comes
       later in raster order (index y * w + x).
@@ -111,7 +112,7 @@ def clip_area(rect, w: int, h: int):
 
 
 def candidates(g: np.ndarray, rect, tf: int, t: int) -> dict:
-    """R22: {(x, y): R} for the FAST corners of the clipped area with R > t."""
+    """R22: {(x, y): R} for the FAST corners of the clipped area with R >= t."""
     h, w = g.shape
     x0, y0, rw, rh = clip_area(rect, w, h)
     out = {}
@@ -119,7 +120,7 @@ def candidates(g: np.ndarray, rect, tf: int, t: int) -> dict:
         for x in range(x0, x0 + rw):
             if fast_corner(g, x, y, tf):
                 r = harris(g, x, y)
-                if r > t:
+                if r >= t:
                     out[(x, y)] = r
     return out
 

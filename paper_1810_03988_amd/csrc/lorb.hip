@@ -7,7 +7,7 @@
 //                   darker than g - tf
 //   Harris          central-difference gradients, 5x5 binomial window b b^T (sigma = 1),
 //                   R = 64 (A B - C^2) - 3 (A + B)^2  (alpha = 3/64, scaled by 64), int64
-//   candidates      FAST corners with R > t; suppression over 3x3 among candidates, ties
+//   candidates      FAST corners with R >= t; suppression over 3x3 among candidates, ties
 //                   to the first in raster order; the N of largest R, ties by raster order
 //   BRIEF           three-valued tests of n_d point pairs on S = b b^T * g (integer sums),
 //                   kept as a "greater" and a "less" bit string
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(256) k_lorb_detect(const AreaTable T, int tf, 
                     6 * (int64_t)sH[q][r + 2][c];
           const int64_t A = mm[0], B = mm[1], C = mm[2];
           const int64_t R = 64 * (A * B - C * C) - 3 * (A + B) * (A + B);
-          if (R > t) out = R;
+          if (R >= t) out = R;
         }
       }
     }

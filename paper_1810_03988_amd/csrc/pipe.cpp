@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <new>
 #include <vector>
 
 #include "stitch_internal.h"
@@ -16,8 +17,8 @@ struct stitch_pipe {
   int depth = 0, n = 0, W = 0, H = 0;
   int fw[kMaxCameras] = {}, fh[kMaxCameras] = {};
   hipStream_t s_in = nullptr, s_comp = nullptr, s_out = nullptr;
-  std::vector<void*> frames;   // depth x n device frames, packed rows
-  std::vector<void*> panos;    // depth device panoramas, packed rows
+  std::vector<void*> frames;   // depth x n device frames, packed rows (in the caller's workspace)
+  std::vector<void*> panos;    // depth device panoramas, packed rows (in the caller's workspace)
   std::vector<hipEvent_t> ev_in, ev_comp, ev_out;   // per slot: copied in, stitched, copied out
 };
 
@@ -26,10 +27,6 @@ namespace {
 void release(stitch_pipe* q) {
   for (hipStream_t s : {q->s_in, q->s_comp, q->s_out})
     if (s) (void)hipStreamSynchronize(s);
-  for (void* p : q->frames)
-    if (p) (void)hipFree(p);
-  for (void* p : q->panos)
-    if (p) (void)hipFree(p);
   for (auto* v : {&q->ev_in, &q->ev_comp, &q->ev_out})
     for (hipEvent_t e : *v)
       if (e) (void)hipEventDestroy(e);
@@ -38,15 +35,37 @@ void release(stitch_pipe* q) {
   delete q;
 }
 
+size_t round256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Bytes of one slot (a frame set and a panorama, each buffer 256-byte aligned).
+size_t slot_bytes(int n, const int* fw, const int* fh, int W, int H) {
+  size_t b = 0;
+  for (int i = 0; i < n; ++i) b += round256((size_t)fw[i] * fh[i] * 3);
+  return b + round256((size_t)W * H * 3);
+}
+
 }  // namespace
 
 extern "C" {
 
-stitch_status stitch_pipe_create(stitch_plan* plan, int32_t depth, stitch_pipe** out) {
+size_t stitch_pipe_workspace_bytes(const stitch_plan* plan, int32_t depth) {
+  if (!plan || depth < 1 || depth > 8) return 0;
+  int n = 0, W = 0, H = 0, fw[kMaxCameras], fh[kMaxCameras];
+  bool bound = false;
+  plan_geometry(plan, &n, fw, fh, &W, &H, &bound);
+  return (size_t)depth * slot_bytes(n, fw, fh, W, H);
+}
+
+stitch_status stitch_pipe_create(stitch_plan* plan, int32_t depth, void* workspace, size_t bytes, stitch_pipe** out) {
   if (!plan || !out) return fail(STITCH_E_NULL, "plan or out is NULL");
   *out = nullptr;
   if (depth < 1 || depth > 8) return fail(STITCH_E_SHAPE, "depth %d outside 1..8", depth);
-  stitch_pipe* q = new stitch_pipe;
+  const size_t need = stitch_pipe_workspace_bytes(plan, depth);
+  if (!workspace) return fail(STITCH_E_WORKSPACE, "workspace is NULL");
+  if (((uintptr_t)workspace & 255) != 0) return fail(STITCH_E_WORKSPACE, "workspace is not 256-byte aligned");
+  if (bytes < need) return fail(STITCH_E_WORKSPACE, "workspace has %zu bytes, the pipe needs %zu", bytes, need);
+  stitch_pipe* q = new (std::nothrow) stitch_pipe;
+  if (!q) return fail(STITCH_E_UNSUPPORTED, "out of host memory");
   bool bound = false;
   plan_geometry(plan, &q->n, q->fw, q->fh, &q->W, &q->H, &bound);
   if (!bound) {
@@ -58,12 +77,17 @@ stitch_status stitch_pipe_create(stitch_plan* plan, int32_t depth, stitch_pipe**
   hipError_t e = hipSuccess;
   for (hipStream_t* s : {&q->s_in, &q->s_comp, &q->s_out})
     if (e == hipSuccess) e = hipStreamCreateWithFlags(s, hipStreamNonBlocking);
+  // the slots, carved from the caller's workspace
   q->frames.assign((size_t)depth * q->n, nullptr);
   q->panos.assign(depth, nullptr);
-  for (int d = 0; d < depth && e == hipSuccess; ++d) {
-    for (int i = 0; i < q->n && e == hipSuccess; ++i)
-      e = hipMalloc(&q->frames[(size_t)d * q->n + i], (size_t)q->fw[i] * q->fh[i] * 3);
-    if (e == hipSuccess) e = hipMalloc(&q->panos[d], (size_t)q->W * q->H * 3);
+  uint8_t* top = (uint8_t*)workspace;
+  for (int d = 0; d < depth; ++d) {
+    for (int i = 0; i < q->n; ++i) {
+      q->frames[(size_t)d * q->n + i] = top;
+      top += round256((size_t)q->fw[i] * q->fh[i] * 3);
+    }
+    q->panos[d] = top;
+    top += round256((size_t)q->W * q->H * 3);
   }
   for (auto* v : {&q->ev_in, &q->ev_comp, &q->ev_out}) {
     v->assign(depth, nullptr);

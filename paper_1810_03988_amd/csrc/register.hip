@@ -608,6 +608,10 @@ stitch_status stitch_prosac(const int32_t* pts_a, const int32_t* pts_b, int32_t 
   if (nhyp < 1 || nhyp > kMaxHyp) return fail(STITCH_E_SHAPE, "nhyp = %d outside 1..%d", nhyp, kMaxHyp);
   if (!(T_N > 0.0) || !std::isfinite(T_N) || !(eps > 0.0) || !std::isfinite(eps))
     return fail(STITCH_E_SHAPE, "T_N and eps must be positive and finite");
+  // the schedule T'_n grows to about T_N + M and is kept in int64: T_N up to 2^53 (where
+  // every integer is still a double) leaves it far inside the range
+  if (T_N > 0x1p53)
+    return fail(STITCH_E_SHAPE, "T_N = %g exceeds 2^53", T_N);
   size_t need = 0;
   const ProsacWs L = prosac_layout(cap_a, nhyp, &need);
   if (!workspace || workspace_bytes < need || ((uintptr_t)workspace & 255))

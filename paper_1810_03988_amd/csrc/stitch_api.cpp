@@ -228,6 +228,11 @@ struct stitch_plan {
   std::vector<PyrItem> items[kMaxLevels];
   int tiles[kMaxLevels] = {};
   size_t off_items[kMaxLevels] = {};
+  // pyramid-pass settings: requested tile sub-steps (0: the planner's choice), the ones in
+  // use, and persistent workgroups per compute unit (0: as many as fit, -1: one per tile)
+  int sub_req[kMaxLevels] = {};
+  int sub[kMaxLevels] = {};
+  int wg_cap[kMaxLevels] = {};
   std::vector<BlendCam> bcams[kMaxLevels];
   size_t off_bcams[kMaxLevels] = {};
   std::vector<BlendItem> bitems;            // one per level
@@ -400,7 +405,8 @@ void build_tables(stitch_plan* p) {
       tiles += it.tiles_x * it.tiles_y;
       p->items[k].push_back(it);
     }
-    set_sub(p->items[k], choose_sub(tiles), tiles);
+    p->sub[k] = p->sub_req[k] > 0 ? p->sub_req[k] : choose_sub(tiles);
+    set_sub(p->items[k], p->sub[k], tiles);
     p->tiles[k] = tiles;
   }
   for (int k = 0; k < L; ++k) {
@@ -459,6 +465,28 @@ void build_tables(stitch_plan* p) {
       bi.rout_plane = p->r_plane[k];
     }
   }
+}
+
+// Check a frame set against the plan and collect its pointers for the level-0 pass.
+stitch_status frame_args(const stitch_plan* p, const stitch_image* frames, FrameArgs& fa) {
+  std::memset(&fa, 0, sizeof fa);
+  fa.n = p->n;
+  for (int i = 0; i < p->n; ++i) {
+    char name[32];
+    snprintf(name, sizeof name, "frames[%d]", i);
+    const stitch_status st = check_image(&frames[i], name, STITCH_U8, STITCH_HWC, 3);
+    if (st) return st;
+    if (frames[i].width != p->cam[i].fw || frames[i].height != p->cam[i].fh)
+      return fail(STITCH_E_SHAPE, "frames[%d] is %dx%d, planned %dx%d", i, frames[i].width, frames[i].height,
+                  p->cam[i].fw, p->cam[i].fh);
+    if (frames[i].row_pitch * (int64_t)frames[i].height >= ((int64_t)1 << 31) ||
+        frames[i].row_pitch >= ((int64_t)1 << 24))
+      return fail(STITCH_E_SHAPE, "frames[%d] spans 2 GiB or more, or its rows 16 MiB or more (offsets are "
+                  "32-bit, row offsets 24-bit products)", i);
+    fa.ptr[i] = (const uint8_t*)frames[i].data;
+    fa.row[i] = frames[i].row_pitch;
+  }
+  return STITCH_OK;
 }
 
 }  // namespace
@@ -996,23 +1024,7 @@ stitch_status stitch_frame(stitch_plan* p, const stitch_image* frames, stitch_im
   if (pano->width != p->W || pano->height != p->H)
     return fail(STITCH_E_SHAPE, "pano is %dx%d, the plan's canvas is %dx%d", pano->width, pano->height, p->W, p->H);
   FrameArgs fa;
-  std::memset(&fa, 0, sizeof fa);
-  fa.n = p->n;
-  for (int i = 0; i < p->n; ++i) {
-    char name[32];
-    snprintf(name, sizeof name, "frames[%d]", i);
-    st = check_image(&frames[i], name, STITCH_U8, STITCH_HWC, 3);
-    if (st) return st;
-    if (frames[i].width != p->cam[i].fw || frames[i].height != p->cam[i].fh)
-      return fail(STITCH_E_SHAPE, "frames[%d] is %dx%d, planned %dx%d", i, frames[i].width, frames[i].height,
-                  p->cam[i].fw, p->cam[i].fh);
-    if (frames[i].row_pitch * (int64_t)frames[i].height >= ((int64_t)1 << 31) ||
-        frames[i].row_pitch >= ((int64_t)1 << 24))
-      return fail(STITCH_E_SHAPE, "frames[%d] spans 2 GiB or more, or its rows 16 MiB or more (offsets are "
-                  "32-bit, row offsets 24-bit products)", i);
-    fa.ptr[i] = (const uint8_t*)frames[i].data;
-    fa.row[i] = frames[i].row_pitch;
-  }
+  if ((st = frame_args(p, frames, fa))) return st;
   const hipStream_t s = (hipStream_t)stream;
   const bool f16 = p->storage == STITCH_F16;
   const int L = p->L;
@@ -1038,7 +1050,7 @@ stitch_status stitch_frame(stitch_plan* p, const stitch_image* frames, stitch_im
   for (int k = 0; k + 1 < L; ++k) {
     if (p->tiles[k] <= 0) continue;
     e = launch_pyr(f16, true, k == 0, (const PyrItem*)(p->ws + p->off_items[k]), (int)p->items[k].size(),
-                   p->tiles[k], fa, s);
+                   p->tiles[k], fa, s, p->wg_cap[k]);
     if (e != hipSuccess) return hip_fail(e, "pyramid pass launch");
     if ((st = mark(k == 0 ? 0 : 1))) return st;
   }
@@ -1273,6 +1285,152 @@ uint64_t fnv1a(uint64_t h, const void* data, size_t n) {
   return h;
 }
 
+// One pyramid pass's tunable settings and where its launch table lives.
+struct PassTune {
+  std::vector<PyrItem>* items;   // host table (tile counts follow the sub-steps)
+  uint8_t* dev_table;            // its device copy
+  int* tiles;                    // the pass's tile count
+  int* sub;                      // 16-row sub-steps per tile
+  int* cap;                      // persistent workgroups per compute unit
+  int64_t t16;                   // 16-row tiles of the pass (independent of sub)
+  bool warp;                     // the level-0 pass (warp + pyramid)
+};
+
+// Use sub_k sub-steps per tile: rewrite the host table and upload it (waited for, since
+// the host table is rewritten by the next choice).
+stitch_status apply_sub(PassTune& pt, int sub_k, hipStream_t s) {
+  *pt.sub = sub_k;
+  set_sub(*pt.items, sub_k, *pt.tiles);
+  stitch_status r = upload(pt.dev_table, pt.items->data(), pt.items->size() * sizeof(PyrItem), s, "table upload");
+  if (r) return r;
+  const hipError_t e = hipStreamSynchronize(s);
+  return e == hipSuccess ? STITCH_OK : hip_fail(e, "table upload");
+}
+
+// Pick, per pass, the tile height (16 * sub rows, sub in 1, 2, 4, 8; the taller ones only
+// while the pass still has a tile per compute unit) and the workgroups per compute unit
+// (as many as fit, 1, 2, or one per tile) by timing every pair on the stream (the other
+// passes keep their settings).  cache_path: a text file of earlier choices keyed by the
+// device, the storage type, the form (salt) and every pass's 16-row tile count.
+stitch_status tune_passes(int np, PassTune* passes, bool f16, const FrameArgs& fa, hipStream_t s,
+                          const char* cache_path, uint64_t salt) {
+  prepare_launches();
+  hipDeviceProp_t prop;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(STITCH_E_DEVICE, "cannot query the device");
+  int64_t t16[kMaxLevels] = {};
+  for (int k = 0; k < np; ++k) t16[k] = passes[k].t16;
+  uint64_t key = fnv1a(1469598103934665603ull, prop.gcnArchName, strlen(prop.gcnArchName));
+  key = fnv1a(key, &f16, sizeof f16);
+  if (salt) key = fnv1a(key, &salt, sizeof salt);
+  key = fnv1a(key, t16, sizeof t16);
+  constexpr int kFields = 2 * kMaxLevels;   // per pass: sub-steps per tile, workgroups per CU
+  int cached[kFields];
+  bool hit = false;
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "r");
+    if (f) {
+      char line[1024];
+      while (!hit && fgets(line, sizeof line, f)) {
+        unsigned long long k2 = 0;
+        int n = 0, off = 0;
+        if (sscanf(line, "%llx %d%n", &k2, &n, &off) == 2 && k2 == key && n == kFields) {
+          hit = true;
+          const char* q = line + off;
+          for (int i = 0; i < kFields && hit; ++i) {
+            int used = 0;
+            if (sscanf(q, "%d%n", &cached[i], &used) != 1) hit = false;
+            q += used;
+          }
+          for (int k = 0; k < kMaxLevels && hit; ++k)
+            if (cached[2 * k] < 1 || cached[2 * k] > 8 || (cached[2 * k] & (cached[2 * k] - 1)) != 0 ||
+                cached[2 * k + 1] < -1 || cached[2 * k + 1] > 2)
+              hit = false;
+        }
+      }
+      fclose(f);
+    }
+  }
+  stitch_status st = STITCH_OK;
+  if (hit) {
+    for (int k = 0; k < np && !st; ++k) {
+      *passes[k].cap = cached[2 * k + 1];
+      st = apply_sub(passes[k], cached[2 * k], s);
+    }
+    return st;
+  }
+  const int subs[] = {1, 2, 4, 8};
+  const int caps[] = {0, 1, 2, -1};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(STITCH_E_DEVICE, "event create failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(STITCH_E_DEVICE, "event create failed");
+  }
+  for (int k = 0; k < np && !st; ++k) {
+    PassTune& pt = passes[k];
+    if (pt.t16 <= 0) continue;
+    float best = 1e30f;
+    int best_sub = *pt.sub, best_cap = 0;
+    for (int sub_k : subs) {
+      if (sub_k > 1 && pt.t16 / sub_k < 256) continue;   // at least a tile per compute unit
+      st = apply_sub(pt, sub_k, s);
+      for (int c : caps) {
+        float score = 1e30f;   // fastest of five launches after a warm-up one
+        for (int rep = 0; rep < 6 && !st; ++rep) {
+          hipError_t e = hipEventRecord(e0, s);
+          if (e == hipSuccess)
+            e = launch_pyr(f16, true, pt.warp, (const PyrItem*)pt.dev_table, (int)pt.items->size(), *pt.tiles, fa,
+                           s, c);
+          if (e == hipSuccess) e = hipEventRecord(e1, s);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.0f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e != hipSuccess) st = hip_fail(e, "autotune timing");
+          if (rep > 0) score = std::min(score, ms);
+        }
+        if (!st && score < best) {
+          best = score;
+          best_sub = sub_k;
+          best_cap = c;
+        }
+      }
+      if (st) break;
+    }
+    *pt.cap = best_cap;
+    if (!st) st = apply_sub(pt, best_sub, s);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "a");
+    if (f) {
+      fprintf(f, "%llx %d", (unsigned long long)key, kFields);
+      for (int k = 0; k < kMaxLevels; ++k)
+        fprintf(f, " %d %d", k < np && *passes[k].sub > 0 ? *passes[k].sub : 1, k < np ? *passes[k].cap : 0);
+      fprintf(f, "\n");
+      fclose(f);
+    }
+  }
+  return STITCH_OK;
+}
+
+// Validate caller-given settings: tile_rows[k] in {0 (keep), 16, 32, 64, 128} and
+// wg_per_cu[k] in {-1, 0, 1, 2} for the np passes.
+stitch_status check_config(int np, const int32_t* wg_per_cu, const int32_t* tile_rows) {
+  if (!wg_per_cu || !tile_rows) return fail(STITCH_E_NULL, "wg_per_cu or tile_rows is NULL");
+  for (int k = 0; k < np; ++k) {
+    const int t = tile_rows[k];
+    if (t != 0 && t != 16 && t != 32 && t != 64 && t != 128)
+      return fail(STITCH_E_SHAPE, "tile_rows[%d] = %d is not 0, 16, 32, 64 or 128", k, t);
+    if (wg_per_cu[k] < -1 || wg_per_cu[k] > 2)
+      return fail(STITCH_E_SHAPE, "wg_per_cu[%d] = %d outside -1..2", k, wg_per_cu[k]);
+  }
+  return STITCH_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1392,112 +1550,15 @@ stitch_status stitch_batch_autotune(stitch_batch* b, const stitch_image* const* 
   const hipStream_t s = (hipStream_t)stream;
   stitch_status st = batch_prepare(b, frames, panos, s);
   if (st) return st;
-  prepare_launches();
-  hipDeviceProp_t prop;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
-    return fail(STITCH_E_DEVICE, "cannot query the device");
-  // cache key: device, storage type and each phase's 16-row tile count
-  uint64_t key = fnv1a(1469598103934665603ull, prop.gcnArchName, strlen(prop.gcnArchName));
-  key = fnv1a(key, &b->f16, sizeof b->f16);
-  key = fnv1a(key, b->t16, sizeof b->t16);
-  constexpr int kFields = 2 * kMaxLevels;   // per phase: sub-steps per tile, workgroups per CU
-  int cached[kFields];
-  bool hit = false;
-  if (cache_path) {
-    FILE* f = fopen(cache_path, "r");
-    if (f) {
-      char line[1024];
-      while (!hit && fgets(line, sizeof line, f)) {
-        unsigned long long k2 = 0;
-        int n = 0, off = 0;
-        if (sscanf(line, "%llx %d%n", &k2, &n, &off) == 2 && k2 == key && n == kFields) {
-          hit = true;
-          const char* q = line + off;
-          for (int i = 0; i < kFields && hit; ++i) {
-            int used = 0;
-            if (sscanf(q, "%d%n", &cached[i], &used) != 1) hit = false;
-            q += used;
-          }
-          for (int k = 0; k < kMaxLevels && hit; ++k)
-            if (cached[2 * k] < 1 || cached[2 * k] > 8 || (cached[2 * k] & (cached[2 * k] - 1)) != 0) hit = false;
-        }
-      }
-      fclose(f);
-    }
-  }
-  // the host table is rewritten by the next choice, so each upload is waited for
-  auto use = [&](int k, int sub_k) {
-    b->sub[k] = sub_k;
-    set_sub(b->pyr[k], sub_k, b->pyr_tiles[k]);
-    stitch_status r = upload(b->ws + b->off_pyr[k], b->pyr[k].data(), b->pyr[k].size() * sizeof(PyrItem), s,
-                             "batch table upload");
-    if (r) return r;
-    const hipError_t e = hipStreamSynchronize(s);
-    return e == hipSuccess ? STITCH_OK : hip_fail(e, "batch table upload");
-  };
   drop_graph(b);
-  if (hit) {
-    for (int k = 0; k + 1 < b->maxL && !st; ++k) {
-      b->wg_cap[k] = cached[2 * k + 1];
-      st = use(k, cached[2 * k]);
-    }
-    return st;
-  }
-  // per pyramid phase, time every (sub-steps per tile, workgroups per CU) pair; the other
-  // phases keep their settings
-  const int subs[] = {1, 2, 4, 8};
-  const int caps[] = {0, 1, 2, -1};
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-    return fail(STITCH_E_DEVICE, "event create failed");
+  PassTune passes[kMaxLevels];
+  int np = 0;
+  for (int k = 0; k + 1 < b->maxL; ++k)
+    passes[np++] = PassTune{&b->pyr[k], b->ws + b->off_pyr[k], &b->pyr_tiles[k], &b->sub[k], &b->wg_cap[k],
+                            b->t16[k], k == 0};
   FrameArgs fa;
-  std::memset(&fa, 0, sizeof fa);
-  for (int k = 0; k + 1 < b->maxL && !st; ++k) {
-    if (b->t16[k] <= 0) continue;
-    float best = 1e30f;
-    int best_sub = b->sub[k], best_cap = 0;
-    for (int sub_k : subs) {
-      if (sub_k > 1 && b->t16[k] / sub_k < 256) continue;   // at least a tile per compute unit
-      st = use(k, sub_k);
-      for (int c : caps) {
-        float score = 1e30f;   // fastest of five launches after a warm-up one
-        for (int rep = 0; rep < 6 && !st; ++rep) {
-          hipError_t e = hipEventRecord(e0, s);
-          if (e == hipSuccess)
-            e = launch_pyr(b->f16, true, k == 0, (const PyrItem*)(b->ws + b->off_pyr[k]), (int)b->pyr[k].size(),
-                           b->pyr_tiles[k], fa, s, c);
-          if (e == hipSuccess) e = hipEventRecord(e1, s);
-          if (e == hipSuccess) e = hipEventSynchronize(e1);
-          float ms = 0.0f;
-          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-          if (e != hipSuccess) st = hip_fail(e, "autotune timing");
-          if (rep > 0) score = std::min(score, ms);
-        }
-        if (!st && score < best) {
-          best = score;
-          best_sub = sub_k;
-          best_cap = c;
-        }
-      }
-      if (st) break;
-    }
-    b->wg_cap[k] = best_cap;
-    if (!st) st = use(k, best_sub);
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (st) return st;
-  if (cache_path) {
-    FILE* f = fopen(cache_path, "a");
-    if (f) {
-      fprintf(f, "%llx %d", (unsigned long long)key, kFields);
-      for (int k = 0; k < kMaxLevels; ++k) fprintf(f, " %d %d", b->sub[k] > 0 ? b->sub[k] : 1, b->wg_cap[k]);
-      fprintf(f, "\n");
-      fclose(f);
-    }
-  }
-  return STITCH_OK;
+  std::memset(&fa, 0, sizeof fa);   // n = 0: frames come from the item tables
+  return tune_passes(np, passes, b->f16, fa, s, cache_path, 0x62617463ull /* batch */);
 }
 
 stitch_status stitch_batch_config(const stitch_batch* b, int32_t wg_per_cu[STITCH_MAX_LEVELS],
@@ -1525,5 +1586,87 @@ stitch_status stitch_batch_read_timing(stitch_batch* b, double ms[STITCH_BATCH_T
 }
 
 void stitch_batch_destroy(stitch_batch* b) { delete b; }
+
+stitch_status stitch_batch_set_config(stitch_batch* b, const int32_t wg_per_cu[STITCH_MAX_LEVELS],
+                                      const int32_t tile_rows[STITCH_MAX_LEVELS]) {
+  if (!b) return fail(STITCH_E_NULL, "batch is NULL");
+  const int np = std::max(0, b->maxL - 1);
+  stitch_status st = check_config(np, wg_per_cu, tile_rows);
+  if (st) return st;
+  for (int k = 0; k < np; ++k) {
+    b->wg_cap[k] = wg_per_cu[k];
+    if (tile_rows[k]) {
+      b->sub[k] = tile_rows[k] / kPyrTY;
+      set_sub(b->pyr[k], b->sub[k], b->pyr_tiles[k]);
+    }
+  }
+  b->uploaded = false;   // the next run uploads the tables and captures a new graph
+  drop_graph(b);
+  return STITCH_OK;
+}
+
+// ------------------------------------------------------------------------------------ plan settings
+
+// Upload the pyramid-pass tables of a bound plan and wait for them.
+static stitch_status plan_upload_items(stitch_plan* p, hipStream_t s) {
+  for (int k = 0; k + 1 < p->L; ++k) {
+    const stitch_status st =
+        upload(p->ws + p->off_items[k], p->items[k].data(), p->items[k].size() * sizeof(PyrItem), s, "table upload");
+    if (st) return st;
+  }
+  const hipError_t e = hipStreamSynchronize(s);
+  return e == hipSuccess ? STITCH_OK : hip_fail(e, "table upload");
+}
+
+stitch_status stitch_plan_config(const stitch_plan* p, int32_t wg_per_cu[STITCH_MAX_LEVELS],
+                                 int32_t tile_rows[STITCH_MAX_LEVELS]) {
+  if (!p || !wg_per_cu || !tile_rows) return fail(STITCH_E_NULL, "plan, wg_per_cu or tile_rows is NULL");
+  for (int k = 0; k < kMaxLevels; ++k) {
+    const bool pass = k + 1 < p->L;
+    wg_per_cu[k] = pass ? p->wg_cap[k] : 0;
+    tile_rows[k] = pass ? kPyrTY * (p->sub[k] > 0 ? p->sub[k] : (p->sub_req[k] > 0 ? p->sub_req[k] : 1)) : 0;
+  }
+  return STITCH_OK;
+}
+
+stitch_status stitch_plan_set_config(stitch_plan* p, const int32_t wg_per_cu[STITCH_MAX_LEVELS],
+                                     const int32_t tile_rows[STITCH_MAX_LEVELS], void* stream) {
+  if (!p) return fail(STITCH_E_NULL, "plan is NULL");
+  const int np = std::max(0, p->L - 1);
+  stitch_status st = check_config(np, wg_per_cu, tile_rows);
+  if (st) return st;
+  for (int k = 0; k < np; ++k) {
+    p->wg_cap[k] = wg_per_cu[k];
+    if (tile_rows[k]) {
+      p->sub_req[k] = tile_rows[k] / kPyrTY;
+      if (p->ws) {
+        p->sub[k] = p->sub_req[k];
+        set_sub(p->items[k], p->sub[k], p->tiles[k]);
+      }
+    }
+  }
+  return p->ws ? plan_upload_items(p, (hipStream_t)stream) : STITCH_OK;
+}
+
+stitch_status stitch_autotune(stitch_plan* p, const stitch_image* frames, void* stream, const char* cache_path) {
+  if (!p) return fail(STITCH_E_NULL, "plan is NULL");
+  if (!frames) return fail(STITCH_E_NULL, "frames is NULL");
+  if (!p->ws) return fail(STITCH_E_STATE, "plan has no workspace bound");
+  FrameArgs fa;
+  stitch_status st = frame_args(p, frames, fa);
+  if (st) return st;
+  PassTune passes[kMaxLevels];
+  int np = 0;
+  for (int k = 0; k + 1 < p->L; ++k) {
+    int64_t t16 = 0;
+    for (const PyrItem& it : p->items[k]) t16 += (int64_t)it.tiles_x * it.rows16;
+    passes[np++] = PassTune{&p->items[k], p->ws + p->off_items[k], &p->tiles[k], &p->sub[k], &p->wg_cap[k], t16,
+                            k == 0};
+  }
+  st = tune_passes(np, passes, p->storage == STITCH_F16, fa, (hipStream_t)stream, cache_path,
+                   0x706c61696eull /* plain */);
+  for (int k = 0; k < np; ++k) p->sub_req[k] = p->sub[k];   // kept across rebinds
+  return st;
+}
 
 }  // extern "C"

@@ -77,6 +77,10 @@ SIGNATURES = {
     "stitch_batch_autotune": (c_int32, [c_void_p, POINTER(POINTER(StitchImage)), POINTER(StitchImage), c_void_p,
                                         c_char_p]),
     "stitch_batch_config": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
+    "stitch_batch_set_config": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
+    "stitch_plan_config": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
+    "stitch_plan_set_config": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32), c_void_p]),
+    "stitch_autotune": (c_int32, [c_void_p, POINTER(StitchImage), c_void_p, c_char_p]),
     "stitch_batch_set_timing": (c_int32, [c_void_p, c_int32]),
     "stitch_batch_read_timing": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int32)]),
     "stitch_batch_destroy": (None, [c_void_p]),
@@ -89,7 +93,8 @@ SIGNATURES = {
                                       c_void_p]),
     "stitch_grad_backward": (c_int32, [c_void_p, POINTER(StitchImage), POINTER(c_double), c_void_p]),
     "stitch_grad_destroy": (None, [c_void_p]),
-    "stitch_pipe_create": (c_int32, [c_void_p, c_int32, POINTER(c_void_p)]),
+    "stitch_pipe_workspace_bytes": (c_size_t, [c_void_p, c_int32]),
+    "stitch_pipe_create": (c_int32, [c_void_p, c_int32, c_void_p, c_size_t, POINTER(c_void_p)]),
     "stitch_pipe_run": (c_int32, [c_void_p, c_int32, POINTER(c_void_p), POINTER(c_void_p)]),
     "stitch_pipe_destroy": (None, [c_void_p]),
     "stitch_host_alloc": (c_int32, [c_size_t, POINTER(c_void_p)]),
@@ -151,8 +156,16 @@ _DT = {torch.uint8: U8, torch.float16: F16, torch.float32: F32}
 _TORCH_DT = {U8: torch.uint8, F16: torch.float16, F32: torch.float32}
 
 
+def _on_gpu(t: torch.Tensor, name: str) -> None:
+    """Every pointer the device calls take must be device memory: a host tensor's address
+    handed to a kernel would fault, so it is refused before any launch."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (got {getattr(t, 'device', type(t))})")
+
+
 def image_hwc(t: torch.Tensor) -> StitchImage:
-    """(H, W, C) tensor with unit channel stride -> HWC image view."""
+    """(H, W, C) GPU tensor with unit channel stride -> HWC image view."""
+    _on_gpu(t, "image")
     if t.dim() != 3 or t.stride(2) != 1 or t.stride(1) != t.shape[2]:
         raise ValueError("HWC images need shape (H, W, C) with packed pixels")
     es = t.element_size()
@@ -160,7 +173,8 @@ def image_hwc(t: torch.Tensor) -> StitchImage:
 
 
 def image_chw(t: torch.Tensor) -> StitchImage:
-    """(C, H, W) or (H, W) tensor with unit column stride -> CHW image view."""
+    """(C, H, W) or (H, W) GPU tensor with unit column stride -> CHW image view."""
+    _on_gpu(t, "image")
     if t.dim() == 2:
         t = t.unsqueeze(0)
     if t.dim() != 3 or t.stride(2) != 1:
@@ -359,6 +373,23 @@ class Plan:
         check(lib().stitch_plan_read_timing(self._h, ms, n))
         return {TIMING_KINDS[i]: (ms[i], n[i]) for i in range(8) if n[i]}
 
+    def config(self) -> dict:
+        """{"wg_per_cu": [...], "tile_rows": [...]} of the plain form's pyramid passes."""
+        wg = (c_int32 * MAX_LEVELS)()
+        rows = (c_int32 * MAX_LEVELS)()
+        check(lib().stitch_plan_config(self._h, wg, rows))
+        return {"wg_per_cu": list(wg), "tile_rows": list(rows)}
+
+    def set_config(self, wg_per_cu=None, tile_rows=None, stream=None) -> None:
+        check(lib().stitch_plan_set_config(self._h, *_config_arrays(wg_per_cu, tile_rows), _stream(stream)))
+
+    def autotune(self, frames, stream=None, cache_path=None) -> dict:
+        """Time the pyramid passes' settings on these frames (stitch_autotune) and keep the
+        fastest; returns config()."""
+        fr = (StitchImage * self.n)(*[image_hwc(f) for f in frames])
+        check(lib().stitch_autotune(self._h, fr, _stream(stream), str(cache_path).encode() if cache_path else None))
+        return self.config()
+
     def regions(self, camera: int, level: int):
         roi = (c_int32 * 4)()
         band = (c_int32 * 4)()
@@ -377,14 +408,25 @@ class Plan:
             pass
 
 
+def _config_arrays(wg_per_cu, tile_rows):
+    wg = list(wg_per_cu or [])
+    rows = list(tile_rows or [])
+    return ((c_int32 * MAX_LEVELS)(*(wg + [0] * (MAX_LEVELS - len(wg)))),
+            (c_int32 * MAX_LEVELS)(*(rows + [0] * (MAX_LEVELS - len(rows)))))
+
+
 # ----------------------------------------------------------------------------- pipelined sequences
 class Pipe:
     """Stream-pipelined frame sequences over a bound plan (Sec. 4.3.2, Fig. 3): host frame
     sets in, host panoramas out, with uploads, stitching and downloads on three streams."""
 
     def __init__(self, plan: "Plan", depth: int = 2):
+        nbytes = lib().stitch_pipe_workspace_bytes(plan._h, depth)
+        if nbytes == 0:
+            raise StitchError(2, f"no pipe workspace for depth {depth}")
+        self._buf, self._ws = _aligned_workspace(nbytes, plan.device)   # the device slots
         handle = c_void_p()
-        check(lib().stitch_pipe_create(plan._h, depth, ctypes.byref(handle)))
+        check(lib().stitch_pipe_create(plan._h, depth, self._ws.data_ptr(), nbytes, ctypes.byref(handle)))
         self._h = handle
         self.plan = plan
         self.depth = depth
@@ -477,6 +519,11 @@ class Batch:
         rows = (c_int32 * MAX_LEVELS)()
         check(lib().stitch_batch_config(self._h, wg, rows))
         return {"wg_per_cu": list(wg), "tile_rows": list(rows)}
+
+    def set_config(self, wg_per_cu=None, tile_rows=None) -> None:
+        """Per-pass settings (lists indexed by level; missing entries keep the tile height
+        and take as many workgroups as fit)."""
+        check(lib().stitch_batch_set_config(self._h, *_config_arrays(wg_per_cu, tile_rows)))
 
     def close(self) -> None:
         if getattr(self, "_h", None):
@@ -664,6 +711,7 @@ class Lorb:
         """Queue the extraction of `frame` (H, W, 3 uint8 device) with `pattern` (nd, 4 int32
         device) on a raw stream handle; outputs land in counts/points/responses/descriptors."""
         img = image_hwc(frame)
+        _on_gpu(pattern, "pattern")
         check(lib().stitch_lorb(ctypes.byref(img), self.m, self.areas, self.tf, self.t, self.n_max, self.nd,
                                 pattern.data_ptr(), self.counts.data_ptr(), self.points.data_ptr(),
                                 self.responses.data_ptr(), self.descriptors.data_ptr(), self._ws.data_ptr(),
@@ -713,6 +761,7 @@ class LorbSet:
 
     def run_raw(self, frames, pattern: torch.Tensor, stream_handle: int) -> None:
         imgs = (StitchImage * self.nframes)(*[image_hwc(f) for f in frames])
+        _on_gpu(pattern, "pattern")
         check(lib().stitch_lorb_multi(self.nframes, imgs, self.mpf, self.areas, self.tf, self.t, self.n_max, self.nd,
                                       pattern.data_ptr(), self.counts.data_ptr(), self.points.data_ptr(),
                                       self.responses.data_ptr(), self.descriptors.data_ptr(), self._ws.data_ptr(),
@@ -759,6 +808,8 @@ class Matcher:
         self.dist = torch.full((self.cap_a,), -1, dtype=torch.int32, device=device)
 
     def run_raw(self, desc_a, count_a, desc_b, count_b, stream_handle: int) -> None:
+        for t, name in ((desc_a, "desc_a"), (count_a, "count_a"), (desc_b, "desc_b"), (count_b, "count_b")):
+            _on_gpu(t, name)
         check(lib().stitch_lsh_match(self.nd, desc_a.data_ptr(), count_a.data_ptr(), self.cap_a, desc_b.data_ptr(),
                                      count_b.data_ptr(), self.cap_b, self.tables, self.kbits, self.positions,
                                      self.max_dist, self.match.data_ptr(), self.dist.data_ptr(),
@@ -797,6 +848,9 @@ class Prosac:
         self.hyp_counts = torch.zeros(self.nhyp, dtype=torch.int32, device=device)
 
     def run_raw(self, pts_a, pts_b, match, dist, count_a, uniforms, stream_handle: int) -> None:
+        for t, name in ((pts_a, "pts_a"), (pts_b, "pts_b"), (match, "match"), (dist, "dist"), (count_a, "count_a"),
+                        (uniforms, "uniforms")):
+            _on_gpu(t, name)
         check(lib().stitch_prosac(pts_a.data_ptr(), pts_b.data_ptr(), self.cap_b, match.data_ptr(), dist.data_ptr(),
                                   count_a.data_ptr(), self.cap_a, self.nhyp, uniforms.data_ptr(), self.T_N, self.eps,
                                   self.H.data_ptr(), self.inliers.data_ptr(), self.mask.data_ptr(),

@@ -181,10 +181,19 @@ def test_pipe_validates_on_host():
     assert st == 0
     try:
         out = ctypes.c_void_p()
-        assert lib.stitch_pipe_create(None, 2, ctypes.byref(out)) == E["E_NULL"]
-        assert lib.stitch_pipe_create(h, 0, ctypes.byref(out)) == E["E_SHAPE"]
-        assert lib.stitch_pipe_create(h, 9, ctypes.byref(out)) == E["E_SHAPE"]
-        assert lib.stitch_pipe_create(h, 2, ctypes.byref(out)) == E["E_STATE"]   # no workspace bound
+        fake = 0x10000
+        # slots: each frame set and panorama, every buffer rounded up to 256 bytes
+        slot = sum(-(-w * hh * 3 // 256) * 256 for w, hh in wl.rig_c1().frame_sizes) + -(-1040 * 480 * 3 // 256) * 256
+        need = lib.stitch_pipe_workspace_bytes(h, 2)
+        assert need == 2 * slot
+        assert lib.stitch_pipe_workspace_bytes(h, 0) == 0 and lib.stitch_pipe_workspace_bytes(None, 2) == 0
+        assert lib.stitch_pipe_create(None, 2, fake, need, ctypes.byref(out)) == E["E_NULL"]
+        assert lib.stitch_pipe_create(h, 0, fake, need, ctypes.byref(out)) == E["E_SHAPE"]
+        assert lib.stitch_pipe_create(h, 9, fake, need, ctypes.byref(out)) == E["E_SHAPE"]
+        assert lib.stitch_pipe_create(h, 2, None, need, ctypes.byref(out)) == E["E_WORKSPACE"]
+        assert lib.stitch_pipe_create(h, 2, fake + 16, need, ctypes.byref(out)) == E["E_WORKSPACE"]
+        assert lib.stitch_pipe_create(h, 2, fake, need - 1, ctypes.byref(out)) == E["E_WORKSPACE"]
+        assert lib.stitch_pipe_create(h, 2, fake, need, ctypes.byref(out)) == E["E_STATE"]   # no workspace bound
         assert out.value is None
         assert lib.stitch_pipe_run(None, 1, None, None) == E["E_NULL"]
         assert lib.stitch_host_alloc(16, None) == E["E_NULL"]
@@ -285,6 +294,7 @@ def test_registration_calls_validate_on_host():
     assert prosac(pa=None) == E["E_NULL"]
     assert prosac(nhyp=0) == E["E_SHAPE"] and prosac(nhyp=65537) == E["E_SHAPE"]
     assert prosac(T_N=0.0) == E["E_SHAPE"] and prosac(eps=float("nan")) == E["E_SHAPE"]
+    assert prosac(T_N=2.0 ** 53 * 1.5) == E["E_SHAPE"] and prosac(T_N=float("inf")) == E["E_SHAPE"]
     assert prosac(cap_a=70000) == E["E_SHAPE"]
     need = lib.stitch_prosac_workspace_bytes(100, 512)
     assert need >= 512 * 9 * 8
@@ -372,3 +382,25 @@ def test_corner_parameterisation_matches_the_oracle_chain_rule():
     with pytest.raises(P.StitchError) as e:
         P.corners_to_h(flat, 64, 48)
     assert e.value.status == E["E_HOMOGRAPHY"]
+
+
+def test_binding_refuses_host_tensors_before_any_launch():
+    """A host tensor's address given to a device call would make the kernel fault; the
+    binding raises ValueError before anything reaches the library."""
+    import torch
+    t = torch.zeros((8, 8, 3), dtype=torch.uint8)
+    with pytest.raises(ValueError):
+        S.image_hwc(t)
+    with pytest.raises(ValueError):
+        S.image_chw(torch.zeros((3, 8, 8), dtype=torch.float32))
+    pat = torch.zeros((32, 4), dtype=torch.int32)
+    lorb = object.__new__(S.Lorb)
+    with pytest.raises(ValueError):
+        S.Lorb.run_raw(lorb, t, pat, 0)
+    pro = object.__new__(S.Prosac)
+    i32 = torch.zeros(8, dtype=torch.int32)
+    with pytest.raises(ValueError):
+        S.Prosac.run_raw(pro, i32, i32, i32, i32, i32, torch.zeros((4, 4), dtype=torch.float64), 0)
+    mat = object.__new__(S.Matcher)
+    with pytest.raises(ValueError):
+        S.Matcher.run_raw(mat, i32, i32, i32, i32, 0)

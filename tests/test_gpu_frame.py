@@ -104,10 +104,16 @@ def test_frames_at_odd_addresses_and_pitches_give_the_same_panorama(offset, pad)
     assert torch.equal(got, want)
 
 
-@pytest.mark.parametrize("seed", range(6))
+# uint8 outputs of the small-canvas tests, held together to the 0.01 % bound at the end
+RANDOM_RIG_U8 = {}
+
+
+@pytest.mark.parametrize("seed", range(12))
 def test_random_small_rigs(seed):
     """Odd and even canvases spanning several tiles with ragged tails, 1-3 cameras,
-    projective maps, noisy or cut seam weights, 1..5 levels."""
+    projective maps, noisy or cut seam weights, 1..5 levels.  Each rig: no uint8 sample off
+    by more than 1 and every float level within 1e-4; the 0.01 % bound on samples off by
+    one is held over all the rigs together (a single rig holds a few thousand samples)."""
     rng = np.random.default_rng(100 + seed)
     W = int(rng.integers(40, 300))
     H = int(rng.integers(24, 200))
@@ -128,8 +134,11 @@ def test_random_small_rigs(seed):
     masks = random_partition(rng, n, H, W, "noise" if seed % 2 else "cuts")
     plan, pano = _run(sizes, Hs, masks, W, H, L, frames)
     so = o.StitchOracle(frames, Hs, masks, W, H, L)
-    assert_u8_parity(pano, so.panorama(), max_frac=2e-3 if W * H < 20000 else 1e-3)
+    want = so.panorama()
+    assert_u8_parity(pano, want, max_frac=1.0)
+    RANDOM_RIG_U8[seed] = (pano.reshape(-1), want.reshape(-1))
     _check_intermediates(plan, so)
+
 
 
 def test_single_level_and_camera_outside_canvas():
@@ -142,7 +151,9 @@ def test_single_level_and_camera_outside_canvas():
     for L in (1, 3):
         plan, pano = _run([(90, 50)] * 3, Hs, masks, W, H, L, frames)
         so = o.StitchOracle(frames, Hs, masks, W, H, L)
-        assert_u8_parity(pano, so.panorama(), max_frac=2e-3)
+        want = so.panorama()
+        assert_u8_parity(pano, want, max_frac=1.0)
+        RANDOM_RIG_U8[("outside", L)] = (pano.reshape(-1), want.reshape(-1))
         _check_intermediates(plan, so)
         roi, band = plan.regions(2, 0)
         assert roi[2] == 0 and band[2] == 0
@@ -161,7 +172,9 @@ def test_footprint_beyond_the_horizon_is_stitched_exactly():
     roi, band = plan.regions(1, 0)
     assert band[2] > 0 and roi[0] <= band[0] - 8 and roi[0] + roi[2] >= min(W, band[0] + band[2] + 8)
     so = o.StitchOracle([frame, frame[::-1].copy()], [np.eye(3), Hp], masks, W, H, L)
-    assert_u8_parity(pano, so.panorama(), max_frac=2e-3)
+    want = so.panorama()
+    assert_u8_parity(pano, want, max_frac=1.0)
+    RANDOM_RIG_U8["horizon"] = (pano.reshape(-1), want.reshape(-1))
 
 
 def test_identity_rig_reproduces_the_input_exactly():
@@ -185,15 +198,33 @@ def test_c2_full_size_sampled_windows():
     r0, _ = plan.view("r", 0, 0)
     r0 = r0.cpu().numpy()
     so = o.StitchOracle(frames, r.H, masks, r.canvas_w, r.canvas_h, r.levels)
-    wins = [(0, 0), (0, 6384), (1064, 0), (1064, 6384), (530, 1560), (530, 3192), (530, 4824), (7, 2500),
-            (1060, 4000), (300, 100), (700, 6000), (540, 1568)]
+    # 64 windows of 32 x 32 (196,608 uint8 samples, so the 0.01 % bound is 19 samples):
+    # canvas corners and edges, the three seams, frame overhangs, and random points
+    wins = [(0, 0), (0, 6368), (1048, 0), (1048, 6368), (524, 1552), (524, 3184), (524, 4816), (7, 2500),
+            (1048, 4000), (300, 100), (700, 6000), (540, 1552), (0, 1552), (1048, 3184), (0, 4816), (200, 200)]
+    rng = np.random.default_rng(12)
+    while len(wins) < 64:
+        wins.append((int(rng.integers(0, 1080 - 32 + 1)), int(rng.integers(0, 6400 - 32 + 1))))
     got_u8, want_u8 = [], []
     for (y, x) in wins:
-        rows, cols = np.arange(y, min(y + 16, 1080)), np.arange(x, min(x + 16, 6400))
+        rows, cols = np.arange(y, y + 32), np.arange(x, x + 32)
         R = so.R(0, rows, cols)
         assert_float_parity(r0[:, rows[:, None], cols[None, :]], R, 1e-4, f"R0 window {(y, x)}")
         got_u8.append(pano[rows[:, None], cols[None, :]])
         want_u8.append(o.quantise(R))
         so.clear()
-    assert_u8_parity(np.concatenate([g.reshape(-1) for g in got_u8]),
-                     np.concatenate([w_.reshape(-1) for w_ in want_u8]), max_frac=2e-3)
+    got_u8 = np.concatenate([g.reshape(-1) for g in got_u8])
+    assert got_u8.size == 64 * 32 * 32 * 3
+    assert_u8_parity(got_u8, np.concatenate([w_.reshape(-1) for w_ in want_u8]), max_frac=1e-4)
+
+
+def test_small_canvases_together_hold_the_uint8_bound():
+    """The random rigs, the single-level / off-canvas rig and the horizon rig: each holds a
+    few thousand samples (one off-by-one is already 0.01 %), so the bound on samples off by
+    one is checked over all of them together (run after them, in file order)."""
+    if len([k for k in RANDOM_RIG_U8 if isinstance(k, int)]) < 12:
+        pytest.skip("runs after the random rigs of this file")
+    got = np.concatenate([g for g, _ in RANDOM_RIG_U8.values()])
+    want = np.concatenate([w for _, w in RANDOM_RIG_U8.values()])
+    assert got.size >= 100_000, got.size
+    assert_u8_parity(got, want, max_frac=1e-4)

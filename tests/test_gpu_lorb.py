@@ -95,6 +95,26 @@ def test_ragged_clipped_and_empty_areas():
     _check(frame, [(0, 0, 640, 480)], n=1)
 
 
+def test_threshold_equal_to_a_response_keeps_that_corner():
+    """Alg. 1, step 5 keeps a response equal to t: with t set to the response of one of
+    the area's candidates, the GPU keeps exactly what the oracle keeps, that corner among
+    them, and t + 1 drops it."""
+    rig = wl.rig_c1()
+    frame = wl.render_rig_frames(rig)[0].numpy()
+    area = (200, 100, 96, 64)
+    g = lo.gray(frame)
+    surv = sorted(lo.suppress(lo.candidates(g, area, 20, 0), frame.shape[1]), key=lambda k: k[2])
+    x, y, r = surv[len(surv) // 2]     # a survivor stays one when t removes weaker neighbours
+    assert _check(frame, [area], t=r, n=2000) >= 1
+    h, w = frame.shape[:2]
+    lorb = P.Lorb(w, h, [area], n_max=2000, harris_threshold=r)
+    pts = lorb.run(torch.from_numpy(frame).cuda(), torch.from_numpy(wl.brief_pattern(256, seed=256)).cuda())[0][0]
+    assert [x, y] in pts.tolist()
+    lorb1 = P.Lorb(w, h, [area], n_max=2000, harris_threshold=r + 1)
+    pts1 = lorb1.run(torch.from_numpy(frame).cuda(), torch.from_numpy(wl.brief_pattern(256, seed=256)).cuda())[0][0]
+    assert [x, y] not in pts1.tolist()
+
+
 def test_noise_frame_and_strided_view():
     """Uniform noise (a dense field of candidates) read through a frame view whose rows are
     longer than the frame (row pitch 3 * 700 bytes)."""

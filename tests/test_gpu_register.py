@@ -233,10 +233,29 @@ def test_matching_with_the_most_tables_and_key_bits():
     assert got_idx.tolist() == want_idx.tolist() and got_d.tolist() == want_d.tolist()
 
 
+@pytest.mark.parametrize("T_N, nhyp", [(300.0, 2048), (5000.0, 1024)])
+def test_prosac_past_the_last_growth_step(T_N, nhyp):
+    """A small T_N makes the subset reach all M matches early; every later hypothesis draws
+    its 4 matches from the whole top-M set (T'_n < t), the branch a large T_N never reaches.
+    Every hypothesis' count, the inliers and H against the oracle."""
+    H = _H()
+    rng = np.random.default_rng(int(T_N))
+    pa = rng.integers(0, 600, (150, 2))
+    pb = np.array([np.rint(_apply(H, p)) for p in pa]).astype(np.int64)
+    pb[90:] = rng.integers(0, 800, (60, 2))
+    dist = rng.integers(0, 100, 150)
+    sizes = ro.subset_sizes(150, nhyp, T_N)
+    uniform = [t for t, (n, nth) in enumerate(sizes) if not nth]
+    assert len(uniform) > nhyp // 3 and all(sizes[t][0] == 150 for t in uniform)
+    got = _check_prosac(pa, pb, np.arange(150), dist, 150, np.random.default_rng(3).random((nhyp, 4)), T_N=T_N)
+    assert got["inliers"] >= 80
+
+
 def test_the_largest_hypothesis_budget_extends_a_smaller_one():
-    """65536 hypotheses (the maximum): the first 1024 are the same hypotheses as a budget of
-    1024 (the schedule depends on t only, the uniforms are a prefix), so their inlier counts
-    agree and the larger budget's best is at least as good."""
+    """65536 hypotheses (the maximum): every hypothesis' count, the inlier set and H equal
+    the oracle's; the first 1024 are the same hypotheses as a budget of 1024 (the schedule
+    depends on t only, the uniforms are a prefix), so their inlier counts agree and the
+    larger budget's best is at least as good."""
     H = _H()
     rng = np.random.default_rng(41)
     pa = rng.integers(0, 600, (150, 2))
@@ -246,6 +265,6 @@ def test_the_largest_hypothesis_budget_extends_a_smaller_one():
     us = np.random.default_rng(42).random((65536, 4))
     args = (_dev(pa), _dev(pb), _dev(np.arange(150)), _dev(dist), _dev([150]))
     small = P.Prosac(150, 150, 1024, 200000.0, 2.0).run(*args, _dev(us[:1024], torch.float64))
-    big = P.Prosac(150, 150, 65536, 200000.0, 2.0).run(*args, _dev(us, torch.float64))
+    big = _check_prosac(pa, pb, np.arange(150), dist, 150, us)
     assert np.array_equal(big["hyp_counts"][:1024], small["hyp_counts"])
     assert big["hyp_counts"].max() >= small["hyp_counts"].max() and big["inliers"] >= 60

@@ -129,3 +129,16 @@ def test_equal_responses_go_to_the_first_in_raster_order():
     assert [(x, y) for x, y, _ in sel] == [(20, 8), (10, 5), (50, 1)]   # R 9, 7, then the first R 5
     sel = lo.select(lo.suppress(cand, w), 6, w)
     assert [(x, y) for x, y, _ in sel][2:] == [(50, 1), (40, 2), (60, 2), (30, 3)]
+
+
+def test_threshold_keeps_a_response_equal_to_t():
+    """Alg. 1, step 5 deletes the corners whose response is less than t: a FAST corner with
+    R == t stays a candidate, and raising t by one removes it."""
+    g = np.full((48, 48), 60, dtype=np.int64)
+    g[24:, 24:] = 190
+    assert lo.fast_corner(g, 24, 24, 20)
+    r = lo.harris(g, 24, 24)
+    rect = (20, 20, 9, 9)
+    assert lo.candidates(g, rect, 20, r).get((24, 24)) == r
+    assert (24, 24) not in lo.candidates(g, rect, 20, r + 1)
+    assert lo.candidates(g, rect, 20, r - 1).get((24, 24)) == r
