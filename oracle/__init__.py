@@ -9,5 +9,6 @@ from .stitch_oracle import (  # noqa: F401
     blend_pyramids, StitchOracle, check_masks,
 )
 from .adjoint_oracle import (  # noqa: F401
-    GradOracle, dlt_from_corners, dlt_jacobian, canvas_map_jacobian, reduce_T, expand_T, corners,
+    GradOracle, FrameVjpOracle, dlt_from_corners, dlt_jacobian, canvas_map_jacobian, reduce_T, expand_T,
+    corners,
 )

@@ -273,3 +273,144 @@ class GradOracle:
         dH = canvas_map_jacobian(H1).T @ d_M[1].ravel()
         dq = dlt_jacobian(q, w, h).T @ dH
         return st["loss"], dq, d_frames
+
+
+# ----------------------------------------------------------------------------- the whole path's VJP
+class FrameVjpOracle:
+    """The stitching path of any number of cameras as a function of FLOAT frames and the
+    cameras' canvas -> source maps, R_0 = F(frames, M) (Alg. 4 steps 1 and 6, before
+    quantisation), and its vector-Jacobian product: given an upstream dl/dR_0 (and
+    optionally a direct dl/dG_0 per camera, a term on the warped frame itself), the
+    gradients dl/dframe_i and dl/dM_i.
+
+    Readings: the maps are the FP32 normalised inverses of the source -> canvas homographies
+    (R3, 'spec') or their FP64 values ('ideal'); the bilinear cell is floor of the source
+    coordinates at the given maps (at integers the right derivative), fixed while
+    differentiating; every array lives on the full canvas (R12); masks are the plan's uint8
+    seam weights (R9).  Transposes scatter every tap back with np.add.at, as GradOracle."""
+
+    def __init__(self, frames, Hs, masks, canvas_w: int, canvas_h: int, levels: int, coords: str = "spec"):
+        self.frames = [np.asarray(f, dtype=np.float64) for f in frames]
+        self.Hs = [np.asarray(h, dtype=np.float64) for h in Hs]
+        self.masks = [np.asarray(m, dtype=np.uint8) for m in masks]
+        self.W, self.H, self.L = canvas_w, canvas_h, levels
+        self.dims = level_dims(canvas_h, canvas_w, levels)
+        self.coords = coords
+        self.gm = []
+        for m in self.masks:
+            g = [m[None].astype(np.float64) / 255.0]
+            for _ in range(levels - 1):
+                g.append(reduce_full(g[-1]))
+            self.gm.append(g)
+        self.M = [hinv_ideal(h).astype(np.float32) if coords == "spec" else hinv_ideal(h) for h in self.Hs]
+        self.cells = [self._cell(M) for M in self.M]
+
+    def _coords(self, M):
+        ft = np.float32 if M.dtype == np.float32 else np.float64
+        g = M.ravel().astype(ft)
+        X = np.arange(self.W, dtype=ft)[None, :]
+        Y = np.arange(self.H, dtype=ft)[:, None]
+        with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+            u = (g[0] * X + g[1] * Y) + g[2]
+            v = (g[3] * X + g[4] * Y) + g[5]
+            z = (g[6] * X + g[7] * Y) + g[8]
+            x = u / z
+            y = v / z
+        return x, y, z.astype(np.float64) > 0      # x, y in the maps' precision
+
+    def _cell(self, M):
+        x, y, zpos = self._coords(M)
+        ok = zpos & np.isfinite(x) & np.isfinite(y) & (np.abs(x) < 1e7) & (np.abs(y) < 1e7)
+        with np.errstate(invalid="ignore"):
+            x0 = np.where(ok, np.floor(np.where(ok, x, 0.0)), -10).astype(np.int64)
+            y0 = np.where(ok, np.floor(np.where(ok, y, 0.0)), -10).astype(np.int64)
+        return x0, y0, ok
+
+    def _warp(self, f, M, cell):
+        """G_0 of a float frame through M with the fixed cell; taps outside count 0."""
+        h, w = f.shape[1:]
+        x, y, _ = self._coords(M)
+        x0, y0, ok = cell
+        # the fraction in the coordinates' precision, as the forward path takes it (R3):
+        # for -1 < x < 0 the FP32 difference x - (-1) is rounded
+        with np.errstate(invalid="ignore", over="ignore"):
+            fx = np.where(ok, (x - x0.astype(x.dtype)).astype(np.float64), 0.0)
+            fy = np.where(ok, (y - y0.astype(y.dtype)).astype(np.float64), 0.0)
+        x, y = x.astype(np.float64), y.astype(np.float64)
+        taps, okt = [], []
+        for dy, dx in ((0, 0), (0, 1), (1, 0), (1, 1)):
+            yy, xx = y0 + dy, x0 + dx
+            k = ok & (yy >= 0) & (yy < h) & (xx >= 0) & (xx < w)
+            taps.append(np.where(k[None], f[:, np.clip(yy, 0, h - 1), np.clip(xx, 0, w - 1)], 0.0))
+            okt.append(k)
+        val = (1 - fy) * ((1 - fx) * taps[0] + fx * taps[1]) + fy * ((1 - fx) * taps[2] + fx * taps[3])
+        return val, dict(x=x, y=y, fx=fx, fy=fy, ok=ok, taps=taps, okt=okt)
+
+    def _collapse_of(self, G0s):
+        laps = []
+        for g in G0s:
+            gp = [g]
+            for _ in range(self.L - 1):
+                gp.append(reduce_full(gp[-1]))
+            laps.append([gp[k] - expand_full(gp[k + 1], *gp[k].shape[-2:]) for k in range(self.L - 1)] + [gp[-1]])
+        B = [sum(self.gm[i][k] * laps[i][k] for i in range(len(G0s))) for k in range(self.L)]
+        R = B[-1]
+        for k in range(self.L - 2, -1, -1):
+            R = B[k] + expand_full(R, *B[k].shape[-2:])
+        return R
+
+    def forward(self, frames=None, maps=None):
+        """R_0 (3, H, W) of the float frames through the maps (default: the object's own),
+        with the cells fixed at the object's maps."""
+        frames = self.frames if frames is None else [np.asarray(f, dtype=np.float64) for f in frames]
+        maps = self.M if maps is None else maps
+        return self._collapse_of([self._warp(f, M, c)[0] for f, M, c in zip(frames, maps, self.cells)])
+
+    def vjp(self, dR0, dG0=None):
+        """(d_frames, d_M) for the upstream gradient dR0 (3, H, W) and optional direct
+        gradients dG0[i] (3, H, W) on the warped frames."""
+        L = self.L
+        dR = [np.asarray(dR0, dtype=np.float64)]
+        for _ in range(L - 1):
+            dR.append(expand_T(dR[-1]))
+        d_frames, d_M = [], []
+        for i, f in enumerate(self.frames):
+            dL = [self.gm[i][k] * dR[k] for k in range(L)]
+            if L == 1:
+                dG = dL[0]
+            else:
+                g = dL[L - 1] - expand_T(dL[L - 2])
+                for k in range(L - 2, 0, -1):
+                    g = dL[k] - expand_T(dL[k - 1]) + reduce_T(g, *self.dims[k])
+                dG = dL[0] + reduce_T(g, *self.dims[0])
+            if dG0 is not None and dG0[i] is not None:
+                dG = dG + dG0[i]
+            df, dm = self._warp_T(f, self.M[i], self.cells[i], dG)
+            d_frames.append(df)
+            d_M.append(dm)
+        return d_frames, d_M
+
+    def _warp_T(self, f, M, cell, dG):
+        h, w = f.shape[1:]
+        _, a = self._warp(f, M, cell)
+        x0, y0, ok = cell
+        fx, fy = a["fx"], a["fy"]
+        wts = [(1 - fy) * (1 - fx), (1 - fy) * fx, fy * (1 - fx), fy * fx]
+        df = np.zeros_like(f)
+        for wt, (dy, dx), k in zip(wts, ((0, 0), (0, 1), (1, 0), (1, 1)), a["okt"]):
+            for c in range(3):
+                np.add.at(df[c], ((y0 + dy)[k], (x0 + dx)[k]), (wt * dG[c])[k])
+        p00, p01, p10, p11 = a["taps"]
+        gx = np.sum(dG * ((1 - fy) * (p01 - p00) + fy * (p11 - p10)), axis=0) * ok
+        gy = np.sum(dG * ((1 - fx) * (p10 - p00) + fx * (p11 - p01)), axis=0) * ok
+        g = M.ravel().astype(np.float64)
+        X = np.arange(self.W, dtype=np.float64)[None, :]
+        Y = np.arange(self.H, dtype=np.float64)[:, None]
+        z = (g[6] * X + g[7] * Y) + g[8]
+        x, y = a["x"], a["y"]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            iz = np.where(ok, 1.0 / z, 0.0)
+            s = -(gx * np.where(ok, x, 0.0) + gy * np.where(ok, y, 0.0)) * iz
+            terms = [gx * X * iz, gx * Y * iz, gx * iz, gy * X * iz, gy * Y * iz, gy * iz, s * X, s * Y, s]
+        dm = np.array([np.sum(np.where(ok, t, 0.0)) for t in terms]).reshape(3, 3)
+        return df, dm

@@ -138,3 +138,89 @@ def test_single_level_loss_closed_form():
     om = st["omega"]
     want = np.sum((((1 - m) ** 2 + m ** 2)[None] * (A - B) ** 2)[:, om]) / (6.0 * om.sum())
     assert abs(st["loss"] - want) <= 1e-12 * want
+
+
+# ----------------------------------------------------------------------------- the whole path's VJP
+def _rig3(seed=3, W=61, H=37, L=3):
+    """Three float frames with projective maps on a small odd canvas, noisy seam weights."""
+    from helpers import random_partition
+    rng = np.random.default_rng(seed)
+    frames_u8, Hs = [], []
+    for i in range(3):
+        fw, fh = int(rng.integers(24, 40)), int(rng.integers(20, 34))
+        frames_u8.append(rng.integers(0, 256, (fh, fw, 3), dtype=np.uint8))
+        A = np.eye(3) + rng.normal(0, [[0.03, 0.03, 0], [0.03, 0.03, 0], [4e-4, 4e-4, 0]])
+        A[0, 2] = rng.uniform(-4, W - fw + 4)
+        A[1, 2] = rng.uniform(-3, H - fh + 3)
+        Hs.append(A)
+    masks = random_partition(rng, 3, H, W, "noise")
+    return frames_u8, Hs, masks, W, H, L
+
+
+def test_vjp_forward_of_byte_frames_is_the_stitch_oracle():
+    """F(u8/255 frames) is R_0 of the forward oracle (the same warp, pyramids and blend)."""
+    fu8, Hs, masks, W, H, L = _rig3()
+    fo = o.FrameVjpOracle([np.moveaxis(f, -1, 0) / 255.0 for f in fu8], Hs, masks, W, H, L)
+    want = o.StitchOracle(fu8, Hs, masks, W, H, L).R(0)
+    assert np.max(np.abs(fo.forward() - want)) <= 1e-12
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_vjp_frames_satisfy_the_dot_product_identity(L):
+    """R_0 is linear in the frames (fixed maps and cells): <F(v), u> = sum_i <v_i, J_i^T u>,
+    and a direct term on G_0 enters as the warp's own transpose."""
+    fu8, Hs, masks, W, H, _ = _rig3(seed=4 + L)
+    rng = np.random.default_rng(L)
+    fo = o.FrameVjpOracle([np.moveaxis(f, -1, 0) / 255.0 for f in fu8], Hs, masks, W, H, L)
+    v = [rng.normal(size=(3,) + f.shape[:2]) for f in fu8]
+    u = rng.normal(size=(3, H, W))
+    lhs = float(np.sum(fo.forward(frames=v) * u))
+    d_frames, _ = fo.vjp(u)
+    rhs = sum(float(np.sum(a * b)) for a, b in zip(v, d_frames))
+    assert abs(lhs - rhs) <= 1e-11 * max(1.0, abs(lhs))
+    g = [rng.normal(size=(3, H, W)) for _ in fu8]
+    d_frames2, _ = fo.vjp(np.zeros((3, H, W)), g)
+    lhs2 = sum(float(np.sum(fo._warp(vi, M, c)[0] * gi)) for vi, M, c, gi in zip(v, fo.M, fo.cells, g))
+    rhs2 = sum(float(np.sum(a * b)) for a, b in zip(v, d_frames2))
+    assert abs(lhs2 - rhs2) <= 1e-11 * max(1.0, abs(lhs2))
+
+
+def test_vjp_maps_match_central_differences():
+    """d<F, u>/dM_i against FP64 central differences of the map entries (FP64 maps, cells
+    fixed, so the piece is smooth), every camera and entry."""
+    fu8, Hs, masks, W, H, L = _rig3(seed=9)
+    fo = o.FrameVjpOracle([np.moveaxis(f, -1, 0) / 255.0 for f in fu8], Hs, masks, W, H, L, coords="ideal")
+    u = np.random.default_rng(2).normal(size=(3, H, W))
+    _, d_M = fo.vjp(u)
+    for i in range(3):
+        M = fo.M[i]
+        fd = np.zeros(9)
+        for j in range(9):
+            step = 1e-6 * max(abs(M.flat[j]), 1e-4)
+            maps_p = [m.copy() for m in fo.M]
+            maps_m = [m.copy() for m in fo.M]
+            maps_p[i].flat[j] += step
+            maps_m[i].flat[j] -= step
+            fd[j] = (np.sum(fo.forward(maps=maps_p) * u) - np.sum(fo.forward(maps=maps_m) * u)) / (2 * step)
+        an = d_M[i].ravel()
+        assert np.linalg.norm(an - fd) <= 1e-6 * np.linalg.norm(fd), (i, an, fd)
+
+
+def test_vjp_gives_the_pair_loss_gradient():
+    """The overlap loss of a pair through the VJP (dl/dP upstream, dl/dA and dl/dB as direct
+    terms on the warped frames) equals the pair-loss oracle's own adjoint."""
+    rig, frames, go, q0, frozen, w, h = _setup()
+    H1 = o.dlt_from_corners(q0, w, h)
+    st = go.forward([np.eye(3), H1], frozen)
+    d_frames, d_M = go.backward(st)
+    fo = o.FrameVjpOracle(frames, [np.eye(3), H1], rig.masks(), rig.canvas_w, rig.canvas_h, rig.levels,
+                          coords="ideal")
+    om = st["omega"][None].astype(np.float64)
+    n = st["n"]
+    gP = (2.0 / (6.0 * n)) * ((st["P"] - st["G"][0]) + (st["P"] - st["G"][1])) * om
+    gd = [-(2.0 / (6.0 * n)) * (st["P"] - st["G"][i]) * om for i in range(2)]
+    vf, vm = fo.vjp(gP, gd)
+    for a, b in zip(vf, d_frames):
+        assert np.max(np.abs(a - b)) <= 1e-12 * max(1e-30, np.max(np.abs(b))) + 1e-18
+    for a, b in zip(vm, d_M):
+        assert np.allclose(a, b, rtol=1e-10, atol=1e-14 * np.max(np.abs(b)))
