@@ -371,7 +371,44 @@ stitch_status stitch_grad_forward(stitch_grad* grad, const stitch_image* frames,
  * the warp uses.  Synchronises the stream.  Errors: NULL, STATE, SHAPE, UNSUPPORTED,
  * DEVICE. */
 stitch_status stitch_grad_backward(stitch_grad* grad, stitch_image* d_frames, double d_map[18], void* stream);
+/* The last forward's gradients as the upstream terms of stitch_frame_backward: d_pano =
+ * dl/dP and d_warped[i] = dl/dG_0 of frame i taken directly (the loss's own terms on the
+ * warped frames), each F32 CHW, 3 channels, canvas-sized; queued on the stream.  Feeding
+ * them to stitch_frame_backward with a plan of the pair at the frozen maps gives this loss's
+ * gradient.  Errors: NULL, STATE, SHAPE, DEVICE. */
+stitch_status stitch_grad_upstream(stitch_grad* grad, stitch_image* d_pano, stitch_image* d_warped, void* stream);
 void          stitch_grad_destroy(stitch_grad* grad);
+
+/* The whole path of a plan as a differentiable function of FLOAT frames: for frames F_i
+ * (F32 CHW, 3 channels, the planned sizes, values in [0, 1]) the blended and collapsed
+ * panorama before quantisation, R_0 = F(F_1..F_n, M_1..M_n) (Alg. 4 steps 1 and 6, with the
+ * definitions at the top of this file), where M_i is the FP32 canvas -> source map the warp
+ * uses.  Every array lives on the whole canvas in FP64; the bilinear cell of a canvas pixel
+ * is floor of its FP32 source coordinates at the plan's maps (the right derivative at
+ * integers) and the fraction x - floor(x) is the FP32 one, as in stitch_frame.  Meant for
+ * refining registration (Alg. 3 / Alg. 4 step 5 give the maps), not for the throughput path:
+ * canvases up to 2^26 pixels.  The plan needs no bound workspace; both calls take a
+ * workspace of stitch_frame_backward_workspace_bytes(plan) bytes (256-byte aligned; about
+ * 140 bytes per canvas pixel; 0 on bad arguments).
+ *
+ * stitch_frame_forward_f32: r0 (F32 CHW, 3 channels, canvas size) receives R_0.  Queued on
+ * the stream (waits only for the upload of each camera's seam weights).
+ * Errors: NULL, SHAPE, WORKSPACE, HOMOGRAPHY, DEVICE. */
+size_t        stitch_frame_backward_workspace_bytes(const stitch_plan* plan);
+stitch_status stitch_frame_forward_f32(stitch_plan* plan, const stitch_image* frames, stitch_image* r0,
+                                       void* workspace, size_t workspace_bytes, void* stream);
+/* Vector-Jacobian product of F: given d_pano = dl/dR_0 (F32 CHW, 3 channels, canvas size)
+ * and optionally d_warped (NULL, or n images of which those with data NULL are skipped:
+ * dl/dG_0 of camera i taken directly on its warped frame, F32 CHW canvas-sized), writes
+ * d_frames[i] = dl/dF_i (F32 CHW, the frame's size; overwritten) and d_hinv[9 i + j] =
+ * dl/dM_i[j] (HOST, n x 9 doubles, row-major).  The frame transpose gathers over the canvas
+ * pixels whose cell holds each source pixel (deterministic, no atomics); maps that magnify a
+ * source pixel more than about 20 times, or whose horizon crosses a frame, return
+ * UNSUPPORTED.  Synchronises the stream.  Errors: NULL, SHAPE, WORKSPACE, HOMOGRAPHY,
+ * UNSUPPORTED, DEVICE. */
+stitch_status stitch_frame_backward(stitch_plan* plan, const stitch_image* frames, const stitch_image* d_pano,
+                                    const stitch_image* d_warped, stitch_image* d_frames, double* d_hinv,
+                                    void* workspace, size_t workspace_bytes, void* stream);
 
 /* Corner parameterisation of a homography (host, FP64): H (h33 = 1) is the direct linear
  * transform taking the frame corners (0,0), (w-1,0), (w-1,h-1), (0,h-1) to the canvas

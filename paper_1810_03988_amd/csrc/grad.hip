@@ -359,6 +359,174 @@ __global__ void __launch_bounds__(kT) k_gzero(double* __restrict__ out, int64_t 
 
 int blocks(int64_t n) { return (int)((n + kT - 1) / kT); }
 
+// ------------------------------------------------------------------------------------
+// The whole path as a function of float frames and the cameras' maps, and its
+// vector-Jacobian product (any number of cameras, full-canvas FP64 arrays).  The bilinear
+// cell is floor of the forward path's FP32 coordinates at the plan's maps, and the
+// fraction x - floor(x) is taken in FP32 as the forward path takes it.
+
+struct VCam {
+  Map9 m;            // canvas -> source, FP32
+  double hf[9];      // source -> canvas: the FP64 inverse of m (w = 1/z > 0 where z > 0)
+  int fw, fh;
+  const float* src;  // float CHW frame (elements)
+  int64_t srow, splane;
+};
+
+// The forward path's coordinate sequence at canvas pixel (X, Y): FP32 coordinates, the
+// cell, the fraction in FP32, and whether the sample is defined (z > 0, finite).
+__device__ __forceinline__ bool vcell(const float* h, int X, int Y, int& x0, int& y0, double& fx, double& fy,
+                                      double& xd, double& yd) {
+  float x, y;
+  bool zpos;
+  double z;
+  gcoords(h, X, Y, x, y, zpos, z);
+  if (!(zpos && fabsf(x) < 1.0e7f && fabsf(y) < 1.0e7f)) return false;
+  const float xf = floorf(x), yf = floorf(y);
+  x0 = (int)xf;
+  y0 = (int)yf;
+  fx = (double)(x - xf);
+  fy = (double)(y - yf);
+  xd = (double)x;
+  yd = (double)y;
+  return true;
+}
+
+// Full-canvas weight plane (u8 / 255) from the weights on their support box.
+__global__ void __launch_bounds__(kT) k_vmask(const uint8_t* __restrict__ w, int wx, int wy, int ww, int wh, int W,
+                                              int H, double* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (p >= (int64_t)W * H) return;
+  const int X = (int)(p % W), Y = (int)(p / W);
+  const int x = X - wx, y = Y - wy;
+  out[p] = (w && x >= 0 && x < ww && y >= 0 && y < wh) ? (double)w[(int64_t)y * ww + x] / 255.0 : 0.0;
+}
+
+// out (3 planes, W x H) = [out +] a pitched F32 CHW image.
+__global__ void __launch_bounds__(kT) k_vfromf32(const float* __restrict__ in, int64_t row, int64_t plane, int W,
+                                                 int H, int add, double* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+  const int64_t np = (int64_t)W * H;
+  if (p >= 3 * np) return;
+  const int c = (int)(p / np);
+  const int64_t q = p - c * np;
+  const double v = (double)in[c * plane + (q / W) * row + (q % W)];
+  out[p] = add ? out[p] + v : v;
+}
+
+// G_0 of a float frame at the current cells; taps outside the frame count 0.
+__global__ void __launch_bounds__(kT) k_vwarp(VCam c, int W, int H, double* __restrict__ G) {
+  const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+  const int64_t np = (int64_t)W * H;
+  if (p >= np) return;
+  const int X = (int)(p % W), Y = (int)(p / W);
+  int x0, y0;
+  double fx, fy, xd, yd;
+  const bool ok = vcell(c.m.h, X, Y, x0, y0, fx, fy, xd, yd);
+  for (int ch = 0; ch < 3; ++ch) {
+    double v = 0.0;
+    if (ok) {
+      double t[4];
+      for (int k = 0; k < 4; ++k) {
+        const int xx = x0 + (k & 1), yy = y0 + (k >> 1);
+        t[k] = (xx >= 0 && xx < c.fw && yy >= 0 && yy < c.fh) ? (double)c.src[ch * c.splane + (int64_t)yy * c.srow + xx]
+                                                               : 0.0;
+      }
+      v = (1.0 - fy) * ((1.0 - fx) * t[0] + fx * t[1]) + fy * ((1.0 - fx) * t[2] + fx * t[3]);
+    }
+    G[ch * np + p] = v;
+  }
+}
+
+// Transpose of the warp with respect to the frame, as a gather (deterministic, no
+// atomics): source pixel (x, y) collects w * dG from every canvas pixel whose cell holds it
+// as a tap.  Those canvas pixels map into the source square [x-1, x+1) x [y-1, y+1), so the
+// candidates are the canvas pixels in that square's image under the inverse map, one pixel
+// wider for the FP32 rounding of the coordinates.  A candidate box over 48 pixels a side (a
+// map magnifying about 20 times) or a square reaching the map's horizon sets *flag.
+__global__ void __launch_bounds__(kT) k_vwarpT(VCam c, int W, int H, const double* __restrict__ dG,
+                                               float* __restrict__ dsrc, int64_t drow, int64_t dplane,
+                                               int* __restrict__ flag) {
+  const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (p >= (int64_t)c.fw * c.fh) return;
+  const int x = (int)(p % c.fw), y = (int)(p / c.fw);
+  const int64_t np = (int64_t)W * H;
+  double bx0 = 1e300, bx1 = -1e300, by0 = 1e300, by1 = -1e300;
+  bool bounded = true;
+  for (int k = 0; k < 4; ++k) {
+    const double sx = (double)(x - 1 + 2 * (k & 1)), sy = (double)(y - 1 + (k & 2));
+    const double w = (c.hf[6] * sx + c.hf[7] * sy) + c.hf[8];
+    if (!(w > 0.0)) { bounded = false; break; }
+    const double X = ((c.hf[0] * sx + c.hf[1] * sy) + c.hf[2]) / w;
+    const double Y = ((c.hf[3] * sx + c.hf[4] * sy) + c.hf[5]) / w;
+    bx0 = fmin(bx0, X); bx1 = fmax(bx1, X); by0 = fmin(by0, Y); by1 = fmax(by1, Y);
+  }
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (bounded && bx1 >= -2.0 && by1 >= -2.0 && bx0 <= W + 1.0 && by0 <= H + 1.0) {
+    if (bx1 - bx0 > 46.0 || by1 - by0 > 46.0) {
+      atomicOr(flag, 1);
+    } else {
+      const int X0 = max(0, (int)floor(bx0) - 1), X1 = min(W - 1, (int)ceil(bx1) + 1);
+      const int Y0 = max(0, (int)floor(by0) - 1), Y1 = min(H - 1, (int)ceil(by1) + 1);
+      for (int Y = Y0; Y <= Y1; ++Y)
+        for (int X = X0; X <= X1; ++X) {
+          int x0, y0;
+          double fx, fy, xd, yd;
+          if (!vcell(c.m.h, X, Y, x0, y0, fx, fy, xd, yd)) continue;
+          const int a = x - x0, b = y - y0;
+          if (a < 0 || a > 1 || b < 0 || b > 1) continue;
+          const double wt = (a ? fx : 1.0 - fx) * (b ? fy : 1.0 - fy);
+          const int64_t q = (int64_t)Y * W + X;
+          for (int ch = 0; ch < 3; ++ch) acc[ch] += wt * dG[ch * np + q];
+        }
+    }
+  } else if (!bounded) {
+    atomicOr(flag, 2);
+  }
+  for (int ch = 0; ch < 3; ++ch) dsrc[ch * dplane + (int64_t)y * drow + x] = (float)acc[ch];
+}
+
+// Transpose of the warp with respect to the map's nine entries: per block partial sums of
+// dl/dM (deterministic), from the coordinates' derivative at each canvas pixel.
+__global__ void __launch_bounds__(kT) k_vmapT(VCam c, int W, int H, const double* __restrict__ dG,
+                                              double* __restrict__ part9) {
+  __shared__ double sh[kT / 64];
+  const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+  const int64_t np = (int64_t)W * H;
+  double t9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (p < np) {
+    const int X = (int)(p % W), Y = (int)(p / W);
+    int x0, y0;
+    double fx, fy, xd, yd;
+    if (vcell(c.m.h, X, Y, x0, y0, fx, fy, xd, yd)) {
+      double gx = 0.0, gy = 0.0;
+      for (int ch = 0; ch < 3; ++ch) {
+        const double g = dG[ch * np + p];
+        double t[4];
+        for (int k = 0; k < 4; ++k) {
+          const int xx = x0 + (k & 1), yy = y0 + (k >> 1);
+          t[k] = (xx >= 0 && xx < c.fw && yy >= 0 && yy < c.fh)
+                     ? (double)c.src[ch * c.splane + (int64_t)yy * c.srow + xx] : 0.0;
+        }
+        gx += g * ((1 - fy) * (t[1] - t[0]) + fy * (t[3] - t[2]));
+        gy += g * ((1 - fx) * (t[2] - t[0]) + fx * (t[3] - t[1]));
+      }
+      if (gx != 0.0 || gy != 0.0) {
+        const float* h = c.m.h;
+        const double z = ((double)h[6] * (double)X + (double)h[7] * (double)Y) + (double)h[8];
+        const double iz = 1.0 / z, s = -(gx * xd + gy * yd) * iz;
+        t9[0] = gx * X * iz; t9[1] = gx * Y * iz; t9[2] = gx * iz;
+        t9[3] = gy * X * iz; t9[4] = gy * Y * iz; t9[5] = gy * iz;
+        t9[6] = s * X; t9[7] = s * Y; t9[8] = s;
+      }
+    }
+  }
+  for (int k = 0; k < 9; ++k) {
+    const double t = block_sum(t9[k], sh);
+    if (threadIdx.x == 0) part9[(int64_t)blockIdx.x * 9 + k] = t;
+  }
+}
+
 }  // namespace
 
 // ==================================================================================== host
@@ -708,7 +876,284 @@ stitch_status stitch_grad_backward(stitch_grad* g, stitch_image* d_frames, doubl
   return STITCH_OK;
 }
 
+stitch_status stitch_grad_upstream(stitch_grad* g, stitch_image* d_pano, stitch_image* d_warped, void* stream) {
+  if (!g || !d_pano || !d_warped) return fail(STITCH_E_NULL, "grad, d_pano or d_warped is NULL");
+  if (!g->have_forward) return fail(STITCH_E_STATE, "call stitch_grad_forward first");
+  stitch_image* outs[3] = {d_pano, &d_warped[0], &d_warped[1]};
+  const char* names[3] = {"d_pano", "d_warped[0]", "d_warped[1]"};
+  for (int i = 0; i < 3; ++i) {
+    const stitch_status st = check_image(outs[i], names[i], STITCH_F32, STITCH_CHW, 3);
+    if (st) return st;
+    if (outs[i]->width != g->W || outs[i]->height != g->H) return fail(STITCH_E_SHAPE, "%s is not canvas-sized", names[i]);
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  const size_t src[3] = {g->o_gp, g->o_ga, g->o_gb};
+  for (int i = 0; i < 3; ++i)
+    hipLaunchKernelGGL(k_gtof32, dim3(blocks(3 * (int64_t)g->W * g->H)), dim3(kT), 0, s, g->dptr(src[i]),
+                       (float*)outs[i]->data, g->W, g->H, outs[i]->row_pitch / 4, outs[i]->plane_pitch / 4);
+  return dev_ok(hipGetLastError(), "upstream launch");
+}
+
 void stitch_grad_destroy(stitch_grad* g) { delete g; }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------ VJP host
+namespace {
+
+// Workspace layout of the float-frame forward and its VJP for one plan: per level a weight
+// plane and four 3-plane arrays (A, B, C, T), all on the whole level canvas, then the
+// partial sums and a flag.
+struct VjpLayout {
+  int n = 0, W = 0, H = 0, L = 0;
+  int dw[kMaxLevels] = {}, dh[kMaxLevels] = {};
+  size_t o_gm[kMaxLevels] = {}, o_a[kMaxLevels] = {}, o_b[kMaxLevels] = {}, o_c[kMaxLevels] = {},
+         o_t[kMaxLevels] = {};
+  size_t o_part = 0, o_res = 0, o_flag = 0, bytes = 0;
+  int64_t nblk = 0;
+};
+
+stitch_status vjp_layout(const stitch_plan* p, VjpLayout& v) {
+  if (!p) return fail(STITCH_E_NULL, "plan is NULL");
+  int fw[kMaxCameras], fh[kMaxCameras];
+  bool bound = false;
+  plan_geometry(p, &v.n, fw, fh, &v.W, &v.H, &bound);
+  v.L = plan_levels(p);
+  if ((int64_t)v.W * v.H > (1 << 26))
+    return fail(STITCH_E_SHAPE, "canvas %dx%d above the differentiable form's 2^26 pixels", v.W, v.H);
+  v.dw[0] = v.W;
+  v.dh[0] = v.H;
+  for (int k = 1; k < v.L; ++k) { v.dw[k] = (v.dw[k - 1] + 1) / 2; v.dh[k] = (v.dh[k - 1] + 1) / 2; }
+  size_t top = 0;
+  for (int k = 0; k < v.L; ++k) {
+    const size_t nk = (size_t)v.dw[k] * v.dh[k] * 8;
+    v.o_gm[k] = take(top, nk);
+    v.o_a[k] = take(top, 3 * nk);
+    v.o_b[k] = take(top, 3 * nk);
+    v.o_c[k] = take(top, 3 * nk);
+    v.o_t[k] = take(top, 3 * nk);
+  }
+  v.nblk = blocks((int64_t)v.W * v.H);
+  v.o_part = take(top, (size_t)v.nblk * 9 * 8);
+  v.o_res = take(top, 9 * 8);
+  v.o_flag = take(top, 8);
+  v.bytes = top;
+  return STITCH_OK;
+}
+
+stitch_status vjp_check_frames(const stitch_plan* p, int n, const stitch_image* frames, const char* what,
+                               VCam* cams) {
+  for (int i = 0; i < n; ++i) {
+    PlanCamera pc;
+    plan_camera(p, i, &pc);
+    char name[48];
+    snprintf(name, sizeof name, "%s[%d]", what, i);
+    const stitch_status st = check_image(&frames[i], name, STITCH_F32, STITCH_CHW, 3);
+    if (st) return st;
+    if (frames[i].width != pc.fw || frames[i].height != pc.fh)
+      return fail(STITCH_E_SHAPE, "%s is %dx%d, planned %dx%d", name, frames[i].width, frames[i].height, pc.fw, pc.fh);
+    if (cams) {
+      std::memcpy(cams[i].m.h, pc.hinv, sizeof pc.hinv);
+      double M[9];
+      for (int j = 0; j < 9; ++j) M[j] = (double)pc.hinv[j];
+      if (!inv3(M, cams[i].hf)) return fail(STITCH_E_HOMOGRAPHY, "camera %d: its map is singular", i);
+      cams[i].fw = pc.fw;
+      cams[i].fh = pc.fh;
+      cams[i].src = (const float*)frames[i].data;
+      cams[i].srow = frames[i].row_pitch / 4;
+      cams[i].splane = frames[i].plane_pitch / 4;
+    }
+  }
+  return STITCH_OK;
+}
+
+stitch_status vjp_check_ws(const VjpLayout& v, void* ws, size_t bytes) {
+  if (!ws || ((uintptr_t)ws & 255) || bytes < v.bytes)
+    return fail(STITCH_E_WORKSPACE, "workspace missing, misaligned or smaller than %zu bytes", v.bytes);
+  return STITCH_OK;
+}
+
+// Camera i's weight pyramid into gm[k].
+void vjp_weights(const stitch_plan* p, int i, const VjpLayout& v, uint8_t* ws, uint8_t* wbuf, hipStream_t s) {
+  PlanCamera pc;
+  plan_camera(p, i, &pc);
+  const int64_t np = (int64_t)v.W * v.H;
+  hipLaunchKernelGGL(k_vmask, dim3(blocks(np)), dim3(kT), 0, s, pc.weights ? wbuf : nullptr, pc.wx, pc.wy, pc.ww,
+                     pc.wh, v.W, v.H, (double*)(ws + v.o_gm[0]));
+  for (int k = 0; k + 1 < v.L; ++k)
+    hipLaunchKernelGGL(k_greduce, dim3(blocks((int64_t)v.dw[k + 1] * v.dh[k + 1])), dim3(kT), 0, s,
+                       (const double*)(ws + v.o_gm[k]), v.dw[k], v.dh[k], 1, (double*)(ws + v.o_gm[k + 1]),
+                       v.dw[k + 1], v.dh[k + 1]);
+}
+
+// Upload camera i's support-box weights into the staging area at the end of the T arrays
+// of level 0 (3 W H doubles hold far more than W H bytes) and wait for the copy.
+stitch_status vjp_stage_weights(const stitch_plan* p, int i, const VjpLayout& v, uint8_t* ws, hipStream_t s,
+                                uint8_t** wbuf) {
+  PlanCamera pc;
+  plan_camera(p, i, &pc);
+  *wbuf = ws + v.o_t[0];
+  if (!pc.weights) return STITCH_OK;
+  stitch_status st = dev_ok(hipMemcpyAsync(*wbuf, pc.weights, (size_t)pc.ww * pc.wh, hipMemcpyHostToDevice, s),
+                            "weight upload");
+  if (!st) st = dev_ok(hipStreamSynchronize(s), "weight upload");
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t stitch_frame_backward_workspace_bytes(const stitch_plan* plan) {
+  VjpLayout v;
+  return vjp_layout(plan, v) ? 0 : v.bytes;
+}
+
+stitch_status stitch_frame_forward_f32(stitch_plan* plan, const stitch_image* frames, stitch_image* r0,
+                                       void* workspace, size_t bytes, void* stream) {
+  if (!plan || !frames || !r0) return fail(STITCH_E_NULL, "plan, frames or r0 is NULL");
+  VjpLayout v;
+  stitch_status st = vjp_layout(plan, v);
+  if (st) return st;
+  if ((st = vjp_check_ws(v, workspace, bytes))) return st;
+  VCam cams[kMaxCameras];
+  if ((st = vjp_check_frames(plan, v.n, frames, "frames", cams))) return st;
+  if ((st = check_image(r0, "r0", STITCH_F32, STITCH_CHW, 3))) return st;
+  if (r0->width != v.W || r0->height != v.H) return fail(STITCH_E_SHAPE, "r0 is not canvas-sized");
+  const hipStream_t s = (hipStream_t)stream;
+  uint8_t* ws = (uint8_t*)workspace;
+  auto D = [&](size_t o) { return (double*)(ws + o); };
+  const int L = v.L;
+  // B_k (in C) accumulates over cameras
+  for (int k = 0; k < L; ++k)
+    hipLaunchKernelGGL(k_gzero, dim3(blocks(3 * (int64_t)v.dw[k] * v.dh[k])), dim3(kT), 0, s, D(v.o_c[k]),
+                       3 * (int64_t)v.dw[k] * v.dh[k]);
+  for (int i = 0; i < v.n && !st; ++i) {
+    uint8_t* wbuf = nullptr;
+    if ((st = vjp_stage_weights(plan, i, v, ws, s, &wbuf))) break;
+    vjp_weights(plan, i, v, ws, wbuf, s);
+    // G_k in A, L_k in B (the top band is G_{L-1} itself)
+    hipLaunchKernelGGL(k_vwarp, dim3(blocks((int64_t)v.W * v.H)), dim3(kT), 0, s, cams[i], v.W, v.H, D(v.o_a[0]));
+    for (int k = 0; k + 1 < L; ++k)
+      hipLaunchKernelGGL(k_greduce, dim3(blocks(3 * (int64_t)v.dw[k + 1] * v.dh[k + 1])), dim3(kT), 0, s,
+                         D(v.o_a[k]), v.dw[k], v.dh[k], 3, D(v.o_a[k + 1]), v.dw[k + 1], v.dh[k + 1]);
+    for (int k = 0; k < L; ++k) {
+      const int64_t nk = (int64_t)v.dw[k] * v.dh[k];
+      const double* lap = D(v.o_a[k]);
+      if (k + 1 < L) {
+        hipLaunchKernelGGL(k_gexpand, dim3(blocks(3 * nk)), dim3(kT), 0, s, D(v.o_a[k + 1]), v.dw[k + 1],
+                           v.dh[k + 1], D(v.o_a[k]), -1.0, D(v.o_b[k]), v.dw[k], v.dh[k], 3);
+        lap = D(v.o_b[k]);
+      }
+      hipLaunchKernelGGL(k_gweigh, dim3(blocks(3 * nk)), dim3(kT), 0, s, D(v.o_gm[k]), lap, nullptr, nullptr,
+                         D(v.o_c[k]), D(v.o_c[k]), nk);
+    }
+    st = dev_ok(hipGetLastError(), "forward launch");
+  }
+  if (st) return st;
+  // collapse: R_{L-1} = B_{L-1}, R_k = B_k + EXPAND(R_{k+1}) (R_k in A)
+  const double* R = D(v.o_c[L - 1]);
+  for (int k = L - 2; k >= 0; --k) {
+    hipLaunchKernelGGL(k_gexpand, dim3(blocks(3 * (int64_t)v.dw[k] * v.dh[k])), dim3(kT), 0, s, R, v.dw[k + 1],
+                       v.dh[k + 1], D(v.o_c[k]), 1.0, D(v.o_a[k]), v.dw[k], v.dh[k], 3);
+    R = D(v.o_a[k]);
+  }
+  hipLaunchKernelGGL(k_gtof32, dim3(blocks(3 * (int64_t)v.W * v.H)), dim3(kT), 0, s, R, (float*)r0->data, v.W, v.H,
+                     r0->row_pitch / 4, r0->plane_pitch / 4);
+  return dev_ok(hipGetLastError(), "forward launch");
+}
+
+stitch_status stitch_frame_backward(stitch_plan* plan, const stitch_image* frames, const stitch_image* d_pano,
+                                    const stitch_image* d_warped, stitch_image* d_frames, double* d_hinv,
+                                    void* workspace, size_t bytes, void* stream) {
+  if (!plan || !frames || !d_pano || !d_frames || !d_hinv)
+    return fail(STITCH_E_NULL, "plan, frames, d_pano, d_frames or d_hinv is NULL");
+  VjpLayout v;
+  stitch_status st = vjp_layout(plan, v);
+  if (st) return st;
+  if ((st = vjp_check_ws(v, workspace, bytes))) return st;
+  VCam cams[kMaxCameras];
+  if ((st = vjp_check_frames(plan, v.n, frames, "frames", cams))) return st;
+  if ((st = vjp_check_frames(plan, v.n, d_frames, "d_frames", nullptr))) return st;
+  if ((st = check_image(d_pano, "d_pano", STITCH_F32, STITCH_CHW, 3))) return st;
+  if (d_pano->width != v.W || d_pano->height != v.H) return fail(STITCH_E_SHAPE, "d_pano is not canvas-sized");
+  if (d_warped)
+    for (int i = 0; i < v.n; ++i) {
+      if (!d_warped[i].data) continue;
+      char name[40];
+      snprintf(name, sizeof name, "d_warped[%d]", i);
+      if ((st = check_image(&d_warped[i], name, STITCH_F32, STITCH_CHW, 3))) return st;
+      if (d_warped[i].width != v.W || d_warped[i].height != v.H)
+        return fail(STITCH_E_SHAPE, "%s is not canvas-sized", name);
+    }
+  const hipStream_t s = (hipStream_t)stream;
+  uint8_t* ws = (uint8_t*)workspace;
+  auto D = [&](size_t o) { return (double*)(ws + o); };
+  const int L = v.L;
+  const int64_t np = (int64_t)v.W * v.H;
+  hipLaunchKernelGGL(k_gzero, dim3(1), dim3(kT), 0, s, D(v.o_flag), (int64_t)1);
+  // transposed collapse: dR_0 = d_pano, dR_{k+1} = EXPAND^T dR_k (in A); dB_k = dR_k
+  hipLaunchKernelGGL(k_vfromf32, dim3(blocks(3 * np)), dim3(kT), 0, s, (const float*)d_pano->data,
+                     d_pano->row_pitch / 4, d_pano->plane_pitch / 4, v.W, v.H, 0, D(v.o_a[0]));
+  for (int k = 0; k + 1 < L; ++k)
+    hipLaunchKernelGGL(k_gexpandT, dim3(blocks(3 * (int64_t)v.dw[k + 1] * v.dh[k + 1])), dim3(kT), 0, s,
+                       D(v.o_a[k]), v.dw[k], v.dh[k], nullptr, 1.0, D(v.o_a[k + 1]), v.dw[k + 1], v.dh[k + 1], 3);
+  st = dev_ok(hipGetLastError(), "backward launch");
+  std::vector<double> res(9 * (size_t)v.n, 0.0);
+  for (int i = 0; i < v.n && !st; ++i) {
+    uint8_t* wbuf = nullptr;
+    if ((st = vjp_stage_weights(plan, i, v, ws, s, &wbuf))) break;
+    vjp_weights(plan, i, v, ws, wbuf, s);
+    // dL_k = Gm_k dB_k (in B)
+    for (int k = 0; k < L; ++k) {
+      const int64_t nk = (int64_t)v.dw[k] * v.dh[k];
+      hipLaunchKernelGGL(k_gweigh, dim3(blocks(3 * nk)), dim3(kT), 0, s, D(v.o_gm[k]), D(v.o_a[k]), nullptr, nullptr,
+                         nullptr, D(v.o_b[k]), nk);
+    }
+    // dG_{L-1} = dL_{L-1} - EXPAND^T dL_{L-2}; dG_k = dL_k - EXPAND^T dL_{k-1} + REDUCE^T dG_{k+1}
+    // (in C, T holding dL_k - EXPAND^T dL_{k-1}); dG_0 = dL_0 + REDUCE^T dG_1
+    double* dG0 = D(v.o_b[0]);
+    if (L > 1) {
+      hipLaunchKernelGGL(k_gexpandT, dim3(blocks(3 * (int64_t)v.dw[L - 1] * v.dh[L - 1])), dim3(kT), 0, s,
+                         D(v.o_b[L - 2]), v.dw[L - 2], v.dh[L - 2], D(v.o_b[L - 1]), -1.0, D(v.o_c[L - 1]),
+                         v.dw[L - 1], v.dh[L - 1], 3);
+      for (int k = L - 2; k >= 0; --k) {
+        const int64_t nk3 = 3 * (int64_t)v.dw[k] * v.dh[k];
+        const double* base = D(v.o_b[0]);
+        if (k >= 1) {
+          hipLaunchKernelGGL(k_gexpandT, dim3(blocks(nk3)), dim3(kT), 0, s, D(v.o_b[k - 1]), v.dw[k - 1],
+                             v.dh[k - 1], D(v.o_b[k]), -1.0, D(v.o_t[k]), v.dw[k], v.dh[k], 3);
+          base = D(v.o_t[k]);
+        }
+        hipLaunchKernelGGL(k_greduceT, dim3(blocks(nk3)), dim3(kT), 0, s, D(v.o_c[k + 1]), v.dw[k + 1], v.dh[k + 1],
+                           base, 1.0, D(v.o_c[k]), v.dw[k], v.dh[k], 3);
+      }
+      dG0 = D(v.o_c[0]);
+    }
+    // the caller's direct term on the warped frame
+    if (d_warped && d_warped[i].data)
+      hipLaunchKernelGGL(k_vfromf32, dim3(blocks(3 * np)), dim3(kT), 0, s, (const float*)d_warped[i].data,
+                         d_warped[i].row_pitch / 4, d_warped[i].plane_pitch / 4, v.W, v.H, 1, dG0);
+    hipLaunchKernelGGL(k_vwarpT, dim3(blocks((int64_t)cams[i].fw * cams[i].fh)), dim3(kT), 0, s, cams[i], v.W, v.H,
+                       (const double*)dG0, (float*)d_frames[i].data, d_frames[i].row_pitch / 4,
+                       d_frames[i].plane_pitch / 4, (int*)(ws + v.o_flag));
+    hipLaunchKernelGGL(k_vmapT, dim3(v.nblk), dim3(kT), 0, s, cams[i], v.W, v.H, (const double*)dG0, D(v.o_part));
+    hipLaunchKernelGGL(k_gsum, dim3(1), dim3(kT), 0, s, D(v.o_part), (int)v.nblk, 9, 9, D(v.o_res));
+    st = dev_ok(hipGetLastError(), "backward launch");
+    if (!st)
+      st = dev_ok(hipMemcpyAsync(res.data() + 9 * i, D(v.o_res), 72, hipMemcpyDeviceToHost, s), "gradient copy");
+    if (!st) st = dev_ok(hipStreamSynchronize(s), "backward synchronise");
+  }
+  int flag = 0;
+  if (!st) st = dev_ok(hipMemcpyAsync(&flag, ws + v.o_flag, 4, hipMemcpyDeviceToHost, s), "flag copy");
+  if (!st) st = dev_ok(hipStreamSynchronize(s), "backward synchronise");
+  if (st) return st;
+  if (flag)
+    return fail(STITCH_E_UNSUPPORTED, "a map magnifies a source pixel beyond the gather's reach or crosses its "
+                "horizon inside a frame (flags %d); d_frames is incomplete", flag);
+  for (size_t j = 0; j < res.size(); ++j) d_hinv[j] = res[j];
+  return STITCH_OK;
+}
 
 stitch_status stitch_corners_to_h(const double q[8], int32_t w, int32_t h, double H[9]) {
   if (!q || !H) return fail(STITCH_E_NULL, "q or H is NULL");

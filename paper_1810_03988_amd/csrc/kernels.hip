@@ -88,6 +88,16 @@ __device__ __forceinline__ void stg4nt(GLB _Float16* p, const float v[4]) {
                               reinterpret_cast<GLB vh4*>(p));
 }
 
+// Eight FP16 samples as one 16-byte streaming store: four dwords of packed halves (low
+// half = lower column).
+__device__ __forceinline__ uint32_t pack_h2(float a, float b) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)a) | ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)b) << 16);
+}
+__device__ __forceinline__ void stg8nt(GLB _Float16* p, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  typedef uint32_t vu4s __attribute__((ext_vector_type(4)));
+  __builtin_nontemporal_store(vu4s{a, b, c, d}, reinterpret_cast<GLB vu4s*>(p));
+}
+
 __device__ __forceinline__ float ldv(const float* p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float ldv(const _Float16* p, int64_t i) { return (float)p[i]; }
 __device__ __forceinline__ void stv(float* p, int64_t i, float v) { p[i] = v; }
@@ -726,6 +736,15 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
         const float4 v4 = *reinterpret_cast<const float4*>(&sC[ch][i][CO + j]);
         const float v[4] = {v4.x, v4.y, v4.z, v4.w};
         const int cy = Y0 / 2 - 1 + i - it.croi_y, cx = X0 / 2 - 1 + j - it.croi_x;
+        // FP16: lanes 2m and 2m+1 hold eight adjacent samples; the even lane stores all
+        // eight as one 16-byte vector (the partner's four halves come by a lane swap)
+        uint32_t h01 = 0, h23 = 0, p01 = 0, p23 = 0;
+        if (sizeof(T) == 2) {
+          h01 = pack_h2(v[0], v[1]);
+          h23 = pack_h2(v[2], v[3]);
+          p01 = __shfl_xor(h01, 1);
+          p23 = __shfl_xor(h23, 1);
+        }
         if (cy >= 0 && cy < it.croi_h) {
           GLB T* out = ch < 3 ? mg<T>(it.g_out) : mg<T>(it.gm_out);
           // 32-bit element offsets (the host keeps every level's planes under 2^31
@@ -733,7 +752,11 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
           const uint32_t orow = (uint32_t)(ch < 3 ? it.g_row : it.gm_row);
           const uint32_t obase = ch < 3 ? (uint32_t)ch * (uint32_t)it.g_plane : 0u;
           const int ob = (int)(obase + __umul24((uint32_t)cy, orow)) + cx;
-          if (cx >= 0 && cx + 3 < it.croi_w && ((uintptr_t)(out + ob) & (4 * sizeof(T) - 1)) == 0) {
+          const bool odd = (lane & 1) != 0;
+          const int cxe = cx - (odd ? 4 : 0), obe = ob - (odd ? 4 : 0);
+          if (sizeof(T) == 2 && cxe >= 0 && cxe + 7 < it.croi_w && ((uintptr_t)(out + obe) & 15) == 0) {
+            if (!odd) stg8nt(reinterpret_cast<GLB _Float16*>(out + obe), h01, h23, p01, p23);
+          } else if (cx >= 0 && cx + 3 < it.croi_w && ((uintptr_t)(out + ob) & (4 * sizeof(T) - 1)) == 0) {
             stg4nt(out + ob, v);
           } else {
 #pragma unroll
@@ -764,6 +787,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
         }
         const int X = X0 + x - it.lw_x;
         GLB T* lout = mg<T>(it.l_out);
+        float l[4][4];
 #pragma unroll
         for (int yy = 0; yy < 4; ++yy) {
           const int y = 4 * rq + yy, k = yy >> 1;
@@ -778,20 +802,62 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
             ev.w = 0.125f * (eh[k].w + eh[k + 2].w) + 0.75f * eh[k + 1].w;
           }
           const float4 gv = *reinterpret_cast<const float4*>(rowp(y + 4) + x + 4);
-          const float l[4] = {gv.x - ev.x, gv.y - ev.y, gv.z - ev.z, gv.w - ev.w};
+          l[yy][0] = gv.x - ev.x; l[yy][1] = gv.y - ev.y; l[yy][2] = gv.z - ev.z; l[yy][3] = gv.w - ev.w;
+        }
+        // FP16: lanes 2m and 2m+1 hold eight adjacent columns of the same four rows; the
+        // even lane stores rows 0-1 and the odd lane rows 2-3 as 16-byte vectors, each
+        // taking the partner's halves of those rows by a lane swap
+        const bool odd = (mm & 1) != 0;
+        const int Xe = X - (odd ? 4 : 0);
+        bool pair = false;
+        uint32_t own[2][2] = {}, oth[2][2] = {};
+        if (sizeof(T) == 2) {
+          uint32_t hp[4][2];
+#pragma unroll
+          for (int yy = 0; yy < 4; ++yy) {
+            hp[yy][0] = pack_h2(l[yy][0], l[yy][1]);
+            hp[yy][1] = pack_h2(l[yy][2], l[yy][3]);
+          }
+#pragma unroll
+          for (int r2 = 0; r2 < 2; ++r2)
+#pragma unroll
+            for (int w2 = 0; w2 < 2; ++w2) {
+              // send the rows the partner stores, keep the ones this lane stores
+              own[r2][w2] = odd ? hp[2 + r2][w2] : hp[r2][w2];
+              oth[r2][w2] = __shfl_xor(odd ? hp[r2][w2] : hp[2 + r2][w2], 1);
+            }
+          pair = Xe >= 0 && Xe + 7 < it.lw_w && ((uintptr_t)(lout + Xe) & 15) == 0 &&
+                 ((it.l_row | it.l_plane) & 7) == 0;
+        }
+#pragma unroll
+        for (int yy = 0; yy < 4; ++yy) {
+          const int y = 4 * rq + yy;
           const int Y = Y0 + y - it.lw_y;
           const bool rowin = Y >= 0 && Y < it.lw_h;
+          if (sizeof(T) == 2 && pair) {
+            // this lane's two rows (the even lane's 0-1, the odd lane's 2-3)
+            if (yy < 2) {
+              const int Ys = Y + (odd ? 2 : 0);
+              if (Ys >= 0 && Ys < it.lw_h) {
+                const int base = ch * (int)it.l_plane + __mul24(Ys, (int)it.l_row) + Xe;
+                GLB _Float16* q = reinterpret_cast<GLB _Float16*>(lout + base);
+                if (odd) stg8nt(q, oth[yy][0], oth[yy][1], own[yy][0], own[yy][1]);
+                else stg8nt(q, own[yy][0], own[yy][1], oth[yy][0], oth[yy][1]);
+              }
+            }
+            continue;
+          }
           const bool full = rowin && X >= 0 && X + 3 < it.lw_w;
           const int base = ch * (int)it.l_plane + __mul24(Y, (int)it.l_row) + X;
           if (full && ((uintptr_t)(lout + base) & (4 * sizeof(T) - 1)) == 0) {
-            stg4nt(lout + base, l);
+            stg4nt(lout + base, l[yy]);
           } else if (full) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) stgnt(lout, base + u, l[u]);
+            for (int u = 0; u < 4; ++u) stgnt(lout, base + u, l[yy][u]);
           } else if (rowin) {
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-              if (X + u >= 0 && X + u < it.lw_w) stgnt(lout, base + u, l[u]);
+              if (X + u >= 0 && X + u < it.lw_w) stgnt(lout, base + u, l[yy][u]);
           }
         }
       }

@@ -207,7 +207,15 @@ struct CamPlan {
   float hinv[9] = {};
   Rect roi[kMaxLevels];
   Rect band[kMaxLevels];
+  // where L_k is stored and read: the band window widened to 8-sample column boundaries
+  // (inside roi), so band rows go out as whole 16-byte vectors at either storage size; the
+  // added columns carry seam weight 0
+  Rect lwin[kMaxLevels];
   std::vector<uint8_t> mask0;     // seam weights on roi[0], rows of mask_row bytes
+  // the seam weights on their own support box (for the float-frame forward and its
+  // vector-Jacobian product, which define every array on the whole canvas)
+  std::vector<uint8_t> wsup;
+  int wsx = 0, wsy = 0, wsw = 0, wsh = 0;
   int64_t mask_row = 0;
   size_t off_mask0 = 0;
   size_t off_g[kMaxLevels] = {};  int64_t g_row[kMaxLevels] = {}, g_plane[kMaxLevels] = {};
@@ -241,6 +249,17 @@ struct stitch_plan {
   uint8_t* ws = nullptr;
   EventLog timing;   // optional per-launch event timing (diagnostics)
 };
+
+int stitch::plan_levels(const stitch_plan* p) { return p->L; }
+
+void stitch::plan_camera(const stitch_plan* p, int i, PlanCamera* out) {
+  const CamPlan& c = p->cam[i];
+  out->fw = c.fw;
+  out->fh = c.fh;
+  for (int j = 0; j < 9; ++j) out->hinv[j] = c.hinv[j];
+  out->wx = c.wsx; out->wy = c.wsy; out->ww = c.wsw; out->wh = c.wsh;
+  out->weights = c.wsup.empty() ? nullptr : c.wsup.data();
+}
 
 void stitch::plan_geometry(const stitch_plan* p, int* n, int* frame_w, int* frame_h, int* canvas_w, int* canvas_h,
                            bool* bound) {
@@ -395,7 +414,7 @@ void build_tables(stitch_plan* p) {
       it.g_plane = c.g_plane[k + 1];
       it.gm_out = ws + c.off_gm[k + 1];
       it.gm_row = c.gm_row[k + 1];
-      const Rect b = c.band[k];
+      const Rect b = c.lwin[k];
       if (!b.empty()) {
         it.lw_x = b.x; it.lw_y = b.y; it.lw_w = b.w; it.lw_h = b.h;
         it.l_out = ws + c.off_l[k];
@@ -413,7 +432,7 @@ void build_tables(stitch_plan* p) {
     p->bcams[k].clear();
     for (int i = 0; i < p->n; ++i) {
       const CamPlan& c = p->cam[i];
-      const Rect b = c.band[k];
+      const Rect b = c.lwin[k];
       if (b.empty()) continue;
       BlendCam bc;
       std::memset(&bc, 0, sizeof bc);
@@ -861,6 +880,12 @@ stitch_status stitch_plan_create(int32_t n, const int32_t* frame_w, const int32_
           my0 = std::min<int64_t>(my0, y); my1 = std::max<int64_t>(my1, y);
         }
     }
+    if (mx1 >= mx0) {
+      c.wsx = (int)mx0; c.wsy = (int)my0; c.wsw = (int)(mx1 - mx0 + 1); c.wsh = (int)(my1 - my0 + 1);
+      c.wsup.resize((size_t)c.wsw * c.wsh);
+      for (int y = 0; y < c.wsh; ++y)
+        std::memcpy(&c.wsup[(size_t)y * c.wsw], m + (size_t)(c.wsy + y) * canvas_w + c.wsx, c.wsw);
+    }
     Interval nx{mx0, mx1}, ny{my0, my1};
     for (int k = 0; k < L; ++k) {
       if (k > 0) { nx = reduce_support(nx); ny = reduce_support(ny); }
@@ -926,6 +951,13 @@ stitch_status stitch_plan_create(int32_t n, const int32_t* frame_w, const int32_
         c.band[k] = intersect(c.band[k], c.roi[k]);
       }
     }
+    // --- band storage windows: columns widened to multiples of 8 within the roi ---
+    for (int k = 0; k < L; ++k) {
+      const Rect b = c.band[k], r = c.roi[k];
+      if (b.empty()) { c.lwin[k] = Rect{}; continue; }
+      const int x0 = std::max(r.x, b.x & ~7), x1 = std::min(r.x + r.w, (b.x + b.w + 7) & ~7);
+      c.lwin[k] = Rect{x0, b.y, x1 - x0, b.h};
+    }
     // --- keep the seam weights on roi[0] ---
     const Rect r0 = c.roi[0];
     if (!r0.empty()) {
@@ -953,7 +985,7 @@ stitch_status stitch_plan_create(int32_t n, const int32_t* frame_w, const int32_
       }
     }
     for (int k = 0; k + 1 < L; ++k) {
-      const Rect b = c.band[k];
+      const Rect b = c.lwin[k];
       if (b.empty()) continue;
       c.l_row[k] = row_elems(b.w, es);
       c.l_plane[k] = c.l_row[k] * b.h;
@@ -1106,7 +1138,8 @@ stitch_status stitch_plan_view(const stitch_plan* p, int32_t what, int32_t camer
     if (r.empty()) return STITCH_OK;
     view->channels = 3;
     if (level + 1 < p->L) {
-      view->data = p->ws + c.off_l[level];
+      const Rect w = c.lwin[level];   // the band inside its storage window
+      view->data = p->ws + c.off_l[level] + ((int64_t)(r.y - w.y) * c.l_row[level] + (r.x - w.x)) * es;
       view->row_pitch = c.l_row[level] * es; view->plane_pitch = c.l_plane[level] * es;
     } else {
       const Rect g = c.roi[level];

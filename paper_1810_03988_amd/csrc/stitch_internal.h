@@ -116,6 +116,18 @@ hipError_t launch_convert(bool f16_out, int nch, bool src_u8, const void* src, i
 void plan_geometry(const stitch_plan* p, int* n, int* frame_w, int* frame_h, int* canvas_w, int* canvas_h,
                    bool* bound);
 
+// One camera of a plan for the float-frame forward and its vector-Jacobian product: frame
+// size, the FP32 canvas -> source map and the seam weights on their support box (weights
+// holds ww x wh bytes row-major, or is NULL when the camera has no weight anywhere).
+struct PlanCamera {
+  int fw, fh;
+  float hinv[9];
+  int wx, wy, ww, wh;
+  const uint8_t* weights;
+};
+int plan_levels(const stitch_plan* p);
+void plan_camera(const stitch_plan* p, int i, PlanCamera* out);
+
 // Host helpers shared by the API files (stitch_api.cpp).
 stitch_status fail(stitch_status s, const char* fmt, ...);
 stitch_status hip_fail(hipError_t e, const char* what);

@@ -92,6 +92,7 @@ SIGNATURES = {
     "stitch_grad_forward": (c_int32, [c_void_p, POINTER(StitchImage), POINTER(c_double), POINTER(c_double),
                                       c_void_p]),
     "stitch_grad_backward": (c_int32, [c_void_p, POINTER(StitchImage), POINTER(c_double), c_void_p]),
+    "stitch_grad_upstream": (c_int32, [c_void_p, POINTER(StitchImage), POINTER(StitchImage), c_void_p]),
     "stitch_grad_destroy": (None, [c_void_p]),
     "stitch_pipe_workspace_bytes": (c_size_t, [c_void_p, c_int32]),
     "stitch_pipe_create": (c_int32, [c_void_p, c_int32, c_void_p, c_size_t, POINTER(c_void_p)]),
@@ -99,6 +100,11 @@ SIGNATURES = {
     "stitch_pipe_destroy": (None, [c_void_p]),
     "stitch_host_alloc": (c_int32, [c_size_t, POINTER(c_void_p)]),
     "stitch_host_free": (None, [c_void_p]),
+    "stitch_frame_backward_workspace_bytes": (c_size_t, [c_void_p]),
+    "stitch_frame_forward_f32": (c_int32, [c_void_p, POINTER(StitchImage), POINTER(StitchImage), c_void_p, c_size_t,
+                                           c_void_p]),
+    "stitch_frame_backward": (c_int32, [c_void_p, POINTER(StitchImage), POINTER(StitchImage), POINTER(StitchImage),
+                                        POINTER(StitchImage), POINTER(c_double), c_void_p, c_size_t, c_void_p]),
     "stitch_corners_to_h": (c_int32, [POINTER(c_double), c_int32, c_int32, POINTER(c_double)]),
     "stitch_map_grad_to_corners": (c_int32, [POINTER(c_double), c_int32, c_int32, POINTER(c_double),
                                              POINTER(c_double)]),
@@ -390,6 +396,55 @@ class Plan:
         check(lib().stitch_autotune(self._h, fr, _stream(stream), str(cache_path).encode() if cache_path else None))
         return self.config()
 
+    # ---- the plan as a differentiable function of float frames (stitch_frame_forward_f32,
+    # ---- stitch_frame_backward); needs no bound workspace
+    def _vjp_workspace(self, device):
+        if getattr(self, "_vjp_ws", None) is None:
+            nbytes = lib().stitch_frame_backward_workspace_bytes(self._h)
+            if nbytes == 0:
+                raise StitchError(2, "no workspace size for the differentiable form: " + last_error())
+            self._vjp_ws = _aligned_workspace(nbytes, device) + (nbytes,)
+        return self._vjp_ws
+
+    def forward_f32(self, frames, stream=None) -> torch.Tensor:
+        """R_0 (3, H, W) float32 of float (3, h, w) frames in [0, 1]."""
+        frames = [f.contiguous() for f in frames]
+        _, ws, nbytes = self._vjp_workspace(frames[0].device)
+        r0 = torch.empty((3, self.canvas_h, self.canvas_w), dtype=torch.float32, device=frames[0].device)
+        arr = (StitchImage * self.n)(*[image_chw(f) for f in frames])
+        check(lib().stitch_frame_forward_f32(self._h, arr, ctypes.byref(image_chw(r0)), ws.data_ptr(), nbytes,
+                                             _stream(stream)))
+        return r0
+
+    def backward(self, frames, d_pano, d_warped=None, stream=None):
+        """(dl/dframes as n (3, h, w) float32 tensors, dl/dM as (n, 3, 3) float64) for the
+        upstream dl/dR_0 d_pano (3, H, W) and optional direct terms d_warped[i] on the warped
+        frames (None entries skipped)."""
+        frames = [f.contiguous() for f in frames]
+        dev = frames[0].device
+        _, ws, nbytes = self._vjp_workspace(dev)
+        outs = [torch.empty((3, h, w), dtype=torch.float32, device=dev) for w, h in self.frame_sizes]
+        fa = (StitchImage * self.n)(*[image_chw(f) for f in frames])
+        oa = (StitchImage * self.n)(*[image_chw(t) for t in outs])
+        dp = d_pano.contiguous()
+        keep = [dp]
+        dw = None
+        if d_warped is not None:
+            views = []
+            for t in d_warped:
+                if t is None:
+                    views.append(StitchImage())
+                else:
+                    t = t.contiguous()
+                    keep.append(t)
+                    views.append(image_chw(t))
+            dw = (StitchImage * self.n)(*views)
+        dh = (c_double * (9 * self.n))()
+        check(lib().stitch_frame_backward(self._h, fa, ctypes.byref(image_chw(dp)), dw, oa, dh, ws.data_ptr(), nbytes,
+                                          _stream(stream)))
+        del keep
+        return outs, np.array(dh[:], dtype=np.float64).reshape(self.n, 3, 3)
+
     def regions(self, camera: int, level: int):
         roi = (c_int32 * 4)()
         band = (c_int32 * 4)()
@@ -575,6 +630,9 @@ class Grad:
         h = c_void_p()
         check(lib().stitch_grad_create(fw, fh, mptrs, canvas_w, canvas_h, levels, ctypes.byref(h)))
         self._h = h
+        self.masks, self.canvas_w, self.canvas_h, self.levels = ms, canvas_w, canvas_h, levels
+        self.frozen_maps = None
+        self._plan = None
         self.device = torch.device(device)
         self.ws_bytes = lib().stitch_grad_workspace_bytes(self._h)
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
@@ -592,7 +650,26 @@ class Grad:
         n = c_int64()
         check(lib().stitch_grad_freeze(self._h, self._h18(Hs), ctypes.byref(n), _stream(stream)))
         self.omega = n.value
+        self.frozen_maps = np.stack([np.asarray(H, dtype=np.float64) for H in Hs])
         return self.omega
+
+    def upstream(self, stream=None):
+        """The last forward's dl/dP and its direct terms dl/dA, dl/dB on the warped frames,
+        as (3, H, W) float32 tensors (stitch_grad_upstream)."""
+        outs = [torch.empty((3, self.canvas_h, self.canvas_w), dtype=torch.float32, device=self.device)
+                for _ in range(3)]
+        dw = (StitchImage * 2)(image_chw(outs[1]), image_chw(outs[2]))
+        check(lib().stitch_grad_upstream(self._h, ctypes.byref(image_chw(outs[0])), dw, _stream(stream)))
+        return outs[0], outs[1:]
+
+    def plan_at(self, Hs) -> "Plan":
+        """An unbound plan of the pair at the maps Hs (for stitch_frame_backward), reused
+        while the maps stay the same."""
+        key = np.stack([np.asarray(H, dtype=np.float64) for H in Hs])
+        if self._plan is None or not np.array_equal(self._plan[0], key):
+            self._plan = (key, Plan(self.frame_sizes, list(key), self.masks, self.canvas_w, self.canvas_h,
+                                    self.levels, device=self.device, bind=False))
+        return self._plan[1]
 
     def forward(self, frames, Hs, stream=None) -> float:
         frames = [f.contiguous() for f in frames]
@@ -633,8 +710,13 @@ class StitchPairLoss(torch.autograd.Function):
         w, h = grad.frame_sizes[1]
         qn = q.detach().cpu().double().numpy().copy()
         H_b = corners_to_h(qn, w, h)
+        maps = np.stack([np.asarray(H_a, dtype=np.float64), H_b])
+        if grad.frozen_maps is None or not np.array_equal(grad.frozen_maps, maps):
+            raise RuntimeError("freeze the Grad object at these maps first: the loss and its gradient take the "
+                               "cells at the frozen maps")
         loss = grad.forward([frame_a.detach(), frame_b.detach()], [H_a, H_b])
-        ctx.grad_obj, ctx.q, ctx.gen = grad, qn, grad.generation
+        ctx.grad_obj, ctx.q, ctx.gen, ctx.maps = grad, qn, grad.generation, maps
+        ctx.frames = (frame_a.detach(), frame_b.detach())
         return torch.tensor(loss, dtype=torch.float64)
 
     @staticmethod
@@ -642,7 +724,9 @@ class StitchPairLoss(torch.autograd.Function):
         grad = ctx.grad_obj
         if grad.generation != ctx.gen:
             raise RuntimeError("another forward ran on this Grad object since this loss was computed")
-        d_frames, d_map = grad.backward()
+        # the loss's upstream gradients through the whole path's vector-Jacobian product
+        d_pano, d_warped = grad.upstream()
+        d_frames, d_map = grad.plan_at(ctx.maps).backward(list(ctx.frames), d_pano, d_warped)
         w, h = grad.frame_sizes[1]
         dq = torch.from_numpy(map_grad_to_corners(ctx.q, w, h, d_map[1]))
         gs = float(g_out)

@@ -404,3 +404,44 @@ def test_binding_refuses_host_tensors_before_any_launch():
     mat = object.__new__(S.Matcher)
     with pytest.raises(ValueError):
         S.Matcher.run_raw(mat, i32, i32, i32, i32, 0)
+
+
+def test_frame_backward_validates_on_host():
+    """The float-frame forward and its VJP: workspace size, NULLs, wrong dtypes, sizes and a
+    misaligned or short workspace are refused before anything reaches the device."""
+    lib = P.lib()
+    args, keep = _plan_args()
+    st, h = _create(*args)
+    assert st == 0
+    try:
+        need = lib.stitch_frame_backward_workspace_bytes(h)
+        W, H = 1040, 480
+        assert need >= 13 * 8 * W * H and lib.stitch_frame_backward_workspace_bytes(None) == 0
+        fake = 0x10000
+
+        def img(w, hh, dtype=S.F32):
+            return S.StitchImage(fake, w, hh, 3, dtype, S.CHW, 4 * w, 4 * w * hh)
+
+        fr = (S.StitchImage * 2)(img(640, 480), img(640, 480))
+        bad = (S.StitchImage * 2)(img(640, 480), img(639, 480))
+        u8 = (S.StitchImage * 2)(img(640, 480), img(640, 480, S.U8))
+        out = (S.StitchImage * 2)(img(640, 480), img(640, 480))
+        dp = img(W, H)
+        dh = (ctypes.c_double * 18)()
+
+        def bwd(frames=fr, d_pano=ctypes.byref(dp), d_frames=out, ws=fake, nbytes=need, d_hinv=dh):
+            return lib.stitch_frame_backward(h, frames, d_pano, None, d_frames, d_hinv, ws, nbytes, None)
+
+        assert bwd(frames=None) == E["E_NULL"] and bwd(d_hinv=None) == E["E_NULL"]
+        assert bwd(ws=None) == E["E_WORKSPACE"] and bwd(ws=fake + 8) == E["E_WORKSPACE"]
+        assert bwd(nbytes=need - 1) == E["E_WORKSPACE"]
+        assert bwd(frames=bad) == E["E_SHAPE"] and bwd(frames=u8) == E["E_SHAPE"]
+        assert bwd(d_frames=bad) == E["E_SHAPE"]
+        small = img(W - 1, H)
+        assert bwd(d_pano=ctypes.byref(small)) == E["E_SHAPE"]
+        r0 = img(W, H)
+        assert lib.stitch_frame_forward_f32(h, fr, ctypes.byref(small), fake, need, None) == E["E_SHAPE"]
+        assert lib.stitch_frame_forward_f32(h, bad, ctypes.byref(r0), fake, need, None) == E["E_SHAPE"]
+        assert lib.stitch_frame_forward_f32(h, fr, ctypes.byref(r0), fake, need // 2, None) == E["E_WORKSPACE"]
+    finally:
+        lib.stitch_plan_destroy(h)
