@@ -8,13 +8,16 @@ fails, an exception is raised.
 from __future__ import annotations
 
 import ctypes
+import os
 from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_size_t, c_uint8, c_void_p
 from pathlib import Path
 
 import numpy as np
 import torch
 
-LIB_PATH = Path(__file__).resolve().with_name("libstitch.so")
+# the in-tree build; STITCH_LIB names another build of the same sources (the host-sanitized
+# one the ABI tests use), never a substitute for the HIP kernels
+LIB_PATH = Path(os.environ.get("STITCH_LIB") or Path(__file__).resolve().with_name("libstitch.so"))
 
 U8, F16, F32 = 0, 1, 2
 HWC, CHW = 0, 1

@@ -233,7 +233,7 @@ def test_matching_with_the_most_tables_and_key_bits():
     assert got_idx.tolist() == want_idx.tolist() and got_d.tolist() == want_d.tolist()
 
 
-@pytest.mark.parametrize("T_N, nhyp", [(300.0, 2048), (5000.0, 1024)])
+@pytest.mark.parametrize("T_N, nhyp", [(300.0, 2048), (1000.0, 3072)])
 def test_prosac_past_the_last_growth_step(T_N, nhyp):
     """A small T_N makes the subset reach all M matches early; every later hypothesis draws
     its 4 matches from the whole top-M set (T'_n < t), the branch a large T_N never reaches.
