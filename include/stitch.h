@@ -295,6 +295,19 @@ stitch_status stitch_batch_config(const stitch_batch* batch, int32_t wg_per_cu[S
  * new graph.  Errors: NULL, SHAPE. */
 stitch_status stitch_batch_set_config(stitch_batch* batch, const int32_t wg_per_cu[STITCH_MAX_LEVELS],
                                       const int32_t tile_rows[STITCH_MAX_LEVELS]);
+/* Run the jobs as `groups` (1..8, at most the job count) sub-batches balanced by their
+ * warp-pass work, software-pipelined over the caller's stream and a side stream the batch
+ * owns (default priority): the warp + level-0 pass of group g + 1 is queued on the caller's
+ * stream while group g's later pyramid passes and blends run on the side stream, so the
+ * arithmetic-heavy warp pass of one group can overlap the memory-bound passes of another (the
+ * paper overlaps images of different sizes on stream queues, Sec. 4.3.2).  1 restores the
+ * single sequence.  Runs on a non-null stream only (captured into one graph with the fork
+ * and join); timed runs and the null stream use the single sequence.  The results do not
+ * depend on the grouping.  Needs a bound batch; discards a captured graph.
+ * stitch_batch_group_count returns the current count (0 for NULL).
+ * Errors: NULL, SHAPE, STATE, WORKSPACE, DEVICE. */
+stitch_status stitch_batch_set_groups(stitch_batch* batch, int32_t groups);
+int32_t       stitch_batch_group_count(const stitch_batch* batch);
 void          stitch_batch_destroy(stitch_batch* batch);
 
 /* ---- stream-pipelined frame sequences: host frames in, host panoramas out -------- */

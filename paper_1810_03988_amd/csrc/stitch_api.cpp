@@ -1193,6 +1193,10 @@ void stitch_plan_destroy(stitch_plan* p) { delete p; }
 
 }  // extern "C"
 
+namespace stitch {
+constexpr int kMaxGroups = 8;
+}
+
 struct stitch_batch {
   int njobs = 0, maxL = 0;
   bool f16 = false;
@@ -1214,9 +1218,22 @@ struct stitch_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   EventLog timing;   // per-launch timing; while on, runs are launched eagerly
+  // Grouped schedule (ngroups > 1): the jobs split into sub-batches; the level-0 pass of
+  // group g + 1 runs on the caller's stream while group g's later passes and blends run on a
+  // side stream, so the VALU-heavy warp pass of one group overlaps the memory-bound rest of
+  // the previous one.  The sub-batches' tables live in this batch's workspace after its own.
+  int ngroups = 1;
+  std::vector<stitch_batch*> groups;
+  std::vector<std::vector<int>> group_jobs;
+  size_t own_bytes = 0;                       // this batch's own tables (the rest: groups)
+  hipStream_t side = nullptr;
+  std::vector<hipEvent_t> gev;                // per group: its level-0 pass queued; last: join
   ~stitch_batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    for (stitch_batch* g : groups) delete g;
+    for (hipEvent_t e : gev) (void)hipEventDestroy(e);
+    if (side) (void)hipStreamDestroy(side);
   }
 };
 
@@ -1229,24 +1246,21 @@ void drop_graph(stitch_batch* b) {
   b->graph = nullptr;
 }
 
-// Enqueue every phase of the batch: pyramid passes by level, then blends from the top
-// level down; a job joins the phases its own level count has.
-stitch_status enqueue_batch(stitch_batch* b, hipStream_t s) {
+// Enqueue the phases of the batch: pyramid passes by level (from level k_first; k_first =
+// 0 starts with the warp + level-0 pass), then, with blends, the blends from the top level
+// down; a job joins the phases its own level count has.
+stitch_status enqueue_phases(stitch_batch* b, hipStream_t s, int k_first, int k_end, bool blends) {
   FrameArgs fa;
   std::memset(&fa, 0, sizeof fa);   // n = 0: frames come from the item tables
-  struct EndCall {
-    EventLog& log;
-    ~EndCall() { log.end_call(); }
-  } end_call{b->timing};
-  stitch_status st = b->timing.mark(s, -1);
-  for (int k = 0; !st && k + 1 < b->maxL; ++k) {
+  stitch_status st = STITCH_OK;
+  for (int k = k_first; !st && k < k_end && k + 1 < b->maxL; ++k) {
     if (b->pyr_tiles[k] <= 0) continue;
     const hipError_t e = launch_pyr(b->f16, true, k == 0, (const PyrItem*)(b->ws + b->off_pyr[k]),
                                     (int)b->pyr[k].size(), b->pyr_tiles[k], fa, s, b->wg_cap[k]);
     if (e != hipSuccess) return hip_fail(e, "batch pyramid launch");
     st = b->timing.mark(s, k);
   }
-  for (int k = b->maxL - 1; !st && k >= 0; --k) {
+  for (int k = b->maxL - 1; blends && !st && k >= 0; --k) {
     if (b->blend_tiles[k] <= 0) continue;
     const hipError_t e = launch_blend(b->f16, k == 0, (const BlendItem*)(b->ws + b->off_blend[k]),
                                       (int)b->blend[k].size(), b->blend_tiles[k], PanoArg{nullptr, 0}, s);
@@ -1254,6 +1268,33 @@ stitch_status enqueue_batch(stitch_batch* b, hipStream_t s) {
     st = b->timing.mark(s, kMaxLevels + k);
   }
   return st;
+}
+
+// Every phase of the batch on one stream (with the per-launch timing events when enabled).
+stitch_status enqueue_batch(stitch_batch* b, hipStream_t s) {
+  struct EndCall {
+    EventLog& log;
+    ~EndCall() { log.end_call(); }
+  } end_call{b->timing};
+  stitch_status st = b->timing.mark(s, -1);
+  if (!st) st = enqueue_phases(b, s, 0, kMaxLevels, true);
+  return st;
+}
+
+// The grouped schedule: level-0 passes of the groups in turn on s; after group g's, its
+// later passes and blends on the side stream; s joins the side stream at the end.
+stitch_status enqueue_grouped(stitch_batch* b, hipStream_t s) {
+  for (int g = 0; g < b->ngroups; ++g) {
+    stitch_status st = enqueue_phases(b->groups[g], s, 0, 1, false);
+    if (st) return st;
+    hipError_t e = hipEventRecord(b->gev[g], s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->gev[g], 0);
+    if (e != hipSuccess) return hip_fail(e, "group fork");
+    if ((st = enqueue_phases(b->groups[g], b->side, 1, kMaxLevels, true))) return st;
+  }
+  hipError_t e = hipEventRecord(b->gev[b->ngroups], b->side);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, b->gev[b->ngroups], 0);
+  return e == hipSuccess ? STITCH_OK : hip_fail(e, "group join");
 }
 
 // Check the run's frames and panoramas, write their pointers into the tables and upload
@@ -1309,6 +1350,47 @@ stitch_status batch_prepare(stitch_batch* b, const stitch_image* const* frames, 
     if (st) return st;
   }
   b->uploaded = true;
+  return STITCH_OK;
+}
+
+// Copy the batch's per-level settings (tile height, workgroups per CU) to its groups.
+void sync_groups(stitch_batch* b) {
+  for (stitch_batch* g : b->groups) {
+    for (int k = 0; k + 1 < g->maxL; ++k) {
+      g->wg_cap[k] = b->wg_cap[k];
+      if (b->sub[k] > 0 && g->sub[k] != b->sub[k]) {
+        g->sub[k] = b->sub[k];
+        set_sub(g->pyr[k], g->sub[k], g->pyr_tiles[k]);
+        g->uploaded = false;
+      }
+    }
+  }
+}
+
+// Point the groups' tables at their slices of the batch's workspace (after its own tables).
+void bind_groups(stitch_batch* b) {
+  size_t off = b->own_bytes;
+  for (stitch_batch* g : b->groups) {
+    g->ws = b->ws ? b->ws + off : nullptr;
+    g->uploaded = false;
+    off += g->ws_bytes;
+  }
+}
+
+// Each group's frames and panoramas (its jobs' entries of the run's arrays) into its tables.
+stitch_status prepare_groups(stitch_batch* b, const stitch_image* const* frames, stitch_image* panos, hipStream_t s) {
+  std::vector<const stitch_image*> fr;
+  std::vector<stitch_image> pv;
+  for (int g = 0; g < b->ngroups; ++g) {
+    fr.clear();
+    pv.clear();
+    for (int j : b->group_jobs[g]) {
+      fr.push_back(frames[j]);
+      pv.push_back(panos[j]);
+    }
+    const stitch_status st = batch_prepare(b->groups[g], fr.data(), pv.data(), s);
+    if (st) return st;
+  }
   return STITCH_OK;
 }
 
@@ -1528,7 +1610,10 @@ stitch_status stitch_batch_create(int32_t njobs, stitch_plan* const* plans, stit
     b->off_pyr[k] = lay.take(std::max<size_t>(1, b->pyr[k].size()) * sizeof(PyrItem));
     b->off_blend[k] = lay.take(std::max<size_t>(1, b->blend[k].size()) * sizeof(BlendItem));
   }
-  b->ws_bytes = lay.top;
+  b->own_bytes = lay.top;
+  // room for the tables of up to kMaxGroups groups (stitch_batch_set_groups): together they
+  // hold every item once, plus each group's per-level alignment
+  b->ws_bytes = 2 * b->own_bytes + (size_t)kMaxGroups * 2 * kMaxLevels * 256;
   *out = b;
   b = nullptr;
   return STITCH_OK;
@@ -1543,6 +1628,7 @@ stitch_status stitch_batch_bind(stitch_batch* b, void* workspace, size_t bytes) 
   if (bytes < b->ws_bytes) return fail(STITCH_E_WORKSPACE, "workspace has %zu bytes, the batch needs %zu", bytes, b->ws_bytes);
   b->ws = (uint8_t*)workspace;
   b->uploaded = false;
+  bind_groups(b);
   drop_graph(b);
   return STITCH_OK;
 }
@@ -1554,11 +1640,13 @@ stitch_status stitch_batch_run(stitch_batch* b, const stitch_image* const* frame
   if (st) return st;
   // the null stream cannot be captured, and timing events stay out of graphs: launch eagerly
   if (!s || b->timing.on) return enqueue_batch(b, s);
+  const bool grouped = b->ngroups > 1;
+  if (grouped && (st = prepare_groups(b, frames, panos, s))) return st;
   if (!b->exec) {
     prepare_launches();
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "batch capture begin");
-    st = enqueue_batch(b, s);
+    st = grouped ? enqueue_grouped(b, s) : enqueue_batch(b, s);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(s, &g);
     if (st) {
@@ -1591,7 +1679,9 @@ stitch_status stitch_batch_autotune(stitch_batch* b, const stitch_image* const* 
                             b->t16[k], k == 0};
   FrameArgs fa;
   std::memset(&fa, 0, sizeof fa);   // n = 0: frames come from the item tables
-  return tune_passes(np, passes, b->f16, fa, s, cache_path, 0x62617463ull /* batch */);
+  st = tune_passes(np, passes, b->f16, fa, s, cache_path, 0x62617463ull /* batch */);
+  sync_groups(b);
+  return st;
 }
 
 stitch_status stitch_batch_config(const stitch_batch* b, int32_t wg_per_cu[STITCH_MAX_LEVELS],
@@ -1634,9 +1724,76 @@ stitch_status stitch_batch_set_config(stitch_batch* b, const int32_t wg_per_cu[S
     }
   }
   b->uploaded = false;   // the next run uploads the tables and captures a new graph
+  sync_groups(b);
   drop_graph(b);
   return STITCH_OK;
 }
+
+stitch_status stitch_batch_set_groups(stitch_batch* b, int32_t ngroups) {
+  if (!b) return fail(STITCH_E_NULL, "batch is NULL");
+  if (ngroups < 1 || ngroups > kMaxGroups || ngroups > b->njobs)
+    return fail(STITCH_E_SHAPE, "groups = %d outside 1..%d (and at most the %d jobs)", ngroups, kMaxGroups, b->njobs);
+  drop_graph(b);
+  for (stitch_batch* g : b->groups) delete g;
+  b->groups.clear();
+  b->group_jobs.clear();
+  b->ngroups = 1;
+  if (ngroups == 1) return STITCH_OK;
+  // longest-processing-time split by level-0 work (16-row tiles of the warp pass), each
+  // group's jobs in their batch order
+  std::vector<int64_t> work(b->njobs, 0);
+  for (size_t q = 0; q < b->pyr[0].size(); ++q)
+    work[b->frame_job[q]] += (int64_t)b->pyr[0][q].tiles_x * b->pyr[0][q].rows16;
+  std::vector<int> order(b->njobs);
+  for (int j = 0; j < b->njobs; ++j) order[j] = j;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+  std::vector<int64_t> load(ngroups, 0);
+  b->group_jobs.assign(ngroups, {});
+  for (int j : order) {
+    const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    b->group_jobs[g].push_back(j);
+    load[g] += std::max<int64_t>(work[j], 1);
+  }
+  for (auto& v : b->group_jobs) std::sort(v.begin(), v.end());
+  size_t need = b->own_bytes;
+  for (int g = 0; g < ngroups; ++g) {
+    std::vector<stitch_plan*> pl;
+    for (int j : b->group_jobs[g]) pl.push_back(b->plans[j]);
+    stitch_batch* sub = nullptr;
+    stitch_status st = stitch_batch_create((int32_t)pl.size(), pl.data(), &sub);
+    if (st) {
+      for (stitch_batch* x : b->groups) delete x;
+      b->groups.clear();
+      b->group_jobs.clear();
+      return st;
+    }
+    b->groups.push_back(sub);
+    need += sub->own_bytes;
+    sub->ws_bytes = sub->own_bytes;   // a group holds only its own tables
+  }
+  if (need > b->ws_bytes) {   // cannot happen: create reserved room for kMaxGroups groups
+    for (stitch_batch* x : b->groups) delete x;
+    b->groups.clear();
+    b->group_jobs.clear();
+    return fail(STITCH_E_WORKSPACE, "group tables need %zu bytes, the batch reserved %zu", need, b->ws_bytes);
+  }
+  if (!b->side) {
+    const hipError_t e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "side stream");
+  }
+  while ((int)b->gev.size() < kMaxGroups + 1) {
+    hipEvent_t ev;
+    const hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "group events");
+    b->gev.push_back(ev);
+  }
+  b->ngroups = ngroups;
+  bind_groups(b);
+  sync_groups(b);
+  return STITCH_OK;
+}
+
+int32_t stitch_batch_group_count(const stitch_batch* b) { return b ? b->ngroups : 0; }
 
 // ------------------------------------------------------------------------------------ plan settings
 

@@ -81,6 +81,8 @@ SIGNATURES = {
                                         c_char_p]),
     "stitch_batch_config": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
     "stitch_batch_set_config": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
+    "stitch_batch_set_groups": (c_int32, [c_void_p, c_int32]),
+    "stitch_batch_group_count": (c_int32, [c_void_p]),
     "stitch_plan_config": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
     "stitch_plan_set_config": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32), c_void_p]),
     "stitch_autotune": (c_int32, [c_void_p, POINTER(StitchImage), c_void_p, c_char_p]),
@@ -582,6 +584,14 @@ class Batch:
         """Per-pass settings (lists indexed by level; missing entries keep the tile height
         and take as many workgroups as fit)."""
         check(lib().stitch_batch_set_config(self._h, *_config_arrays(wg_per_cu, tile_rows)))
+
+    def set_groups(self, groups: int) -> None:
+        """Run the jobs as `groups` sub-batches pipelined over two streams (1: one sequence)."""
+        check(lib().stitch_batch_set_groups(self._h, int(groups)))
+
+    @property
+    def groups(self) -> int:
+        return lib().stitch_batch_group_count(self._h)
 
     def close(self) -> None:
         if getattr(self, "_h", None):

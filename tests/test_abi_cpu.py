@@ -308,6 +308,12 @@ def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
         S.lib()
 
 
+def test_batch_group_calls_validate_on_host():
+    lib = P.lib()
+    assert lib.stitch_batch_set_groups(None, 2) == E["E_NULL"]
+    assert lib.stitch_batch_group_count(None) == 0
+
+
 def test_batch_create_validates_on_host():
     lib = P.lib()
     args, keep = _plan_args()

@@ -108,3 +108,35 @@ def test_autotune_keeps_results_and_uses_its_cache(tmp_path):
     assert cfg2 == cfg and len(cache.read_text().strip().splitlines()) == 1
     for a, c in zip(panos, ref):
         assert torch.equal(a, c)
+
+
+@pytest.mark.parametrize("groups", [2, 3, 7])
+def test_grouped_schedule_equals_one_by_one(groups):
+    """The jobs as sub-batches pipelined over two streams: every replay equals one by one,
+    also after new frame buffers and after the settings change."""
+    rigs, plans, frames, panos = _jobs()
+    ref = _one_by_one(plans, frames)
+    torch.cuda.synchronize()
+    b = P.Batch(plans)
+    b.set_groups(groups)
+    assert b.groups == groups
+    s = torch.cuda.Stream()
+    for rep in range(3):
+        for p in panos:
+            p.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            b.run(frames, panos, stream=s)
+        s.synchronize()
+        _ = torch.ones(1000, device=DEV).sum().item()
+        for j, (a, c) in enumerate(zip(panos, ref)):
+            assert torch.equal(a, c), f"replay {rep}, job {j}"
+    b.set_config([-1] * 8, [32] * 8)
+    frames2 = [[torch.flip(f, dims=[0]).contiguous() for f in fr] for fr in frames]
+    ref2 = _one_by_one(plans, frames2)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        b.run(frames2, panos, stream=s)
+    s.synchronize()
+    for a, c in zip(panos, ref2):
+        assert torch.equal(a, c)

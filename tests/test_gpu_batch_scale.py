@@ -54,9 +54,13 @@ def test_batched_tall_tiles_equal_one_by_one_and_the_oracle(storage):
     # the planner's own choice at this size is a tall tile for the level-0 pass
     assert cfg0["tile_rows"][0] >= 64, cfg0
     s = torch.cuda.Stream()
-    settings = [None, ([-1] * 6, [128] * 6), ([2] * 6, [64] * 6), ([0] * 6, [16, 32, 128, 64, 16, 32])]
+    settings = [None, ([-1] * 6, [128] * 6), ([2] * 6, [64] * 6), ([0] * 6, [16, 32, 128, 64, 16, 32]),
+                ("groups", 2), ("groups", 4), ("groups", 1)]
     for st in settings:
-        if st is not None:
+        if st is not None and st[0] == "groups":
+            b.set_groups(st[1])
+            assert b.groups == st[1]
+        elif st is not None:
             b.set_config(*st)
             got = b.config()
             assert got["tile_rows"][:6] == st[1] and got["wg_per_cu"][:6] == st[0]

@@ -99,14 +99,16 @@ def test_autograd_function_routes_the_adjoint():
     g.freeze([Ha, P.corners_to_h(q.detach().numpy(), w, h)])
     loss = P.StitchPairLoss.apply(frames[0], frames[1], q, g, Ha)
     (3.0 * loss).backward()
-    # the same quantities straight from the ABI
+    # the same quantities from the pair's own adjoint (stitch_grad_backward): the autograd
+    # function takes them through stitch_frame_backward from the loss's FP32 upstream terms,
+    # so they agree to the FP32 rounding of those terms
     loss2 = g.forward([f.detach() for f in frames], [Ha, P.corners_to_h(q.detach().numpy(), w, h)])
     d_frames, d_map = g.backward()
     assert loss2 == float(loss)
     for f, d in zip(frames, d_frames):
-        assert torch.allclose(f.grad, 3.0 * d, rtol=1e-6, atol=0)
-    assert np.allclose(q.grad.numpy(), 3.0 * P.map_grad_to_corners(q.detach().numpy(), w, h, d_map[1]),
-                       rtol=1e-12, atol=0)
+        assert float((f.grad - 3.0 * d).norm() / (3.0 * d).norm()) <= 1e-6
+    dq = 3.0 * P.map_grad_to_corners(q.detach().numpy(), w, h, d_map[1])
+    assert np.linalg.norm(q.grad.numpy() - dq) <= 1e-6 * np.linalg.norm(dq)
     # a second forward invalidates the first loss's backward
     loss_a = P.StitchPairLoss.apply(frames[0], frames[1], q, g, Ha)
     P.StitchPairLoss.apply(frames[0], frames[1], q, g, Ha)
