@@ -554,6 +554,19 @@ stitch_status stitch_lsh_match(int32_t nd, const uint32_t* desc_a, const int32_t
  * workspace: stitch_prosac_workspace_bytes, 256-byte aligned.
  * Errors: NULL, SHAPE, WORKSPACE, DEVICE. */
 size_t        stitch_prosac_workspace_bytes(int32_t cap_a, int32_t nhyp);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): stitch_prosac without a workspace
+ * argument.  Its scratch is a 1 MiB array the library holds on each device it runs on until
+ * the process ends; calls whose stitch_prosac_workspace_bytes(cap_a, nhyp) exceeds 1 MiB
+ * (cap_a 4096 with more than 12,280 hypotheses, for instance) return SHAPE.  Every call on
+ * a device shares that device's array: calls that overlap on one GPU (other streams, other
+ * threads) race, so serialise them.  The kernels write every scratch value before reading it.  It allocates
+ * nothing (the array's address is looked up on the first call on each device).  Outputs and
+ * errors as stitch_prosac. */
+stitch_status stitch_prosac_noalloc(const int32_t* pts_a, const int32_t* pts_b, int32_t cap_b, const int32_t* match,
+                                    const int32_t* dist, const int32_t* count_a, int32_t cap_a, int32_t nhyp,
+                                    const double* uniforms, double T_N, double eps, double* H, int32_t* inliers,
+                                    uint8_t* inlier_mask, int32_t* hyp_counts, void* stream);
 stitch_status stitch_prosac(const int32_t* pts_a, const int32_t* pts_b, int32_t cap_b, const int32_t* match,
                             const int32_t* dist, const int32_t* count_a, int32_t cap_a, int32_t nhyp,
                             const double* uniforms, double T_N, double eps, double* H, int32_t* inliers,

@@ -20,6 +20,8 @@
 // the reference keys and descriptors from L2 is faster than bucket lists.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -596,11 +598,73 @@ size_t stitch_prosac_workspace_bytes(int32_t cap_a, int32_t nhyp) {
   return total;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Scratch of the allocation-free PROSAC entry point: one array per device that runs it,
+// held until the process ends.  Host code never passes `scratch` itself to a kernel (on the
+// host it only names the symbol); it passes the device address from hipGetSymbolAddress.
+constexpr size_t kProsacScratchBytes = (size_t)1 << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) uint8_t scratch[kProsacScratchBytes];
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of the scratch array (its address is looked up once per device,
+// with that device current).
+stitch_status prosac_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "current device");
+  if (dev < 0 || dev >= kMaxDevices) return fail(STITCH_E_DEVICE, "device %d outside 0..%d", dev, kMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return STITCH_OK;
+}
+
+stitch_status prosac_run(const int32_t* pts_a, const int32_t* pts_b, int32_t cap_b, const int32_t* match,
+                         const int32_t* dist, const int32_t* count_a, int32_t cap_a, int32_t nhyp,
+                         const double* uniforms, double T_N, double eps, double* H, int32_t* inliers,
+                         uint8_t* inlier_mask, int32_t* hyp_counts, void* workspace, size_t workspace_bytes,
+                         void* stream, bool own_scratch);
+
+}  // namespace
+
+extern "C" {
+
 stitch_status stitch_prosac(const int32_t* pts_a, const int32_t* pts_b, int32_t cap_b, const int32_t* match,
                             const int32_t* dist, const int32_t* count_a, int32_t cap_a, int32_t nhyp,
                             const double* uniforms, double T_N, double eps, double* H, int32_t* inliers,
                             uint8_t* inlier_mask, int32_t* hyp_counts, void* workspace, size_t workspace_bytes,
                             void* stream) {
+  return prosac_run(pts_a, pts_b, cap_b, match, dist, count_a, cap_a, nhyp, uniforms, T_N, eps, H, inliers,
+                    inlier_mask, hyp_counts, workspace, workspace_bytes, stream, false);
+}
+
+stitch_status stitch_prosac_noalloc(const int32_t* pts_a, const int32_t* pts_b, int32_t cap_b, const int32_t* match,
+                                    const int32_t* dist, const int32_t* count_a, int32_t cap_a, int32_t nhyp,
+                                    const double* uniforms, double T_N, double eps, double* H, int32_t* inliers,
+                                    uint8_t* inlier_mask, int32_t* hyp_counts, void* stream) {
+  return prosac_run(pts_a, pts_b, cap_b, match, dist, count_a, cap_a, nhyp, uniforms, T_N, eps, H, inliers,
+                    inlier_mask, hyp_counts, nullptr, 0, stream, true);
+}
+
+}  // extern "C"
+
+namespace {
+
+stitch_status prosac_run(const int32_t* pts_a, const int32_t* pts_b, int32_t cap_b, const int32_t* match,
+                         const int32_t* dist, const int32_t* count_a, int32_t cap_a, int32_t nhyp,
+                         const double* uniforms, double T_N, double eps, double* H, int32_t* inliers,
+                         uint8_t* inlier_mask, int32_t* hyp_counts, void* workspace, size_t workspace_bytes,
+                         void* stream, bool own_scratch) {
   if (!pts_a || !pts_b || !match || !dist || !count_a || !uniforms || !H || !inliers || !inlier_mask || !hyp_counts)
     return fail(STITCH_E_NULL, "an input or output is NULL");
   if (cap_a < 1 || cap_a > kMaxPoints || cap_b < 1 || cap_b > kMaxPoints)
@@ -614,6 +678,14 @@ stitch_status stitch_prosac(const int32_t* pts_a, const int32_t* pts_b, int32_t 
     return fail(STITCH_E_SHAPE, "T_N = %g exceeds 2^53", T_N);
   size_t need = 0;
   const ProsacWs L = prosac_layout(cap_a, nhyp, &need);
+  if (own_scratch) {
+    if (need > kProsacScratchBytes)
+      return fail(STITCH_E_SHAPE, "cap_a = %d and nhyp = %d need %zu bytes of scratch; the allocation-free call "
+                  "holds %zu", cap_a, nhyp, need, kProsacScratchBytes);
+    const stitch_status st = prosac_scratch(&workspace);
+    if (st) return st;
+    workspace_bytes = kProsacScratchBytes;
+  }
   if (!workspace || workspace_bytes < need || ((uintptr_t)workspace & 255))
     return fail(STITCH_E_WORKSPACE, "workspace missing, misaligned or smaller than %zu bytes", need);
   uint8_t* ws = (uint8_t*)workspace;
@@ -637,4 +709,4 @@ stitch_status stitch_prosac(const int32_t* pts_a, const int32_t* pts_b, int32_t 
   return STITCH_OK;
 }
 
-}  // extern "C"
+}  // namespace

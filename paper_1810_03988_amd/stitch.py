@@ -131,6 +131,9 @@ SIGNATURES = {
                                 c_void_p, c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                 c_size_t, c_void_p]),
     "stitch_lorb_read_timing": (c_int32, [POINTER(c_double), POINTER(c_int32)]),
+    "stitch_prosac_noalloc": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
+                                        c_void_p, c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_void_p]),
 }
 
 TIMING_KINDS = ["warp_level0_pass", "level_pass", "blend_level0", "blend_middle", "blend_top",
