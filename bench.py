@@ -42,6 +42,9 @@ def parse():
                     help="c3 (default): 64 jobs of 2-6 cameras, one frame set each, batched against one by one; "
                          "c2/c4: one rig's frame sequence; c5: the adjoint's refinement report over 16 pairs")
     ap.add_argument("--jobs", type=int, default=64, help="jobs of the c3 batch")
+    ap.add_argument("--profile-form", choices=["f16", "f32"],
+                    help="c3 under a profiler: only the batched form of this storage, one sequence (no groups), "
+                         "no plain forms, no CPU baseline")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16"])
     ap.add_argument("--form", default="batched", choices=["batched", "plain"],
                     help="the headline form: all frames of the step as one batch, or one stitch_frame per frame")
@@ -853,7 +856,8 @@ def run_c3(a):
     tune = os.environ.get("STITCH_TUNE_CACHE")
     forms, ref_panos, tables, configs, plans0 = {}, {}, {}, {}, {}
     mpx = lambda ms_: round(px / (ms_ / 1e3) / 1e6, 1)
-    for st in ("f16", "f32"):
+    prof = a.profile_form
+    for st in ((prof,) if prof else ("f16", "f32")):
         t = time.perf_counter()
         plans = [P.Plan(r.frame_sizes, r.H, r.masks(), r.canvas_w, r.canvas_h, r.levels, storage=st) for r in rigs]
         panos = [torch.empty((r.canvas_h, r.canvas_w, 3), dtype=torch.uint8, device="cuda") for r in rigs]
@@ -867,31 +871,44 @@ def run_c3(a):
                 p.frame_raw(ar, sh)
 
         with torch.cuda.stream(stream):
-            for _ in range(a.warmup):
+            ms1 = float("nan")
+            if not prof:
+                for _ in range(a.warmup):
+                    one_by_one()
+                stream.synchronize()
+                t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                t0.record(stream)
+                for _ in range(a.steps):
+                    one_by_one()
+                t1.record(stream)
+                stream.synchronize()
+                ms1 = t0.elapsed_time(t1) / a.steps
+                forms[f"plain_{st}"] = {"Mpx_s": mpx(ms1), "ms_per_step": round(ms1, 4),
+                                        "how": "one stitch_frame per job, eager launches, default tiles"}
+                print(f"# plain_{st}: {ms1:.3f} ms/step, {mpx(ms1):.0f} Mpx/s", file=sys.stderr, flush=True)
+            else:
                 one_by_one()
-            stream.synchronize()
-            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            t0.record(stream)
-            for _ in range(a.steps):
-                one_by_one()
-            t1.record(stream)
-            stream.synchronize()
-            ms1 = t0.elapsed_time(t1) / a.steps
-            forms[f"plain_{st}"] = {"Mpx_s": mpx(ms1), "ms_per_step": round(ms1, 4),
-                                    "how": "one stitch_frame per job, eager launches, default tiles"}
-            print(f"# plain_{st}: {ms1:.3f} ms/step, {mpx(ms1):.0f} Mpx/s", file=sys.stderr, flush=True)
             batch = P.Batch(plans)
             cfg = batch.autotune(frames, panos, stream=stream, cache_path=tune)
             bargs = batch.args(frames, panos)
             # the schedule: one sequence, or the jobs as groups pipelined over two streams
             # (the warp pass of one group under the memory-bound passes of the previous)
+            # (persistent grids hold every compute unit until they end, so the grouped schedule
+            # is also tried with one workgroup per tile, which lets the two streams' kernels share
+            # the compute units)
             by_groups = {}
-            for G in [g for g in (1, 2, 3, 4) if g <= len(rigs)]:
-                batch.set_groups(G)
-                by_groups[G] = round(time_graph_and_events(batch, bargs, stream, max(3, a.steps // 2), 2,
-                                                           events=False)["graph"][0], 4)
+            tuned_wg = list(cfg["wg_per_cu"])
+            for G in [g for g in (1, 2, 3, 4) if g <= len(rigs) and (not prof or g == 1)]:
+                for per_tile in ((False, True) if G > 1 else (False,)):
+                    batch.set_groups(G)
+                    batch.set_config([-1] * len(tuned_wg) if per_tile else tuned_wg, [0] * len(tuned_wg))
+                    key = f"{G}{'/per-tile' if per_tile else ''}"
+                    by_groups[key] = round(time_graph_and_events(batch, bargs, stream, max(3, a.steps // 2), 2,
+                                                                 events=False)["graph"][0], 4)
             best_g = min(by_groups, key=by_groups.get)
-            batch.set_groups(best_g)
+            G_best, per_tile_best = int(best_g.split("/")[0]), best_g.endswith("per-tile")
+            batch.set_groups(G_best)
+            batch.set_config([-1] * len(tuned_wg) if per_tile_best else tuned_wg, [0] * len(tuned_wg))
             print(f"# {st} batched graph ms by groups: {by_groups} -> {best_g}", file=sys.stderr, flush=True)
             res = time_graph_and_events(batch, bargs, stream, a.steps, a.warmup, events=not a.no_kernel_events)
         torch.cuda.synchronize()
@@ -914,6 +931,11 @@ def run_c3(a):
                   f"{v['achieved_GBs']:8.1f} GB/s", file=sys.stderr, flush=True)
         del batch, plans, panos, one, args
         torch.cuda.empty_cache()
+    if prof:
+        if a.copy_calibration_mib > 0:
+            copy_calibration(a.copy_calibration_mib)
+        print(json.dumps({"profile_form": prof, "forms": forms}), flush=True)
+        return
     head = forms["batched_graph_f16"]
     roof = None
     if "f16" in tables:
