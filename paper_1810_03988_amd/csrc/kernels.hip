@@ -274,12 +274,15 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
   constexpr int NCT = WARP ? EW : 1, NRT = WARP ? EH : 1;
   __shared__ __attribute__((aligned(16))) float sColT[NCT][4];
   __shared__ __attribute__((aligned(16))) float sRowT[NRT][4];
-  __shared__ int sCls[2];   // warp only: window classes of the 16-row and the 7-row stage
+  // warp only: the class of every sub-step's 16-row window, classified together at the
+  // tile's first sub-step (slot kMaxSub: the 7 rows that sub-step also stages)
+  constexpr int kMaxSub = 8;
+  __shared__ int sCls[kMaxSub + 1];
   // warp only: the source rectangle under a source-interior 16-row window, one 256-byte
   // LDS row per source row (read as aligned 16-byte chunks), and its origin
   constexpr int FH = 24, FWB = 256;
   __shared__ __attribute__((aligned(16))) uint32_t sSrc[WARP ? FH : 1][FWB / 4];
-  __shared__ int sBox[4];   // bx0, by0, rows, 16-byte chunks per row
+  __shared__ int sBox[kMaxSub][4];   // per sub-step: bx0, by0, rows, 16-byte chunks per row
   constexpr uint32_t kPlaneRing = EH * SW * 4;       // bytes of one channel's ring of rows
 
   const int tid = threadIdx.x;
@@ -315,19 +318,22 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
       const uint32_t off4 = (uint32_t)off * (SW * 4);
       const bool interior = X0 >= 4 && X0 + TX + 3 <= fw && Y0 >= 4 && Y0 + TY + 3 <= fh;
       if (WARP) {
-        // this sub-step's coordinate tables; their last readers (the previous sub-step's
-        // stage A) finished before its closing barrier
+        // the coordinate tables (the columns once per tile, the rows per sub-step); their
+        // last readers (the previous sub-step's stage A) finished before its closing barrier
         if (tid < EW) {
-          const float Xf = (float)(X0 - 4 + tid);
-          const float4 c = {it.hinv[0] * Xf, it.hinv[3] * Xf, it.hinv[6] * Xf, 0.0f};
-          *reinterpret_cast<float4*>(sColT[tid]) = c;
+          if (s == 0) {
+            const float Xf = (float)(X0 - 4 + tid);
+            const float4 c = {it.hinv[0] * Xf, it.hinv[3] * Xf, it.hinv[6] * Xf, 0.0f};
+            *reinterpret_cast<float4*>(sColT[tid]) = c;
+          }
         } else if (tid >= 128 && tid < 128 + EH) {
           const float Yf = (float)(Y0 - 4 + (tid - 128));
           const float4 r = {it.hinv[1] * Yf, it.hinv[4] * Yf, it.hinv[7] * Yf, 0.0f};
           *reinterpret_cast<float4*>(sRowT[tid - 128]) = r;
-        } else if (tid >= 192) {
-          // Window classes, once for the workgroup (wave 3; lanes 0-3: the corners of the
-          // 16 new rows, lanes 4-7: of the 7 rows a tile's first sub-step also stages).
+        } else if (tid >= 192 && s == 0) {
+          // Window classes of every sub-step of the tile, once per tile (wave 3; lanes
+          // 8 u .. 8 u + 3: the corners of sub-step u's 16 new rows, lanes 4-7: of the 7
+          // rows the first sub-step also stages).
           // Source-interior (bit 0): z > 0 at the four corners (so on all of the window: z
           // is affine) and their source positions inside [1, w-3) x [1, h-2).  The map is
           // projective there, so every staged sample lies in the convex hull of the corner
@@ -338,18 +344,19 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
           // x >= w + 1, y <= -2 or y >= h + 1): every staged sample's taps are outside,
           // its G_0 is 0.  Either also needs the window inside the canvas (checked by the
           // stage).
-          const int lane = tid - 192;
+          const int lane = tid - 192, u = lane >> 3, j = lane & 7;
+          const int nsc = min(d.nsub, kMaxSub);
           bool bad = false, zok = false, lft = false, rgt = false, top = false, bot = false;
           float xc = 0.0f, yc = 0.0f;
           const int w = it.frame_w, h = it.frame_h;
-          if (lane < 8) {
+          if (u < nsc && (j < 4 || u == 0)) {
             float hv[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) hv[i] = it.hinv[i];
-            const int r0 = lane < 4 ? EH - TY : 0, r1 = lane < 4 ? EH - 1 : EH - TY - 1;
+            const int r0 = j < 4 ? EH - TY : 0, r1 = j < 4 ? EH - 1 : EH - TY - 1;
             float zc;
-            warp_coords_z(hv, (float)(X0 - 4 + ((lane & 1) ? EW - 1 : 0)),
-                          (float)(Y0 - 4 + ((lane & 2) ? r1 : r0)), xc, yc, zc);
+            warp_coords_z(hv, (float)(X0 - 4 + ((j & 1) ? EW - 1 : 0)),
+                          (float)(d.Y0 + u * TY - 4 + ((j & 2) ? r1 : r0)), xc, yc, zc);
             zok = zc >= 0x1p-10f && zc <= 0x1p20f;
             bad = !(zok && xc >= 1.0f && xc < (float)(w - 3) && yc >= 1.0f && yc < (float)(h - 2));
             lft = xc <= -2.0f;
@@ -359,21 +366,21 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
           }
           const uint64_t mb = __ballot(bad), mz = __ballot(zok), ml = __ballot(lft), mr = __ballot(rgt),
                          mt = __ballot(top), mo = __ballot(bot);
-          // bounding box of the 16-row window's corner images (lanes 0-3)
+          // bounding box of each group of four corner images
           float mnx = xc, mxx = xc, mny = yc, mxy = yc;
 #pragma unroll
-          for (int d = 1; d < 4; d <<= 1) {
-            mnx = fminf(mnx, __shfl_xor(mnx, d));
-            mxx = fmaxf(mxx, __shfl_xor(mxx, d));
-            mny = fminf(mny, __shfl_xor(mny, d));
-            mxy = fmaxf(mxy, __shfl_xor(mxy, d));
+          for (int dd = 1; dd < 4; dd <<= 1) {
+            mnx = fminf(mnx, __shfl_xor(mnx, dd));
+            mxx = fmaxf(mxx, __shfl_xor(mxx, dd));
+            mny = fminf(mny, __shfl_xor(mny, dd));
+            mxy = fmaxf(mxy, __shfl_xor(mxy, dd));
           }
-          if (lane < 2) {
-            const int sh = 4 * lane;
+          if (u < nsc && (j == 0 || (j == 4 && u == 0))) {
+            const int sh = lane;
             auto all4 = [sh](uint64_t m) { return ((m >> sh) & 15ull) == 15ull; };
             const bool fast = ((mb >> sh) & 15ull) == 0ull;
             const bool outside = all4(mz) && (all4(ml) || all4(mr) || all4(mt) || all4(mo));
-            // Staged (bit 2, 16-row window only): every tap lies in the box [bx0, bx1] x
+            // Staged (bit 2, 16-row windows only): every tap lies in the box [bx0, bx1] x
             // [by0, by1] (the corner images' bounding box, one sample wider on each side
             // for rounding), which fits the LDS rows, and the 16-byte chunks covering a
             // box row (from its start rounded down to 16 bytes, at most 15 + 3 nbx + 15
@@ -382,19 +389,19 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
             // in its LDS row.
             bool staged = false;
             const int64_t srow = fa.n ? fa.row[it.frame_slot] : it.img_row;
-            if (lane == 0 && fast && (srow & 15) == 0) {
+            if (j == 0 && fast && (srow & 15) == 0) {
               const int bx0 = (int)floorf(mnx) - 1, bx1 = (int)floorf(mxx) + 2;
               const int by0 = (int)floorf(mny) - 1, by1 = (int)floorf(mxy) + 2;
               const int nbx = bx1 - bx0 + 1, nby = by1 - by0 + 1;
               staged = bx0 >= 5 && bx1 <= w - 11 && by0 >= 0 && by1 <= h - 1 && 15 + 3 * nbx <= FWB && nby <= FH;
               if (staged) {
-                sBox[0] = bx0;
-                sBox[1] = by0;
-                sBox[2] = nby;
-                sBox[3] = (15 + 3 * nbx + 15) / 16;
+                sBox[u][0] = bx0;
+                sBox[u][1] = by0;
+                sBox[u][2] = nby;
+                sBox[u][3] = (15 + 3 * nbx + 15) / 16;
               }
             }
-            sCls[lane] = (fast ? 1 : 0) | (outside ? 2 : 0) | (staged ? 4 : 0);
+            sCls[j == 0 ? u : kMaxSub] = (fast ? 1 : 0) | (outside ? 2 : 0) | (staged ? 4 : 0);
           }
         }
       }
@@ -420,6 +427,10 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
           // used), so stores need no branch and loads are never sunk into one
           lo[q] = (uint32_t)((rr[q] < 0 ? R0 : rr[q]) * SW + (rr[q] < 0 ? EW : cc[q])) * 4u;
         }
+        // When the stage's samples end inside its last round of slots, that round is idle
+        // for whole waves (the 16-row stage: the waves of threads 128 .. 255); they skip it.
+        const bool last_live = NE % kThreads == 0 || __builtin_amdgcn_readfirstlane(tid >> 6) * 64 + (NQ - 1) * kThreads < NE;
+        auto live = [&](int q) { return q < NQ - 1 || last_live; };
         // the slot's cell in channel plane ch, rotated into the ring
         auto cell = [&](int ch, int q) -> float& {
           const uint32_t a = lo[q] + off4;
@@ -452,10 +463,11 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
             const uint32_t mrow = (uint32_t)it.msk_row;
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
-              mv[q] = m0[__umul24((uint32_t)(rr[q] < 0 ? 0 : rr[q] - R0), mrow) + (uint32_t)cc[q]];
+              if (live(q)) mv[q] = m0[__umul24((uint32_t)(rr[q] < 0 ? 0 : rr[q] - R0), mrow) + (uint32_t)cc[q]];
           } else {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
+              if (!live(q)) continue;
               int X, Y;
               canvas(q, X, Y);
               const int my = Y - ry, mx = X - rx;
@@ -466,11 +478,12 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
           }
           const float fwf = (float)w, fhf = (float)h, fwm1 = (float)(w - 1), fhm1 = (float)(h - 1);
           // the window's class, computed before the sub-step's barrier
-          const int cls = interior ? sCls[R0 == 0 ? 1 : 0] : 0;
+          const int cls = !interior ? 0 : R0 == 0 ? sCls[kMaxSub] : s < kMaxSub ? sCls[s] : 0;
           const bool fast = (cls & 1) != 0, outside = (cls & 2) != 0;
           if (outside) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
+              if (!live(q)) continue;
               cell(0, q) = 0.0f;
               cell(1, q) = 0.0f;
               cell(2, q) = 0.0f;
@@ -480,7 +493,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
             // Source rectangle staged in LDS: its rows are read as aligned 16-byte chunks
             // (the reads of the whole workgroup cover it once), each sample's coordinates
             // are computed meanwhile, and its two 8-byte tap pairs come from LDS.
-            const int bx0 = sBox[0], by0 = sBox[1], nby = sBox[2], nck = sBox[3];
+            const int bx0 = sBox[s][0], by0 = sBox[s][1], nby = sBox[s][2], nck = sBox[s][3];
             constexpr int NCK = (FH * (FWB / 16) + kThreads - 1) / kThreads;
             typedef uint32_t vu4 __attribute__((ext_vector_type(4)));
             vu4 ck[NCK];
@@ -497,6 +510,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
             uint32_t o1[NQ];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
+              if (!live(q)) continue;
               // the coordinate sequence from the tabled products (the same roundings as
               // the direct one; the in-range division is the IEEE one)
               const float4 ct = *reinterpret_cast<const float4*>(sColT[cc[q]]);
@@ -533,11 +547,13 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
             unsigned long long ras[NQ], rbs[NQ];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
+              if (!live(q)) continue;
               ras[q] = ld8s(o1[q]);
               rbs[q] = ld8s(o1[q] + FWB);
             }
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
+              if (!live(q)) continue;
               const unsigned long long ra = ras[q], rb = rbs[q];
               const float fx = fxq[q], fy = fyq[q], gx = 1.0f - fx, gy = 1.0f - fy;
               const float gyi = gy * kInv255, fyi = fy * kInv255;
@@ -560,6 +576,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
             float fxq[NQ], fyq[NQ];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
+              if (!live(q)) continue;
               // z lies between its corner values and x, y in [1, w) x [1, h): the in-range
               // division is the IEEE one, x - floor(x) is exact and truncation is floor
               // the coordinate sequence from the tabled products (the same roundings)
@@ -581,6 +598,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
             }
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
+              if (!live(q)) continue;
               const float fx = fxq[q], fy = fyq[q], gx = 1.0f - fx, gy = 1.0f - fy;
               const float gyi = gy * kInv255, fyi = fy * kInv255;
               const float w00 = gyi * gx, w01 = gyi * fx, w10 = fyi * gx, w11 = fyi * fx;
@@ -606,6 +624,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
             const uint32_t lastc = 3u * (uint32_t)w - 8u;
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
+              if (!live(q)) continue;
               int Xc, Yc;
               canvas(q, Xc, Yc);
               float x, y;
@@ -628,6 +647,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
             }
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
+              if (!live(q)) continue;
               const int sh = (int)(tapq[q] >> 4) - 3;              // byte offset of tap 0: -3 .. 5
               const unsigned long long a = sh >= 0 ? ra[q] >> (8 * sh) : ra[q] << 24;
               const unsigned long long bq = sh >= 0 ? rb[q] >> (8 * sh) : rb[q] << 24;
@@ -661,6 +681,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
           bool inq[NQ];
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
+            if (!live(q)) continue;
             int X, Y;
             canvas(q, X, Y);
             Y -= ry;
@@ -674,6 +695,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
           }
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
+            if (!live(q)) continue;
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) cell(ch, q) = (inq[q] && ch < nimg) ? from_raw(raw[q][ch]) : 0.0f;
             cell(3, q) = (inq[q] && has_mask) ? from_raw(raw[q][3]) : 0.0f;
@@ -690,7 +712,12 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
       const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
       const int lane = tid & 63;
       if (wv >= nact) continue;
-      const int ch = wv < nimg ? wv : 3;
+      // With all four channels, the mask (whose wave has no D+E) goes to wave s & 1: a
+      // workgroup's waves run on the compute unit's four SIMDs one each, and waves 0 and 1
+      // also took stage A's last, partial round of samples, so every SIMD gets about the
+      // same arithmetic per two sub-steps.
+      const int mw = s & 1;
+      const int ch = nact == 4 && nimg == 3 ? (wv == mw ? 3 : wv - (wv > mw ? 1 : 0)) : (wv < nimg ? wv : 3);
       // logical row r of the channel's ring (byte offsets keep the arithmetic 32-bit)
       const char* plane = reinterpret_cast<const char*>(&sIn[ch][0][0]);
       auto rowp = [&](int r) -> const float* {
