@@ -64,6 +64,9 @@ def parse():
                          "oracle per level (on windows through their dependency cones) and on the uint8 "
                          "output, and FP16 against FP32 on the whole canvas; prints one JSON line")
     ap.add_argument("--windows", type=int, default=8, help="oracle windows for --precision")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the HBM traffic summary of two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE) "
+                         "taken with --copy-calibration-mib 512, then exit")
     ap.add_argument("--rocprof-summary", metavar="DIR",
                     help="summarise the rocprofv3 CSV output under DIR (kernel stats and counters per "
                          "kernel) and exit; needs no GPU")
@@ -78,6 +81,8 @@ KERNEL_KINDS = {
     "k_blend<_Float16, true, true>": "blend_level0 (f16)", "k_blend<_Float16, false, true>": "blend_middle/top (f16)",
     "k_blend<float, true, false>": "blend_level0, batched (f32)",
     "k_blend<float, false, false>": "blend_middle/top, batched (f32)",
+    "k_blend<_Float16, true, false>": "blend_level0, batched (f16)",
+    "k_blend<_Float16, false, false>": "blend_middle/top, batched (f16)",
     "k_lorb_clear": "L-ORB clear", "k_lorb_detect": "L-ORB detect (FAST, R, suppression)",
     "k_lorb_select": "L-ORB select (histogram threshold)", "k_lorb_rank": "L-ORB rank",
     "k_lorb_brief": "L-ORB BRIEF",
@@ -93,6 +98,15 @@ def _short_kernel(name: str) -> str:
     m = re.search(r"(k_[a-z_]+)<([^()]*)>", name)
     if m:
         return m.group(1) + "<" + m.group(2) + ">"
+    # mangled names (as some rocprofv3 builds report them): this library's kernels
+    m = re.search(r"\d+(k_[a-z_]+?)I(DF16_|f)Lb([01])ELb([01])E", name)
+    if m:
+        t = "_Float16" if m.group(2) == "DF16_" else "float"
+        b = lambda v: "true" if v == "1" else "false"
+        return f"{m.group(1)}<{t}, {b(m.group(3))}, {b(m.group(4))}>"
+    m = re.search(r"_GLOBAL__N_1\d+(k_[a-z0-9_]+?)E", name)
+    if m:
+        return m.group(1)
     return name.split("(")[0][-90:]
 
 
@@ -144,6 +158,59 @@ def rocprof_summary(root: str) -> None:
                     print(f"{_short_kernel(row['Name']):44s} calls={row['Calls']:>6s} "
                           f"avg_ns={float(row['AverageNs']):12.1f} total_ns={float(row['TotalDurationNs']):14.1f} "
                           f"pct={float(row['Percentage']):6.2f}")
+
+
+def traffic_summary(fetch_dir: str, write_dir: str) -> None:
+    """The body of a profiles/hbm_traffic_*.txt file from two rocprofv3 counter runs of the
+    same command (FETCH_SIZE in one, WRITE_SIZE in the other, each with the calibration copy
+    kernel): the source hash the figures belong to, the calibration, the raw per-dispatch
+    averages, and one line per kernel: traffic <kind> <kernel> <HBM bytes per dispatch>."""
+    import csv
+    import glob
+    from collections import defaultdict
+    raw = defaultdict(dict)
+    scale = {}
+    for ctr, root in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        agg, disp = defaultdict(float), defaultdict(set)
+        for f in glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for row in csv.DictReader(fh):
+                    if row["Counter_Name"] != ctr:
+                        continue
+                    k = _short_kernel(row["Kernel_Name"])
+                    agg[k] += float(row["Counter_Value"])
+                    disp[k].add(row["Dispatch_Id"])
+        copy = [k for k in agg if COPY_KERNEL_HINT in k]
+        if not copy:
+            raise SystemExit(f"no calibration kernel in {root}")
+        c = agg[copy[0]] / len(disp[copy[0]])
+        scale[ctr] = (c, COPY_MIB * 1024 / c)
+        for k in agg:
+            if COPY_KERNEL_HINT not in k:
+                raw[k][ctr] = (agg[k] / len(disp[k]), len(disp[k]))
+    print(f"# source sha256: {source_hash()}   (code of kernels.hip + stitch_api.cpp: comments and whitespace "
+          f"removed, see bench.source_hash)")
+    print(f"# Calibration: the copy kernel y = -x over {COPY_MIB} MiB float32 reads and writes {COPY_MIB * 1024} KiB "
+          f"per dispatch;")
+    print(f"#   FETCH_SIZE reads {scale['FETCH_SIZE'][0]:.0f} KiB, WRITE_SIZE reads {scale['WRITE_SIZE'][0]:.0f} KiB "
+          f"for it")
+    print(f"# scale factors: FETCH_SIZE x {scale['FETCH_SIZE'][1]:.3f}, WRITE_SIZE x {scale['WRITE_SIZE'][1]:.3f}")
+    print("#")
+    print("# raw counters (KiB per dispatch, averaged over the dispatches of each kernel):")
+    for k in sorted(raw):
+        f_, w_ = raw[k].get("FETCH_SIZE", (0.0, 0)), raw[k].get("WRITE_SIZE", (0.0, 0))
+        print(f"#   {k:34s} {KERNEL_KINDS.get(k, ''):34s} n={f_[1]:4d} FETCH_SIZE={f_[0]:.6g} WRITE_SIZE={w_[0]:.6g}")
+    print("#")
+    print("# scaled HBM bytes per dispatch (x 1024):")
+    for k in sorted(raw):
+        kind = KERNEL_KINDS.get(k, "").split(" (")[0].split(",")[0]
+        if not kind or "FETCH_SIZE" not in raw[k] or "WRITE_SIZE" not in raw[k]:
+            continue
+        b = (raw[k]["FETCH_SIZE"][0] * scale["FETCH_SIZE"][1] + raw[k]["WRITE_SIZE"][0] * scale["WRITE_SIZE"][1]) * 1024
+        print(f"traffic {kind:18s} {k:34s} {int(round(b))}")
+
+
+COPY_MIB = 512
 
 
 def _window_list(rig, n, win):
@@ -886,8 +953,6 @@ def run_c3(a):
                 forms[f"plain_{st}"] = {"Mpx_s": mpx(ms1), "ms_per_step": round(ms1, 4),
                                         "how": "one stitch_frame per job, eager launches, default tiles"}
                 print(f"# plain_{st}: {ms1:.3f} ms/step, {mpx(ms1):.0f} Mpx/s", file=sys.stderr, flush=True)
-            else:
-                one_by_one()
             batch = P.Batch(plans)
             cfg = batch.autotune(frames, panos, stream=stream, cache_path=tune)
             bargs = batch.args(frames, panos)
@@ -912,7 +977,7 @@ def run_c3(a):
             print(f"# {st} batched graph ms by groups: {by_groups} -> {best_g}", file=sys.stderr, flush=True)
             res = time_graph_and_events(batch, bargs, stream, a.steps, a.warmup, events=not a.no_kernel_events)
         torch.cuda.synchronize()
-        same = all(torch.equal(x, y) for x, y in zip(panos, one))
+        same = None if prof else all(torch.equal(x, y) for x, y in zip(panos, one))
         ms = res["graph"][0]
         forms[f"batched_graph_{st}"] = {
             "Mpx_s": mpx(ms), "ms_per_step": round(ms, 4), "how": "one HIP graph replay per step",
@@ -1042,6 +1107,9 @@ def cpu_baseline(rig, frames0):
 
 def main():
     a = parse()
+    if a.traffic_summary:
+        traffic_summary(*a.traffic_summary)
+        return
     if a.rocprof_summary:
         rocprof_summary(a.rocprof_summary)
         return
