@@ -991,39 +991,64 @@ __global__ void __launch_bounds__(kThreads) k_blend(const BlendItem* __restrict_
     const int cx0 = X0 / 2 - 1, cy0 = Y0 / 2 - 1;
     constexpr int NC = 3 * CH * CW;
     constexpr int NIT = (NC + kThreads - 1) / kThreads;
-    float v[NIT];
+    // Sample e = tid + q kThreads of the coarse tile is (channel c, row i, column j); the
+    // triple steps from q to q + 1 by kThreads = DI rows + DJ columns, without a division.
+    // Round q's samples past the tile repeat the tile's last one.
+    constexpr int DI = kThreads / CW, DJ = kThreads % CW;
+    static_assert(kThreads < CH * CW && DI + 1 < 2 * CH, "one carry per step");
+    int cq[NIT], iq[NIT], jq[NIT];
+    {
+      int c = 0, i = tid / CW, j = tid - (tid / CW) * CW;
 #pragma unroll
-    for (int q = 0; q < NIT; ++q) {
-      const int e = min(tid + q * kThreads, NC - 1);
-      const int c = e / (CH * CW), rem = e - c * (CH * CW);
-      const int i = rem / CW, j = rem - i * CW;
-      // coarse index of the fine-domain fold of fine sample 2*c, kept inside the level
-      const int cy = min(fold(2 * (cy0 + i), a.H) >> 1, a.cH - 1);
-      const int cx = min(fold(2 * (cx0 + j), a.W) >> 1, a.cW - 1);
-      v[q] = ldg(r, c * a.rin_plane + (int64_t)cy * a.rin_row + cx);
-    }
-#pragma unroll
-    for (int q = 0; q < NIT; ++q) {
-      const int e = tid + q * kThreads;
-      if (e < NC) {
-        const int c = e / (CH * CW), rem = e - c * (CH * CW);
-        const int i = rem / CW, j = rem - i * CW;
-        sC[c][i][j] = v[q];
+      for (int q = 0; q < NIT; ++q) {
+        const bool past = c >= 3;
+        cq[q] = past ? 2 : c;
+        iq[q] = past ? CH - 1 : i;
+        jq[q] = past ? CW - 1 : j;
+        j += DJ;
+        i += DI + (j >= CW ? 1 : 0);
+        j -= j >= CW ? CW : 0;
+        c += i >= CH ? 1 : 0;
+        i -= i >= CH ? CH : 0;
       }
     }
+    // A tile whose coarse samples all have their fine position inside the level needs no
+    // folding (the fold is then the identity and the coarse index is in range); the offsets
+    // come first and the reads after them, one straight run.
+    const bool inner = cx0 >= 0 && 2 * (cx0 + CW - 1) < a.W && cy0 >= 0 && 2 * (cy0 + CH - 1) < a.H;
+    int64_t off[NIT];
+#pragma unroll
+    for (int q = 0; q < NIT; ++q) {
+      const int cy = inner ? cy0 + iq[q] : min(fold(2 * (cy0 + iq[q]), a.H) >> 1, a.cH - 1);
+      const int cx = inner ? cx0 + jq[q] : min(fold(2 * (cx0 + jq[q]), a.W) >> 1, a.cW - 1);
+      off[q] = cq[q] * a.rin_plane + (int64_t)cy * a.rin_row + cx;
+    }
+    typename RawOf<T>::type v[NIT];
+#pragma unroll
+    for (int q = 0; q < NIT; ++q) v[q] = ld_raw(r, off[q]);
+#pragma unroll
+    for (int q = 0; q < NIT; ++q)
+      if (tid + q * kThreads < NC) sC[cq[q]][iq[q]][jq[q]] = from_raw(v[q]);
     __syncthreads();
+    // horizontal EXPAND: item e = tid + k kThreads is (channel, row, quad m) of the
+    // 3 x CH x 16 quads
     constexpr int PER = CH * (TX / 4);
-    for (int e = tid; e < 3 * PER; e += kThreads) {
-      const int ch = e / PER, rem = e - ch * PER;
-      const int i = rem / (TX / 4), m = rem - i * (TX / 4);
-      const float2 lo = *reinterpret_cast<const float2*>(&sC[ch][i][2 * m]);
-      const float2 hi = *reinterpret_cast<const float2*>(&sC[ch][i][2 * m + 2]);
-      float4 o;
-      o.x = 0.125f * (lo.x + hi.x) + 0.75f * lo.y;
-      o.y = 0.5f * (lo.y + hi.x);
-      o.z = 0.125f * (lo.y + hi.y) + 0.75f * hi.x;
-      o.w = 0.5f * (hi.x + hi.y);
-      *reinterpret_cast<float4*>(&sE[ch][i][4 * m]) = o;
+    static_assert(TX / 4 == 16 && kThreads < 2 * PER && 3 * PER <= 2 * kThreads, "two rounds, one carry");
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int e = tid + k * kThreads;
+      if (e < 3 * PER) {
+        const int ch = (e >= PER ? 1 : 0) + (e >= 2 * PER ? 1 : 0), rem = e - ch * PER;
+        const int i = rem >> 4, m = rem & 15;
+        const float2 lo = *reinterpret_cast<const float2*>(&sC[ch][i][2 * m]);
+        const float2 hi = *reinterpret_cast<const float2*>(&sC[ch][i][2 * m + 2]);
+        float4 o;
+        o.x = 0.125f * (lo.x + hi.x) + 0.75f * lo.y;
+        o.y = 0.5f * (lo.y + hi.x);
+        o.z = 0.125f * (lo.y + hi.y) + 0.75f * hi.x;
+        o.w = 0.5f * (hi.x + hi.y);
+        *reinterpret_cast<float4*>(&sE[ch][i][4 * m]) = o;
+      }
     }
     __syncthreads();
   }
