@@ -519,7 +519,7 @@ def time_lorb(rig, frames, steps, warmup, n_max=500, nd=256):
     import paper_1810_03988_amd as P
     from paper_1810_03988_amd import stitch as S
     import workloads as wl
-    areas = wl.overlap_areas(rig)
+    areas = P.detection_areas(rig.frame_sizes, rig.H, rig.canvas_w, rig.canvas_h)   # Alg. 2 step 1
     pattern = torch.from_numpy(wl.brief_pattern(nd)).cuda()
     cams = [i for i in range(rig.n) if areas[i]]
     lorbs = {i: P.Lorb(*rig.frame_sizes[i], areas[i], n_max=n_max, nd=nd) for i in cams}
@@ -621,7 +621,7 @@ def time_register(rig, frames, steps, warmup, n_max=500, nd=256, nhyp=1024):
     the whole chain and as matching + PROSAC alone; accuracy against the rig's true maps."""
     import paper_1810_03988_amd as P
     import workloads as wl
-    areas = wl.overlap_areas(rig)
+    areas = P.detection_areas(rig.frame_sizes, rig.H, rig.canvas_w, rig.canvas_h)   # Alg. 2 step 1
     pattern = torch.from_numpy(wl.brief_pattern(nd)).cuda()
     cams = [i for i in range(rig.n) if areas[i]]
     lset = P.LorbSet([rig.frame_sizes[i] for i in cams], [areas[i] for i in cams], n_max=n_max, nd=nd)
@@ -728,9 +728,10 @@ def _scanned(rect, w, h, margin=17):
 def lorb_cpu_baseline(rig, frames0, n_max=500, nd=256):
     """The L-ORB oracle on one detection area of camera 0 (exact integer numpy and Python
     loops, one thread): area samples per second."""
+    import oracle
     from oracle import lorb_oracle as lo
     import workloads as wl
-    area = wl.overlap_areas(rig)[0][0]
+    area = oracle.detection_areas(rig.frame_sizes, rig.H, rig.canvas_w, rig.canvas_h)[0][0]
     w, h = rig.frame_sizes[0]
     frame = frames0[0].cpu().numpy()
     t = time.perf_counter()

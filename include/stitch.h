@@ -434,6 +434,32 @@ stitch_status stitch_map_grad_to_corners(const double q[8], int32_t w, int32_t h
 
 /* ---- L-ORB features in the detection areas (registration front end) ------------ */
 
+/* The feature detection areas of n frames from the cameras' rough alignment (Alg. 2, step
+ * 1; Sec. 4.1: the areas are where the pre-aligned neighbouring frames overlap).  Host-only:
+ * touches no GPU.  Camera i's footprint is the bounding box of its frame rectangle's
+ * corners (0,0), (w,0), (w,h), (0,h) mapped by H_i (row-major, source -> canvas, as for
+ * stitch_plan_create).  For every pair i < j whose footprints overlap with positive area,
+ * the overlap, widened by `margin` canvas pixels on every side and clipped to the canvas
+ * [0, canvas_w] x [0, canvas_h], is mapped back into each frame of the pair through
+ * adj(H_k); the bounding box of its corner images, rounded outward with a slack of 1e-6
+ * sample and clipped to the frame, is one area (x, y, width, height) of frame k when it
+ * is not empty.  Each frame's areas follow the partner camera's index.  The footprint (or
+ * an overlap's corner images) is bounded only when the projective depth has one sign,
+ * never zero, at its four corners: a camera with an unbounded footprint gets no areas,
+ * and an overlap whose corner images in frame k are unbounded gives frame k its whole
+ * rectangle.  All arithmetic is FP64.
+ * frame_w, frame_h: n sides (1 .. 2^20); n in 1..64; canvas sides 1 .. 2^20; margin 0 .. 2^20.
+ * Outputs (HOST): counts[n] the areas of each frame (0 .. max_areas), areas[n][max_areas][4]
+ *   with frame k's areas at areas + 4 k max_areas (entries past counts[k] not written);
+ *   max_areas >= 1 (n - 1 is always enough).  The result feeds stitch_lorb and
+ *   stitch_lorb_multi directly.
+ * Errors: NULL, SHAPE (also more areas in a frame than max_areas), HOMOGRAPHY (a
+ *   non-finite entry of H). */
+stitch_status stitch_detection_areas(int32_t n, const int32_t* frame_w, const int32_t* frame_h, const double* H,
+                                     int32_t canvas_w, int32_t canvas_h, int32_t margin, int32_t max_areas,
+                                     int32_t* counts, int32_t* areas);
+
+
 /* L-ORB (Sec. 4.1, Alg. 1 and Alg. 2): in each of m feature detection areas of a frame
  * (Alg. 2, step 1: the pre-aligned overlap of neighbouring cameras), FAST corners scored
  * by the Harris response, non-maximal suppression, the n_max strongest, and a BRIEF

@@ -12,3 +12,4 @@ from .adjoint_oracle import (  # noqa: F401
     GradOracle, FrameVjpOracle, dlt_from_corners, dlt_jacobian, canvas_map_jacobian, reduce_T, expand_T,
     corners,
 )
+from .areas_oracle import detection_areas, footprint  # noqa: F401

@@ -11,7 +11,7 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libstitch.so"
 SOURCES = [CSRC / "kernels.hip", CSRC / "stitch_api.cpp", CSRC / "grad.hip", CSRC / "pipe.cpp", CSRC / "lorb.hip",
-           CSRC / "register.hip"]
+           CSRC / "register.hip", CSRC / "areas.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -117,6 +117,8 @@ SIGNATURES = {
     "stitch_lorb": (c_int32, [POINTER(StitchImage), c_int32, POINTER(c_int32), c_int32, c_int64, c_int32, c_int32,
                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "stitch_lorb_set_timing": (c_int32, [c_int32]),
+    "stitch_detection_areas": (c_int32, [c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_double), c_int32,
+                                         c_int32, c_int32, c_int32, POINTER(c_int32), POINTER(c_int32)]),
     "stitch_lorb_multi_workspace_bytes": (c_size_t, [c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
                                                      POINTER(c_int32)]),
     "stitch_lorb_multi": (c_int32, [c_int32, POINTER(StitchImage), POINTER(c_int32), POINTER(c_int32), c_int32,
@@ -783,6 +785,21 @@ def refine_pair(grad: Grad, frame_a, frame_b, H_a, q0, steps: int = 50, lr: floa
 
 
 # ----------------------------------------------------------------------------- L-ORB features
+def detection_areas(frame_sizes, Hs, canvas_w: int, canvas_h: int, margin: int = 24) -> list:
+    """Per camera, the feature detection areas (x, y, w, h) of its frame (Alg. 2, step 1):
+    where the footprints of the pre-aligned neighbours overlap it, by stitch_detection_areas
+    (host-only)."""
+    n = len(frame_sizes)
+    fw = (c_int32 * n)(*[int(w) for w, _ in frame_sizes])
+    fh = (c_int32 * n)(*[int(h) for _, h in frame_sizes])
+    hs = (c_double * (9 * n))(*[float(v) for H in Hs for v in np.asarray(H, dtype=np.float64).reshape(9)])
+    cap = max(1, n - 1)
+    counts = (c_int32 * n)()
+    out = (c_int32 * (4 * n * cap))()
+    check(lib().stitch_detection_areas(n, fw, fh, hs, int(canvas_w), int(canvas_h), int(margin), cap, counts, out))
+    return [[tuple(out[4 * (k * cap + a) + i] for i in range(4)) for a in range(counts[k])] for k in range(n)]
+
+
 class Lorb:
     """L-ORB feature extraction (Sec. 4.1, Alg. 1 and Alg. 2) in fixed detection areas of
     frames of one size: device outputs and workspace are allocated once and reused."""

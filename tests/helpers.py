@@ -56,3 +56,13 @@ def random_partition(rng, n: int, h: int, w: int, kind: str = "noise") -> list[n
         np.put_along_axis(q, idx[None], np.take_along_axis(q, idx[None], 0) + sel[None], 0)
     assert np.all(q.sum(0) == 255)
     return [q[i].astype(np.uint8) for i in range(n)]
+
+
+def rig_areas(rig, margin: int = 24) -> list:
+    """The rig's feature detection areas (Alg. 2 step 1) from the library's host call,
+    checked equal to the oracle's before use (so GPU and oracle work on the same areas)."""
+    import oracle
+    import paper_1810_03988_amd as P
+    got = P.detection_areas(rig.frame_sizes, rig.H, rig.canvas_w, rig.canvas_h, margin)
+    assert got == oracle.detection_areas(rig.frame_sizes, rig.H, rig.canvas_w, rig.canvas_h, margin)
+    return got

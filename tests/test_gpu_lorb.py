@@ -9,7 +9,7 @@ import torch
 import paper_1810_03988_amd as P
 import workloads as wl
 from oracle import lorb_oracle as lo
-from helpers import gpu_available
+from helpers import gpu_available, rig_areas
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
@@ -38,7 +38,7 @@ def test_rig_frames_in_their_overlap_areas():
     500 points of 256-pair descriptors: more survivors than kept, so the cut is exercised."""
     rig = wl.rig_c1()
     frames = wl.render_rig_frames(rig)
-    for cam, areas in enumerate(wl.overlap_areas(rig)):
+    for cam, areas in enumerate(rig_areas(rig)):
         assert _check(frames[cam].numpy(), areas) == 500 * len(areas), cam
 
 
@@ -46,7 +46,7 @@ def test_full_hd_frame_with_two_areas():
     """A 1920x1080 camera of the four-camera rig with its two overlap areas (both sides)."""
     rig = wl.rig_c2()
     frame = wl.render_rig_frames(rig)[1].numpy()
-    areas = wl.overlap_areas(rig)[1]
+    areas = rig_areas(rig)[1]
     assert len(areas) == 2
     assert _check(frame, areas, n=1000) > 0
 
@@ -154,7 +154,7 @@ def test_launch_timing_and_per_camera_streams():
     from paper_1810_03988_amd import stitch as S
     rig = wl.rig_c1()
     frames = [f.cuda() for f in wl.render_rig_frames(rig)]
-    areas = wl.overlap_areas(rig)
+    areas = rig_areas(rig)
     pat = torch.from_numpy(wl.brief_pattern(256)).cuda()
     lorbs = [P.Lorb(640, 480, areas[i], n_max=300) for i in range(rig.n)]
     S.lorb_set_timing(True)
@@ -180,7 +180,7 @@ def test_one_call_for_several_frames_equals_one_call_per_frame():
     sizes gives exactly the per-frame results; the per-frame results are the oracle's."""
     rig = wl.rig_c2()
     frames = [f.cuda() for f in wl.render_rig_frames(rig)]
-    areas = wl.overlap_areas(rig)
+    areas = rig_areas(rig)
     pat = torch.from_numpy(wl.brief_pattern(256)).cuda()
     ls = P.LorbSet(rig.frame_sizes, areas, n_max=400)
     ls.run_raw(frames, pat, torch.cuda.current_stream().cuda_stream)
@@ -218,7 +218,7 @@ def test_frame_set_call_replays_from_a_hip_graph():
     between them, each equal to the eager call."""
     rig = wl.rig_c2()
     frames = [f.cuda() for f in wl.render_rig_frames(rig)]
-    areas = wl.overlap_areas(rig)
+    areas = rig_areas(rig)
     pat = torch.from_numpy(wl.brief_pattern(256)).cuda()
     ls = P.LorbSet(rig.frame_sizes, areas, n_max=300)
     ls.run_raw(frames, pat, torch.cuda.current_stream().cuda_stream)

@@ -11,7 +11,7 @@ import paper_1810_03988_amd as P
 import workloads as wl
 from oracle import register_oracle as ro
 from oracle import lorb_oracle as lo
-from helpers import gpu_available
+from helpers import gpu_available, rig_areas
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
@@ -130,7 +130,7 @@ def test_prosac_degenerate_samples_are_skipped():
 def _pair_features(rig, cam, side_a, n_max=500):
     """L-ORB of cameras cam (its right area) and cam + 1 (its left area) on the GPU."""
     frames = wl.render_rig_frames(rig)
-    areas = wl.overlap_areas(rig)
+    areas = rig_areas(rig)
     pat = torch.from_numpy(wl.brief_pattern(256)).cuda()
     out = []
     for c, area in ((cam, areas[cam][-1]), (cam + 1, areas[cam + 1][0])):
@@ -158,7 +158,7 @@ def test_rig_pair_registration_matches_the_oracle_and_the_true_map(rig_name, cam
     us = np.random.default_rng(7).random((1024, 4))
     got = _check_prosac(pa.cpu().numpy(), pb.cpu().numpy(), got_idx.numpy(), got_d.numpy(), na, us, eps=3.0)
     H_true = np.linalg.inv(np.asarray(rig.H[cam + 1])) @ np.asarray(rig.H[cam])
-    x0, y0, w, h = lo.clip_area(wl.overlap_areas(rig)[cam][-1], *rig.frame_sizes[cam])
+    x0, y0, w, h = lo.clip_area(rig_areas(rig)[cam][-1], *rig.frame_sizes[cam])
     corners = [(x0, y0), (x0 + w, y0), (x0, y0 + h), (x0 + w, y0 + h)]
     err = max(np.hypot(*(_apply(got["H"], p) - _apply(H_true, p))) for p in corners)
     assert got["inliers"] >= 30 and err < 1.5, (got["inliers"], err)
@@ -173,7 +173,7 @@ def test_registration_feeds_the_gradient_refinement():
     r = wl.rig_c5_pairs(1)[0]
     w, h = r.frame_sizes[1]
     frames = wl.render_rig_frames(r)
-    areas = wl.overlap_areas(r)
+    areas = rig_areas(r)
     pat = torch.from_numpy(wl.brief_pattern(256)).cuda()
     feats = []
     for c, area in ((0, areas[0][-1]), (1, areas[1][0])):

@@ -7,5 +7,5 @@ consume it without sharing any of the method.
 from .synth import (  # noqa: F401
     ROOT_SEED, Rig, rig_c1, rig_c2, rig_c4, rig_c3_jobs, rig_c5_pairs, rig_ring,
     render_frames, render_rig_frames, render_rig_sequence, seam_masks, hash32_noise, scene_params,
-    brief_pattern, overlap_areas, rotated_frame,
+    brief_pattern, rotated_frame,
 )

@@ -285,35 +285,6 @@ def brief_pattern(nd: int = 256, seed: int = 0) -> np.ndarray:
     return np.clip(d, -15, 15).astype(np.int32)
 
 
-def overlap_areas(rig: Rig, margin: int = 24) -> list[list[tuple[int, int, int, int]]]:
-    """Per camera, the frame rectangles (x, y, w, h) that the pre-aligned neighbours overlap
-    (Alg. 2, step 1): the canvas overlap of adjacent footprints, widened by margin canvas
-    pixels, mapped back through the camera's H and clipped to its frame.  Input data only."""
-    n = rig.n
-    boxes = []
-    for i in range(n):
-        w, h = rig.frame_sizes[i]
-        c = np.array([[0, 0, 1], [w, 0, 1], [0, h, 1], [w, h, 1]], float) @ np.asarray(rig.H[i]).T
-        c = c[:, :2] / c[:, 2:]
-        boxes.append((c[:, 0].min(), c[:, 0].max()))
-    out = [[] for _ in range(n)]
-    for i in range(n - 1):
-        x0 = max(boxes[i][0], boxes[i + 1][0]) - margin
-        x1 = min(boxes[i][1], boxes[i + 1][1]) + margin
-        if x1 <= x0:
-            continue
-        for cam in (i, i + 1):
-            w, h = rig.frame_sizes[cam]
-            Hi = np.linalg.inv(np.asarray(rig.H[cam]))
-            pts = np.array([[x0, 0, 1], [x1, 0, 1], [x0, rig.canvas_h, 1], [x1, rig.canvas_h, 1]], float) @ Hi.T
-            pts = pts[:, :2] / pts[:, 2:]
-            fx0 = int(max(0, np.floor(pts[:, 0].min())))
-            fx1 = int(min(w, np.ceil(pts[:, 0].max())))
-            if fx1 > fx0:
-                out[cam].append((fx0, 0, fx1 - fx0, h))
-    return out
-
-
 def rotated_frame(frame: np.ndarray, deg: float) -> np.ndarray:
     """The (h, w, 3) uint8 frame turned by deg about its centre, nearest sample, 0 outside:
     the synthetic rotations the BRIEF descriptor is probed with (Fig. 2).  Input data only."""
