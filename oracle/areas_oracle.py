@@ -5,9 +5,9 @@ does, and the two share no code, header, table or helper.
 
 The paper reduces L-ORB's detection to the parts of each frame that the neighbouring
 frames overlap once the cameras are roughly aligned, without fixing how the overlap is
-measured.  Reading R27 (numbered after the L-ORB oracle's R17-R26):
+measured.  Reading R37 (numbered after the registration readings R27-R36):
 
-  R27 camera i's footprint is the axis-aligned bounding box of the images under H_i
+  R37 camera i's footprint is the axis-aligned bounding box of the images under H_i
       (source -> canvas) of its frame rectangle's corners (0, 0), (w, 0), (w, h), (0, h);
       it is bounded only when the projective depth keeps one sign, never zero, at the
       four corners (otherwise the camera gets no areas).  For every pair i < j whose
@@ -29,7 +29,7 @@ SLACK = 1e-6
 
 
 def footprint(H, w: int, h: int):
-    """R27: (x0, y0, x1, y1) of the frame's corner images under H, or None when unbounded."""
+    """R37: (x0, y0, x1, y1) of the frame's corner images under H, or None when unbounded."""
     return _image_box(np.asarray(H, dtype=np.float64), 0.0, 0.0, float(w), float(h))
 
 
@@ -47,7 +47,7 @@ def _image_box(M, x0: float, y0: float, x1: float, y1: float):
 
 
 def detection_areas(frame_sizes, Hs, canvas_w: int, canvas_h: int, margin: int = 24):
-    """Alg. 2 step 1 under R27: per camera, the list of areas (x, y, width, height)."""
+    """Alg. 2 step 1 under R37: per camera, the list of areas (x, y, width, height)."""
     n = len(frame_sizes)
     F = [footprint(Hs[i], *frame_sizes[i]) for i in range(n)]
     out = [[] for _ in range(n)]

@@ -1,4 +1,4 @@
-"""Pins of the detection-area oracle (Alg. 2 step 1 under reading R27) to closed forms,
+"""Pins of the detection-area oracle (Alg. 2 step 1 under reading R37) to closed forms,
 symmetry and a dense brute-force check of its defining property."""
 
 import numpy as np
