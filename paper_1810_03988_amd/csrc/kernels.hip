@@ -281,6 +281,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
   // warp only: the source rectangle under a source-interior 16-row window, one 256-byte
   // LDS row per source row (read as aligned 16-byte chunks), and its origin
   constexpr int FH = 24, FWB = 256;
+  static_assert(FWB == 256, "an LDS row of the source rectangle is 1 << 8 bytes");
   __shared__ __attribute__((aligned(16))) uint32_t sSrc[WARP ? FH : 1][FWB / 4];
   __shared__ int sBox[kMaxSub][4];   // per sub-step: bx0, by0, rows, 16-byte chunks per row
   constexpr uint32_t kPlaneRing = EH * SW * 4;       // bytes of one channel's ring of rows
@@ -526,8 +527,9 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
               fxq[q] = __builtin_amdgcn_fractf(x);
               fyq[q] = __builtin_amdgcn_fractf(y);
               const uint32_t xi = (uint32_t)(int)x, yi = (uint32_t)(int)y;
-              const uint32_t r = yi - (uint32_t)by0, dx = 3u * (xi - (uint32_t)bx0);
-              o1[q] = r * FWB + s1 + dx;
+              // 24-bit multiplies (full rate): the box is under 256 samples wide and 24 rows
+              const uint32_t r = yi - (uint32_t)by0, dx = __umul24(xi - (uint32_t)bx0, 3u);
+              o1[q] = (r << 8) + s1 + dx;
             }
 #pragma unroll
             for (int k = 0; k < NCK; ++k) {
@@ -592,7 +594,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
               div2_in_range(u, v, z, x, y);
               fxq[q] = __builtin_amdgcn_fractf(x);
               fyq[q] = __builtin_amdgcn_fractf(y);
-              const uint32_t o = __umul24((uint32_t)(int)y, srow32) + 3u * (uint32_t)(int)x;
+              const uint32_t o = __umul24((uint32_t)(int)y, srow32) + __umul24((uint32_t)(int)x, 3u);
               ra[q] = ld8(src + o);
               rb[q] = ld8(src + (o + srow32));
             }
@@ -894,8 +896,9 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
 
 // ------------------------------------------------------------------------------------
 // One synthesis level: B_k over cameras + EXPAND(R_{k+1}) -> R_k (and the panorama at k = 0).
-// 64x16 tile; thread (x = tid & 63) handles rows (tid >> 6) + 4 j, j = 0..3, so every
-// global access of a wave is one contiguous row segment.
+// 64x16 tile; thread (x = tid & 63) handles rows 4 (tid >> 6) + j, j = 0..3, so every
+// global access of a wave is one contiguous row segment, and a wave's four consecutive rows
+// share the four coarse rows their vertical EXPAND reads.
 __device__ __forceinline__ int find_blend_item(const BlendItem* __restrict__ items, int nitems, int t) {
   int lo = 0, hi = nitems - 1;
   while (lo < hi) {
@@ -938,7 +941,7 @@ __global__ void __launch_bounds__(kThreads) k_blend(const BlendItem* __restrict_
 
   // one camera's band and weight samples of this thread's four pixels, as raw bits from
   // always-valid addresses (offset 0 outside the windows); used after the coarse stage
-  const int x = tid & 63, ybase = tid >> 6;
+  const int x = tid & 63, ybase = 4 * (tid >> 6);   // wave w: tile rows 4w .. 4w+3
   const int X = X0 + x;
   using RawT = typename RawOf<T>::type;
   struct CamSamples {
@@ -959,7 +962,7 @@ __global__ void __launch_bounds__(kThreads) k_blend(const BlendItem* __restrict_
     cs.u8 = c.wgt_u8 != 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int Y = Y0 + ybase + 4 * j;
+      const int Y = Y0 + ybase + j;
       const int ly = Y - c.ly, wy = Y - c.wy;
       cs.in[j] = xin & (ly >= 0) & (ly < c.lh) & (wy >= 0) & (wy < c.wh);
       const uint32_t loff = cs.in[j] ? __umul24((uint32_t)ly, lrow) + (uint32_t)lx : 0u;
@@ -1065,7 +1068,7 @@ __global__ void __launch_bounds__(kThreads) k_blend(const BlendItem* __restrict_
   GLB T* ro = mg<T>(a.r_out);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int y = ybase + 4 * j;
+    const int y = ybase + j;
     const int Y = Y0 + y;
     if (has_coarse) {
       const int yh = y >> 1;
@@ -1092,7 +1095,7 @@ __global__ void __launch_bounds__(kThreads) k_blend(const BlendItem* __restrict_
     GLB uint8_t* pano = mg<uint8_t>(pano_ptr);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int Y = Y0 + ybase + 4 * j;
+      const int Y = Y0 + ybase + j;
       uint32_t q[3];
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) q[ch] = (uint32_t)fminf(fmaxf(rintf(255.0f * acc[j][ch]), 0.0f), 255.0f);
