@@ -318,6 +318,13 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
       const int off = (s * TY) % EH;   // logical row r of the window lives in ring row (r + off) mod EH
       const uint32_t off4 = (uint32_t)off * (SW * 4);
       const bool interior = X0 >= 4 && X0 + TX + 3 <= fw && Y0 >= 4 && Y0 + TY + 3 <= fh;
+      // stored levels of an interior window can be staged as aligned 16-byte chunks (above
+      // level 0; see stage A)
+      constexpr int kChunk = 16 / (int)sizeof(T);
+      const bool chunked = !WARP && interior && rw > 0 && rh > 0 && ((X0 - rx) % kChunk) == 0 &&
+                           (nimg == 0 || (((uintptr_t)it.img & 15) == 0 && (it.img_row % kChunk) == 0 &&
+                                          (it.img_plane % kChunk) == 0)) &&
+                           (!has_mask || (((uintptr_t)it.msk & 15) == 0 && (it.msk_row % kChunk) == 0));
       if (WARP) {
         // the coordinate tables (the columns once per tile, the rows per sub-step); their
         // last readers (the previous sub-step's stage A) finished before its closing barrier
@@ -668,6 +675,69 @@ __global__ void __launch_bounds__(kThreads, 4) k_pyr(const PyrItem* __restrict__
               for (int ch = 0; ch < 3; ++ch)
                 cell(ch, q) = w00 * p00[ch] + w01 * p01[ch] + w10 * p10[ch] + w11 * p11[ch];
               cell(3, q) = (float)mv[q] * kInv255;
+            }
+          }
+        } else if (chunked) {
+          // Stored G_k planes and Gm_k on the ROI (0 outside) as aligned 16-byte chunks of C
+          // samples: window row r of channel slot c is chunks k = 0 .. NCH-1 of plane row
+          // Y0 - 4 + R0 + r - ry from plane column X0 - C - rx + C k (the tile's X0 - rx, the
+          // row pitches and plane strides are multiples of C, the planes start on 16-byte
+          // boundaries, and a row's pitch covers its width rounded up to C).  Every read is
+          // issued, without a branch, from a chunk clamped into the plane (its row into
+          // [0, rh), its column into the rounded width); samples outside the ROI, the
+          // channel set or the window are dropped afterwards.
+          constexpr int C = 16 / (int)sizeof(T);
+          constexpr int NCH = 64 / C + 2;
+          constexpr int NT = NR * 4 * NCH;
+          constexpr int NQC = (NT + kThreads - 1) / kThreads;
+          typedef uint32_t vu4c __attribute__((ext_vector_type(4)));
+          const int rwc = (rw + C - 1) / C;
+          const int k0 = (X0 - C - rx) / C;   // plane chunk of k = 0
+          // the descriptor's fields once, as scalars (a per-lane choice between two fields
+          // would read them per lane and wait for each)
+          const GLB T* const gimg = cg<T>(it.img);
+          const GLB T* const gmsk = cg<T>(it.msk);
+          const uint32_t iplane = (uint32_t)it.img_plane, irow = (uint32_t)it.img_row, mrow = (uint32_t)it.msk_row;
+          uint32_t raw[NQC][4];   // plain dwords: an array of 4-vectors lost its upper elements at NQC = 5
+#pragma unroll
+          for (int q = 0; q < NQC; ++q) {
+            const int e = min(tid_l + q * kThreads, NT - 1);
+            const int k = e % NCH, rest = e / NCH, slot = rest & 3, r = rest >> 2;
+            const bool from_img = slot < 3 ? nimg > 0 : !has_mask;
+            const GLB T* base = from_img ? gimg + (uint32_t)min(slot, max(nimg - 1, 0)) * iplane : gmsk;
+            const uint32_t pitch = from_img ? irow : mrow;
+            const int prow = min(max(Y0 - 4 + R0 + r - ry, 0), rh - 1);
+            const int pck = min(max(k0 + k, 0), rwc - 1);
+            const vu4c t = *reinterpret_cast<const GLB vu4c*>(base + (__umul24((uint32_t)prow, pitch) + (uint32_t)(C * pck)));
+            raw[q][0] = t.x;
+            raw[q][1] = t.y;
+            raw[q][2] = t.z;
+            raw[q][3] = t.w;
+          }
+#pragma unroll
+          for (int q = 0; q < NQC; ++q) {
+            const int e = tid_l + q * kThreads;
+            if (e >= NT) continue;
+            const int k = e % NCH, rest = e / NCH, slot = rest & 3, r = rest >> 2;
+            const int prow = Y0 - 4 + R0 + r - ry, c0 = C * (k0 + k);
+            const bool ok = (slot < 3 ? slot < nimg : has_mask) && prow >= 0 && prow < rh;
+            const int keep = ok ? min(max(rw - c0, 0), (c0 < 0 ? 0 : C)) : 0;   // leading samples kept
+            float v[C];
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+              const float smp = sizeof(T) == 4 ? __builtin_bit_cast(float, raw[q][i & 3])
+                                               : from_raw((uint16_t)(raw[q][i >> 1] >> (16 * (i & 1))));
+              v[i] = i < keep ? smp : 0.0f;
+            }
+            // window column of v[0], a multiple of 4; only columns 0 .. SW-1 exist
+            const int wc = C * k - C + 4;
+            const uint32_t a0 = (uint32_t)((R0 + r) * SW) * 4u + off4;
+            char* rowb = reinterpret_cast<char*>(&sIn[slot][0][0]) + min(a0, a0 - kPlaneRing);
+#pragma unroll
+            for (int h = 0; h < C / 4; ++h) {
+              const int col = wc + 4 * h;
+              if (col >= 0 && col < SW)
+                *reinterpret_cast<float4*>(rowb + 4 * col) = float4{v[4 * h], v[4 * h + 1], v[4 * h + 2], v[4 * h + 3]};
             }
           }
         } else {
