@@ -88,6 +88,9 @@ KERNEL_KINDS = {
     "k_lorb_brief": "L-ORB BRIEF",
     "k_lsh_keys": "LSH keys", "k_lsh_match": "LSH matching", "k_prosac_prepare": "PROSAC order + growth",
     "k_prosac_hyp": "PROSAC hypotheses", "k_prosac_final": "PROSAC best + refit",
+    "k_lsh_keys_multi": "LSH keys, all pairs", "k_lsh_match_multi": "LSH matching, all pairs",
+    "k_prosac_prepare_multi": "PROSAC order + growth, all pairs", "k_prosac_hyp_multi": "PROSAC hyps, all pairs",
+    "k_prosac_final_multi": "PROSAC best + refit, all pairs",
 }
 COPY_KERNEL_HINT = "neg"
 
@@ -633,6 +636,8 @@ def time_register(rig, frames, steps, warmup, n_max=500, nd=256, nhyp=1024):
     pairs = [i for i in range(rig.n - 1) if areas[i] and areas[i + 1]]
     matchers = {i: P.Matcher(n_max, n_max, nd, pos, nd // 4) for i in pairs}
     prosacs = {i: P.Prosac(n_max, n_max, nhyp, 200000.0, 3.0) for i in pairs}
+    mset = P.MatcherSet([(n_max, n_max)] * len(pairs), nd, pos, nd // 4)
+    pset = P.ProsacSet([(n_max, n_max)] * len(pairs), nhyp, 200000.0, 3.0)
     h = torch.cuda.current_stream().cuda_stream
 
     def feats(i):
@@ -640,15 +645,23 @@ def time_register(rig, frames, steps, warmup, n_max=500, nd=256, nhyp=1024):
         return (lset.points[za], lset.descriptors[za], lset.counts[za:za + 1],
                 lset.points[zb], lset.descriptors[zb], lset.counts[zb:zb + 1])
 
+    ins = [feats(i) for i in pairs]                 # views of the L-ORB set's outputs
+    m_in = [(da, ca, db, cb) for pa, da, ca, pb, db, cb in ins]
+    p_in = [(pa, pb, mset.match[p], mset.dist[p], ca, uni) for p, (pa, da, ca, pb, db, cb) in enumerate(ins)]
+
     def match_prosac():
         for i in pairs:
             pa, da, ca, pb, db, cb = feats(i)
             matchers[i].run_raw(da, ca, db, cb, h)
             prosacs[i].run_raw(pa, pb, matchers[i].match, matchers[i].dist, ca, uni, h)
 
+    def match_prosac_one_call():
+        mset.run_raw(m_in, h)
+        pset.run_raw(p_in, h)
+
     def chain(t):
         lset.run_raw([frames[t % len(frames)][c] for c in cams], pattern, h)
-        match_prosac()
+        match_prosac_one_call()
 
     def timed(fn):
         for t in range(warmup):
@@ -665,6 +678,7 @@ def time_register(rig, frames, steps, warmup, n_max=500, nd=256, nhyp=1024):
     ms_chain = timed(chain)
     chain(0)                                        # features and maps of frame set 0
     torch.cuda.synchronize()
+    ms_one = timed(lambda t: match_prosac_one_call())
     ms_mp = timed(lambda t: match_prosac())
     # the pairs are independent (own workspaces and outputs): one stream per pair
     main = torch.cuda.current_stream()
@@ -684,9 +698,11 @@ def time_register(rig, frames, steps, warmup, n_max=500, nd=256, nhyp=1024):
             main.wait_event(ev)
 
     ms_mp_streams = timed(match_prosac_streams)
+    match_prosac_one_call()
+    torch.cuda.synchronize()
     res = []
-    for i in pairs:
-        H = prosacs[i].H.cpu().numpy().reshape(3, 3)
+    for p, i in enumerate(pairs):
+        H = pset.H[p].cpu().numpy().reshape(3, 3)
         H_true = np.linalg.inv(np.asarray(rig.H[i + 1])) @ np.asarray(rig.H[i])
         x0, y0, w, hh = areas[i][-1]
         err = 0.0
@@ -694,9 +710,12 @@ def time_register(rig, frames, steps, warmup, n_max=500, nd=256, nhyp=1024):
             a = H @ np.array([x, y, 1.0])
             b = H_true @ np.array([x, y, 1.0])
             err = max(err, float(np.hypot(*(a[:2] / a[2] - b[:2] / b[2]))))
-        res.append({"pair": [i, i + 1], "matches": int((matchers[i].match >= 0).sum()),
-                    "inliers": int(prosacs[i].inliers[0]), "max_corner_error_px": round(err, 3)})
-    return {"ms_chain": ms_chain, "ms_match_prosac": ms_mp, "ms_match_prosac_streams": ms_mp_streams,
+        res.append({"pair": [i, i + 1], "matches": int((mset.match[p] >= 0).sum()),
+                    "inliers": int(pset.inliers[p]), "max_corner_error_px": round(err, 3),
+                    "same_as_per_pair_calls": bool(torch.equal(pset.H[p], prosacs[i].H) and
+                                                   torch.equal(mset.match[p], matchers[i].match))})
+    return {"ms_chain": ms_chain, "ms_match_prosac_one_call": ms_one, "ms_match_prosac": ms_mp,
+            "ms_match_prosac_streams": ms_mp_streams,
             "pairs": res, "nhyp": nhyp,
             "features": (feats, pos, uni)}
 
@@ -1183,12 +1202,13 @@ def main():
             feats, pos, uni = G.pop("features")
             forms["register"] = {
                 "ms_per_rig_registration": round(G["ms_chain"], 4),
-                "ms_match_prosac_all_pairs": round(G["ms_match_prosac"], 4),
+                "ms_match_prosac_all_pairs_one_call_per_stage": round(G["ms_match_prosac_one_call"], 4),
+                "ms_match_prosac_all_pairs_per_pair_calls": round(G["ms_match_prosac"], 4),
                 "ms_match_prosac_all_pairs_stream_per_pair": round(G["ms_match_prosac_streams"], 4),
-                "how": "L-ORB of every camera in its overlap areas (one stitch_lorb_multi call), then per "
-                       "neighbouring pair multi-probe LSH "
-                       "matching (6 tables x 14 bits, distance <= 64) and PROSAC (1024 hypotheses, T_N 2e5, "
-                       "eps 3 px, least-squares refit); one stream, frames in HBM",
+                "how": "L-ORB of every camera in its overlap areas (one stitch_lorb_multi call), then every "
+                       "neighbouring pair's multi-probe LSH matching (6 tables x 14 bits, distance <= 64; one "
+                       "stitch_lsh_match_multi call) and PROSAC (1024 hypotheses, T_N 2e5, eps 3 px, "
+                       "least-squares refit; one stitch_prosac_multi call); one stream, frames in HBM",
                 "pairs": G["pairs"], "nhyp": G["nhyp"]}
             if not a.no_cpu_baseline:
                 forms["register"]["cpu_baseline"] = register_cpu_baseline(rig, frames[0], feats, pos, uni)

@@ -599,6 +599,52 @@ stitch_status stitch_prosac(const int32_t* pts_a, const int32_t* pts_b, int32_t 
                             uint8_t* inlier_mask, int32_t* hyp_counts, void* workspace, size_t workspace_bytes,
                             void* stream);
 
+/* ---- every camera pair of a rig in one launch per stage ----------------------------- */
+
+/* Matching and PROSAC of several area pairs at once (Alg. 3 for every neighbouring pair of
+ * a rig; the paper overlaps its images on stream queues, Sec. 4.3.2): one launch per stage
+ * covers all pairs, each pair computed exactly as by stitch_lsh_match / stitch_prosac with
+ * the same settings (results equal bit for bit).  The pair tables are HOST arrays of npairs
+ * (1..256) entries; every pointer inside them is DEVICE memory with the meaning, layout and
+ * limits of the single-pair call.  The calls upload their pair table into the head of the
+ * workspace on the stream (so they are not for graph capture) and then launch two
+ * (matching) or three (PROSAC) kernels.
+ * workspace: stitch_lsh_match_multi_workspace_bytes / stitch_prosac_multi_workspace_bytes
+ *   (0 on bad arguments), 256-byte aligned, caller-owned.
+ * Errors: NULL, SHAPE, WORKSPACE, DEVICE (as the single-pair calls, per pair). */
+typedef struct {
+  const uint32_t* desc_a;  /* cap_a rows of descriptors (stitch_lorb's layout) */
+  const int32_t* count_a;  /* rows in use */
+  int32_t cap_a;
+  const uint32_t* desc_b;
+  const int32_t* count_b;
+  int32_t cap_b;
+  int32_t* match;          /* [cap_a] outputs */
+  int32_t* dist;           /* [cap_a] */
+} stitch_match_pair;
+size_t        stitch_lsh_match_multi_workspace_bytes(int32_t npairs, const stitch_match_pair* pairs, int32_t tables);
+stitch_status stitch_lsh_match_multi(int32_t npairs, const stitch_match_pair* pairs, int32_t nd, int32_t tables,
+                                     int32_t kbits, const int32_t* positions, int32_t max_dist, void* workspace,
+                                     size_t workspace_bytes, void* stream);
+
+typedef struct {
+  const int32_t* pts_a;     /* [cap_a][2] */
+  const int32_t* pts_b;     /* [cap_b][2] */
+  int32_t cap_b;
+  const int32_t* match;     /* [cap_a], as stitch_lsh_match wrote it */
+  const int32_t* dist;      /* [cap_a] */
+  const int32_t* count_a;
+  int32_t cap_a;
+  const double* uniforms;   /* [nhyp][4] */
+  double* H;                /* [9] outputs */
+  int32_t* inliers;         /* [1] */
+  uint8_t* inlier_mask;     /* [cap_a] */
+  int32_t* hyp_counts;      /* [nhyp] */
+} stitch_prosac_pair;
+size_t        stitch_prosac_multi_workspace_bytes(int32_t npairs, const stitch_prosac_pair* pairs, int32_t nhyp);
+stitch_status stitch_prosac_multi(int32_t npairs, const stitch_prosac_pair* pairs, int32_t nhyp, double T_N,
+                                  double eps, void* workspace, size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,6 +5,6 @@ include/stitch.h (libstitch.so, built in-tree by paper_1810_03988_amd.build);
 paper_1810_03988_amd.stitch is the ctypes binding.
 """
 from . import stitch  # noqa: F401
-from .stitch import (Batch, Grad, Lorb, LorbSet, Matcher, Pipe, Plan, Prosac, StitchError, StitchPairLoss, blend, corners_to_h,  # noqa: F401
-                     detection_areas, lib,
+from .stitch import (Batch, Grad, Lorb, LorbSet, Matcher, MatcherSet, Pipe, Plan, Prosac, ProsacSet,  # noqa: F401
+                     StitchError, StitchPairLoss, blend, corners_to_h, detection_areas, lib,
                      map_grad_to_corners, pyramid, refine_pair, warp, warp_coords)

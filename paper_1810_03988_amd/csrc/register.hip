@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <mutex>
+#include <vector>
 
 #include <algorithm>
 #include <climits>
@@ -36,6 +37,7 @@ constexpr int kMaxTables = 16, kMaxKeyBits = 24;
 constexpr int kMaxPoints = 1 << 16;
 constexpr int kMaxHyp = 1 << 16;
 constexpr int kSample = 4;
+constexpr int kMaxPairs = 256;
 
 struct LshParams {
   int32_t tables, kbits, words, pad;          // words: 32-bit words per bit string (nd / 32)
@@ -53,10 +55,10 @@ __device__ __forceinline__ uint32_t key_of(const uint32_t* gt, const LshParams& 
 
 // keys[l][i] of the first count rows of desc (rows of 2 * words uint32); each thread copies
 // its row's "greater" words to LDS first, so the bit reads are LDS reads
-__global__ void __launch_bounds__(256) k_lsh_keys(const uint32_t* __restrict__ desc, const int32_t* __restrict__ count,
-                                                  int cap, const LshParams P, uint32_t* __restrict__ keys) {
+__device__ __forceinline__ void lsh_keys_body(const uint32_t* __restrict__ desc, const int32_t* __restrict__ count,
+                                              int cap, const LshParams& P, uint32_t* __restrict__ keys, int bx) {
   __shared__ uint32_t sRow[256][17];
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int i = bx * 256 + threadIdx.x;
   const int n = min(*count, cap);
   if (i >= n) return;                               // no block barrier below
   const uint32_t* gt = desc + (int64_t)i * 2 * P.words;
@@ -65,16 +67,21 @@ __global__ void __launch_bounds__(256) k_lsh_keys(const uint32_t* __restrict__ d
   for (int l = 0; l < P.tables; ++l) keys[(int64_t)l * cap + i] = key_of(row, P, l);
 }
 
+__global__ void __launch_bounds__(256) k_lsh_keys(const uint32_t* __restrict__ desc, const int32_t* __restrict__ count,
+                                                  int cap, const LshParams P, uint32_t* __restrict__ keys) {
+  lsh_keys_body(desc, count, cap, P, keys, blockIdx.x);
+}
+
 // one wave per query: lanes stride over the reference points, then a (distance, index) min
-__global__ void __launch_bounds__(256) k_lsh_match(const uint32_t* __restrict__ desc_a,
-                                                   const int32_t* __restrict__ count_a, int cap_a,
-                                                   const uint32_t* __restrict__ desc_b,
-                                                   const int32_t* __restrict__ count_b, int cap_b, const LshParams P,
-                                                   const uint32_t* __restrict__ keys_a,
-                                                   const uint32_t* __restrict__ keys_b, int max_dist,
-                                                   int32_t* __restrict__ match, int32_t* __restrict__ dist) {
+__device__ __forceinline__ void lsh_match_body(const uint32_t* __restrict__ desc_a,
+                                               const int32_t* __restrict__ count_a, int cap_a,
+                                               const uint32_t* __restrict__ desc_b,
+                                               const int32_t* __restrict__ count_b, int cap_b, const LshParams& P,
+                                               const uint32_t* __restrict__ keys_a,
+                                               const uint32_t* __restrict__ keys_b, int max_dist,
+                                               int32_t* __restrict__ match, int32_t* __restrict__ dist, int bx) {
   const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int i = bx * 4 + (threadIdx.x >> 6);
   if (i >= cap_a) return;                           // whole waves leave; no block barrier below
   const int na = min(*count_a, cap_a), nb = min(*count_b, cap_b);
   if (i >= na) {
@@ -114,6 +121,46 @@ __global__ void __launch_bounds__(256) k_lsh_match(const uint32_t* __restrict__ 
   }
 }
 
+__global__ void __launch_bounds__(256) k_lsh_match(const uint32_t* __restrict__ desc_a,
+                                                   const int32_t* __restrict__ count_a, int cap_a,
+                                                   const uint32_t* __restrict__ desc_b,
+                                                   const int32_t* __restrict__ count_b, int cap_b, const LshParams P,
+                                                   const uint32_t* __restrict__ keys_a,
+                                                   const uint32_t* __restrict__ keys_b, int max_dist,
+                                                   int32_t* __restrict__ match, int32_t* __restrict__ dist) {
+  lsh_match_body(desc_a, count_a, cap_a, desc_b, count_b, cap_b, P, keys_a, keys_b, max_dist, match, dist, blockIdx.x);
+}
+
+// Several pairs per launch: blockIdx.y selects the pair (keys: pair y / 2, side y % 2), its
+// descriptor read from a device table; blocks past a pair's own extent leave at once.
+struct LshPairDev {
+  const uint32_t* desc_a;
+  const int32_t* count_a;
+  const uint32_t* desc_b;
+  const int32_t* count_b;
+  uint32_t* keys_a;
+  uint32_t* keys_b;
+  int32_t* match;
+  int32_t* dist;
+  int32_t cap_a, cap_b;
+};
+
+__global__ void __launch_bounds__(256) k_lsh_keys_multi(const LshPairDev* __restrict__ pairs, const LshParams P) {
+  const LshPairDev& q = pairs[blockIdx.y >> 1];
+  const bool b = blockIdx.y & 1;
+  const int cap = b ? q.cap_b : q.cap_a;
+  if ((int)blockIdx.x * 256 >= cap) return;
+  lsh_keys_body(b ? q.desc_b : q.desc_a, b ? q.count_b : q.count_a, cap, P, b ? q.keys_b : q.keys_a, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_lsh_match_multi(const LshPairDev* __restrict__ pairs, const LshParams P,
+                                                         int max_dist) {
+  const LshPairDev& q = pairs[blockIdx.y];
+  if ((int)blockIdx.x * 4 >= q.cap_a) return;
+  lsh_match_body(q.desc_a, q.count_a, q.cap_a, q.desc_b, q.count_b, q.cap_b, P, q.keys_a, q.keys_b, max_dist, q.match,
+                 q.dist, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------- PROSAC
 struct ProsacWs {            // offsets into the workspace
   size_t misc, qa, qb, qi, tp, hyp_h, hyp_ok;
@@ -121,14 +168,14 @@ struct ProsacWs {            // offsets into the workspace
 
 // misc: [0] M = number of matches
 // one block of 1024 threads: matches in quality order, and T'_n for n = 4 .. M
-__global__ void __launch_bounds__(1024) k_prosac_prepare(const int32_t* __restrict__ pts_a,
-                                                         const int32_t* __restrict__ pts_b, int cap_b,
-                                                         const int32_t* __restrict__ match,
-                                                         const int32_t* __restrict__ dist,
-                                                         const int32_t* __restrict__ count_a, int cap_a, double T_N,
-                                                         int32_t* __restrict__ misc, int2* __restrict__ qa,
-                                                         int2* __restrict__ qb, int32_t* __restrict__ qi,
-                                                         int64_t* __restrict__ tp) {
+__device__ __forceinline__ void prosac_prepare_body(const int32_t* __restrict__ pts_a,
+                                                    const int32_t* __restrict__ pts_b, int cap_b,
+                                                    const int32_t* __restrict__ match,
+                                                    const int32_t* __restrict__ dist,
+                                                    const int32_t* __restrict__ count_a, int cap_a, double T_N,
+                                                    int32_t* __restrict__ misc, int2* __restrict__ qa,
+                                                    int2* __restrict__ qb, int32_t* __restrict__ qi,
+                                                    int64_t* __restrict__ tp) {
   constexpr int kStage = 16384;                      // ranking keys staged in LDS up to here
   __shared__ int sM;
   __shared__ __attribute__((aligned(16))) int32_t sKey[kStage];
@@ -187,6 +234,17 @@ __global__ void __launch_bounds__(1024) k_prosac_prepare(const int32_t* __restri
     qb[r] = make_int2(pts_b[2 * mi], pts_b[2 * mi + 1]);
     qi[r] = i;
   }
+}
+
+__global__ void __launch_bounds__(1024) k_prosac_prepare(const int32_t* __restrict__ pts_a,
+                                                         const int32_t* __restrict__ pts_b, int cap_b,
+                                                         const int32_t* __restrict__ match,
+                                                         const int32_t* __restrict__ dist,
+                                                         const int32_t* __restrict__ count_a, int cap_a, double T_N,
+                                                         int32_t* __restrict__ misc, int2* __restrict__ qa,
+                                                         int2* __restrict__ qb, int32_t* __restrict__ qi,
+                                                         int64_t* __restrict__ tp) {
+  prosac_prepare_body(pts_a, pts_b, cap_b, match, dist, count_a, cap_a, T_N, misc, qa, qb, qi, tp);
 }
 
 __device__ __forceinline__ bool collinear(int2 p, int2 q, int2 r) {
@@ -286,16 +344,16 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // one wave per hypothesis t: its sample, its model and its inlier count
-__global__ void __launch_bounds__(256) k_prosac_hyp(const int32_t* __restrict__ misc, const int2* __restrict__ qa,
-                                                    const int2* __restrict__ qb, const int64_t* __restrict__ tp,
-                                                    int nhyp, const double* __restrict__ uniforms, double eps2,
-                                                    double* __restrict__ hyp_h, int32_t* __restrict__ hyp_ok,
-                                                    int32_t* __restrict__ hyp_counts) {
+__device__ __forceinline__ void prosac_hyp_body(const int32_t* __restrict__ misc, const int2* __restrict__ qa,
+                                                const int2* __restrict__ qb, const int64_t* __restrict__ tp,
+                                                int nhyp, const double* __restrict__ uniforms, double eps2,
+                                                double* __restrict__ hyp_h, int32_t* __restrict__ hyp_ok,
+                                                int32_t* __restrict__ hyp_counts, int bx) {
   __shared__ double sH[4][9];
   __shared__ int sOk[4];
   __shared__ int2 sPts[4][8];                         // the sample: 4 points of A, then of B
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int t = blockIdx.x * 4 + wv;                  // hypothesis t + 1 of the schedule
+  const int t = bx * 4 + wv;                          // hypothesis t + 1 of the schedule
   if (t >= nhyp) return;                              // whole waves; no block barrier below
   const int M = misc[0];
   if (M < kSample) {
@@ -364,6 +422,14 @@ __global__ void __launch_bounds__(256) k_prosac_hyp(const int32_t* __restrict__ 
   if (lane < 9) hyp_h[(int64_t)t * 9 + lane] = H[lane];
 }
 
+__global__ void __launch_bounds__(256) k_prosac_hyp(const int32_t* __restrict__ misc, const int2* __restrict__ qa,
+                                                    const int2* __restrict__ qb, const int64_t* __restrict__ tp,
+                                                    int nhyp, const double* __restrict__ uniforms, double eps2,
+                                                    double* __restrict__ hyp_h, int32_t* __restrict__ hyp_ok,
+                                                    int32_t* __restrict__ hyp_counts) {
+  prosac_hyp_body(misc, qa, qb, tp, nhyp, uniforms, eps2, hyp_h, hyp_ok, hyp_counts, blockIdx.x);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
@@ -403,14 +469,14 @@ constexpr int kFinalThreads = 512, kFinalWaves = kFinalThreads / 64;
 constexpr int kParts = 7;                             // 72 x 7 = 504 of the 512 threads
 
 // one block of kFinalThreads: the best hypothesis, its inliers, the least-squares refit
-__global__ void __launch_bounds__(kFinalThreads) k_prosac_final(const int32_t* __restrict__ misc,
-                                                       const int2* __restrict__ qa, const int2* __restrict__ qb,
-                                                       const int32_t* __restrict__ qi, int cap_a, int nhyp,
-                                                       const double* __restrict__ hyp_h,
-                                                       const int32_t* __restrict__ hyp_ok,
-                                                       const int32_t* __restrict__ hyp_counts, double eps2,
-                                                       double* __restrict__ H_out, int32_t* __restrict__ inliers,
-                                                       uint8_t* __restrict__ mask) {
+__device__ __forceinline__ void prosac_final_body(const int32_t* __restrict__ misc,
+                                                  const int2* __restrict__ qa, const int2* __restrict__ qb,
+                                                  const int32_t* __restrict__ qi, int cap_a, int nhyp,
+                                                  const double* __restrict__ hyp_h,
+                                                  const int32_t* __restrict__ hyp_ok,
+                                                  const int32_t* __restrict__ hyp_counts, double eps2,
+                                                  double* __restrict__ H_out, int32_t* __restrict__ inliers,
+                                                  uint8_t* __restrict__ mask) {
   __shared__ unsigned long long sBest;
   __shared__ double sRed[kFinalWaves * 5];
   __shared__ double sPart[kParts][72];
@@ -527,6 +593,59 @@ __global__ void __launch_bounds__(kFinalThreads) k_prosac_final(const int32_t* _
   }
 }
 
+__global__ void __launch_bounds__(kFinalThreads) k_prosac_final(const int32_t* __restrict__ misc,
+                                                       const int2* __restrict__ qa, const int2* __restrict__ qb,
+                                                       const int32_t* __restrict__ qi, int cap_a, int nhyp,
+                                                       const double* __restrict__ hyp_h,
+                                                       const int32_t* __restrict__ hyp_ok,
+                                                       const int32_t* __restrict__ hyp_counts, double eps2,
+                                                       double* __restrict__ H_out, int32_t* __restrict__ inliers,
+                                                       uint8_t* __restrict__ mask) {
+  prosac_final_body(misc, qa, qb, qi, cap_a, nhyp, hyp_h, hyp_ok, hyp_counts, eps2, H_out, inliers, mask);
+}
+
+// Several pairs per launch of each PROSAC stage: blockIdx.y selects the pair and its
+// descriptor (inputs, outputs and workspace region) from a device table.
+struct ProsacPairDev {
+  const int32_t* pts_a;
+  const int32_t* pts_b;
+  const int32_t* match;
+  const int32_t* dist;
+  const int32_t* count_a;
+  const double* uniforms;
+  int32_t* misc;
+  int2* qa;
+  int2* qb;
+  int32_t* qi;
+  int64_t* tp;
+  double* hyp_h;
+  int32_t* hyp_ok;
+  int32_t* hyp_counts;
+  double* H;
+  int32_t* inliers;
+  uint8_t* mask;
+  int32_t cap_a, cap_b;
+};
+
+__global__ void __launch_bounds__(1024) k_prosac_prepare_multi(const ProsacPairDev* __restrict__ pairs, double T_N) {
+  const ProsacPairDev& q = pairs[blockIdx.y];
+  prosac_prepare_body(q.pts_a, q.pts_b, q.cap_b, q.match, q.dist, q.count_a, q.cap_a, T_N, q.misc, q.qa, q.qb, q.qi,
+                      q.tp);
+}
+
+__global__ void __launch_bounds__(256) k_prosac_hyp_multi(const ProsacPairDev* __restrict__ pairs, int nhyp,
+                                                          double eps2) {
+  const ProsacPairDev& q = pairs[blockIdx.y];
+  prosac_hyp_body(q.misc, q.qa, q.qb, q.tp, nhyp, q.uniforms, eps2, q.hyp_h, q.hyp_ok, q.hyp_counts, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kFinalThreads) k_prosac_final_multi(const ProsacPairDev* __restrict__ pairs,
+                                                                      int nhyp, double eps2) {
+  const ProsacPairDev& q = pairs[blockIdx.y];
+  prosac_final_body(q.misc, q.qa, q.qb, q.qi, q.cap_a, nhyp, q.hyp_h, q.hyp_ok, q.hyp_counts, eps2, q.H, q.inliers,
+                    q.mask);
+}
+
 size_t up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 ProsacWs prosac_layout(int cap_a, int nhyp, size_t* total) {
@@ -587,6 +706,73 @@ stitch_status stitch_lsh_match(int32_t nd, const uint32_t* desc_a, const int32_t
   hipLaunchKernelGGL(k_lsh_match, dim3((cap_a + 3) / 4), dim3(256), 0, s, desc_a, count_a, cap_a, desc_b, count_b,
                      cap_b, P, keys_a, keys_b, max_dist, match, dist);
   const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "matching launch");
+  return STITCH_OK;
+}
+
+size_t stitch_lsh_match_multi_workspace_bytes(int32_t npairs, const stitch_match_pair* pairs, int32_t tables) {
+  if (npairs < 1 || npairs > kMaxPairs || !pairs) return 0;
+  size_t total = up((size_t)npairs * sizeof(LshPairDev));
+  for (int p = 0; p < npairs; ++p) {
+    const size_t one = stitch_lsh_match_workspace_bytes(pairs[p].cap_a, pairs[p].cap_b, tables);
+    if (!one) return 0;
+    total += one;
+  }
+  return total;
+}
+
+stitch_status stitch_lsh_match_multi(int32_t npairs, const stitch_match_pair* pairs, int32_t nd, int32_t tables,
+                                     int32_t kbits, const int32_t* positions, int32_t max_dist, void* workspace,
+                                     size_t workspace_bytes, void* stream) {
+  if (!pairs || (kbits > 0 && !positions)) return fail(STITCH_E_NULL, "pairs or the positions is NULL");
+  if (npairs < 1 || npairs > kMaxPairs) return fail(STITCH_E_SHAPE, "npairs = %d outside 1..%d", npairs, kMaxPairs);
+  if (nd < 32 || nd > 512 || nd % 32) return fail(STITCH_E_SHAPE, "nd = %d is not a multiple of 32 in 32..512", nd);
+  if (tables < 1 || tables > kMaxTables || kbits < 0 || kbits > kMaxKeyBits)
+    return fail(STITCH_E_SHAPE, "tables in 1..%d and key bits in 0..%d", kMaxTables, kMaxKeyBits);
+  LshParams P{};
+  P.tables = tables;
+  P.kbits = kbits;
+  P.words = nd / 32;
+  for (int l = 0; l < tables; ++l)
+    for (int b = 0; b < kbits; ++b) {
+      const int q = positions[l * kbits + b];
+      if (q < 0 || q >= nd) return fail(STITCH_E_SHAPE, "bit position %d outside 0..%d", q, nd - 1);
+      P.pos[l][b] = (int16_t)q;
+    }
+  for (int p = 0; p < npairs; ++p) {
+    const stitch_match_pair& m = pairs[p];
+    if (!m.desc_a || !m.count_a || !m.desc_b || !m.count_b || !m.match || !m.dist)
+      return fail(STITCH_E_NULL, "pair %d: a descriptor, count or output is NULL", p);
+    if (m.cap_a < 1 || m.cap_b < 1 || m.cap_a > kMaxPoints || m.cap_b > kMaxPoints)
+      return fail(STITCH_E_SHAPE, "pair %d: capacities must lie in 1..%d", p, kMaxPoints);
+    if ((uintptr_t)m.desc_a & 7 || (uintptr_t)m.desc_b & 7)
+      return fail(STITCH_E_SHAPE, "pair %d: descriptors must be 8-byte aligned", p);
+  }
+  const size_t need = stitch_lsh_match_multi_workspace_bytes(npairs, pairs, tables);
+  if (!workspace || workspace_bytes < need || ((uintptr_t)workspace & 255))
+    return fail(STITCH_E_WORKSPACE, "workspace missing, misaligned or smaller than %zu bytes", need);
+  int cap_max = 1, capa_max = 1;
+  std::vector<LshPairDev> tab((size_t)npairs);
+  uint8_t* ws = (uint8_t*)workspace;
+  size_t o = up((size_t)npairs * sizeof(LshPairDev));
+  for (int p = 0; p < npairs; ++p) {
+    const stitch_match_pair& m = pairs[p];
+    LshPairDev& d = tab[p];
+    d.desc_a = m.desc_a; d.count_a = m.count_a; d.cap_a = m.cap_a;
+    d.desc_b = m.desc_b; d.count_b = m.count_b; d.cap_b = m.cap_b;
+    d.match = m.match; d.dist = m.dist;
+    d.keys_a = (uint32_t*)(ws + o); o += up((size_t)tables * m.cap_a * 4);
+    d.keys_b = (uint32_t*)(ws + o); o += up((size_t)tables * m.cap_b * 4);
+    cap_max = std::max(cap_max, std::max(m.cap_a, m.cap_b));
+    capa_max = std::max(capa_max, m.cap_a);
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(workspace, tab.data(), tab.size() * sizeof(LshPairDev), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "matching table upload");
+  const LshPairDev* dev = (const LshPairDev*)workspace;
+  hipLaunchKernelGGL(k_lsh_keys_multi, dim3((cap_max + 255) / 256, 2 * npairs), dim3(256), 0, s, dev, P);
+  hipLaunchKernelGGL(k_lsh_match_multi, dim3((capa_max + 3) / 4, npairs), dim3(256), 0, s, dev, P, max_dist);
+  e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "matching launch");
   return STITCH_OK;
 }
@@ -710,3 +896,79 @@ stitch_status prosac_run(const int32_t* pts_a, const int32_t* pts_b, int32_t cap
 }
 
 }  // namespace
+
+namespace {
+
+size_t prosac_multi_bytes(int32_t npairs, const stitch_prosac_pair* pairs, int32_t nhyp) {
+  if (npairs < 1 || npairs > kMaxPairs || !pairs || nhyp < 1 || nhyp > kMaxHyp) return 0;
+  size_t total = up((size_t)npairs * sizeof(ProsacPairDev));
+  for (int p = 0; p < npairs; ++p) {
+    if (pairs[p].cap_a < 1 || pairs[p].cap_a > kMaxPoints) return 0;
+    size_t one = 0;
+    prosac_layout(pairs[p].cap_a, nhyp, &one);
+    total += one;
+  }
+  return total;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t stitch_prosac_multi_workspace_bytes(int32_t npairs, const stitch_prosac_pair* pairs, int32_t nhyp) {
+  return prosac_multi_bytes(npairs, pairs, nhyp);
+}
+
+stitch_status stitch_prosac_multi(int32_t npairs, const stitch_prosac_pair* pairs, int32_t nhyp, double T_N,
+                                  double eps, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!pairs) return fail(STITCH_E_NULL, "pairs is NULL");
+  if (npairs < 1 || npairs > kMaxPairs) return fail(STITCH_E_SHAPE, "npairs = %d outside 1..%d", npairs, kMaxPairs);
+  if (nhyp < 1 || nhyp > kMaxHyp) return fail(STITCH_E_SHAPE, "nhyp = %d outside 1..%d", nhyp, kMaxHyp);
+  if (!(T_N > 0.0) || !std::isfinite(T_N) || !(eps > 0.0) || !std::isfinite(eps))
+    return fail(STITCH_E_SHAPE, "T_N and eps must be positive and finite");
+  if (T_N > 0x1p53) return fail(STITCH_E_SHAPE, "T_N = %g exceeds 2^53", T_N);
+  for (int p = 0; p < npairs; ++p) {
+    const stitch_prosac_pair& m = pairs[p];
+    if (!m.pts_a || !m.pts_b || !m.match || !m.dist || !m.count_a || !m.uniforms || !m.H || !m.inliers ||
+        !m.inlier_mask || !m.hyp_counts)
+      return fail(STITCH_E_NULL, "pair %d: an input or output is NULL", p);
+    if (m.cap_a < 1 || m.cap_a > kMaxPoints || m.cap_b < 1 || m.cap_b > kMaxPoints)
+      return fail(STITCH_E_SHAPE, "pair %d: capacities must lie in 1..%d", p, kMaxPoints);
+  }
+  const size_t need = prosac_multi_bytes(npairs, pairs, nhyp);
+  if (!workspace || workspace_bytes < need || ((uintptr_t)workspace & 255))
+    return fail(STITCH_E_WORKSPACE, "workspace missing, misaligned or smaller than %zu bytes", need);
+  std::vector<ProsacPairDev> tab((size_t)npairs);
+  uint8_t* ws = (uint8_t*)workspace;
+  size_t o = up((size_t)npairs * sizeof(ProsacPairDev));
+  for (int p = 0; p < npairs; ++p) {
+    const stitch_prosac_pair& m = pairs[p];
+    size_t one = 0;
+    const ProsacWs L = prosac_layout(m.cap_a, nhyp, &one);
+    ProsacPairDev& d = tab[p];
+    d.pts_a = m.pts_a; d.pts_b = m.pts_b; d.match = m.match; d.dist = m.dist; d.count_a = m.count_a;
+    d.uniforms = m.uniforms; d.cap_a = m.cap_a; d.cap_b = m.cap_b;
+    d.misc = (int32_t*)(ws + o + L.misc);
+    d.qa = (int2*)(ws + o + L.qa);
+    d.qb = (int2*)(ws + o + L.qb);
+    d.qi = (int32_t*)(ws + o + L.qi);
+    d.tp = (int64_t*)(ws + o + L.tp);
+    d.hyp_h = (double*)(ws + o + L.hyp_h);
+    d.hyp_ok = (int32_t*)(ws + o + L.hyp_ok);
+    d.hyp_counts = m.hyp_counts; d.H = m.H; d.inliers = m.inliers; d.mask = m.inlier_mask;
+    o += one;
+  }
+  const double eps2 = eps * eps;
+  const hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(workspace, tab.data(), tab.size() * sizeof(ProsacPairDev), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "PROSAC table upload");
+  const ProsacPairDev* dev = (const ProsacPairDev*)workspace;
+  hipLaunchKernelGGL(k_prosac_prepare_multi, dim3(1, npairs), dim3(1024), 0, s, dev, T_N);
+  hipLaunchKernelGGL(k_prosac_hyp_multi, dim3((nhyp + 3) / 4, npairs), dim3(256), 0, s, dev, nhyp, eps2);
+  hipLaunchKernelGGL(k_prosac_final_multi, dim3(1, npairs), dim3(kFinalThreads), 0, s, dev, nhyp, eps2);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "PROSAC launch");
+  return STITCH_OK;
+}
+
+}  // extern "C"

@@ -38,6 +38,19 @@ class StitchLevels(ctypes.Structure):
                 ("level", StitchImage * MAX_LEVELS)]
 
 
+class MatchPair(ctypes.Structure):
+    """One area pair of stitch_lsh_match_multi (stitch_match_pair): device pointers."""
+    _fields_ = [("desc_a", c_void_p), ("count_a", c_void_p), ("cap_a", c_int32), ("desc_b", c_void_p),
+                ("count_b", c_void_p), ("cap_b", c_int32), ("match", c_void_p), ("dist", c_void_p)]
+
+
+class ProsacPair(ctypes.Structure):
+    """One area pair of stitch_prosac_multi (stitch_prosac_pair): device pointers."""
+    _fields_ = [("pts_a", c_void_p), ("pts_b", c_void_p), ("cap_b", c_int32), ("match", c_void_p),
+                ("dist", c_void_p), ("count_a", c_void_p), ("cap_a", c_int32), ("uniforms", c_void_p),
+                ("H", c_void_p), ("inliers", c_void_p), ("inlier_mask", c_void_p), ("hyp_counts", c_void_p)]
+
+
 class StitchError(RuntimeError):
     def __init__(self, status: int, message: str):
         self.status = status
@@ -136,6 +149,12 @@ SIGNATURES = {
     "stitch_prosac_noalloc": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                         c_void_p, c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p,
                                         c_void_p]),
+    "stitch_lsh_match_multi_workspace_bytes": (c_size_t, [c_int32, POINTER(MatchPair), c_int32]),
+    "stitch_lsh_match_multi": (c_int32, [c_int32, POINTER(MatchPair), c_int32, c_int32, c_int32, POINTER(c_int32),
+                                         c_int32, c_void_p, c_size_t, c_void_p]),
+    "stitch_prosac_multi_workspace_bytes": (c_size_t, [c_int32, POINTER(ProsacPair), c_int32]),
+    "stitch_prosac_multi": (c_int32, [c_int32, POINTER(ProsacPair), c_int32, c_double, c_double, c_void_p,
+                                      c_size_t, c_void_p]),
 }
 
 TIMING_KINDS = ["warp_level0_pass", "level_pass", "blend_level0", "blend_middle", "blend_top",
@@ -987,3 +1006,76 @@ class Prosac:
         torch.cuda.synchronize()
         return {"H": self.H.cpu().numpy().reshape(3, 3), "inliers": int(self.inliers[0]),
                 "mask": self.mask.cpu().numpy().astype(bool), "hyp_counts": self.hyp_counts.cpu().numpy()}
+
+
+class MatcherSet:
+    """Matching (Sec. 4.2.1; Alg. 3, step 1) of several area pairs with one launch per stage
+    (stitch_lsh_match_multi): caps is [(cap_a, cap_b)] per pair, the settings are shared.
+    Pair p's outputs match[p], dist[p] (cap_a entries) equal a Matcher's for that pair."""
+
+    def __init__(self, caps, nd: int, positions, max_dist: int, device="cuda"):
+        pos = np.ascontiguousarray(np.asarray(positions, dtype=np.int32).reshape(len(positions), -1))
+        self.tables, self.kbits = pos.shape
+        self.positions = (c_int32 * max(pos.size, 1))(*pos.reshape(-1).tolist())
+        self.caps = [(int(a), int(b)) for a, b in caps]
+        self.n, self.nd, self.max_dist = len(self.caps), int(nd), int(max_dist)
+        self.pairs = (MatchPair * max(self.n, 1))()
+        for p, (a, b) in enumerate(self.caps):
+            self.pairs[p].cap_a, self.pairs[p].cap_b = a, b
+        nbytes = lib().stitch_lsh_match_multi_workspace_bytes(self.n, self.pairs, self.tables)
+        if nbytes == 0:
+            raise StitchError(2, "no workspace size for these pairs and tables")
+        self._buf, self._ws = _aligned_workspace(nbytes, device)
+        self.match = [torch.full((a,), -1, dtype=torch.int32, device=device) for a, _ in self.caps]
+        self.dist = [torch.full((a,), -1, dtype=torch.int32, device=device) for a, _ in self.caps]
+
+    def run_raw(self, inputs, stream_handle: int) -> None:
+        """inputs: per pair (desc_a, count_a, desc_b, count_b) device tensors."""
+        if len(inputs) != self.n:
+            raise ValueError(f"{len(inputs)} input pairs for a set of {self.n}")
+        for p, (da, ca, db, cb) in enumerate(inputs):
+            for t, name in ((da, "desc_a"), (ca, "count_a"), (db, "desc_b"), (cb, "count_b")):
+                _on_gpu(t, f"pair {p} {name}")
+            e = self.pairs[p]
+            e.desc_a, e.count_a, e.desc_b, e.count_b = da.data_ptr(), ca.data_ptr(), db.data_ptr(), cb.data_ptr()
+            e.match, e.dist = self.match[p].data_ptr(), self.dist[p].data_ptr()
+        check(lib().stitch_lsh_match_multi(self.n, self.pairs, self.nd, self.tables, self.kbits, self.positions,
+                                           self.max_dist, self._ws.data_ptr(), self._ws.numel(), stream_handle))
+
+
+class ProsacSet:
+    """PROSAC (Sec. 4.2.2; Alg. 3, step 2) of several area pairs with one launch per stage
+    (stitch_prosac_multi), nhyp hypotheses each; caps is [(cap_a, cap_b)] per pair.  Pair
+    p's H[p] (9 float64), inliers[p], mask[p] (cap_a) and hyp_counts[p] equal a Prosac's."""
+
+    def __init__(self, caps, nhyp: int, T_N: float = 200000.0, eps: float = 3.0, device="cuda"):
+        self.caps = [(int(a), int(b)) for a, b in caps]
+        self.n, self.nhyp = len(self.caps), int(nhyp)
+        self.T_N, self.eps = float(T_N), float(eps)
+        self.pairs = (ProsacPair * max(self.n, 1))()
+        for p, (a, b) in enumerate(self.caps):
+            self.pairs[p].cap_a, self.pairs[p].cap_b = a, b
+        nbytes = lib().stitch_prosac_multi_workspace_bytes(self.n, self.pairs, self.nhyp)
+        if nbytes == 0:
+            raise StitchError(2, "no workspace size for these pairs and hypotheses")
+        self._buf, self._ws = _aligned_workspace(nbytes, device)
+        self.H = torch.zeros(max(self.n, 1), 9, dtype=torch.float64, device=device)
+        self.inliers = torch.zeros(max(self.n, 1), dtype=torch.int32, device=device)
+        self.mask = [torch.zeros(a, dtype=torch.uint8, device=device) for a, _ in self.caps]
+        self.hyp_counts = torch.zeros(max(self.n, 1), self.nhyp, dtype=torch.int32, device=device)
+
+    def run_raw(self, inputs, stream_handle: int) -> None:
+        """inputs: per pair (pts_a, pts_b, match, dist, count_a, uniforms) device tensors."""
+        if len(inputs) != self.n:
+            raise ValueError(f"{len(inputs)} input pairs for a set of {self.n}")
+        for p, (pa, pb, m, d, ca, u) in enumerate(inputs):
+            for t, name in ((pa, "pts_a"), (pb, "pts_b"), (m, "match"), (d, "dist"), (ca, "count_a"),
+                            (u, "uniforms")):
+                _on_gpu(t, f"pair {p} {name}")
+            e = self.pairs[p]
+            e.pts_a, e.pts_b, e.match, e.dist = pa.data_ptr(), pb.data_ptr(), m.data_ptr(), d.data_ptr()
+            e.count_a, e.uniforms = ca.data_ptr(), u.data_ptr()
+            e.H, e.inliers = self.H[p].data_ptr(), self.inliers[p:p + 1].data_ptr()
+            e.inlier_mask, e.hyp_counts = self.mask[p].data_ptr(), self.hyp_counts[p].data_ptr()
+        check(lib().stitch_prosac_multi(self.n, self.pairs, self.nhyp, self.T_N, self.eps, self._ws.data_ptr(),
+                                        self._ws.numel(), stream_handle))

@@ -301,6 +301,74 @@ def test_registration_calls_validate_on_host():
     assert prosac(nbytes=need - 1) == E["E_WORKSPACE"] and prosac(ws=fake + 8) == E["E_WORKSPACE"]
 
 
+def test_multi_pair_registration_calls_validate_on_host():
+    """stitch_lsh_match_multi / stitch_prosac_multi: workspace = a table head plus each
+    pair's single-pair workspace (which also pins the pair structs' field offsets), and every
+    argument check, per pair, before anything reaches the device."""
+    lib = P.lib()
+    fake = 0x10000
+    pos = (ctypes.c_int32 * 24)(*range(24))
+    caps = [(10, 20), (500, 300), (7, 7)]
+
+    def mpairs(**over):
+        t = (S.MatchPair * 3)()
+        for p, (a, b) in enumerate(caps):
+            t[p] = S.MatchPair(fake, fake, a, fake, fake, b, fake, fake)
+        for k, v in over.items():
+            setattr(t[1], k, v)
+        return t
+
+    single = sum(lib.stitch_lsh_match_workspace_bytes(a, b, 2) for a, b in caps)
+    need = lib.stitch_lsh_match_multi_workspace_bytes(3, mpairs(), 2)
+    assert single < need <= single + 4096
+    assert lib.stitch_lsh_match_multi_workspace_bytes(0, mpairs(), 2) == 0
+    assert lib.stitch_lsh_match_multi_workspace_bytes(257, mpairs(), 2) == 0
+    assert lib.stitch_lsh_match_multi_workspace_bytes(3, mpairs(cap_b=0), 2) == 0
+
+    def match(t=None, n=3, nd=256, tables=2, kbits=12, p=pos, ws=fake, nbytes=need):
+        return lib.stitch_lsh_match_multi(n, mpairs() if t is None else t, nd, tables, kbits, p, 64, ws, nbytes,
+                                          None)
+
+    assert lib.stitch_lsh_match_multi(3, None, 256, 2, 12, pos, 64, fake, need, None) == E["E_NULL"]
+    assert match(p=None) == E["E_NULL"]
+    assert match(t=mpairs(desc_b=None)) == E["E_NULL"] and "pair 1" in S.last_error()
+    assert match(t=mpairs(dist=None)) == E["E_NULL"]
+    assert match(n=0) == E["E_SHAPE"] and match(n=257) == E["E_SHAPE"]
+    assert match(nd=48) == E["E_SHAPE"] and match(tables=17) == E["E_SHAPE"] and match(kbits=25) == E["E_SHAPE"]
+    assert match(t=mpairs(cap_a=0)) == E["E_SHAPE"] and match(t=mpairs(cap_b=65537)) == E["E_SHAPE"]
+    assert match(t=mpairs(desc_a=fake + 4)) == E["E_SHAPE"] and "pair 1" in S.last_error()
+    assert match(ws=None) == E["E_WORKSPACE"] and match(ws=fake + 16) == E["E_WORKSPACE"]
+    assert match(nbytes=need - 1) == E["E_WORKSPACE"]
+
+    def ppairs(**over):
+        t = (S.ProsacPair * 3)()
+        for p, (a, b) in enumerate(caps):
+            t[p] = S.ProsacPair(fake, fake, b, fake, fake, fake, a, fake, fake, fake, fake, fake)
+        for k, v in over.items():
+            setattr(t[2], k, v)
+        return t
+
+    single = sum(lib.stitch_prosac_workspace_bytes(a, 512) for a, _ in caps)
+    pneed = lib.stitch_prosac_multi_workspace_bytes(3, ppairs(), 512)
+    assert single < pneed <= single + 4096
+    assert lib.stitch_prosac_multi_workspace_bytes(3, ppairs(), 0) == 0
+    assert lib.stitch_prosac_multi_workspace_bytes(3, ppairs(cap_a=70000), 512) == 0
+
+    def prosac(t=None, n=3, nhyp=512, T_N=2e5, eps=3.0, ws=fake, nbytes=pneed):
+        return lib.stitch_prosac_multi(n, ppairs() if t is None else t, nhyp, T_N, eps, ws, nbytes, None)
+
+    assert lib.stitch_prosac_multi(3, None, 512, 2e5, 3.0, fake, pneed, None) == E["E_NULL"]
+    assert prosac(t=ppairs(uniforms=None)) == E["E_NULL"] and "pair 2" in S.last_error()
+    assert prosac(t=ppairs(hyp_counts=None)) == E["E_NULL"]
+    assert prosac(n=0) == E["E_SHAPE"] and prosac(n=257) == E["E_SHAPE"]
+    assert prosac(nhyp=0) == E["E_SHAPE"] and prosac(nhyp=65537) == E["E_SHAPE"]
+    assert prosac(T_N=0.0) == E["E_SHAPE"] and prosac(eps=float("inf")) == E["E_SHAPE"]
+    assert prosac(T_N=2.0 ** 53 * 1.5) == E["E_SHAPE"]
+    assert prosac(t=ppairs(cap_a=0)) == E["E_SHAPE"] and prosac(t=ppairs(cap_b=65537)) == E["E_SHAPE"]
+    assert prosac(ws=None) == E["E_WORKSPACE"] and prosac(ws=fake + 8) == E["E_WORKSPACE"]
+    assert prosac(nbytes=pneed - 1) == E["E_WORKSPACE"]
+
+
 def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(S, "LIB_PATH", tmp_path / "missing.so")
     monkeypatch.setattr(S, "_lib", None)
@@ -410,6 +478,16 @@ def test_binding_refuses_host_tensors_before_any_launch():
     mat = object.__new__(S.Matcher)
     with pytest.raises(ValueError):
         S.Matcher.run_raw(mat, i32, i32, i32, i32, 0)
+    mset = object.__new__(S.MatcherSet)
+    mset.n, mset.pairs = 1, (S.MatchPair * 1)()
+    with pytest.raises(ValueError):
+        S.MatcherSet.run_raw(mset, [(i32, i32, i32, i32)], 0)
+    with pytest.raises(ValueError):
+        S.MatcherSet.run_raw(mset, [], 0)
+    pset = object.__new__(S.ProsacSet)
+    pset.n, pset.pairs = 1, (S.ProsacPair * 1)()
+    with pytest.raises(ValueError):
+        S.ProsacSet.run_raw(pset, [(i32, i32, i32, i32, i32, torch.zeros((4, 4), dtype=torch.float64))], 0)
 
 
 def test_frame_backward_validates_on_host():
