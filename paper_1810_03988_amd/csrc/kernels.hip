@@ -1166,12 +1166,12 @@ __global__ void __launch_bounds__(kThreads) k_blend(const BlendItem* __restrict_
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int Y = Y0 + ybase + j;
-      uint32_t q[3];
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) q[ch] = (uint32_t)fminf(fmaxf(rintf(255.0f * acc[j][ch]), 0.0f), 255.0f);
+      // rint(255 R_0) clamped to [0, 255] by the byte conversion, packed byte by byte
+      uint32_t v = __builtin_amdgcn_cvt_pk_u8_f32(255.0f * acc[j][0], 0u, 0u);
+      v = __builtin_amdgcn_cvt_pk_u8_f32(255.0f * acc[j][1], 1u, v);
+      v = __builtin_amdgcn_cvt_pk_u8_f32(255.0f * acc[j][2], 2u, v);
       GLB uint8_t* prow = pano + (int64_t)Y * pano_row + (int64_t)X * 3;
       if (words) {
-        const uint32_t v = q[0] | (q[1] << 8) | (q[2] << 16);
         const uint32_t v1 = __shfl_down(v, 1), v2 = __shfl_down(v, 2), v3 = __shfl_down(v, 3);
         if ((x & 3) == 0 && Y < a.H) {
           typedef uint32_t vu3 __attribute__((ext_vector_type(3)));
@@ -1179,7 +1179,7 @@ __global__ void __launch_bounds__(kThreads) k_blend(const BlendItem* __restrict_
         }
       } else if (X < a.W && Y < a.H) {
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) prow[ch] = (uint8_t)q[ch];
+        for (int ch = 0; ch < 3; ++ch) prow[ch] = (uint8_t)(v >> (8 * ch));
       }
     }
   }

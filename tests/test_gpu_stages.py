@@ -144,3 +144,34 @@ def test_blend_single_level_is_alpha_blend():
                        [[torch.from_numpy(m).to(DEV)], [torch.from_numpy(255 - m).to(DEV)]], w, h)
     want = m / 255.0 * a + (1 - m / 255.0) * b
     assert_float_parity(rs[0].cpu().numpy(), want, 1e-6, "alpha")
+
+
+def test_quantisation_rounds_half_to_even_and_clamps():
+    """The panorama byte is rint(255 R_0) (ties to even) clamped to [0, 255], from FP32 R_0
+    exactly as the kernel forms it (Alg. 4 step 9; reading R11): one camera, one level, FP32
+    band samples and weights of exactly 1, so R_0 is the band itself.  The samples include
+    every float whose product with 255 is an exact half-integer near the integers 0 .. 255,
+    values below 0 and above 1, and random ones; the expectation is numpy's float32 product
+    and rint."""
+    rng = np.random.default_rng(11)
+    vals = []
+    for k in range(-3, 259):
+        for t in (k, k + 0.5):
+            c = np.float32(t) / np.float32(255)
+            for u in (np.nextafter(c, np.float32(-1)), c, np.nextafter(c, np.float32(2))):
+                vals.append(u)
+    vals = np.array(vals, dtype=np.float32)
+    prod = np.float32(255) * vals
+    ties = np.count_nonzero(prod - np.floor(prod) == np.float32(0.5))
+    assert ties > 100
+    h, w = 37, 257
+    band = rng.uniform(-0.3, 1.3, (3, h, w)).astype(np.float32)
+    flat = band.reshape(-1)
+    flat[:len(vals)] = vals
+    band = flat.reshape(3, h, w)
+    wts = np.ones((1, h, w), dtype=np.float32)
+    pano, rs = P.blend([[torch.from_numpy(band).to(DEV)]], [[torch.from_numpy(wts).to(DEV)]], w, h)
+    assert np.array_equal(rs[0].cpu().numpy(), band)
+    want = np.clip(np.rint(np.float32(255) * band), 0, 255).astype(np.uint8).transpose(1, 2, 0)
+    got = pano.cpu().numpy()
+    assert np.array_equal(got, want), np.argwhere(got != want)[:5]
