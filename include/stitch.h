@@ -381,7 +381,10 @@ stitch_status stitch_grad_forward(stitch_grad* grad, const stitch_image* frames,
 /* Gradient of the last forward's loss: d_frames[i] (F32 CHW, 3 channels, the frame's
  * size; overwritten) receives d loss / d frame i, d_map (host) receives d loss / d M_i
  * (row-major, 9 per camera), M_i being the FP32 canvas -> source map adj(H_i)/adj(H_i)[2][2]
- * the warp uses.  Synchronises the stream.  Errors: NULL, STATE, SHAPE, UNSUPPORTED,
+ * the warp uses.  The frame transpose gathers over the canvas pixels whose frozen cell holds
+ * each source pixel, so the result is repeatable bit for bit; UNSUPPORTED when a map the
+ * cells were frozen at magnifies a source pixel over about 20 times or reaches its horizon
+ * over the frame.  Synchronises the stream.  Errors: NULL, STATE, SHAPE, UNSUPPORTED,
  * DEVICE. */
 stitch_status stitch_grad_backward(stitch_grad* grad, stitch_image* d_frames, double d_map[18], void* stream);
 /* The last forward's gradients as the upstream terms of stitch_frame_backward: d_pano =

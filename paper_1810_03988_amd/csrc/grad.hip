@@ -290,12 +290,12 @@ __global__ void __launch_bounds__(kT) k_gcount(const uint8_t* __restrict__ omega
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// Adjoint of the warp for one camera: scatter dG into the source (FP64 atomics) and
-// reduce the 9 map-gradient sums per block.
+// Adjoint of the warp for one camera with respect to its map: the 9 map-gradient sums per
+// block (deterministic).  The frame's adjoint is the gather k_gsrcT.
 __global__ void __launch_bounds__(kT) k_gwarpT(Map9 m, const float* __restrict__ src, int64_t srow, int64_t splane,
                                                int w, int h, const int* __restrict__ x0a, const int* __restrict__ y0a,
                                                int W, int H, const double* __restrict__ dG,
-                                               double* __restrict__ dsrc, double* __restrict__ part9) {
+                                               double* __restrict__ part9) {
   __shared__ double sh[kT / 64];
   const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
   const int64_t np = (int64_t)W * H;
@@ -309,7 +309,6 @@ __global__ void __launch_bounds__(kT) k_gwarpT(Map9 m, const float* __restrict__
     if (zpos) {
       const int x0 = x0a[p], y0 = y0a[p];
       const double fx = (double)x - x0, fy = (double)y - y0;
-      const double wts[4] = {(1 - fy) * (1 - fx), (1 - fy) * fx, fy * (1 - fx), fy * fx};
       double gx = 0.0, gy = 0.0;
       for (int c = 0; c < 3; ++c) {
         const double g = dG[c * np + p];
@@ -317,9 +316,7 @@ __global__ void __launch_bounds__(kT) k_gwarpT(Map9 m, const float* __restrict__
         for (int k = 0; k < 4; ++k) {
           const int xx = x0 + (k & 1), yy = y0 + (k >> 1);
           const bool ok = xx >= 0 && xx < w && yy >= 0 && yy < h;
-          const int64_t off = c * (int64_t)w * h + (int64_t)yy * w + xx;
           t[k] = ok ? (double)src[c * splane + (int64_t)yy * srow + xx] : 0.0;
-          if (ok && g != 0.0) atomicAdd(&dsrc[off], wts[k] * g);
         }
         gx += g * ((1 - fy) * (t[1] - t[0]) + fy * (t[3] - t[2]));
         gy += g * ((1 - fx) * (t[2] - t[0]) + fx * (t[3] - t[1]));
@@ -336,6 +333,62 @@ __global__ void __launch_bounds__(kT) k_gwarpT(Map9 m, const float* __restrict__
     const double t = block_sum(t9[k], sh);
     if (threadIdx.x == 0) part9[(int64_t)blockIdx.x * 9 + k] = t;
   }
+}
+
+// Adjoint of the warp with respect to one camera's frame, as a gather (deterministic, no
+// atomics): source pixel (x, y) collects w dG from every canvas pixel whose frozen cell holds
+// it as a tap, w the bilinear weight at the current map's coordinates (as the forward takes
+// it).  The cells were frozen at the map whose FP64 inverse is hf, so those canvas pixels lie
+// in the image under hf of the source square [x-1, x+1) x [y-1, y+1), one pixel wider for
+// the FP32 rounding of the coordinates.  A candidate box over 48 pixels a side (a map
+// magnifying about 20 times) or a square reaching the map's horizon sets *flag.
+struct Inv9 {
+  double h[9];
+};
+__global__ void __launch_bounds__(kT) k_gsrcT(Map9 m, Inv9 hf, int w, int h, const int* __restrict__ x0a,
+                                              const int* __restrict__ y0a, int W, int H,
+                                              const double* __restrict__ dG, double* __restrict__ dsrc,
+                                              int* __restrict__ flag) {
+  const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (p >= (int64_t)w * h) return;
+  const int x = (int)(p % w), y = (int)(p / w);
+  const int64_t np = (int64_t)W * H;
+  double bx0 = 1e300, bx1 = -1e300, by0 = 1e300, by1 = -1e300;
+  bool bounded = true;
+  for (int k = 0; k < 4; ++k) {
+    const double sx = (double)(x - 1 + 2 * (k & 1)), sy = (double)(y - 1 + (k & 2));
+    const double z = (hf.h[6] * sx + hf.h[7] * sy) + hf.h[8];
+    if (!(z > 0.0)) { bounded = false; break; }
+    const double X = ((hf.h[0] * sx + hf.h[1] * sy) + hf.h[2]) / z;
+    const double Y = ((hf.h[3] * sx + hf.h[4] * sy) + hf.h[5]) / z;
+    bx0 = fmin(bx0, X); bx1 = fmax(bx1, X); by0 = fmin(by0, Y); by1 = fmax(by1, Y);
+  }
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (bounded && bx1 >= -2.0 && by1 >= -2.0 && bx0 <= W + 1.0 && by0 <= H + 1.0) {
+    if (bx1 - bx0 > 46.0 || by1 - by0 > 46.0) {
+      atomicOr(flag, 1);
+    } else {
+      const int X0 = max(0, (int)floor(bx0) - 1), X1 = min(W - 1, (int)ceil(bx1) + 1);
+      const int Y0 = max(0, (int)floor(by0) - 1), Y1 = min(H - 1, (int)ceil(by1) + 1);
+      for (int Y = Y0; Y <= Y1; ++Y)
+        for (int X = X0; X <= X1; ++X) {
+          const int64_t q = (int64_t)Y * W + X;
+          const int a = x - x0a[q], b = y - y0a[q];
+          if (a < 0 || a > 1 || b < 0 || b > 1) continue;
+          float xc, yc;
+          bool zpos;
+          double z;
+          gcoords(m.h, X, Y, xc, yc, zpos, z);
+          if (!zpos) continue;
+          const double fx = (double)xc - (x - a), fy = (double)yc - (y - b);
+          const double wt = (a ? fx : 1 - fx) * (b ? fy : 1 - fy);
+          for (int ch = 0; ch < 3; ++ch) acc[ch] += wt * dG[ch * np + q];
+        }
+    }
+  } else if (!bounded) {
+    atomicOr(flag, 2);
+  }
+  for (int ch = 0; ch < 3; ++ch) dsrc[ch * (int64_t)w * h + p] = acc[ch];
 }
 
 __global__ void __launch_bounds__(kT) k_gtof32(const double* __restrict__ in, float* __restrict__ out, int w, int h,
@@ -540,9 +593,10 @@ struct stitch_grad {
   // offsets
   size_t o_mask, o_gm[2][kMaxLevels], o_x0, o_y0, o_om, o_g[2][kMaxLevels], o_lap[2][kMaxLevels], o_r[kMaxLevels];
   size_t o_gp, o_ga, o_gb, o_dr[kMaxLevels], o_dl[kMaxLevels], o_dg[kMaxLevels], o_tmp[kMaxLevels], o_dsrc[2];
-  size_t o_part, o_res;
+  size_t o_part, o_res, o_flag;
   int64_t nblk = 0;
   bool frozen = false;
+  Inv9 freeze_inv[2];   // FP64 inverses of the maps the cells were frozen at
   double omega_n = 0.0;
   Map9 maps[2];
   const float* fsrc[2] = {};
@@ -692,6 +746,7 @@ stitch_status stitch_grad_create(const int32_t frame_w[2], const int32_t frame_h
   g->nblk = blocks((int64_t)np);
   g->o_part = take(top, (size_t)g->nblk * 9 * 8);
   g->o_res = take(top, 32 * 8);
+  g->o_flag = take(top, 8);
   g->bytes = top;
   *out = g;
   g = nullptr;
@@ -730,6 +785,12 @@ stitch_status stitch_grad_freeze(stitch_grad* g, const double H[18], int64_t* om
   Map9 m[2];
   stitch_status st = maps_from(H, m);
   if (st) return st;
+  Inv9 inv[2];
+  for (int c = 0; c < 2; ++c) {
+    double M[9];
+    for (int j = 0; j < 9; ++j) M[j] = (double)m[c].h[j];
+    if (!inv3(M, inv[c].h)) return fail(STITCH_E_HOMOGRAPHY, "camera %d: its map is singular", c);
+  }
   const hipStream_t s = (hipStream_t)stream;
   const int64_t np = (int64_t)g->W * g->H;
   hipLaunchKernelGGL(k_gcells, dim3(blocks(np)), dim3(kT), 0, s, m[0], m[1], g->fw[0], g->fh[0], g->fw[1], g->fh[1],
@@ -743,6 +804,8 @@ stitch_status stitch_grad_freeze(stitch_grad* g, const double H[18], int64_t* om
   if (st) return st;
   if (n < 1.0) return fail(STITCH_E_SHAPE, "the frames do not overlap at these maps (|Omega| = 0)");
   g->omega_n = n;
+  g->freeze_inv[0] = inv[0];
+  g->freeze_inv[1] = inv[1];
   g->frozen = true;
   g->have_forward = false;
   if (omega_count) *omega_count = (int64_t)n;
@@ -859,17 +922,25 @@ stitch_status stitch_grad_backward(stitch_grad* g, stitch_image* d_frames, doubl
       dG0 = g->dptr(g->o_dg[0]);
     }
     const int64_t ns = 3 * (int64_t)g->fw[c] * g->fh[c];
-    hipLaunchKernelGGL(k_gzero, dim3(blocks(ns)), dim3(kT), 0, s, g->dptr(g->o_dsrc[c]), ns);
+    hipLaunchKernelGGL(k_gzero, dim3(1), dim3(kT), 0, s, g->dptr(g->o_flag), 1);
+    hipLaunchKernelGGL(k_gsrcT, dim3(blocks((int64_t)g->fw[c] * g->fh[c])), dim3(kT), 0, s, g->maps[c],
+                       g->freeze_inv[c], g->fw[c], g->fh[c], (const int*)(g->ws + g->o_x0) + c * np,
+                       (const int*)(g->ws + g->o_y0) + c * np, g->W, g->H, dG0, g->dptr(g->o_dsrc[c]),
+                       (int*)(g->ws + g->o_flag));
     hipLaunchKernelGGL(k_gwarpT, dim3(g->nblk), dim3(kT), 0, s, g->maps[c], g->fsrc[c], g->frow[c], g->fplane[c],
                        g->fw[c], g->fh[c], (const int*)(g->ws + g->o_x0) + c * np,
-                       (const int*)(g->ws + g->o_y0) + c * np, g->W, g->H, dG0, g->dptr(g->o_dsrc[c]),
-                       g->dptr(g->o_part));
+                       (const int*)(g->ws + g->o_y0) + c * np, g->W, g->H, dG0, g->dptr(g->o_part));
     hipLaunchKernelGGL(k_gsum, dim3(1), dim3(kT), 0, s, g->dptr(g->o_part), (int)g->nblk, 9, 9, g->dptr(g->o_res));
     hipLaunchKernelGGL(k_gtof32, dim3(blocks(ns)), dim3(kT), 0, s, g->dptr(g->o_dsrc[c]), (float*)d_frames[c].data,
                        g->fw[c], g->fh[c], d_frames[c].row_pitch / 4, d_frames[c].plane_pitch / 4);
     st = dev_ok(hipGetLastError(), "backward launch");
+    int flag = 0;
     if (!st) st = dev_ok(hipMemcpyAsync(res + 9 * c, g->dptr(g->o_res), 72, hipMemcpyDeviceToHost, s), "grad copy");
+    if (!st) st = dev_ok(hipMemcpyAsync(&flag, g->ws + g->o_flag, 4, hipMemcpyDeviceToHost, s), "flag copy");
     if (!st) st = dev_ok(hipStreamSynchronize(s), "backward synchronise");
+    if (!st && flag)
+      st = fail(STITCH_E_UNSUPPORTED, "camera %d: the frozen map %s", c,
+                (flag & 2) ? "reaches its horizon over the frame" : "magnifies a source pixel over about 20 times");
   }
   if (st) return st;
   for (int i = 0; i < 18; ++i) d_map[i] = res[i];

@@ -127,3 +127,36 @@ def test_adam_refinement_moves_the_corners_towards_the_truth():
         print(r.name, {k: (f"{v[0]:.3e}", f"{v[1]:.3f}px") for k, v in log.items()})
         assert log[50][0] < log[0][0]
         assert log[50][1] < log[0][1]
+
+
+def test_backward_is_deterministic_at_moved_maps():
+    """Cells frozen at one pair of maps, the loss and its adjoint taken at maps moved by a
+    fraction of a pixel (as during the refinement): against the oracle with the same frozen
+    cells, and two backward passes equal bit for bit (the frame adjoint is a gather)."""
+    rng = np.random.default_rng(77)
+    sizes, W, H, L = [(97, 81), (101, 79)], 147, 83, 3
+    frames = [torch.from_numpy(rng.random((3, h, w)).astype(np.float32)).to(DEV) for w, h in sizes]
+    Hs = [_small_h(rng, *sizes[0], 3.0), _small_h(rng, *sizes[1], W - sizes[1][0] - 4.0)]
+    moved = [h.copy() for h in Hs]
+    moved[1][0, 2] += 0.37
+    moved[1][1, 2] -= 0.21
+    masks = random_partition(rng, 2, H, W, "noise")
+    g = P.Grad(sizes, masks, W, H, L)
+    g.freeze(Hs)
+    runs = []
+    for _ in range(2):
+        loss = g.forward(frames, moved)
+        d_frames, d_map = g.backward()
+        torch.cuda.synchronize()
+        runs.append((loss, [d.clone().cpu() for d in d_frames], np.array(d_map, copy=True)))
+    assert runs[0][0] == runs[1][0]
+    for i in range(2):
+        assert torch.equal(runs[0][1][i], runs[1][1][i])
+    assert np.array_equal(runs[0][2], runs[1][2])
+    ora = o.GradOracle([f.double().cpu().numpy() for f in frames], masks, W, H, L, coords="spec")
+    st = ora.forward(moved, ora.cells(Hs))
+    want_frames, want_M = ora.backward(st)
+    assert abs(runs[0][0] - st["loss"]) <= 1e-10 * abs(st["loss"])
+    for i in range(2):
+        assert _rel(runs[0][1][i].numpy(), want_frames[i]) <= 1e-6, f"d frame {i}"
+        assert _rel(runs[0][2][i], want_M[i]) <= 1e-6, f"d M {i}"
