@@ -149,3 +149,19 @@ def test_multi_pair_calls_on_the_c2_rig():
         for x, y in [(x0, y0), (x0 + w, y0), (x0, y0 + h), (x0 + w, y0 + h)]:
             a, b = H @ np.array([x, y, 1.0]), H_true @ np.array([x, y, 1.0])
             assert np.hypot(*(a[:2] / a[2] - b[:2] / b[2])) < 1.0, (i, x, y)
+
+
+def test_the_largest_pair_table():
+    """256 pairs (the most one call takes) of small unequal capacities, some pairs empty:
+    every pair's matches, PROSAC counts, inliers and map equal the single-pair calls'."""
+    rng = np.random.default_rng(256)
+    inputs = []
+    for k in range(256):
+        cap_a, cap_b = int(rng.integers(4, 48)), int(rng.integers(4, 48))
+        count_a = 0 if k % 37 == 5 else int(rng.integers(0, cap_a + 1))
+        inputs.append(_synthetic_pair(rng, cap_a, cap_b, count_a, int(rng.integers(1, cap_b + 1)), k % 7))
+    pos = rng.integers(0, ND, (4, 10))
+    uni = _dev(np.random.default_rng(3).random((64, 4)), torch.float64)
+    want = _single(inputs, pos, uni, 80, 64)
+    ms, ps = _multi(inputs, pos, uni, 80, 64)
+    _assert_equal(ms, ps, want)
