@@ -1134,7 +1134,7 @@ def main():
         rocprof_summary(a.rocprof_summary)
         return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(f"bench.py: this build measures one GPU; --gpus {a.gpus} is not supported "
+        print(f"bench.py: measures one GPU; --gpus {a.gpus} is not supported "
               "(independent frames and jobs would shard round-robin across GPUs with no exchange)",
               file=sys.stderr)
         sys.exit(2)

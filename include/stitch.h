@@ -61,7 +61,7 @@ typedef enum {
   STITCH_E_MASK = 5,        /* seam weights do not sum to 255 at some canvas pixel */
   STITCH_E_WORKSPACE = 6,   /* workspace NULL, too small or not 256-byte aligned */
   STITCH_E_DEVICE = 7,      /* a HIP runtime call failed */
-  STITCH_E_UNSUPPORTED = 8, /* a dtype/layout combination this build does not provide */
+  STITCH_E_UNSUPPORTED = 8, /* a dtype/layout combination or a case the library does not provide */
   STITCH_E_STATE = 9        /* object used in the wrong state (e.g. plan not bound) */
 } stitch_status;
 
