@@ -609,9 +609,10 @@ stitch_status stitch_prosac(const int32_t* pts_a, const int32_t* pts_b, int32_t 
  * covers all pairs, each pair computed exactly as by stitch_lsh_match / stitch_prosac with
  * the same settings (results equal bit for bit).  The pair tables are HOST arrays of npairs
  * (1..256) entries; every pointer inside them is DEVICE memory with the meaning, layout and
- * limits of the single-pair call.  The calls upload their pair table into the head of the
- * workspace on the stream (so they are not for graph capture) and then launch two
- * (matching) or three (PROSAC) kernels.
+ * limits of the single-pair call.  Up to 16 pairs travel to the kernels as launch arguments
+ * (the call then allocates, copies and waits for nothing and can be captured into a graph);
+ * more are uploaded into the head of the workspace on the stream first (not for graph
+ * capture).  Then two (matching) or three (PROSAC) kernels are launched.
  * workspace: stitch_lsh_match_multi_workspace_bytes / stitch_prosac_multi_workspace_bytes
  *   (0 on bad arguments), 256-byte aligned, caller-owned.
  * Errors: NULL, SHAPE, WORKSPACE, DEVICE (as the single-pair calls, per pair). */

@@ -145,17 +145,34 @@ struct LshPairDev {
   int32_t cap_a, cap_b;
 };
 
-__global__ void __launch_bounds__(256) k_lsh_keys_multi(const LshPairDev* __restrict__ pairs, const LshParams P) {
-  const LshPairDev& q = pairs[blockIdx.y >> 1];
+// Up to kArgPairs pairs travel as a kernel argument (taken at launch: no upload and no host
+// wait, and the launch can be captured into a graph); more come from a device table.
+constexpr int kArgPairs = 16;
+template <typename D>
+struct PairArgs {
+  D p[kArgPairs];
+};
+template <typename D>
+__device__ __forceinline__ D pair_of(const D* __restrict__ table, const PairArgs<D>& args, int i) {
+  D q;
+  if (table) q = table[i];
+  else q = args.p[i];
+  return q;
+}
+
+__global__ void __launch_bounds__(256) k_lsh_keys_multi(const LshPairDev* __restrict__ pairs,
+                                                        const PairArgs<LshPairDev> args, const LshParams P) {
+  const LshPairDev q = pair_of(pairs, args, blockIdx.y >> 1);
   const bool b = blockIdx.y & 1;
   const int cap = b ? q.cap_b : q.cap_a;
   if ((int)blockIdx.x * 256 >= cap) return;
   lsh_keys_body(b ? q.desc_b : q.desc_a, b ? q.count_b : q.count_a, cap, P, b ? q.keys_b : q.keys_a, blockIdx.x);
 }
 
-__global__ void __launch_bounds__(256) k_lsh_match_multi(const LshPairDev* __restrict__ pairs, const LshParams P,
+__global__ void __launch_bounds__(256) k_lsh_match_multi(const LshPairDev* __restrict__ pairs,
+                                                         const PairArgs<LshPairDev> args, const LshParams P,
                                                          int max_dist) {
-  const LshPairDev& q = pairs[blockIdx.y];
+  const LshPairDev q = pair_of(pairs, args, blockIdx.y);
   if ((int)blockIdx.x * 4 >= q.cap_a) return;
   lsh_match_body(q.desc_a, q.count_a, q.cap_a, q.desc_b, q.count_b, q.cap_b, P, q.keys_a, q.keys_b, max_dist, q.match,
                  q.dist, blockIdx.x);
@@ -627,21 +644,23 @@ struct ProsacPairDev {
   int32_t cap_a, cap_b;
 };
 
-__global__ void __launch_bounds__(1024) k_prosac_prepare_multi(const ProsacPairDev* __restrict__ pairs, double T_N) {
-  const ProsacPairDev& q = pairs[blockIdx.y];
+__global__ void __launch_bounds__(1024) k_prosac_prepare_multi(const ProsacPairDev* __restrict__ pairs,
+                                                                const PairArgs<ProsacPairDev> args, double T_N) {
+  const ProsacPairDev q = pair_of(pairs, args, blockIdx.y);
   prosac_prepare_body(q.pts_a, q.pts_b, q.cap_b, q.match, q.dist, q.count_a, q.cap_a, T_N, q.misc, q.qa, q.qb, q.qi,
                       q.tp);
 }
 
-__global__ void __launch_bounds__(256) k_prosac_hyp_multi(const ProsacPairDev* __restrict__ pairs, int nhyp,
-                                                          double eps2) {
-  const ProsacPairDev& q = pairs[blockIdx.y];
+__global__ void __launch_bounds__(256) k_prosac_hyp_multi(const ProsacPairDev* __restrict__ pairs,
+                                                          const PairArgs<ProsacPairDev> args, int nhyp, double eps2) {
+  const ProsacPairDev q = pair_of(pairs, args, blockIdx.y);
   prosac_hyp_body(q.misc, q.qa, q.qb, q.tp, nhyp, q.uniforms, eps2, q.hyp_h, q.hyp_ok, q.hyp_counts, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(kFinalThreads) k_prosac_final_multi(const ProsacPairDev* __restrict__ pairs,
-                                                                      int nhyp, double eps2) {
-  const ProsacPairDev& q = pairs[blockIdx.y];
+                                                                      const PairArgs<ProsacPairDev> args, int nhyp,
+                                                                      double eps2) {
+  const ProsacPairDev q = pair_of(pairs, args, blockIdx.y);
   prosac_final_body(q.misc, q.qa, q.qb, q.qi, q.cap_a, nhyp, q.hyp_h, q.hyp_ok, q.hyp_counts, eps2, q.H, q.inliers,
                     q.mask);
 }
@@ -767,11 +786,18 @@ stitch_status stitch_lsh_match_multi(int32_t npairs, const stitch_match_pair* pa
     capa_max = std::max(capa_max, m.cap_a);
   }
   const hipStream_t s = (hipStream_t)stream;
-  hipError_t e = hipMemcpyAsync(workspace, tab.data(), tab.size() * sizeof(LshPairDev), hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return hip_fail(e, "matching table upload");
-  const LshPairDev* dev = (const LshPairDev*)workspace;
-  hipLaunchKernelGGL(k_lsh_keys_multi, dim3((cap_max + 255) / 256, 2 * npairs), dim3(256), 0, s, dev, P);
-  hipLaunchKernelGGL(k_lsh_match_multi, dim3((capa_max + 3) / 4, npairs), dim3(256), 0, s, dev, P, max_dist);
+  PairArgs<LshPairDev> args{};
+  const LshPairDev* dev = nullptr;
+  hipError_t e = hipSuccess;
+  if (npairs <= kArgPairs) {
+    for (int p = 0; p < npairs; ++p) args.p[p] = tab[p];
+  } else {
+    e = hipMemcpyAsync(workspace, tab.data(), tab.size() * sizeof(LshPairDev), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "matching table upload");
+    dev = (const LshPairDev*)workspace;
+  }
+  hipLaunchKernelGGL(k_lsh_keys_multi, dim3((cap_max + 255) / 256, 2 * npairs), dim3(256), 0, s, dev, args, P);
+  hipLaunchKernelGGL(k_lsh_match_multi, dim3((capa_max + 3) / 4, npairs), dim3(256), 0, s, dev, args, P, max_dist);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "matching launch");
   return STITCH_OK;
@@ -960,12 +986,19 @@ stitch_status stitch_prosac_multi(int32_t npairs, const stitch_prosac_pair* pair
   }
   const double eps2 = eps * eps;
   const hipStream_t s = (hipStream_t)stream;
-  hipError_t e = hipMemcpyAsync(workspace, tab.data(), tab.size() * sizeof(ProsacPairDev), hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return hip_fail(e, "PROSAC table upload");
-  const ProsacPairDev* dev = (const ProsacPairDev*)workspace;
-  hipLaunchKernelGGL(k_prosac_prepare_multi, dim3(1, npairs), dim3(1024), 0, s, dev, T_N);
-  hipLaunchKernelGGL(k_prosac_hyp_multi, dim3((nhyp + 3) / 4, npairs), dim3(256), 0, s, dev, nhyp, eps2);
-  hipLaunchKernelGGL(k_prosac_final_multi, dim3(1, npairs), dim3(kFinalThreads), 0, s, dev, nhyp, eps2);
+  PairArgs<ProsacPairDev> args{};
+  const ProsacPairDev* dev = nullptr;
+  hipError_t e = hipSuccess;
+  if (npairs <= kArgPairs) {
+    for (int p = 0; p < npairs; ++p) args.p[p] = tab[p];
+  } else {
+    e = hipMemcpyAsync(workspace, tab.data(), tab.size() * sizeof(ProsacPairDev), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "PROSAC table upload");
+    dev = (const ProsacPairDev*)workspace;
+  }
+  hipLaunchKernelGGL(k_prosac_prepare_multi, dim3(1, npairs), dim3(1024), 0, s, dev, args, T_N);
+  hipLaunchKernelGGL(k_prosac_hyp_multi, dim3((nhyp + 3) / 4, npairs), dim3(256), 0, s, dev, args, nhyp, eps2);
+  hipLaunchKernelGGL(k_prosac_final_multi, dim3(1, npairs), dim3(kFinalThreads), 0, s, dev, args, nhyp, eps2);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "PROSAC launch");
   return STITCH_OK;

@@ -165,3 +165,31 @@ def test_the_largest_pair_table():
     want = _single(inputs, pos, uni, 80, 64)
     ms, ps = _multi(inputs, pos, uni, 80, 64)
     _assert_equal(ms, ps, want)
+
+
+def test_all_pair_calls_replay_from_a_hip_graph():
+    """Up to 16 pairs travel as kernel arguments, so both calls allocate, copy and wait for
+    nothing and can be captured: three replays, with the outputs cleared by eager work and a
+    synchronisation between them, each equal to the eager calls."""
+    rng = np.random.default_rng(5)
+    inputs = [_synthetic_pair(rng, *c, k) for k, c in enumerate(CASES)]
+    pos = rng.integers(0, ND, (6, 14))
+    uni = _dev(np.random.default_rng(9).random((512, 4)), torch.float64)
+    ms, ps = _multi(inputs, pos, uni, 64, 512)
+    outs = ms.match + ms.dist + ps.mask + [ps.H, ps.inliers, ps.hyp_counts]
+    want = [t.clone() for t in outs]
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=side):
+        h = torch.cuda.current_stream().cuda_stream
+        ms.run_raw([(da, ca, db, cb) for da, ca, db, cb, _, _ in inputs], h)
+        ps.run_raw([(pa, pb, ms.match[p], ms.dist[p], ca, uni) for p, (_, ca, _, _, pa, pb) in enumerate(inputs)], h)
+    for _ in range(3):
+        for t in outs:
+            t.fill_(7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for got, ref in zip(outs, want):
+            assert torch.equal(got, ref)
