@@ -655,13 +655,13 @@ def time_register(rig, frames, steps, warmup, n_max=500, nd=256, nhyp=1024):
             matchers[i].run_raw(da, ca, db, cb, h)
             prosacs[i].run_raw(pa, pb, matchers[i].match, matchers[i].dist, ca, uni, h)
 
-    def match_prosac_one_call():
-        mset.run_raw(m_in, h)
-        pset.run_raw(p_in, h)
+    def match_prosac_one_call(handle=None):
+        mset.run_raw(m_in, h if handle is None else handle)
+        pset.run_raw(p_in, h if handle is None else handle)
 
-    def chain(t):
-        lset.run_raw([frames[t % len(frames)][c] for c in cams], pattern, h)
-        match_prosac_one_call()
+    def chain(t, handle=None):
+        lset.run_raw([frames[t % len(frames)][c] for c in cams], pattern, h if handle is None else handle)
+        match_prosac_one_call(handle)
 
     def timed(fn):
         for t in range(warmup):
@@ -698,7 +698,20 @@ def time_register(rig, frames, steps, warmup, n_max=500, nd=256, nhyp=1024):
             main.wait_event(ev)
 
     ms_mp_streams = timed(match_prosac_streams)
-    match_prosac_one_call()
+    # the whole chain captured once per frame set of the cycle and replayed from HIP graphs
+    # (every call of it takes its tables as launch arguments)
+    graphs = []
+    side = torch.cuda.Stream()
+    side.wait_stream(main)
+    for t in range(min(len(frames), warmup + steps)):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            chain(t, side.cuda_stream)
+        graphs.append(g)
+    torch.cuda.synchronize()
+    ms_graph = timed(lambda t: graphs[t % len(graphs)].replay())
+    del graphs
+    chain(0)                                        # frame set 0 again, as the per-pair calls saw it
     torch.cuda.synchronize()
     res = []
     for p, i in enumerate(pairs):
@@ -714,7 +727,8 @@ def time_register(rig, frames, steps, warmup, n_max=500, nd=256, nhyp=1024):
                     "inliers": int(pset.inliers[p]), "max_corner_error_px": round(err, 3),
                     "same_as_per_pair_calls": bool(torch.equal(pset.H[p], prosacs[i].H) and
                                                    torch.equal(mset.match[p], matchers[i].match))})
-    return {"ms_chain": ms_chain, "ms_match_prosac_one_call": ms_one, "ms_match_prosac": ms_mp,
+    return {"ms_chain": ms_chain, "ms_chain_graph": ms_graph, "ms_match_prosac_one_call": ms_one,
+            "ms_match_prosac": ms_mp,
             "ms_match_prosac_streams": ms_mp_streams,
             "pairs": res, "nhyp": nhyp,
             "features": (feats, pos, uni)}
@@ -1202,6 +1216,7 @@ def main():
             feats, pos, uni = G.pop("features")
             forms["register"] = {
                 "ms_per_rig_registration": round(G["ms_chain"], 4),
+                "ms_per_rig_registration_graph_replay": round(G["ms_chain_graph"], 4),
                 "ms_match_prosac_all_pairs_one_call_per_stage": round(G["ms_match_prosac_one_call"], 4),
                 "ms_match_prosac_all_pairs_per_pair_calls": round(G["ms_match_prosac"], 4),
                 "ms_match_prosac_all_pairs_stream_per_pair": round(G["ms_match_prosac_streams"], 4),
