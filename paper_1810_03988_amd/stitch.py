@@ -1042,6 +1042,23 @@ class MatcherSet:
         check(lib().stitch_lsh_match_multi(self.n, self.pairs, self.nd, self.tables, self.kbits, self.positions,
                                            self.max_dist, self._ws.data_ptr(), self._ws.numel(), stream_handle))
 
+    def run(self, inputs, stream=None):
+        """inputs: per pair (desc_a, count_a, desc_b, count_b) as for Matcher.run.  Returns
+        [(match, dist)] as host tensors."""
+        if len(inputs) != self.n:
+            raise ValueError(f"{len(inputs)} input pairs for a set of {self.n}")
+        for (da, ca, db, cb), (cap_a, cap_b) in zip(inputs, self.caps):
+            for d, cap in ((da, cap_a), (db, cap_b)):
+                if d.dtype != torch.int32 or d.dim() != 2 or d.shape[0] < cap or d.shape[1] != 2 * self.nd // 32 \
+                        or not d.is_contiguous() or not d.is_cuda:
+                    raise ValueError("descriptors must be contiguous int32 device tensors of (cap, 2 nd/32)")
+            for c in (ca, cb):
+                if c.dtype != torch.int32 or not c.is_cuda or c.numel() < 1:
+                    raise ValueError("counts must be int32 device tensors")
+        self.run_raw(inputs, _stream(stream))
+        torch.cuda.synchronize()
+        return [(m.cpu(), d.cpu()) for m, d in zip(self.match, self.dist)]
+
 
 class ProsacSet:
     """PROSAC (Sec. 4.2.2; Alg. 3, step 2) of several area pairs with one launch per stage
@@ -1079,3 +1096,21 @@ class ProsacSet:
             e.inlier_mask, e.hyp_counts = self.mask[p].data_ptr(), self.hyp_counts[p].data_ptr()
         check(lib().stitch_prosac_multi(self.n, self.pairs, self.nhyp, self.T_N, self.eps, self._ws.data_ptr(),
                                         self._ws.numel(), stream_handle))
+
+    def run(self, inputs, stream=None) -> list:
+        """inputs: per pair (pts_a, pts_b, match, dist, count_a, uniforms) as for Prosac.run.
+        Returns one dict per pair (H, inliers, mask, hyp_counts) on the host."""
+        if len(inputs) != self.n:
+            raise ValueError(f"{len(inputs)} input pairs for a set of {self.n}")
+        for (pa, pb, m, d, ca, u), (cap_a, cap_b) in zip(inputs, self.caps):
+            if u.dtype != torch.float64 or tuple(u.shape) != (self.nhyp, 4) or not u.is_contiguous():
+                raise ValueError(f"uniforms must be a contiguous ({self.nhyp}, 4) float64 tensor")
+            for t, n, name in ((pa, 2 * cap_a, "pts_a"), (pb, 2 * cap_b, "pts_b"), (m, cap_a, "match"),
+                               (d, cap_a, "dist"), (ca, 1, "count_a")):
+                if t.dtype != torch.int32 or not t.is_contiguous() or t.numel() < n or not t.is_cuda:
+                    raise ValueError(f"{name} must be a contiguous int32 device tensor of at least {n} elements")
+        self.run_raw(inputs, _stream(stream))
+        torch.cuda.synchronize()
+        return [{"H": self.H[p].cpu().numpy().reshape(3, 3), "inliers": int(self.inliers[p]),
+                 "mask": self.mask[p].cpu().numpy().astype(bool), "hyp_counts": self.hyp_counts[p].cpu().numpy()}
+                for p in range(self.n)]

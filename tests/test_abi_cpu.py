@@ -488,6 +488,16 @@ def test_binding_refuses_host_tensors_before_any_launch():
     pset.n, pset.pairs = 1, (S.ProsacPair * 1)()
     with pytest.raises(ValueError):
         S.ProsacSet.run_raw(pset, [(i32, i32, i32, i32, i32, torch.zeros((4, 4), dtype=torch.float64))], 0)
+    # the validating forms check dtype, shape and device first
+    mset.caps, mset.nd = [(8, 8)], 256
+    d = torch.zeros((8, 16), dtype=torch.int32)
+    with pytest.raises(ValueError, match="descriptors"):
+        S.MatcherSet.run(mset, [(d, i32[:1], d, i32[:1])])
+    pset.caps, pset.nhyp = [(8, 8)], 4
+    with pytest.raises(ValueError, match="pts_a"):
+        S.ProsacSet.run(pset, [(i32, i32, i32, i32, i32, torch.zeros((4, 4), dtype=torch.float64))])
+    with pytest.raises(ValueError, match="uniforms"):
+        S.ProsacSet.run(pset, [(i32, i32, i32, i32, i32, torch.zeros((3, 4), dtype=torch.float64))])
 
 
 def test_frame_backward_validates_on_host():

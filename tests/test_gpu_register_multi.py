@@ -193,3 +193,20 @@ def test_all_pair_calls_replay_from_a_hip_graph():
         torch.cuda.synchronize()
         for got, ref in zip(outs, want):
             assert torch.equal(got, ref)
+
+
+def test_validating_forms_return_the_same_results():
+    """MatcherSet.run and ProsacSet.run (argument checks, host results) on the synthetic pairs."""
+    rng = np.random.default_rng(31)
+    inputs = [_synthetic_pair(rng, *c, k) for k, c in enumerate(CASES[:3])]
+    pos = rng.integers(0, ND, (6, 14))
+    uni = _dev(np.random.default_rng(4).random((256, 4)), torch.float64)
+    want = _single(inputs, pos, uni, 64, 256)
+    caps = [(da.shape[0], db.shape[0]) for da, _, db, _, _, _ in inputs]
+    ms, ps = P.MatcherSet(caps, ND, pos, 64), P.ProsacSet(caps, 256)
+    got_m = ms.run([(da, ca, db, cb) for da, ca, db, cb, _, _ in inputs])
+    got_p = ps.run([(pa, pb, ms.match[p], ms.dist[p], ca, uni) for p, (_, ca, _, _, pa, pb) in enumerate(inputs)])
+    for (m, d), g, (wm, wd, wg) in zip(got_m, got_p, want):
+        assert torch.equal(m, wm) and torch.equal(d, wd)
+        assert np.array_equal(g["H"], wg["H"]) and g["inliers"] == wg["inliers"]
+        assert np.array_equal(g["mask"], wg["mask"]) and np.array_equal(g["hyp_counts"], wg["hyp_counts"])
