@@ -951,11 +951,15 @@ stitch_status stitch_plan_create(int32_t n, const int32_t* frame_w, const int32_
         c.band[k] = intersect(c.band[k], c.roi[k]);
       }
     }
-    // --- band storage windows: columns widened to multiples of 8 within the roi ---
+    // --- band storage windows: columns widened, within the roi, to whole 32-byte sectors
+    //     counted from the roi's origin, where the pass's tiles start: a tile's row of the
+    //     band then covers whole sectors, so no sector is written in part by two tiles ---
+    const int q = 32 / p->es;
     for (int k = 0; k < L; ++k) {
       const Rect b = c.band[k], r = c.roi[k];
       if (b.empty()) { c.lwin[k] = Rect{}; continue; }
-      const int x0 = std::max(r.x, b.x & ~7), x1 = std::min(r.x + r.w, (b.x + b.w + 7) & ~7);
+      const int x0 = r.x + (int)floor_div(b.x - r.x, q) * q;
+      const int x1 = std::min<int>(r.x + r.w, r.x + (int)ceil_div(b.x + b.w - r.x, q) * q);
       c.lwin[k] = Rect{x0, b.y, x1 - x0, b.h};
     }
     // --- keep the seam weights on roi[0] ---
