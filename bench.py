@@ -456,6 +456,24 @@ def profiled_traffic(config: str, form: str, storage: str, kind: str):
     return int(m.group(1)) if m else None
 
 
+def profiled_counters(config: str, form: str, storage: str, kernel: str):
+    """The derived per-CU figures (VALU_busy, TD_busy, ...) of one kernel from the committed
+    rocprofv3 counter summary of this workload, or None when there is none or the kernel or
+    planner source has changed since it was taken."""
+    import re
+    f = ROOT / "profiles" / f"counters_{config}_{form}_{storage}.txt"
+    if not f.exists():
+        return None
+    text = f.read_text()
+    m = re.search(r"source sha256: ([0-9a-f]{64})", text)
+    if not m or source_hash() != m.group(1):
+        return None
+    m = re.search(rf"^{re.escape(kernel)}\n(?:  raw .*\n)?  derived (.*)$", text, re.M)
+    if not m:
+        return None
+    return {k: float(v) for k, v in re.findall(r"([\w/]+)=([0-9.eE+-]+)", m.group(1))}
+
+
 def make_frames(rig, nframes, device):
     import workloads as wl
     return wl.render_rig_sequence(rig, range(nframes), device)
@@ -1048,6 +1066,11 @@ def run_c3(a):
                 "step_alg_bytes": int(sum(v["alg_bytes_per_launch"] * v["launches_per_step"] for v in kt.values())),
                 "step_frac": round(sum(v["alg_bytes_per_launch"] * v["launches_per_step"] for v in kt.values())
                                    / (head["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        # what holds the kernel under the HBM roof: its vector-ALU busy fraction from the
+        # committed counter summary (1.0: every SIMD issues a VALU instruction every 4 cycles)
+        kname = next((k for k, v in KERNEL_KINDS.items() if v == f"{dom} (f16)"), None)
+        ctr = profiled_counters("c3", "batched", "f16", kname) if kname else None
+        roof["valu_busy"] = ctr.get("VALU_busy") if ctr else None
     if a.copy_calibration_mib > 0:
         copy_calibration(a.copy_calibration_mib)
     cpu = None
