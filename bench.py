@@ -1068,7 +1068,8 @@ def run_c3(a):
                                    / (head["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
         # what holds the kernel under the HBM roof: its vector-ALU busy fraction from the
         # committed counter summary (1.0: every SIMD issues a VALU instruction every 4 cycles)
-        kname = next((k for k, v in KERNEL_KINDS.items() if v == f"{dom} (f16)"), None)
+        kname = next((k for want in (f"{dom}, batched (f16)", f"{dom} (f16)")
+                      for k, v in KERNEL_KINDS.items() if v == want), None)
         ctr = profiled_counters("c3", "batched", "f16", kname) if kname else None
         roof["valu_busy"] = ctr.get("VALU_busy") if ctr else None
     if a.copy_calibration_mib > 0:
